@@ -1,0 +1,493 @@
+"""Plain CPU oracle of the crane path optimizer (FP64).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  The product path (the HIP library and its
+binding) never imports this package, and this package imports nothing of the
+product except the seeded input generator.
+
+The heavy loops (kinematics, distances, spline, cost, gradient, Philox, EDT)
+are in ``oracle.c``; the optimizer of Algorithm 1 (sampling, selection,
+log-rank weights, mean and covariance update) is written out here with numpy,
+step by step in the paper's order.
+
+Readings of the paper taken here (each is also listed in the design notes):
+* the spline keeps the paper's four copies of the start and goal control
+  points on a uniform knot vector and runs over its K+3 non-constant spans;
+* the collision term uses the scalar d(q), the minimum over every sphere and
+  obstacle pair; sums over checkpoints run over k = 1..n_s;
+* the sampling distribution is N(mu, C) with sigma folded into C
+  (C_0 = sigma0^2 I), sampled through the lower Cholesky factor;
+* the covariance update uses the freshly updated mean;
+* elites are the first nu of the stable order on (cost, index), NaN last.
+
+Parity status: every function here is pinned by a CPU test (closed forms,
+invariants, brute force, finite differences, published Philox vectors) except
+multi-iteration optimizer trajectories beyond one step, which are chaotic and
+"parity unpinned" (only one-step parity and convergence properties are
+checked).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (-O2, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+               "-shared", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Robot(ctypes.Structure):
+    _fields_ = [("n_joints", ctypes.c_int32), ("type", ctypes.c_void_p), ("axis", ctypes.c_void_p),
+                ("origin", ctypes.c_void_p), ("q_min", ctypes.c_void_p), ("q_max", ctypes.c_void_p),
+                ("q_hold", ctypes.c_void_p), ("active", ctypes.c_void_p), ("n_spheres", ctypes.c_int32),
+                ("sphere_frame", ctypes.c_void_p), ("sphere_center", ctypes.c_void_p),
+                ("sphere_radius", ctypes.c_void_p), ("tip", ctypes.c_void_p)]
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [("has_ground", ctypes.c_int32), ("ground_z", ctypes.c_float), ("n_cyl", ctypes.c_int32),
+                ("cyl", ctypes.c_void_p), ("n_box", ctypes.c_int32), ("box", ctypes.c_void_p),
+                ("sdf", ctypes.c_void_p), ("sdf_dims", ctypes.c_int32 * 3),
+                ("sdf_origin", ctypes.c_float * 3), ("voxel", ctypes.c_float)]
+
+
+class _Cost(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("M", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("jp_mode", ctypes.c_int32), ("hinge", ctypes.c_int32), ("margin", ctypes.c_float),
+                ("lambda_c", ctypes.c_float), ("w_c", ctypes.c_float), ("w_l", ctypes.c_float)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.orc_fk.argtypes = [vp, vp, vp, vp, vp]
+        L.orc_sd_cylinder.argtypes = [vp, vp, vp]
+        L.orc_sd_cylinder.restype = ctypes.c_double
+        L.orc_sd_box.argtypes = [vp, vp, vp]
+        L.orc_sd_box.restype = ctypes.c_double
+        L.orc_sdf_query.argtypes = [vp, vp, vp]
+        L.orc_sdf_query.restype = ctypes.c_double
+        L.orc_config_distance.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.orc_config_distance.restype = ctypes.c_double
+        L.orc_n_checkpoints.argtypes = [vp]
+        L.orc_n_checkpoints.restype = ctypes.c_int
+        L.orc_path_points.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.orc_eval_paths.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_grad_paths.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp]
+        L.orc_eval_configs.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, i64, i32, vp]
+        L.orc_occupancy.argtypes = [vp, i64, vp, vp, ctypes.c_float, vp]
+        L.orc_edt_brute.argtypes = [vp, ctypes.c_uint8, vp, vp]
+        L.orc_edt_separable.argtypes = [vp, ctypes.c_uint8, vp, vp]
+        L.orc_sdf_from_edt.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.c_float, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class Model:
+    """Robot + scene + cost parameters marshalled for the C oracle.  Arrays are
+    kept referenced so the raw pointers stay valid."""
+
+    def __init__(self, robot, scene, cost, sdf: Optional[np.ndarray] = None, sdf_spec=None):
+        self.robot, self.scene, self.cost = robot, scene, cost
+        self._keep = []
+
+        def keep(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a.ctypes.data
+
+        r = _Robot()
+        r.n_joints = robot.n_joints
+        r.type = keep(robot.joint_type, np.int32)
+        r.axis = keep(robot.axis, np.float32)
+        r.origin = keep(robot.origin, np.float32)
+        r.q_min = keep(robot.q_min, np.float32)
+        r.q_max = keep(robot.q_max, np.float32)
+        r.q_hold = keep(robot.q_hold, np.float32)
+        r.active = keep(robot.active, np.uint8)
+        r.n_spheres = robot.n_spheres
+        r.sphere_frame = keep(robot.sphere_frame, np.int32)
+        r.sphere_center = keep(robot.sphere_center, np.float32)
+        r.sphere_radius = keep(robot.sphere_radius, np.float32)
+        r.tip = keep(robot.tip, np.float32)
+        s = _Scene()
+        s.has_ground = int(scene.has_ground)
+        s.ground_z = float(scene.ground_z)
+        s.n_cyl = scene.n_cyl
+        s.cyl = keep(scene.cyl if scene.n_cyl else np.zeros((1, 5)), np.float32)
+        s.n_box = scene.n_box
+        s.box = keep(scene.box if scene.n_box else np.zeros((1, 6)), np.float32)
+        if sdf is not None:
+            s.sdf = keep(sdf, np.float32)
+            for a in range(3):
+                s.sdf_dims[a] = int(sdf_spec.dims[a])
+                s.sdf_origin[a] = float(sdf_spec.origin[a])
+            s.voxel = float(sdf_spec.voxel)
+        else:
+            s.sdf = None
+        c = _Cost()
+        if cost is not None:
+            c.K, c.M, c.interp, c.jp_mode, c.hinge = cost.K, cost.M, cost.interp, cost.jp_mode, cost.hinge
+            c.margin, c.lambda_c, c.w_c, c.w_l = cost.margin, cost.lambda_c, cost.w_c, cost.w_l
+        self.r, self.s, self.c = r, s, c
+
+    # pointers
+    @property
+    def pr(self):
+        return ctypes.addressof(self.r)
+
+    @property
+    def ps(self):
+        return ctypes.addressof(self.s)
+
+    @property
+    def pc(self):
+        return ctypes.addressof(self.c)
+
+    def n_s(self) -> int:
+        return lib().orc_n_checkpoints(self.pc)
+
+
+# ----------------------------------------------------------------------------
+# kinematics, distances, path, cost
+# ----------------------------------------------------------------------------
+
+def fk(model: Model, q):
+    """Frames [n+1,12], sphere centres [S,3], tip [3] at joint vector q."""
+    q = np.ascontiguousarray(q, np.float64)
+    n, S = model.robot.n_joints, model.robot.n_spheres
+    frames = np.zeros((n + 1, 12))
+    cen = np.zeros((S, 3))
+    tip = np.zeros(3)
+    lib().orc_fk(model.pr, _p(q), _p(frames), _p(cen), _p(tip))
+    return frames, cen, tip
+
+
+def sd_cylinder(c, cyl, grad=False):
+    c = np.ascontiguousarray(c, np.float64)
+    cyl = np.ascontiguousarray(cyl, np.float32)
+    g = np.zeros(3)
+    d = lib().orc_sd_cylinder(_p(c), _p(cyl), _p(g))
+    return (d, g) if grad else d
+
+
+def sd_box(c, box, grad=False):
+    c = np.ascontiguousarray(c, np.float64)
+    box = np.ascontiguousarray(box, np.float32)
+    g = np.zeros(3)
+    d = lib().orc_sd_box(_p(c), _p(box), _p(g))
+    return (d, g) if grad else d
+
+
+def sdf_query(model: Model, c, grad=False):
+    c = np.ascontiguousarray(c, np.float64)
+    g = np.zeros(3)
+    d = lib().orc_sdf_query(model.ps, _p(c), _p(g))
+    return (d, g) if grad else d
+
+
+def eval_configs(model: Model, Q):
+    """d(q), argmin sphere, argmin obstacle and runner-up pair distance for
+    joint vectors Q [N,n]."""
+    Q = np.ascontiguousarray(Q, np.float64)
+    N = Q.shape[0]
+    d = np.zeros(N)
+    s = np.zeros(N, np.int32)
+    o = np.zeros(N, np.int32)
+    sec = np.zeros(N)
+    lib().orc_eval_configs(model.pr, model.ps, _p(Q), N, _p(d), _p(s), _p(o), _p(sec))
+    return d, s, o, sec
+
+
+def path_points(model: Model, q_start, q_goal, W):
+    """q(s_k), k = 0..n_s, for one path W [K,n] -> [n_s+1, n]."""
+    W = np.ascontiguousarray(W, np.float64)
+    qs = np.ascontiguousarray(q_start, np.float64)
+    qg = np.ascontiguousarray(q_goal, np.float64)
+    out = np.zeros((model.n_s() + 1, model.robot.n_joints))
+    lib().orc_path_points(model.pr, model.pc, _p(qs), _p(qg), _p(W), _p(out))
+    return out
+
+
+def eval_paths(model: Model, q_start, q_goal, W, per_checkpoint: bool = False):
+    """Cost, min distance and flag of each path W [B,K,n].  With
+    ``per_checkpoint`` also d_k, the tape (sphere << 16 | obstacle), the
+    runner-up pair distance [B,n_s] and (J_p, J_c, J_l) [B,3]."""
+    W = np.ascontiguousarray(W, np.float64)
+    B = W.shape[0]
+    qs = np.ascontiguousarray(q_start, np.float64)
+    qg = np.ascontiguousarray(q_goal, np.float64)
+    cost = np.zeros(B)
+    md = np.zeros(B)
+    fl = np.zeros(B, np.uint8)
+    out = {"cost": cost, "min_dist": md, "flags": fl}
+    dk = tape = sec = parts = None
+    if per_checkpoint:
+        ns = model.n_s()
+        dk = np.zeros((B, ns))
+        tape = np.zeros((B, ns), np.int32)
+        sec = np.zeros((B, ns))
+        parts = np.zeros((B, 3))
+        out.update(d=dk, tape=tape, second=sec, parts=parts)
+    lib().orc_eval_paths(model.pr, model.ps, model.pc, _p(qs), _p(qg), _p(W), B, _p(cost), _p(md), _p(fl),
+                         _p(dk), _p(tape), _p(sec), _p(parts))
+    return out
+
+
+def grad_paths(model: Model, q_start, q_goal, W):
+    """Analytic d cost / d W [B,K,n] and the cost [B]."""
+    W = np.ascontiguousarray(W, np.float64)
+    B = W.shape[0]
+    qs = np.ascontiguousarray(q_start, np.float64)
+    qg = np.ascontiguousarray(q_goal, np.float64)
+    cost = np.zeros(B)
+    g = np.zeros(W.shape)
+    lib().orc_grad_paths(model.pr, model.ps, model.pc, _p(qs), _p(qg), _p(W), B, _p(cost), _p(g))
+    return cost, g
+
+
+def fd_grad(model: Model, q_start, q_goal, W, h: float = 1e-6):
+    """Central finite differences of the double-precision cost of each path,
+    (J(W + h e) - J(W - h e)) / 2h for every waypoint entry -> [B,K,n]."""
+    W = np.asarray(W, np.float64)
+    B, K, n = W.shape
+    g = np.zeros(W.shape)
+    for i in range(K):
+        for j in range(n):
+            Wp = W.copy()
+            Wm = W.copy()
+            Wp[:, i, j] += h
+            Wm[:, i, j] -= h
+            cp = eval_paths(model, q_start, q_goal, Wp)["cost"]
+            cm = eval_paths(model, q_start, q_goal, Wm)["cost"]
+            g[:, i, j] = (cp - cm) / (2.0 * h)
+    return g
+
+
+# ----------------------------------------------------------------------------
+# RNG
+# ----------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def normals(seed: int, t: int, B: int, D: int, problem: int = 0):
+    z = np.zeros((B, D))
+    lib().orc_normals(ctypes.c_uint64(seed), t, problem, B, D, _p(z))
+    return z
+
+
+# ----------------------------------------------------------------------------
+# signed-distance grid
+# ----------------------------------------------------------------------------
+
+def occupancy(points, dims, origin, voxel):
+    pts = np.ascontiguousarray(points, np.float32)
+    d = np.ascontiguousarray(dims, np.int32)
+    o = np.ascontiguousarray(origin, np.float32)
+    occ = np.zeros((dims[2], dims[1], dims[0]), np.uint8)
+    lib().orc_occupancy(_p(pts), pts.shape[0], _p(d), _p(o), float(voxel), _p(occ))
+    return occ
+
+
+def edt(mask, target: int = 1, brute: bool = False):
+    """Squared Euclidean distance (voxel units) from every voxel of ``mask``
+    [nz,ny,nx] to the nearest voxel whose value equals ``target``."""
+    mask = np.ascontiguousarray(mask, np.uint8)
+    nz, ny, nx = mask.shape
+    d = np.array([nx, ny, nz], np.int32)
+    out = np.zeros(mask.shape, np.int64)
+    fn = lib().orc_edt_brute if brute else lib().orc_edt_separable
+    fn(_p(mask), target, _p(d), _p(out))
+    return out
+
+
+def sdf_from_occupancy(occ, voxel):
+    occ = np.ascontiguousarray(occ, np.uint8)
+    e_occ = edt(occ, 1)
+    e_free = edt(occ, 0)
+    phi = np.zeros(occ.shape)
+    lib().orc_sdf_from_edt(_p(occ), _p(e_occ), _p(e_free), occ.size, float(voxel), _p(phi))
+    return phi, e_occ, e_free
+
+
+def sdf_build(points, spec):
+    occ = occupancy(points, spec.dims, spec.origin, spec.voxel)
+    phi, e_occ, e_free = sdf_from_occupancy(occ, spec.voxel)
+    return phi, occ, e_occ, e_free
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1: stochastic optimization with log-rank weights
+# ----------------------------------------------------------------------------
+
+class NotPositiveDefinite(RuntimeError):
+    pass
+
+
+def log_rank_weights(nu: int) -> np.ndarray:
+    """Step (4): w_j = (ln(nu + 1/2) - ln j) / sum_k (ln(nu + 1/2) - ln k)."""
+    j = np.arange(1, nu + 1, dtype=np.float64)
+    a = math.log(nu + 0.5) - np.log(j)
+    return a / a.sum()
+
+
+def initial_mean(robot, q_start, q_goal, K: int) -> np.ndarray:
+    """Control points evenly spaced on the segment from start to goal
+    (Sec. 4.1 initial guess): W_i = q_s + (i+1)/(K+1) (q_g - q_s), active
+    joints only, flattened [K * n_active] (waypoint-major)."""
+    act = robot.active.astype(bool)
+    qs = np.asarray(q_start, np.float64)[act]
+    qg = np.asarray(q_goal, np.float64)[act]
+    i = np.arange(K, dtype=np.float64)[:, None]
+    return (qs[None, :] + (i + 1.0) / (K + 1.0) * (qg - qs)[None, :]).reshape(-1)
+
+
+def cholesky_jitter(C: np.ndarray, eps: float) -> np.ndarray:
+    """Lower Cholesky factor of C; if C is not numerically positive definite,
+    retry with C + 10^k eps I for k = 1, 2, 3."""
+    D = C.shape[0]
+    for k in range(4):
+        A = C if k == 0 else C + (10.0 ** k) * eps * np.eye(D)
+        try:
+            return np.linalg.cholesky(A)
+        except np.linalg.LinAlgError:
+            continue
+    raise NotPositiveDefinite("covariance is not positive definite")
+
+
+def expand(robot, xi: np.ndarray, K: int) -> np.ndarray:
+    """Samples xi [B, K*n_active] -> waypoints [B,K,n] (double); joints that
+    are not sampled take their hold value."""
+    B = xi.shape[0]
+    n = robot.n_joints
+    act = robot.active.astype(bool)
+    W = np.empty((B, K, n), np.float64)
+    W[:, :, act] = xi.reshape(B, K, int(act.sum()))
+    W[:, :, ~act] = robot.q_hold[~act]
+    return W
+
+
+def select(cost: np.ndarray, nu: int) -> np.ndarray:
+    """Step (3): indices of the nu lowest costs, stable on (cost, index), NaN
+    ranked after every number."""
+    key = np.where(np.isnan(cost), np.inf, cost)
+    order = np.lexsort((np.arange(cost.shape[0]), key))
+    return order[:nu]
+
+
+def update(xi_elite: np.ndarray, w: np.ndarray, eps: float):
+    """Steps (5)-(6): mu' = sum_j w_j x_(j);
+    C' = sum_j w_j (x_(j) - mu')(x_(j) - mu')^T + eps I."""
+    mu = w @ xi_elite
+    diff = xi_elite - mu[None, :]
+    C = (diff * w[:, None]).T @ diff + eps * np.eye(xi_elite.shape[1])
+    return mu, C
+
+
+class Optimizer:
+    """Algorithm 1 on one problem, step by step, in double precision."""
+
+    def __init__(self, problem, model: Optional[Model] = None, problem_id: int = 0):
+        self.p = problem
+        self.model = model or Model(problem.robot, problem.scene, problem.cost)
+        K = problem.cost.K
+        self.K = K
+        self.D = K * problem.robot.n_active
+        self.mu = initial_mean(problem.robot, problem.q_start, problem.q_goal, K)
+        self.C = (problem.opt.sigma0 ** 2) * np.eye(self.D)
+        self.t = 0
+        self.problem_id = problem_id
+        self.w = log_rank_weights(problem.opt.nu)
+        self.best_cost = math.inf
+        self.best_xi = None
+        self.history = []
+
+    def set_state(self, mu, C, t):
+        self.mu = np.array(mu, np.float64)
+        self.C = np.array(C, np.float64)
+        self.t = int(t)
+
+    def sample(self):
+        """Step (1): xi_b = mu + L z_b with z from Philox/Box-Muller."""
+        L = cholesky_jitter(self.C, self.p.opt.eps)
+        z = normals(self.p.opt.seed, self.t, self.p.opt.B, self.D, self.problem_id)
+        return self.mu[None, :] + z @ L.T
+
+    def polish(self, xi_elite):
+        """Gradient polish of the elites: each takes ``polish_steps`` steps
+        W <- W - eta g / max(1, |g| / g_max) on the active joints."""
+        o = self.p.opt
+        act = self.p.robot.active.astype(bool)
+        xi = xi_elite.copy()
+        for _ in range(o.polish_steps):
+            W = expand(self.p.robot, xi, self.K)
+            _, g = grad_paths(self.model, self.p.q_start, self.p.q_goal, W)
+            g = g[:, :, act].reshape(xi.shape[0], -1)
+            nrm = np.sqrt((g * g).sum(1))
+            scale = o.polish_eta / np.maximum(1.0, nrm / o.polish_clip)
+            xi = xi - scale[:, None] * g
+        return xi
+
+    def step(self):
+        o = self.p.opt
+        xi = self.sample()
+        W = expand(self.p.robot, xi, self.K)
+        r = eval_paths(self.model, self.p.q_start, self.p.q_goal, W)
+        cost = r["cost"]
+        elite = select(cost, o.nu)
+        xe = xi[elite]
+        ce = cost[elite]
+        if o.polish_steps > 0 and o.polish_elites > 0:
+            npol = min(o.polish_elites, o.nu)
+            xe = xe.copy()
+            xe[:npol] = self.polish(xe[:npol])
+            rp = eval_paths(self.model, self.p.q_start, self.p.q_goal, expand(self.p.robot, xe, self.K))
+            ce = rp["cost"]
+            order = select(ce, o.nu)
+            xe, ce = xe[order], ce[order]
+        mu, C = update(xe, self.w, o.eps)
+        # best-so-far over every evaluated sample, ties by (iteration, index)
+        kb = int(select(cost, 1)[0])
+        if cost[kb] < self.best_cost:
+            self.best_cost = float(cost[kb])
+            self.best_xi = xi[kb].copy()
+        if o.polish_steps > 0 and ce.size and ce[0] < self.best_cost:
+            self.best_cost = float(ce[0])
+            self.best_xi = xe[0].copy()
+        self.history.append(dict(t=self.t, elite=elite, cost=cost, mu=mu, C=C))
+        self.mu, self.C = mu, C
+        self.t += 1
+        return dict(xi=xi, cost=cost, elite=elite, mu=mu, C=C)

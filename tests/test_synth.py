@@ -1,0 +1,46 @@
+"""The seeded workloads are well formed: shapes, sizes and start/goal poses
+clear of every obstacle (checked with the oracle's distances)."""
+import numpy as np
+import pytest
+
+from paper_2503_14160_amd import synth
+
+
+def test_robot_layout():
+    for S in (24, 64):
+        rb = synth.make_robot(1000, S)
+        assert rb.n_joints == 6 and rb.n_spheres == S and rb.n_active == 4
+        counts = np.bincount(rb.sphere_frame, minlength=7)
+        assert counts[[1, 2, 3, 4, 6]].min() >= 1 and counts[0] == 0 and counts[5] == 0
+        assert np.all((rb.sphere_radius >= 0.15) & (rb.sphere_radius <= 0.4))
+        assert np.all((rb.link_lengths >= 2) & (rb.link_lengths <= 5))
+
+
+@pytest.mark.parametrize("name", ["c0_plain", "c1_full", "c2_diff"])
+def test_workload_endpoints_clear(orc, name):
+    p = synth.WORKLOADS[name]()
+    assert p.q_start.shape == (6,) and p.q_goal.shape == (6,)
+    assert abs(float(p.q_goal[0] - p.q_start[0])) >= np.pi / 2 - 1e-6
+    m = orc.Model(p.robot, p.scene, p.cost)
+    d, _, _, _ = orc.eval_configs(m, np.stack([p.q_start, p.q_goal]).astype(np.float64))
+    assert np.all(d > 0.0), d
+    _, _, tip = orc.fk(m, p.q_start)
+    assert tip[2] >= 0.5
+
+
+def test_sizes():
+    p0 = synth.c0_plain()
+    assert (p0.opt.B, p0.cost.K, p0.cost.M, p0.cost.n_s, p0.robot.n_spheres, p0.scene.n_cyl) == (256, 8, 16, 176, 24, 32)
+    p1 = synth.c1_full()
+    assert (p1.opt.B, p1.cost.K, p1.cost.M, p1.cost.n_s, p1.robot.n_spheres, p1.scene.n_cyl, p1.scene.n_box,
+            p1.opt.nu) == (16384, 16, 32, 608, 64, 512, 16, 819)
+
+
+def test_batch_problems_clear(orc):
+    probs = synth.c3_batch(24)
+    for p in probs:
+        assert 512 <= p.opt.B <= 8192 and 8 <= p.cost.K <= 24
+        assert 64 <= p.scene.n_cyl + p.scene.n_box <= 1024
+        m = orc.Model(p.robot, p.scene, p.cost)
+        d, _, _, _ = orc.eval_configs(m, np.stack([p.q_start, p.q_goal]).astype(np.float64))
+        assert np.all(d > 0.0), (p.name, d)
