@@ -1,0 +1,249 @@
+/*
+ * craneplan: MI355X (gfx950) library for the GPU stochastic path optimizer of
+ * an underactuated forestry crane (Vu et al., "GPU-Accelerated Motion
+ * Planning of an Underactuated Forestry Crane in Cluttered Environments",
+ * arXiv 2503.14160), first planning step.
+ *
+ * The optimizer (Algorithm 1) samples B perturbed sets of free B-spline
+ * control points ("waypoints") around a mean, evaluates each path
+ *   J = J_p + w_c J_c + w_l J_l                          (Sec. 4.1, path opt.)
+ * over n_s checkpoints, keeps the nu cheapest ("elites"), and re-fits the mean
+ * and covariance to them with log-rank weights.  Path evaluation runs forward
+ * kinematics (Sec. 2) at every checkpoint and takes the signed distance d(q)
+ * of the crane to the scene (Sec. 3.1) as the minimum over every
+ * (link sphere, obstacle) pair.
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are device pointers on the plan's device; everything
+ *    else is host memory.  Device buffers are caller-allocated, contiguous,
+ *    4-byte aligned (8-byte for double), and must not alias each other.
+ *  - Floating-point data is IEEE float32 unless the name says double.
+ *  - Calls marked SYNC return after the work is done; all others only enqueue
+ *    work on `stream` (a hipStream_t; NULL = the default stream) and return.
+ *    Device-side failures surface at the caller's next synchronisation.
+ *  - Return value: CP_OK (0) or a negative CP_ERR_* code; arguments are
+ *    validated on the host before anything is enqueued, and a failed call
+ *    enqueues nothing.  cp_last_error() describes the last failure of the
+ *    calling thread.  No C++ exception crosses this interface.
+ *  - A plan / optimizer / batch must not be used from two threads at once;
+ *    distinct objects are independent.  Calls on one object that are enqueued
+ *    on different streams must be ordered by the caller.
+ *  - Joint vectors have n_joints entries; waypoints are [B][K][n_joints].
+ *
+ * Layout of a path (Sec. 4.1, B-spline path and initial guess): the control
+ * polygon is 4 copies of q_start, the K waypoints, 4 copies of q_goal, on a
+ * uniform knot vector; the path runs over its K+3 non-constant spans, M
+ * checkpoints per span, s_k = k / n_s, n_s = (K+3) M, k = 1..n_s.  In linear
+ * mode the polygon is q_start, the waypoints, q_goal (n_s = (K+1) M).
+ */
+#ifndef CRANEPLAN_H
+#define CRANEPLAN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cp_plan cp_plan;
+typedef struct cp_opt cp_opt;
+typedef void *cp_stream_t; /* a hipStream_t */
+
+enum {
+    CP_OK = 0,
+    CP_ERR_INVALID_ARG = -1, /* null pointer, bad enum value, inconsistent description */
+    CP_ERR_SIZE = -2,        /* a size outside the limits below or the plan's capacity */
+    CP_ERR_HIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
+    CP_ERR_NOT_PD = -4,      /* covariance not positive definite after jitter retries */
+    CP_ERR_STATE = -5,       /* call not valid in the object's current state */
+    CP_ERR_NOMEM = -6        /* device or host allocation failed */
+};
+
+/* limits */
+#define CP_MAX_JOINTS 8
+#define CP_MAX_SPHERES 128
+#define CP_MAX_K 64
+#define CP_MAX_ELITES 4096
+#define CP_MAX_DIM 96 /* K * (number of sampled joints) */
+
+enum { CP_REVOLUTE = 0, CP_PRISMATIC = 1 };
+enum { CP_INTERP_BSPLINE = 0, CP_INTERP_LINEAR = 1 };
+enum { CP_JP_SQUARED = 0, CP_JP_L2 = 1 };
+enum { CP_HINGE_HARD = 0, CP_HINGE_SMOOTH = 1 };
+
+/* tape entry of a checkpoint: (sphere << 16) | obstacle, where obstacle 0 is
+ * the ground, 1..n_cyl the cylinders, n_cyl+1..n_cyl+n_box the boxes, and
+ * CP_OBS_SDF the signed-distance grid (scene and sphere table order). */
+#define CP_OBS_SDF 0xFFFFu
+
+/*
+ * Crane: a serial chain (Sec. 2).  Joint j (0-based) moves frame j+1 relative
+ * to frame j: a fixed translation origin[j] (in frame j), then a rotation by
+ * q_j about the unit axis[j] (revolute) or a translation q_j * axis[j]
+ * (prismatic).  Frame 0 is the world.  Sphere s is rigidly attached to frame
+ * sphere_frame[s] in 0..n_joints at local centre sphere_center[s].
+ * Joints with active[j] = 0 are not sampled; the optimizer holds them at
+ * q_hold[j].  All pointers are host pointers, copied at plan creation.
+ */
+typedef struct {
+    int32_t n_joints;            /* 1..CP_MAX_JOINTS */
+    const int32_t *type;         /* [n] CP_REVOLUTE / CP_PRISMATIC */
+    const float *axis;           /* [n][3] unit vectors */
+    const float *origin;         /* [n][3] */
+    const float *q_min, *q_max;  /* [n] joint limits (feasibility cost) */
+    const float *q_hold;         /* [n] */
+    const uint8_t *active;       /* [n] 1 = sampled */
+    int32_t n_spheres;           /* 1..CP_MAX_SPHERES */
+    const int32_t *sphere_frame; /* [S] */
+    const float *sphere_center;  /* [S][3] */
+    const float *sphere_radius;  /* [S] > 0 */
+} cp_robot_desc;
+
+/*
+ * Scene (Sec. 3.1; the paper's meshes are replaced by primitives with exact
+ * signed distances): vertical solid cylinders (x, y, R, z0, z1), axis-aligned
+ * solid boxes (cx, cy, cz, hx, hy, hz), the half-space z <= ground_z, and/or a
+ * signed-distance grid sampled at voxel centres, queried by trilinear
+ * interpolation.  cyl/box are host pointers copied at creation; d_sdf is a
+ * device pointer that the plan borrows: it must stay alive and unchanged
+ * while the plan is used.
+ */
+typedef struct {
+    int32_t has_ground;
+    float ground_z;
+    int32_t n_cyl;               /* 0..65533 together with n_box */
+    const float *cyl;            /* [n_cyl][5] */
+    int32_t n_box;
+    const float *box;            /* [n_box][6] */
+    const float *d_sdf;          /* [nz][ny][nx] or NULL */
+    int32_t sdf_dims[3];         /* nx, ny, nz (each >= 2) */
+    float sdf_origin[3];         /* lower corner of voxel (0,0,0), metres */
+    float voxel;                 /* voxel edge, metres */
+} cp_scene_desc;
+
+/* Cost of a path (Sec. 4.1, eqs. for J_p, J_c, J_l).  The collision term is
+ * phi(d) = lambda_c max(0, margin - d) (hard hinge; margin 0 is the paper's
+ * ReLU(-d)), or the C1 smooth hinge lambda_c (margin/2 - d) for d < 0,
+ * lambda_c (margin - d)^2 / (2 margin) for 0 <= d < margin, 0 beyond.
+ * J_p sums |q_k - q_{k-1}|^2 (squared, the paper's) or |q_k - q_{k-1}| (L2). */
+typedef struct {
+    int32_t K;        /* free waypoints, 1..CP_MAX_K */
+    int32_t M;        /* checkpoints per span, >= 1 */
+    int32_t interp;   /* CP_INTERP_* */
+    int32_t jp_mode;  /* CP_JP_* */
+    int32_t hinge;    /* CP_HINGE_* (smooth needs margin > 0) */
+    float margin;     /* metres */
+    float lambda_c;
+    float w_c, w_l;
+    int32_t max_B;    /* largest batch any call on this plan will pass */
+} cp_cost_params;
+
+/* Algorithm 1 settings.  C_0 = sigma0^2 I; samples are xi ~ N(mu, C).  The
+ * normal variates of element e of path b in iteration t come from
+ * Philox4x32-10 with key (seed low word, seed high word) and counter
+ * (e / 4, b, t, problem_id), four words -> two Box-Muller pairs. */
+typedef struct {
+    int32_t B;              /* population (lambda), 1..max_B */
+    int32_t nu;             /* elites, 1..min(B, CP_MAX_ELITES) */
+    float sigma0;
+    double eps;             /* covariance regulariser (eps I) */
+    uint64_t seed;
+    uint32_t problem_id;
+    int32_t polish_elites;  /* elites that take gradient steps each iteration (0 = off) */
+    int32_t polish_steps;
+    float polish_eta;       /* step length */
+    float polish_clip;      /* gradient norm clip g_max */
+} cp_opt_params;
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *cp_last_error(void);
+
+/* Create a plan on HIP device `device` (SYNC).  Copies the robot, the
+ * primitive tables and the cost parameters to the device and allocates the
+ * evaluation workspace for up to cost->max_B paths.  Endpoints start at the
+ * hold configuration. */
+int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const cp_cost_params *cost,
+                   int device, cp_plan **out);
+int cp_plan_destroy(cp_plan *plan); /* SYNC; NULL is a no-op */
+
+/* Start and goal configurations q_0 and q_d (host [n_joints]) (SYNC). */
+int cp_plan_set_endpoints(cp_plan *plan, const float *q_start, const float *q_goal);
+
+/* n_s, the checkpoints per path (k = 1..n_s; the start point is not checked). */
+int cp_plan_n_checkpoints(const cp_plan *plan, int32_t *n_s);
+
+/*
+ * Algorithm 1 step (2): evaluate B paths.
+ *  d_waypoints [B][K][n] -> d_cost [B] (J), d_min_dist [B] (min_k d(q_k)),
+ *  d_flags [B] (1 if min_dist < margin; may be NULL),
+ *  d_tape [B][n_s] (argmin pair of every checkpoint; may be NULL).
+ * Non-finite waypoints give a NaN cost.  B must be in 1..max_B.
+ */
+int cp_eval_paths(cp_plan *plan, const float *d_waypoints, int32_t B, float *d_cost, float *d_min_dist,
+                  uint8_t *d_flags, uint32_t *d_tape, cp_stream_t stream);
+
+/*
+ * Adjoint of cp_eval_paths: d_grad_waypoints[b] = d_grad_cost[b] * dJ_b/dW_b
+ * [B][K][n] (every joint, sampled or not).  d_tape is the tape written by
+ * cp_eval_paths for the same waypoints, or NULL to recompute the argmin
+ * pairs.  Forward kinematics is recomputed, never stored.  Where the
+ * minimising pair is tied the lowest (sphere, obstacle) is differentiated.
+ */
+int cp_eval_paths_backward(cp_plan *plan, const float *d_waypoints, int32_t B, const uint32_t *d_tape,
+                           const float *d_grad_cost, float *d_grad_waypoints, cp_stream_t stream);
+
+/* Optimizer on a plan (SYNC).  mu_0 = evenly spaced waypoints on the segment
+ * from q_start to q_goal (sampled joints only), C_0 = sigma0^2 I, t = 0.  The
+ * plan must outlive the optimizer; its endpoints are read at every step. */
+int cp_optimizer_create(cp_plan *plan, const cp_opt_params *params, cp_opt **out);
+int cp_optimizer_destroy(cp_opt *opt); /* SYNC; NULL is a no-op */
+
+/* Run n_iters iterations of Algorithm 1 (Cholesky factor, sampling,
+ * evaluation, selection, optional polish, log-rank weights, mean and
+ * covariance update) without host synchronisation. */
+int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream);
+
+/* State (SYNC): mu [D] and C [D][D] (double, D = K * sampled joints), the
+ * iteration counter, the best cost seen and its waypoints [K][n].  Any
+ * pointer may be NULL.  Returns CP_ERR_NOT_PD if a covariance could not be
+ * factorised since the last call. */
+int cp_optimizer_get_state(cp_opt *opt, double *mu, double *C, int64_t *iter, float *best_cost,
+                           float *best_waypoints);
+/* Replace mu, C and the iteration counter (SYNC); resets best-so-far. */
+int cp_optimizer_set_state(cp_opt *opt, const double *mu, const double *C, int64_t iter);
+
+/* Copies of the last iteration's population (enqueued on stream): the
+ * waypoints [B][K][n], costs [B] and elite indices [nu] in rank order (after
+ * polish: indices >= B denote polished elite slots).  Any may be NULL. */
+int cp_optimizer_last(cp_opt *opt, float *d_waypoints, float *d_cost, int32_t *d_elite, cp_stream_t stream);
+
+/* Signed-distance grid from a point cloud (for scenes given as lidar):
+ * voxels holding at least one point are occupied (index floor((p - o) / h) in
+ * double precision; points outside the grid are dropped); exact squared
+ * distances (voxel units) to the nearest occupied / free voxel; field
+ * h (sqrt(EDT_occ) - 1/2) on free voxels, -h (sqrt(EDT_free) - 1/2) on
+ * occupied ones.  With no occupied (free) voxel the squared distance is
+ * nx^2 + ny^2 + nz^2.  d_points [N][3]; outputs [nz][ny][nx]; the three
+ * optional outputs may be NULL.  Needs 8 bytes of device workspace per voxel,
+ * allocated and freed by the call (which therefore synchronises the stream). */
+int cp_sdf_build(const float *d_points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
+                 float *d_sdf, uint8_t *d_occ, int32_t *d_edt_occ, int32_t *d_edt_free, cp_stream_t stream);
+
+/* Test exports.  Forward kinematics of N joint vectors d_q [N][n]:
+ * sphere centres [N][S][3] (sphere table order) and frames [N][n+1][12]
+ * (row-major rotation then position); either output may be NULL. */
+int cp_debug_fk(cp_plan *plan, const float *d_q, int32_t N, float *d_centers, float *d_frames, cp_stream_t stream);
+/* d(q) and the argmin pair (tape encoding) of N joint vectors. */
+int cp_debug_eval_configs(cp_plan *plan, const float *d_q, int32_t N, float *d_dist, uint32_t *d_argmin,
+                          cp_stream_t stream);
+/* Selection step of Algorithm 1 (step 3) alone: indices of the nu smallest
+ * (cost, index) pairs of d_cost [B] in rank order, NaN after every number,
+ * written to d_elite [nu]; 1 <= nu <= min(B, CP_MAX_ELITES).  Runs on the
+ * current device. */
+int cp_debug_select(const float *d_cost, int32_t B, int32_t nu, int32_t *d_elite, cp_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRANEPLAN_H */

@@ -427,7 +427,9 @@ class Optimizer:
         self.K = K
         self.D = K * problem.robot.n_active
         self.mu = initial_mean(problem.robot, problem.q_start, problem.q_goal, K)
-        self.C = (problem.opt.sigma0 ** 2) * np.eye(self.D)
+        # sigma0 is a single-precision parameter of the problem statement
+        s0 = float(np.float32(problem.opt.sigma0))
+        self.C = (s0 * s0) * np.eye(self.D)
         self.t = 0
         self.problem_id = problem_id
         self.w = log_rank_weights(problem.opt.nu)

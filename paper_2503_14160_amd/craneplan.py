@@ -1,0 +1,342 @@
+"""Python binding of the craneplan C-ABI library (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libcraneplan.so``; this module
+only converts arguments, hands device pointers of torch tensors to the
+library, and enqueues on torch's current HIP stream.  It raises if the
+library has not been built (``python -m paper_2503_14160_amd.build``); there
+is no fallback path.
+
+Robot, scene and parameter arguments are read by attribute name (the field
+names of the declarations in ``include/craneplan.h``), so any object with
+those attributes works, e.g. the dataclasses of ``paper_2503_14160_amd.synth``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcraneplan.so")
+
+_c_i32, _c_f32, _c_f64, _c_u64, _c_u32, _vp = (ctypes.c_int32, ctypes.c_float, ctypes.c_double, ctypes.c_uint64,
+                                               ctypes.c_uint32, ctypes.c_void_p)
+
+CP_OBS_SDF = 0xFFFF
+EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_endpoints", "cp_plan_n_checkpoints",
+           "cp_eval_paths", "cp_eval_paths_backward", "cp_optimizer_create", "cp_optimizer_destroy",
+           "cp_optimizer_step", "cp_optimizer_get_state", "cp_optimizer_set_state", "cp_optimizer_last",
+           "cp_sdf_build", "cp_debug_fk", "cp_debug_eval_configs", "cp_debug_select"]
+
+
+class CranePlanError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"craneplan error {code}: {msg}")
+        self.code = code
+
+
+class _Robot(ctypes.Structure):
+    _fields_ = [("n_joints", _c_i32), ("type", _vp), ("axis", _vp), ("origin", _vp), ("q_min", _vp),
+                ("q_max", _vp), ("q_hold", _vp), ("active", _vp), ("n_spheres", _c_i32), ("sphere_frame", _vp),
+                ("sphere_center", _vp), ("sphere_radius", _vp)]
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [("has_ground", _c_i32), ("ground_z", _c_f32), ("n_cyl", _c_i32), ("cyl", _vp), ("n_box", _c_i32),
+                ("box", _vp), ("d_sdf", _vp), ("sdf_dims", _c_i32 * 3), ("sdf_origin", _c_f32 * 3),
+                ("voxel", _c_f32)]
+
+
+class _Cost(ctypes.Structure):
+    _fields_ = [("K", _c_i32), ("M", _c_i32), ("interp", _c_i32), ("jp_mode", _c_i32), ("hinge", _c_i32),
+                ("margin", _c_f32), ("lambda_c", _c_f32), ("w_c", _c_f32), ("w_l", _c_f32), ("max_B", _c_i32)]
+
+
+class _Opt(ctypes.Structure):
+    _fields_ = [("B", _c_i32), ("nu", _c_i32), ("sigma0", _c_f32), ("eps", _c_f64), ("seed", _c_u64),
+                ("problem_id", _c_u32), ("polish_elites", _c_i32), ("polish_steps", _c_i32),
+                ("polish_eta", _c_f32), ("polish_clip", _c_f32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_14160_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64 = _c_i32, ctypes.c_int64
+        L.cp_last_error.restype = ctypes.c_char_p
+        L.cp_plan_create.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp]
+        L.cp_plan_destroy.argtypes = [_vp]
+        L.cp_plan_set_endpoints.argtypes = [_vp, _vp, _vp]
+        L.cp_plan_n_checkpoints.argtypes = [_vp, _vp]
+        L.cp_eval_paths.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, _vp, _vp]
+        L.cp_eval_paths_backward.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, _vp]
+        L.cp_optimizer_create.argtypes = [_vp, _vp, _vp]
+        L.cp_optimizer_destroy.argtypes = [_vp]
+        L.cp_optimizer_step.argtypes = [_vp, i32, _vp]
+        L.cp_optimizer_get_state.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.cp_optimizer_set_state.argtypes = [_vp, _vp, _vp, ctypes.c_int64]
+        L.cp_optimizer_last.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.cp_sdf_build.argtypes = [_vp, i64, _vp, _vp, _c_f32, _vp, _vp, _vp, _vp, _vp]
+        L.cp_debug_fk.argtypes = [_vp, _vp, i32, _vp, _vp, _vp]
+        L.cp_debug_eval_configs.argtypes = [_vp, _vp, i32, _vp, _vp, _vp]
+        L.cp_debug_select.argtypes = [_vp, i32, i32, _vp, _vp]
+        for name in EXPORTS[1:]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CranePlanError(rc, lib().cp_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dt):
+    return np.ascontiguousarray(np.asarray(a), dtype=dt)
+
+
+class Plan:
+    """A crane, a scene and a path cost on one device (cp_plan_create)."""
+
+    def __init__(self, robot, scene, cost, max_B: int, device: int = 0, sdf: Optional[torch.Tensor] = None,
+                 sdf_spec=None):
+        L = lib()
+        self._keep = []
+
+        def keep(a, dt):
+            a = _host(a, dt)
+            self._keep.append(a)
+            return a.ctypes.data
+
+        r = _Robot()
+        r.n_joints = int(len(robot.joint_type))
+        r.type = keep(robot.joint_type, np.int32)
+        r.axis = keep(robot.axis, np.float32)
+        r.origin = keep(robot.origin, np.float32)
+        r.q_min = keep(robot.q_min, np.float32)
+        r.q_max = keep(robot.q_max, np.float32)
+        r.q_hold = keep(robot.q_hold, np.float32)
+        r.active = keep(robot.active, np.uint8)
+        r.n_spheres = int(len(robot.sphere_radius))
+        r.sphere_frame = keep(robot.sphere_frame, np.int32)
+        r.sphere_center = keep(robot.sphere_center, np.float32)
+        r.sphere_radius = keep(robot.sphere_radius, np.float32)
+        s = _Scene()
+        s.has_ground = int(scene.has_ground)
+        s.ground_z = float(scene.ground_z)
+        s.n_cyl = int(scene.cyl.shape[0])
+        s.cyl = keep(scene.cyl, np.float32) if s.n_cyl else None
+        s.n_box = int(scene.box.shape[0])
+        s.box = keep(scene.box, np.float32) if s.n_box else None
+        self.sdf = sdf
+        if sdf is not None:
+            s.d_sdf = sdf.data_ptr()
+            for a in range(3):
+                s.sdf_dims[a] = int(sdf_spec.dims[a])
+                s.sdf_origin[a] = float(sdf_spec.origin[a])
+            s.voxel = float(sdf_spec.voxel)
+        c = _Cost()
+        c.K, c.M, c.interp, c.jp_mode, c.hinge = cost.K, cost.M, cost.interp, cost.jp_mode, cost.hinge
+        c.margin, c.lambda_c, c.w_c, c.w_l = cost.margin, cost.lambda_c, cost.w_c, cost.w_l
+        c.max_B = int(max_B)
+        h = ctypes.c_void_p()
+        _check(L.cp_plan_create(ctypes.byref(r), ctypes.byref(s), ctypes.byref(c), int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", device)
+        self.n_joints = r.n_joints
+        self.n_spheres = r.n_spheres
+        self.n_active = int(np.count_nonzero(_host(robot.active, np.uint8)))
+        self.K = cost.K
+        self.max_B = int(max_B)
+        ns = _c_i32()
+        _check(L.cp_plan_n_checkpoints(h, ctypes.byref(ns)))
+        self.n_s = ns.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_endpoints(self, q_start, q_goal):
+        qs = _host(q_start, np.float32)
+        qg = _host(q_goal, np.float32)
+        _check(lib().cp_plan_set_endpoints(self._h, qs.ctypes.data, qg.ctypes.data))
+
+    def _w(self, W: torch.Tensor) -> torch.Tensor:
+        if W.dtype != torch.float32 or W.dim() != 3 or W.shape[1] != self.K or W.shape[2] != self.n_joints:
+            raise ValueError(f"waypoints must be float32 [B,{self.K},{self.n_joints}]")
+        return W.contiguous()
+
+    def eval(self, W: torch.Tensor, tape: bool = False):
+        """cost [B], min_dist [B], flags [B] (and tape [B, n_s] if asked)."""
+        W = self._w(W)
+        B = W.shape[0]
+        cost = torch.empty(B, dtype=torch.float32, device=W.device)
+        md = torch.empty(B, dtype=torch.float32, device=W.device)
+        fl = torch.empty(B, dtype=torch.uint8, device=W.device)
+        tp = torch.empty((B, self.n_s), dtype=torch.int32, device=W.device) if tape else None
+        _check(lib().cp_eval_paths(self._h, _ptr(W), B, _ptr(cost), _ptr(md), _ptr(fl), _ptr(tp), _stream()))
+        return (cost, md, fl, tp) if tape else (cost, md, fl)
+
+    def eval_into(self, W, cost, md, fl=None, tape=None):
+        """Enqueue an evaluation into caller-provided buffers (no allocation)."""
+        _check(lib().cp_eval_paths(self._h, _ptr(W), W.shape[0], _ptr(cost), _ptr(md), _ptr(fl), _ptr(tape),
+                                   _stream()))
+
+    def backward(self, W: torch.Tensor, grad_cost: torch.Tensor, tape: Optional[torch.Tensor] = None):
+        """d(sum_b grad_cost[b] J_b) / dW, [B,K,n]."""
+        W = self._w(W)
+        g = torch.empty_like(W)
+        gc = grad_cost.to(torch.float32).contiguous()
+        _check(lib().cp_eval_paths_backward(self._h, _ptr(W), W.shape[0], _ptr(tape), _ptr(gc), _ptr(g), _stream()))
+        return g
+
+    def backward_into(self, W, grad_cost, grad_W, tape=None):
+        _check(lib().cp_eval_paths_backward(self._h, _ptr(W), W.shape[0], _ptr(tape), _ptr(grad_cost),
+                                            _ptr(grad_W), _stream()))
+
+    def debug_fk(self, Q: torch.Tensor):
+        Q = Q.to(torch.float32).contiguous()
+        N = Q.shape[0]
+        cen = torch.empty((N, self.n_spheres, 3), dtype=torch.float32, device=Q.device)
+        fr = torch.empty((N, self.n_joints + 1, 12), dtype=torch.float32, device=Q.device)
+        _check(lib().cp_debug_fk(self._h, _ptr(Q), N, _ptr(cen), _ptr(fr), _stream()))
+        return cen, fr
+
+    def debug_configs(self, Q: torch.Tensor):
+        Q = Q.to(torch.float32).contiguous()
+        N = Q.shape[0]
+        d = torch.empty(N, dtype=torch.float32, device=Q.device)
+        a = torch.empty(N, dtype=torch.int32, device=Q.device)
+        _check(lib().cp_debug_eval_configs(self._h, _ptr(Q), N, _ptr(d), _ptr(a), _stream()))
+        return d, a
+
+
+class EvalPaths(torch.autograd.Function):
+    """cost = J(W) with the hand-written adjoint as its backward; the argmin
+    tape is saved, forward kinematics is recomputed in the backward pass."""
+
+    @staticmethod
+    def forward(ctx, W, plan):
+        cost, md, fl, tape = plan.eval(W.detach(), tape=True)
+        ctx.plan = plan
+        ctx.save_for_backward(W.detach(), tape)
+        ctx.mark_non_differentiable(md, fl)
+        return cost, md, fl
+
+    @staticmethod
+    def backward(ctx, grad_cost, _g_md=None, _g_fl=None):
+        W, tape = ctx.saved_tensors
+        return ctx.plan.backward(W, grad_cost.contiguous(), tape), None
+
+
+class Optimizer:
+    """Algorithm 1 on a plan (cp_optimizer_create)."""
+
+    def __init__(self, plan: Plan, opt, problem_id: int = 0):
+        o = _Opt()
+        o.B, o.nu, o.sigma0, o.eps, o.seed = int(opt.B), int(opt.nu), float(opt.sigma0), float(opt.eps), int(opt.seed)
+        o.problem_id = int(problem_id)
+        o.polish_elites = int(getattr(opt, "polish_elites", 0))
+        o.polish_steps = int(getattr(opt, "polish_steps", 0))
+        o.polish_eta = float(getattr(opt, "polish_eta", 0.0))
+        o.polish_clip = float(getattr(opt, "polish_clip", 1.0))
+        h = ctypes.c_void_p()
+        _check(lib().cp_optimizer_create(plan._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.plan = plan
+        self.B, self.nu = o.B, o.nu
+        self.D = plan.K * plan.n_active
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cp_optimizer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n_iters: int = 1):
+        _check(lib().cp_optimizer_step(self._h, int(n_iters), _stream()))
+
+    def get_state(self):
+        D = self.D
+        mu = np.zeros(D)
+        C = np.zeros((D, D))
+        t = ctypes.c_int64()
+        bc = ctypes.c_float()
+        bw = np.zeros((self.plan.K, self.plan.n_joints), np.float32)
+        rc = lib().cp_optimizer_get_state(self._h, mu.ctypes.data, C.ctypes.data, ctypes.byref(t), ctypes.byref(bc),
+                                          bw.ctypes.data)
+        _check(rc)
+        return dict(mu=mu, C=C, t=t.value, best_cost=bc.value, best_W=bw)
+
+    def set_state(self, mu, C, t: int):
+        mu = _host(mu, np.float64)
+        C = _host(C, np.float64)
+        _check(lib().cp_optimizer_set_state(self._h, mu.ctypes.data, C.ctypes.data, int(t)))
+
+    def last(self):
+        dev = self.plan.device
+        W = torch.empty((self.B, self.plan.K, self.plan.n_joints), dtype=torch.float32, device=dev)
+        cost = torch.empty(self.B, dtype=torch.float32, device=dev)
+        elite = torch.empty(self.nu, dtype=torch.int32, device=dev)
+        _check(lib().cp_optimizer_last(self._h, _ptr(W), _ptr(cost), _ptr(elite), _stream()))
+        return W, cost, elite
+
+
+def select(cost: torch.Tensor, nu: int) -> torch.Tensor:
+    """Indices of the nu smallest (cost, index) pairs in rank order, NaN last
+    (the selection step of the optimizer, exported for tests)."""
+    cost = cost.to(torch.float32).contiguous()
+    out = torch.empty(nu, dtype=torch.int32, device=cost.device)
+    _check(lib().cp_debug_select(_ptr(cost), cost.shape[0], int(nu), _ptr(out), _stream()))
+    return out
+
+
+def sdf_build(points: torch.Tensor, spec, with_edt: bool = False):
+    """Signed-distance grid [nz,ny,nx] from a device point cloud [N,3]."""
+    nx, ny, nz = (int(v) for v in spec.dims)
+    dev = points.device
+    pts = points.to(torch.float32).contiguous()
+    sdf = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+    occ = eo = ef = None
+    if with_edt:
+        occ = torch.empty((nz, ny, nx), dtype=torch.uint8, device=dev)
+        eo = torch.empty((nz, ny, nx), dtype=torch.int32, device=dev)
+        ef = torch.empty((nz, ny, nx), dtype=torch.int32, device=dev)
+    dims = np.array([nx, ny, nz], np.int32)
+    org = np.array(spec.origin, np.float32)
+    _check(lib().cp_sdf_build(_ptr(pts), pts.shape[0], dims.ctypes.data, org.ctypes.data, float(spec.voxel),
+                              _ptr(sdf), _ptr(occ), _ptr(eo), _ptr(ef), _stream()))
+    return (sdf, occ, eo, ef) if with_edt else sdf

@@ -1,0 +1,601 @@
+// C ABI of the craneplan library: argument validation, plan / optimizer
+// objects and their device tables, and the step sequencing of Algorithm 1.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "launch.h"
+
+using namespace cp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? CP_ERR_NOMEM : CP_ERR_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CP_HIP(call, what)                               \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// makes the object's device current for the duration of a call
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+    *dst = nullptr;
+    const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+}  // namespace
+
+struct cp_plan {
+    int device = 0;
+    int n = 0, S = 0, K = 0, M = 0, ns = 0, max_B = 0;
+    int n_cyl = 0, n_box = 0;
+    cp_cost_params cost{};
+    std::vector<JointDev> joints;
+    JointDev *d_joints = nullptr;
+    SphereDev *d_spheres = nullptr;
+    int32_t *d_frame_start = nullptr;
+    float4 *d_cyl = nullptr;
+    GroupDev *d_groups = nullptr;
+    float4 *d_cyl_orig = nullptr;
+    float4 *d_box = nullptr;
+    float *d_qs = nullptr, *d_qg = nullptr;
+    double2 *d_partial = nullptr;
+    PlanView view{};
+
+    ~cp_plan() {
+        DeviceGuard g(device);
+        void *bufs[] = {d_joints, d_spheres, d_frame_start, d_cyl, d_groups, d_cyl_orig, d_box, d_qs, d_qg, d_partial};
+        for (void *p : bufs)
+            if (p) (void)hipFree(p);
+    }
+};
+
+struct cp_opt {
+    cp_plan *plan = nullptr;
+    cp_opt_params prm{};
+    int D = 0, n_act = 0, npol = 0;
+    OptView view{};
+    uint32_t *d_tape_p = nullptr;
+    std::vector<void *> bufs;
+
+    ~cp_opt() {
+        DeviceGuard g(plan->device);
+        for (void *p : bufs)
+            if (p) (void)hipFree(p);
+    }
+    template <class T>
+    hipError_t alloc(T **p, size_t count) {
+        *p = nullptr;
+        hipError_t e = hipMalloc((void **)p, std::max<size_t>(1, count) * sizeof(T));
+        if (e == hipSuccess) bufs.push_back((void *)*p);
+        return e;
+    }
+};
+
+extern "C" {
+
+const char *cp_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+
+static int validate_plan_args(const cp_robot_desc *r, const cp_scene_desc *s, const cp_cost_params *c) {
+    if (!r || !s || !c) return fail(CP_ERR_INVALID_ARG, "null descriptor");
+    if (r->n_joints < 1 || r->n_joints > CP_MAX_JOINTS) return fail(CP_ERR_SIZE, "n_joints out of range");
+    if (!r->type || !r->axis || !r->origin || !r->q_min || !r->q_max || !r->q_hold || !r->active)
+        return fail(CP_ERR_INVALID_ARG, "null joint table");
+    for (int j = 0; j < r->n_joints; ++j) {
+        if (r->type[j] != CP_REVOLUTE && r->type[j] != CP_PRISMATIC) return fail(CP_ERR_INVALID_ARG, "bad joint type");
+        const float *a = r->axis + 3 * j;
+        const double nrm = std::sqrt((double)a[0] * a[0] + (double)a[1] * a[1] + (double)a[2] * a[2]);
+        if (!(std::fabs(nrm - 1.0) < 1e-4)) return fail(CP_ERR_INVALID_ARG, "joint axis is not a unit vector");
+        for (int i = 0; i < 3; ++i)
+            if (!finite(r->origin[3 * j + i])) return fail(CP_ERR_INVALID_ARG, "non-finite joint origin");
+        if (!finite(r->q_min[j]) || !finite(r->q_max[j]) || !(r->q_min[j] <= r->q_max[j]) || !finite(r->q_hold[j]))
+            return fail(CP_ERR_INVALID_ARG, "bad joint limits");
+    }
+    if (r->n_spheres < 1 || r->n_spheres > CP_MAX_SPHERES) return fail(CP_ERR_SIZE, "n_spheres out of range");
+    if (!r->sphere_frame || !r->sphere_center || !r->sphere_radius) return fail(CP_ERR_INVALID_ARG, "null sphere table");
+    for (int i = 0; i < r->n_spheres; ++i) {
+        if (r->sphere_frame[i] < 0 || r->sphere_frame[i] > r->n_joints) return fail(CP_ERR_INVALID_ARG, "bad sphere frame");
+        if (!(r->sphere_radius[i] > 0.0f) || !finite(r->sphere_radius[i])) return fail(CP_ERR_INVALID_ARG, "bad sphere radius");
+    }
+    if (s->n_cyl < 0 || s->n_box < 0 || s->n_cyl + s->n_box > 65533) return fail(CP_ERR_SIZE, "obstacle count out of range");
+    if ((s->n_cyl > 0 && !s->cyl) || (s->n_box > 0 && !s->box)) return fail(CP_ERR_INVALID_ARG, "null obstacle table");
+    for (int o = 0; o < s->n_cyl; ++o) {
+        const float *y = s->cyl + 5 * o;
+        for (int i = 0; i < 5; ++i)
+            if (!finite(y[i])) return fail(CP_ERR_INVALID_ARG, "non-finite cylinder");
+        if (!(y[2] >= 0.0f) || !(y[4] >= y[3])) return fail(CP_ERR_INVALID_ARG, "bad cylinder");
+    }
+    for (int o = 0; o < s->n_box; ++o) {
+        const float *y = s->box + 6 * o;
+        for (int i = 0; i < 6; ++i)
+            if (!finite(y[i])) return fail(CP_ERR_INVALID_ARG, "non-finite box");
+        if (!(y[3] >= 0.0f && y[4] >= 0.0f && y[5] >= 0.0f)) return fail(CP_ERR_INVALID_ARG, "bad box");
+    }
+    if (s->d_sdf) {
+        for (int a = 0; a < 3; ++a)
+            if (s->sdf_dims[a] < 2) return fail(CP_ERR_SIZE, "sdf dims must be >= 2");
+        if (!(s->voxel > 0.0f)) return fail(CP_ERR_INVALID_ARG, "sdf voxel must be > 0");
+    }
+    if (c->K < 1 || c->K > CP_MAX_K || c->M < 1) return fail(CP_ERR_SIZE, "K or M out of range");
+    if (c->interp != CP_INTERP_BSPLINE && c->interp != CP_INTERP_LINEAR) return fail(CP_ERR_INVALID_ARG, "bad interp");
+    if (c->jp_mode != CP_JP_SQUARED && c->jp_mode != CP_JP_L2) return fail(CP_ERR_INVALID_ARG, "bad jp_mode");
+    if (c->hinge != CP_HINGE_HARD && c->hinge != CP_HINGE_SMOOTH) return fail(CP_ERR_INVALID_ARG, "bad hinge");
+    if (!(c->margin >= 0.0f) || (c->hinge == CP_HINGE_SMOOTH && !(c->margin > 0.0f)))
+        return fail(CP_ERR_INVALID_ARG, "bad margin");
+    if (!finite(c->lambda_c) || !finite(c->w_c) || !finite(c->w_l)) return fail(CP_ERR_INVALID_ARG, "bad weights");
+    if (c->max_B < 1) return fail(CP_ERR_SIZE, "max_B must be >= 1");
+    const int64_t ns = (int64_t)(c->interp == CP_INTERP_BSPLINE ? c->K + 3 : c->K + 1) * c->M;
+    if (ns > (1 << 24) || (int64_t)c->max_B * ns > ((int64_t)1 << 31) - 256)
+        return fail(CP_ERR_SIZE, "max_B * n_s exceeds 2^31");
+    return CP_OK;
+}
+
+int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const cp_cost_params *cost, int device,
+                   cp_plan **out) {
+    if (!out) return fail(CP_ERR_INVALID_ARG, "null out");
+    *out = nullptr;
+    int rc = validate_plan_args(robot, scene, cost);
+    if (rc) return rc;
+    int ndev = 0;
+    CP_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(CP_ERR_INVALID_ARG, "bad device");
+    DeviceGuard guard(device);
+    cp_plan *p = new (std::nothrow) cp_plan();
+    if (!p) return fail(CP_ERR_NOMEM, "host allocation");
+    p->device = device;
+    p->n = robot->n_joints;
+    p->S = robot->n_spheres;
+    p->K = cost->K;
+    p->M = cost->M;
+    p->ns = (cost->interp == CP_INTERP_BSPLINE ? cost->K + 3 : cost->K + 1) * cost->M;
+    p->max_B = cost->max_B;
+    p->cost = *cost;
+    p->n_cyl = scene->n_cyl;
+    p->n_box = scene->n_box;
+    auto bail = [&](int code) {
+        delete p;
+        return code;
+    };
+
+    // joints
+    for (int j = 0; j < p->n; ++j) {
+        JointDev J{};
+        J.type = robot->type[j];
+        J.ax = robot->axis[3 * j]; J.ay = robot->axis[3 * j + 1]; J.az = robot->axis[3 * j + 2];
+        J.ox = robot->origin[3 * j]; J.oy = robot->origin[3 * j + 1]; J.oz = robot->origin[3 * j + 2];
+        J.qmin = robot->q_min[j]; J.qmax = robot->q_max[j]; J.qhold = robot->q_hold[j];
+        J.active = robot->active[j] ? 1 : 0;
+        p->joints.push_back(J);
+    }
+    // spheres sorted by frame (stable), with per-frame ranges
+    std::vector<int> order(p->S);
+    for (int i = 0; i < p->S; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return robot->sphere_frame[a] < robot->sphere_frame[b]; });
+    std::vector<SphereDev> spheres;
+    for (int i : order) {
+        SphereDev s{};
+        s.lx = robot->sphere_center[3 * i]; s.ly = robot->sphere_center[3 * i + 1]; s.lz = robot->sphere_center[3 * i + 2];
+        s.r = robot->sphere_radius[i];
+        s.frame = robot->sphere_frame[i];
+        s.orig = i;
+        spheres.push_back(s);
+    }
+    std::vector<int32_t> frame_start(p->n + 2, 0);
+    for (int f = 0; f <= p->n + 1; ++f) {
+        int c = 0;
+        for (const SphereDev &s : spheres) c += s.frame < f;
+        frame_start[f] = c;
+    }
+    // cylinders grouped by shared vertical extent, each group padded to a
+    // multiple of 4 with far-away zero-radius entries
+    std::vector<std::pair<float, float>> ext;
+    std::vector<std::vector<int>> members;
+    std::vector<float4> cyl_orig(p->n_cyl);
+    for (int o = 0; o < p->n_cyl; ++o) {
+        const float *y = scene->cyl + 5 * o;
+        std::pair<float, float> e(y[3], y[4]);
+        int g = -1;
+        for (size_t i = 0; i < ext.size(); ++i)
+            if (ext[i] == e) { g = (int)i; break; }
+        if (g < 0) {
+            g = (int)ext.size();
+            ext.push_back(e);
+            members.emplace_back();
+        }
+        members[g].push_back(o);
+        int gbits;
+        std::memcpy(&gbits, &g, sizeof(int));
+        float gf;
+        std::memcpy(&gf, &gbits, sizeof(float));
+        cyl_orig[o] = make_float4(y[0], y[1], y[2], gf);
+    }
+    std::vector<float4> cyl;
+    std::vector<GroupDev> groups;
+    for (size_t g = 0; g < ext.size(); ++g) {
+        GroupDev G{};
+        G.start = (int)cyl.size();
+        for (int o : members[g]) {
+            const float *y = scene->cyl + 5 * o;
+            cyl.push_back(make_float4(y[0], y[1], y[2], 0.0f));
+        }
+        while ((cyl.size() - G.start) % 4) cyl.push_back(make_float4(1e15f, 1e15f, 0.0f, 0.0f));
+        G.count = (int)cyl.size() - G.start;
+        G.zc = (float)(0.5 * ((double)ext[g].first + (double)ext[g].second));
+        G.hz = (float)(0.5 * ((double)ext[g].second - (double)ext[g].first));
+        groups.push_back(G);
+    }
+    std::vector<float4> box;
+    for (int o = 0; o < p->n_box; ++o) {
+        const float *y = scene->box + 6 * o;
+        box.push_back(make_float4(y[0], y[1], y[2], y[3]));
+        box.push_back(make_float4(y[4], y[5], 0.0f, 0.0f));
+    }
+    std::vector<float> hold(robot->q_hold, robot->q_hold + p->n);
+    hipError_t e;
+    if ((e = upload(&p->d_joints, p->joints)) != hipSuccess || (e = upload(&p->d_spheres, spheres)) != hipSuccess ||
+        (e = upload(&p->d_frame_start, frame_start)) != hipSuccess || (e = upload(&p->d_cyl, cyl)) != hipSuccess ||
+        (e = upload(&p->d_groups, groups)) != hipSuccess || (e = upload(&p->d_cyl_orig, cyl_orig)) != hipSuccess ||
+        (e = upload(&p->d_box, box)) != hipSuccess || (e = upload(&p->d_qs, hold)) != hipSuccess ||
+        (e = upload(&p->d_qg, hold)) != hipSuccess)
+        return bail(hip_fail(e, "plan tables"));
+    e = hipMalloc((void **)&p->d_partial, eval_partial_count(p->max_B, p->ns) * sizeof(double2));
+    if (e != hipSuccess) return bail(hip_fail(e, "plan workspace"));
+
+    PlanView &v = p->view;
+    v.n_joints = p->n;
+    v.n_spheres = p->S;
+    v.n_groups = (int)groups.size();
+    v.n_box = p->n_box;
+    v.n_cyl = p->n_cyl;
+    v.has_ground = scene->has_ground ? 1 : 0;
+    v.ground_z = scene->ground_z;
+    v.K = p->K; v.M = p->M; v.ns = p->ns;
+    v.interp = cost->interp; v.jp_mode = cost->jp_mode; v.hinge = cost->hinge;
+    v.margin = cost->margin; v.lambda_c = cost->lambda_c; v.w_c = cost->w_c; v.w_l = cost->w_l;
+    v.joints = p->d_joints; v.spheres = p->d_spheres; v.frame_start = p->d_frame_start;
+    v.cyl = p->d_cyl; v.groups = p->d_groups; v.cyl_orig = p->d_cyl_orig; v.box = p->d_box;
+    v.qs = p->d_qs; v.qg = p->d_qg;
+    v.sdf = scene->d_sdf;
+    for (int a = 0; a < 3; ++a) {
+        v.sdf_n[a] = scene->d_sdf ? scene->sdf_dims[a] : 2;
+        v.sdf_o[a] = scene->sdf_origin[a];
+    }
+    v.sdf_h = scene->d_sdf ? scene->voxel : 1.0f;
+    v.sdf_inv_h = 1.0f / v.sdf_h;
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return bail(hip_fail(e, "plan create"));
+    *out = p;
+    return CP_OK;
+}
+
+int cp_plan_destroy(cp_plan *plan) {
+    if (!plan) return CP_OK;
+    {
+        DeviceGuard g(plan->device);
+        (void)hipDeviceSynchronize();
+    }
+    delete plan;
+    return CP_OK;
+}
+
+int cp_plan_set_endpoints(cp_plan *plan, const float *q_start, const float *q_goal) {
+    if (!plan || !q_start || !q_goal) return fail(CP_ERR_INVALID_ARG, "null argument");
+    for (int j = 0; j < plan->n; ++j)
+        if (!finite(q_start[j]) || !finite(q_goal[j])) return fail(CP_ERR_INVALID_ARG, "non-finite endpoint");
+    DeviceGuard g(plan->device);
+    CP_HIP(hipDeviceSynchronize(), "sync");
+    CP_HIP(hipMemcpy(plan->d_qs, q_start, plan->n * sizeof(float), hipMemcpyHostToDevice), "endpoints");
+    CP_HIP(hipMemcpy(plan->d_qg, q_goal, plan->n * sizeof(float), hipMemcpyHostToDevice), "endpoints");
+    return CP_OK;
+}
+
+int cp_plan_n_checkpoints(const cp_plan *plan, int32_t *n_s) {
+    if (!plan || !n_s) return fail(CP_ERR_INVALID_ARG, "null argument");
+    *n_s = plan->ns;
+    return CP_OK;
+}
+
+int cp_eval_paths(cp_plan *plan, const float *d_waypoints, int32_t B, float *d_cost, float *d_min_dist,
+                  uint8_t *d_flags, uint32_t *d_tape, cp_stream_t stream) {
+    if (!plan || !d_waypoints || !d_cost || !d_min_dist) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (B < 1 || B > plan->max_B) return fail(CP_ERR_SIZE, "B out of range (1..max_B)");
+    DeviceGuard g(plan->device);
+    CP_HIP(launch_eval_fwd(plan->view, d_waypoints, B, plan->d_partial, d_tape, d_cost, d_min_dist, d_flags,
+                           (hipStream_t)stream),
+           "eval launch");
+    return CP_OK;
+}
+
+int cp_eval_paths_backward(cp_plan *plan, const float *d_waypoints, int32_t B, const uint32_t *d_tape,
+                           const float *d_grad_cost, float *d_grad_waypoints, cp_stream_t stream) {
+    if (!plan || !d_waypoints || !d_grad_cost || !d_grad_waypoints) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (B < 1 || B > plan->max_B) return fail(CP_ERR_SIZE, "B out of range (1..max_B)");
+    DeviceGuard g(plan->device);
+    CP_HIP(launch_eval_bwd(plan->view, d_waypoints, B, d_tape, d_grad_cost, d_grad_waypoints, (hipStream_t)stream),
+           "backward launch");
+    return CP_OK;
+}
+
+int cp_debug_fk(cp_plan *plan, const float *d_q, int32_t N, float *d_centers, float *d_frames, cp_stream_t stream) {
+    if (!plan || !d_q) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (N < 1) return fail(CP_ERR_SIZE, "N must be >= 1");
+    DeviceGuard g(plan->device);
+    CP_HIP(launch_debug_fk(plan->view, d_q, N, d_centers, d_frames, (hipStream_t)stream), "fk launch");
+    return CP_OK;
+}
+
+int cp_debug_eval_configs(cp_plan *plan, const float *d_q, int32_t N, float *d_dist, uint32_t *d_argmin,
+                          cp_stream_t stream) {
+    if (!plan || !d_q || !d_dist) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (N < 1) return fail(CP_ERR_SIZE, "N must be >= 1");
+    DeviceGuard g(plan->device);
+    CP_HIP(launch_debug_configs(plan->view, d_q, N, d_dist, d_argmin, (hipStream_t)stream), "configs launch");
+    return CP_OK;
+}
+
+int cp_debug_select(const float *d_cost, int32_t B, int32_t nu, int32_t *d_elite, cp_stream_t stream) {
+    if (!d_cost || !d_elite) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (B < 1 || nu < 1 || nu > B || nu > CP_MAX_ELITES) return fail(CP_ERR_SIZE, "B or nu out of range");
+    OptView v{};
+    v.cost = const_cast<float *>(d_cost);
+    v.B = B;
+    v.nu = nu;
+    v.elite0 = d_elite;
+    CP_HIP(launch_select(v, (hipStream_t)stream), "select launch");
+    return CP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// optimizer
+// ---------------------------------------------------------------------------
+
+int cp_optimizer_create(cp_plan *plan, const cp_opt_params *prm, cp_opt **out) {
+    if (!out) return fail(CP_ERR_INVALID_ARG, "null out");
+    *out = nullptr;
+    if (!plan || !prm) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (prm->B < 1 || prm->B > plan->max_B) return fail(CP_ERR_SIZE, "B out of range (1..max_B)");
+    if (prm->nu < 1 || prm->nu > prm->B || prm->nu > CP_MAX_ELITES) return fail(CP_ERR_SIZE, "nu out of range");
+    if (!(prm->sigma0 > 0.0f) || !finite(prm->sigma0)) return fail(CP_ERR_INVALID_ARG, "sigma0 must be > 0");
+    if (!(prm->eps >= 0.0) || !std::isfinite(prm->eps)) return fail(CP_ERR_INVALID_ARG, "eps must be >= 0");
+    if (prm->polish_elites < 0 || prm->polish_elites > prm->nu || prm->polish_steps < 0)
+        return fail(CP_ERR_SIZE, "polish settings out of range");
+    if (prm->polish_elites > 0 && prm->polish_steps > 0 &&
+        (!(prm->polish_eta >= 0.0f) || !(prm->polish_clip > 0.0f)))
+        return fail(CP_ERR_INVALID_ARG, "bad polish step");
+    int n_act = 0;
+    int act[CP_MAX_JOINTS] = {0};
+    for (int j = 0; j < plan->n; ++j)
+        if (plan->joints[j].active) act[n_act++] = j;
+    if (n_act < 1) return fail(CP_ERR_INVALID_ARG, "no sampled joint");
+    const int D = plan->K * n_act;
+    if (D > CP_MAX_DIM) return fail(CP_ERR_SIZE, "K * sampled joints exceeds CP_MAX_DIM");
+    DeviceGuard guard(plan->device);
+    cp_opt *o = new (std::nothrow) cp_opt();
+    if (!o) return fail(CP_ERR_NOMEM, "host allocation");
+    o->plan = plan;
+    o->prm = *prm;
+    o->D = D;
+    o->n_act = n_act;
+    o->npol = (prm->polish_steps > 0) ? prm->polish_elites : 0;
+    OptView &v = o->view;
+    v.B = prm->B; v.nu = prm->nu; v.D = D; v.n_act = n_act; v.npol = o->npol;
+    for (int a = 0; a < CP_MAX_JOINTS; ++a) v.act[a] = act[a];
+    v.eps = prm->eps; v.seed = prm->seed; v.problem_id = prm->problem_id;
+    v.eta = prm->polish_eta; v.clip = prm->polish_clip;
+    const size_t per = (size_t)plan->K * plan->n;
+    const size_t np = std::max(1, o->npol);
+    hipError_t e;
+    if ((e = o->alloc(&v.mu, D)) != hipSuccess || (e = o->alloc(&v.C, (size_t)D * D)) != hipSuccess ||
+        (e = o->alloc(&v.L, (size_t)D * D)) != hipSuccess || (e = o->alloc(&v.xi, (size_t)prm->B * D)) != hipSuccess ||
+        (e = o->alloc(&v.W, prm->B * per)) != hipSuccess || (e = o->alloc(&v.cost, prm->B)) != hipSuccess ||
+        (e = o->alloc(&v.min_dist, prm->B)) != hipSuccess || (e = o->alloc(&v.elite, prm->nu)) != hipSuccess ||
+        (e = o->alloc(&v.elite0, prm->nu)) != hipSuccess || (e = o->alloc(&v.Wp, np * per)) != hipSuccess ||
+        (e = o->alloc(&v.cost_p, np)) != hipSuccess || (e = o->alloc(&v.grad_p, np * per)) != hipSuccess ||
+        (e = o->alloc(&v.ones, np)) != hipSuccess || (e = o->alloc(&v.w, prm->nu)) != hipSuccess ||
+        (e = o->alloc(&v.t, 1)) != hipSuccess || (e = o->alloc(&v.status, 1)) != hipSuccess ||
+        (e = o->alloc(&v.best_cost, 1)) != hipSuccess || (e = o->alloc(&v.best_W, per)) != hipSuccess ||
+        (e = o->alloc(&o->d_tape_p, np * plan->ns)) != hipSuccess) {
+        delete o;
+        return hip_fail(e, "optimizer buffers");
+    }
+    std::vector<float> ones(np, 1.0f);
+    e = hipMemcpy(v.ones, ones.data(), np * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_init_state(plan->view, v, prm->sigma0, nullptr);
+    if (e == hipSuccess) e = launch_chol(v, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete o;
+        return hip_fail(e, "optimizer init");
+    }
+    *out = o;
+    return CP_OK;
+}
+
+int cp_optimizer_destroy(cp_opt *opt) {
+    if (!opt) return CP_OK;
+    {
+        DeviceGuard g(opt->plan->device);
+        (void)hipDeviceSynchronize();
+    }
+    delete opt;
+    return CP_OK;
+}
+
+int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
+    if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
+    if (n_iters < 0) return fail(CP_ERR_SIZE, "n_iters must be >= 0");
+    cp_plan *p = opt->plan;
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    const OptView &v = opt->view;
+    const PlanView &P = p->view;
+    for (int it = 0; it < n_iters; ++it) {
+        CP_HIP(launch_sample(P, v, st), "sample");
+        CP_HIP(launch_eval_fwd(P, v.W, v.B, p->d_partial, nullptr, v.cost, v.min_dist, nullptr, st), "eval");
+        CP_HIP(launch_select(v, st), "select");
+        if (opt->npol > 0) {
+            CP_HIP(launch_polish_gather(P, v, st), "polish gather");
+            for (int s = 0; s < opt->prm.polish_steps; ++s) {
+                CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, opt->d_tape_p, v.cost_p, v.min_dist, nullptr,
+                                       st),
+                       "polish eval");
+                CP_HIP(launch_eval_bwd(P, v.Wp, opt->npol, opt->d_tape_p, v.ones, v.grad_p, st), "polish adjoint");
+                CP_HIP(launch_polish_gd(P, v, st), "polish step");
+            }
+            CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, nullptr, v.cost_p, v.min_dist, nullptr, st),
+                   "polish eval");
+            CP_HIP(launch_rerank(v, st), "rerank");
+        } else {
+            CP_HIP(hipMemcpyAsync(v.elite, v.elite0, v.nu * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "elite copy");
+        }
+        CP_HIP(launch_update(P, v, st), "update");
+        CP_HIP(launch_chol(v, st), "cholesky");
+    }
+    return CP_OK;
+}
+
+int cp_optimizer_get_state(cp_opt *opt, double *mu, double *C, int64_t *iter, float *best_cost,
+                           float *best_waypoints) {
+    if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
+    DeviceGuard g(opt->plan->device);
+    const OptView &v = opt->view;
+    CP_HIP(hipDeviceSynchronize(), "sync");
+    const size_t per = (size_t)opt->plan->K * opt->plan->n;
+    if (mu) CP_HIP(hipMemcpy(mu, v.mu, opt->D * sizeof(double), hipMemcpyDeviceToHost), "state");
+    if (C) CP_HIP(hipMemcpy(C, v.C, (size_t)opt->D * opt->D * sizeof(double), hipMemcpyDeviceToHost), "state");
+    if (iter) CP_HIP(hipMemcpy(iter, v.t, sizeof(int64_t), hipMemcpyDeviceToHost), "state");
+    if (best_cost) CP_HIP(hipMemcpy(best_cost, v.best_cost, sizeof(float), hipMemcpyDeviceToHost), "state");
+    if (best_waypoints) CP_HIP(hipMemcpy(best_waypoints, v.best_W, per * sizeof(float), hipMemcpyDeviceToHost), "state");
+    int32_t status = 0;
+    CP_HIP(hipMemcpy(&status, v.status, sizeof(int32_t), hipMemcpyDeviceToHost), "state");
+    if (status) {
+        const int32_t zero = 0;
+        CP_HIP(hipMemcpy(v.status, &zero, sizeof(int32_t), hipMemcpyHostToDevice), "state");
+        return fail(CP_ERR_NOT_PD, "covariance was not positive definite (previous factor kept)");
+    }
+    return CP_OK;
+}
+
+int cp_optimizer_set_state(cp_opt *opt, const double *mu, const double *C, int64_t iter) {
+    if (!opt || !mu || !C) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (iter < 0) return fail(CP_ERR_INVALID_ARG, "iter must be >= 0");
+    for (int i = 0; i < opt->D; ++i)
+        if (!std::isfinite(mu[i])) return fail(CP_ERR_INVALID_ARG, "non-finite mu");
+    for (int i = 0; i < opt->D * opt->D; ++i)
+        if (!std::isfinite(C[i])) return fail(CP_ERR_INVALID_ARG, "non-finite C");
+    DeviceGuard g(opt->plan->device);
+    const OptView &v = opt->view;
+    CP_HIP(hipDeviceSynchronize(), "sync");
+    CP_HIP(hipMemcpy(v.mu, mu, opt->D * sizeof(double), hipMemcpyHostToDevice), "state");
+    CP_HIP(hipMemcpy(v.C, C, (size_t)opt->D * opt->D * sizeof(double), hipMemcpyHostToDevice), "state");
+    CP_HIP(hipMemcpy(v.t, &iter, sizeof(int64_t), hipMemcpyHostToDevice), "state");
+    const float inf = INFINITY;
+    CP_HIP(hipMemcpy(v.best_cost, &inf, sizeof(float), hipMemcpyHostToDevice), "state");
+    CP_HIP(launch_chol(v, nullptr), "cholesky");
+    CP_HIP(hipDeviceSynchronize(), "sync");
+    int32_t status = 0;
+    CP_HIP(hipMemcpy(&status, v.status, sizeof(int32_t), hipMemcpyDeviceToHost), "state");
+    if (status) {
+        const int32_t zero = 0;
+        CP_HIP(hipMemcpy(v.status, &zero, sizeof(int32_t), hipMemcpyHostToDevice), "state");
+        return fail(CP_ERR_NOT_PD, "covariance is not positive definite");
+    }
+    return CP_OK;
+}
+
+int cp_optimizer_last(cp_opt *opt, float *d_waypoints, float *d_cost, int32_t *d_elite, cp_stream_t stream) {
+    if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
+    DeviceGuard g(opt->plan->device);
+    const OptView &v = opt->view;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t per = (size_t)opt->plan->K * opt->plan->n;
+    if (d_waypoints)
+        CP_HIP(hipMemcpyAsync(d_waypoints, v.W, v.B * per * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+    if (d_cost) CP_HIP(hipMemcpyAsync(d_cost, v.cost, v.B * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+    if (d_elite) CP_HIP(hipMemcpyAsync(d_elite, v.elite, v.nu * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "copy");
+    return CP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// signed-distance grid
+// ---------------------------------------------------------------------------
+
+int cp_sdf_build(const float *d_points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
+                 float *d_sdf, uint8_t *d_occ, int32_t *d_edt_occ, int32_t *d_edt_free, cp_stream_t stream) {
+    if (!dims || !origin || !d_sdf || (N > 0 && !d_points)) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (N < 0) return fail(CP_ERR_SIZE, "N must be >= 0");
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] < 2 || dims[a] > 4096) return fail(CP_ERR_SIZE, "dims must be in 2..4096");
+        if (!finite(origin[a])) return fail(CP_ERR_INVALID_ARG, "non-finite origin");
+    }
+    if (!(voxel > 0.0f) || !finite(voxel)) return fail(CP_ERR_INVALID_ARG, "voxel must be > 0");
+    const size_t n = (size_t)dims[0] * dims[1] * dims[2];
+    if (n > ((size_t)1 << 31)) return fail(CP_ERR_SIZE, "grid too large");
+    int dev;
+    CP_HIP(hipGetDevice(&dev), "device");
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t *occ = d_occ;
+    int32_t *eo = d_edt_occ, *ef = d_edt_free, *wa = nullptr, *wb = nullptr;
+    std::vector<void *> owned;
+    auto cleanup = [&]() {
+        for (void *q : owned) (void)hipFree(q);
+    };
+    auto get = [&](void **q, size_t bytes) {
+        hipError_t e = hipMalloc(q, bytes);
+        if (e == hipSuccess) owned.push_back(*q);
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    if (!occ) e = get((void **)&occ, n);
+    if (e == hipSuccess && !eo) e = get((void **)&eo, n * 4);
+    if (e == hipSuccess && !ef) e = get((void **)&ef, n * 4);
+    if (e == hipSuccess) e = get((void **)&wa, n * 4);
+    if (e == hipSuccess) e = get((void **)&wb, n * 4);
+    if (e == hipSuccess) e = launch_sdf_build(d_points, N, dims, origin, voxel, d_sdf, occ, eo, ef, wa, wb, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) return hip_fail(e, "sdf build");
+    return CP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,512 @@
+// Path evaluation (Algorithm 1, step 2) and its adjoint.
+//
+// Forward: one lane per checkpoint configuration (path b, checkpoint k),
+// configurations flattened over all paths so that every wave is full.  Each
+// lane interpolates its configuration from four control points, runs the
+// kinematic chain in registers, and takes the minimum signed distance of its
+// spheres to the scene.  Obstacle records are wave-uniform, so they are read
+// with scalar loads into SGPRs and consumed directly by the vector ALU; no LDS
+// or vector memory traffic sits in the pair loop.  Per-path sums are formed by
+// a fixed-order wave reduction per path segment and a second fixed-order pass
+// over waves, so results are bitwise reproducible.
+#include "launch.h"
+
+namespace cp {
+
+// Minimum signed distance over every obstacle for G sphere centres.
+template <int G>
+__device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&cx)[G], const float (&cy)[G],
+                                               const float (&cz)[G], float (&v)[G]) {
+#pragma unroll
+    for (int s = 0; s < G; ++s) v[s] = P.has_ground ? cz[s] - P.ground_z : kInf;
+    for (int g = 0; g < P.n_groups; ++g) {
+        const GroupDev gr = P.groups[g];
+        const float4 *c = P.cyl + gr.start;
+        float a[G];
+#pragma unroll
+        for (int s = 0; s < G; ++s) a[s] = kInf;
+        for (int o = 0; o < gr.count; o += 4) {
+            const float4 c0 = c[o], c1 = c[o + 1], c2 = c[o + 2], c3 = c[o + 3];
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                float r0 = cyl_radial(cx[s], cy[s], c0);
+                float r1 = cyl_radial(cx[s], cy[s], c1);
+                float r2 = cyl_radial(cx[s], cy[s], c2);
+                float r3 = cyl_radial(cx[s], cy[s], c3);
+                a[s] = fminf(a[s], fminf(fminf(r0, r1), fminf(r2, r3)));
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], cyl_combine(a[s], fabsf(cz[s] - gr.zc) - gr.hz));
+    }
+    for (int o = 0; o < P.n_box; ++o) {
+        const float4 b0 = P.box[2 * o], b1 = P.box[2 * o + 1];
+#pragma unroll
+        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], box_sd(cx[s], cy[s], cz[s], b0, b1));
+    }
+    if (P.sdf) {
+#pragma unroll
+        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], sdf_query(P, cx[s], cy[s], cz[s], nullptr));
+    }
+}
+
+// Lane state of the running minimum over spheres.
+struct Best {
+    float d;
+    int s;           // caller's sphere index
+    float r;         // its radius
+    float cx, cy, cz;
+};
+
+template <int G, bool ARG>
+__device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int s0, Best &best) {
+    float cx[G], cy[G], cz[G], v[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const SphereDev sp = P.spheres[s0 + i];
+        xf_point(T, sp.lx, sp.ly, sp.lz, cx[i], cy[i], cz[i]);
+    }
+    spheres_min_sd<G>(P, cx, cy, cz, v);
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const SphereDev sp = P.spheres[s0 + i];
+        float d = v[i] - sp.r;
+        if (ARG) {
+            if (d < best.d || (d == best.d && sp.orig < best.s)) {
+                best.d = d; best.s = sp.orig; best.r = sp.r;
+                best.cx = cx[i]; best.cy = cy[i]; best.cz = cz[i];
+            }
+        } else {
+            best.d = fminf(best.d, d);
+        }
+    }
+}
+
+// d(q) for one configuration; with ARG also the minimising sphere and its centre.
+template <bool ARG>
+__device__ __forceinline__ Best config_distance(const PlanView &P, const float (&q)[CP_MAX_JOINTS]) {
+    Best best;
+    best.d = kInf; best.s = 0x7fffffff; best.r = 0.0f;
+    best.cx = best.cy = best.cz = 0.0f;
+    Xf T;
+    xf_identity(T);
+    for (int f = 0; f <= P.n_joints; ++f) {
+        if (f > 0) xf_joint(T, P.joints[f - 1], pick(q, f - 1));
+        const int s1 = P.frame_start[f + 1];
+        int s = P.frame_start[f];
+        for (; s + 4 <= s1; s += 4) sphere_group<4, ARG>(P, T, s, best);
+        switch (s1 - s) {
+            case 3: sphere_group<3, ARG>(P, T, s, best); break;
+            case 2: sphere_group<2, ARG>(P, T, s, best); break;
+            case 1: sphere_group<1, ARG>(P, T, s, best); break;
+            default: break;
+        }
+    }
+    return best;
+}
+
+// Obstacle of the minimising pair for centre c (lowest number on ties):
+// recomputes every obstacle's signed distance with the same arithmetic as the
+// forward pass, in the caller's table order.
+__device__ __forceinline__ uint32_t argmin_obstacle(const PlanView &P, float cx, float cy, float cz) {
+    float bv = kInf;
+    uint32_t bo = 0;
+    if (P.has_ground) { bv = cz - P.ground_z; bo = 0; }
+    for (int o = 0; o < P.n_cyl; ++o) {
+        const float4 c = P.cyl_orig[o];
+        const GroupDev gr = P.groups[__float_as_int(c.w)];
+        float val = cyl_combine(cyl_radial(cx, cy, c), fabsf(cz - gr.zc) - gr.hz);
+        if (val < bv) { bv = val; bo = 1u + (uint32_t)o; }
+    }
+    for (int o = 0; o < P.n_box; ++o) {
+        float val = box_sd(cx, cy, cz, P.box[2 * o], P.box[2 * o + 1]);
+        if (val < bv) { bv = val; bo = 1u + (uint32_t)(P.n_cyl + o); }
+    }
+    if (P.sdf) {
+        float val = sdf_query(P, cx, cy, cz, nullptr);
+        if (val < bv) { bv = val; bo = CP_OBS_SDF; }
+    }
+    return bo;
+}
+
+// Configuration of checkpoint k of path b: q (all joints) and the step
+// q_k - q_{k-1}; also the span window start j and the weights.
+__device__ __forceinline__ void interpolate(const PlanView &P, const float *Wb, int k, float (&q)[CP_MAX_JOINTS],
+                                            float (&dq)[CP_MAX_JOINTS], int &j, float (&bw)[4], float (&db)[4]) {
+    checkpoint_weights(P, k, j, bw, db);
+    const float *p0 = control_point(P, Wb, j), *p1 = control_point(P, Wb, j + 1);
+    const float *p2 = control_point(P, Wb, j + 2), *p3 = control_point(P, Wb, j + 3);
+#pragma unroll
+    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+        if (i < P.n_joints) {
+            float a0 = p0[i], a1 = p1[i], a2 = p2[i], a3 = p3[i];
+            q[i] = __builtin_fmaf(bw[0], a0, __builtin_fmaf(bw[1], a1, __builtin_fmaf(bw[2], a2, bw[3] * a3)));
+            // differences centred on the second control point (the db sum to zero)
+            dq[i] = __builtin_fmaf(db[0], a0 - a1, __builtin_fmaf(db[2], a2 - a1, db[3] * (a3 - a1)));
+        } else {
+            q[i] = 0.0f;
+            dq[i] = 0.0f;
+        }
+    }
+}
+
+// J_p and J_l terms of one checkpoint
+__device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[CP_MAX_JOINTS],
+                                           const float (&dq)[CP_MAX_JOINTS], float &jp, float &jl) {
+    float sq = 0.0f, lim = 0.0f;
+#pragma unroll
+    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+        if (i < P.n_joints) {
+            sq = __builtin_fmaf(dq[i], dq[i], sq);
+            const JointDev J = P.joints[i];
+            float hi = fmaxf(q[i] - J.qmax, 0.0f), lo = fmaxf(J.qmin - q[i], 0.0f);
+            lim = __builtin_fmaf(hi, hi, __builtin_fmaf(lo, lo, lim));
+        }
+    }
+    jp = P.jp_mode == CP_JP_SQUARED ? sq : fsqrt(sq);
+    jl = lim;
+}
+
+template <bool TAPE>
+__global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__restrict__ W, int B,
+                                                  double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape) {
+    const int64_t N = (int64_t)B * P.ns;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = g < N;
+    const int b = active ? (int)(g / P.ns) : B - 1;
+    const int k = active ? (int)(g - (int64_t)b * P.ns) + 1 : 1;
+    const float *Wb = W + (size_t)b * P.K * P.n_joints;
+
+    float q[CP_MAX_JOINTS], dq[CP_MAX_JOINTS], bw[4], db[4];
+    int j;
+    interpolate(P, Wb, k, q, dq, j, bw, db);
+    float jp, jl;
+    step_terms(P, q, dq, jp, jl);
+    Best best = config_distance<TAPE>(P, q);
+    float dphi;
+    float phi = hinge_value(P, best.d, dphi);
+    float c = __builtin_fmaf(P.w_c, phi, __builtin_fmaf(P.w_l, jl, jp));
+    if (TAPE && active) {
+        uint32_t o = argmin_obstacle(P, best.cx, best.cy, best.cz);
+        tape[g] = ((uint32_t)best.s << 16) | o;
+    }
+    float dk = best.d;
+    if (!active) { c = 0.0f; dk = kInf; }
+
+    // per-path sums of this wave: paths p0..p1 are contiguous
+    const int64_t w = g / kWave;
+    const int64_t g_first = w * kWave;
+    const int64_t g_last = min(g_first + kWave - 1, N - 1);
+    const int p0 = (int)(g_first / P.ns), p1 = (int)(g_last / P.ns);
+    const int bl = active ? b : -1;
+    for (int p = p0; p <= p1; ++p) {
+        double s = wave_sum_d(bl == p ? (double)c : 0.0);
+        float m = wave_min(bl == p ? dk : kInf);
+        if ((threadIdx.x & (kWave - 1)) == 0) partial[w * slots + (p - p0)] = make_double2(s, (double)m);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_eval_reduce(const double2 *__restrict__ partial, int slots, int B, int ns,
+                                                     float margin, float *__restrict__ cost,
+                                                     float *__restrict__ min_dist, uint8_t *__restrict__ flags) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int64_t g0 = (int64_t)b * ns, g1 = g0 + ns - 1;
+    double s = 0.0;
+    float m = kInf;
+    for (int64_t w = g0 / kWave; w <= g1 / kWave; ++w) {
+        const int p0 = (int)((w * kWave) / ns);
+        const double2 v = partial[w * slots + (b - p0)];
+        s += v.x;
+        m = fminf(m, (float)v.y);
+    }
+    cost[b] = (float)s;
+    if (min_dist) min_dist[b] = m;
+    if (flags) flags[b] = (uint8_t)(m < margin);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+
+// gradient of the signed distance of obstacle o at c (same case split as the
+// exact SDFs); returns the signed distance
+__device__ __forceinline__ float obstacle_sd_grad(const PlanView &P, uint32_t o, float cx, float cy, float cz,
+                                                  float (&gr)[3]) {
+    if (o == CP_OBS_SDF) return sdf_query(P, cx, cy, cz, gr);
+    if (o == 0) {
+        gr[0] = 0.0f; gr[1] = 0.0f; gr[2] = 1.0f;
+        return cz - P.ground_z;
+    }
+    if ((int)o <= P.n_cyl) {
+        const float4 c = P.cyl_orig[o - 1];
+        const GroupDev g = P.groups[__float_as_int(c.w)];
+        float dx = cx - c.x, dy = cy - c.y, dz = cz - g.zc;
+        float rho = fsqrt(__builtin_fmaf(dx, dx, dy * dy));
+        float a = rho - c.z, b = fabsf(dz) - g.hz;
+        float sd = cyl_combine(a, b);
+        float inv = rho > 0.0f ? 1.0f / rho : 0.0f;
+        float gax = dx * inv, gay = dy * inv, gbz = dz >= 0.0f ? 1.0f : -1.0f;
+        if (a > 0.0f && b > 0.0f) {
+            float out = sd;  // sqrt(a^2 + b^2) here
+            gr[0] = a * gax / out; gr[1] = a * gay / out; gr[2] = b * gbz / out;
+        } else if (a > 0.0f || (b <= 0.0f && a >= b)) {
+            gr[0] = gax; gr[1] = gay; gr[2] = 0.0f;
+        } else {
+            gr[0] = 0.0f; gr[1] = 0.0f; gr[2] = gbz;
+        }
+        return sd;
+    }
+    const int bi = (int)o - 1 - P.n_cyl;
+    const float4 b0 = P.box[2 * bi], b1 = P.box[2 * bi + 1];
+    float d[3] = {cx - b0.x, cy - b0.y, cz - b0.z};
+    float h[3] = {b0.w, b1.x, b1.y};
+    float qv[3], sg[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { sg[i] = d[i] >= 0.0f ? 1.0f : -1.0f; qv[i] = fabsf(d[i]) - h[i]; }
+    float sd = box_sd(cx, cy, cz, b0, b1);
+    float px = fmaxf(qv[0], 0.0f), py = fmaxf(qv[1], 0.0f), pz = fmaxf(qv[2], 0.0f);
+    float o2 = __builtin_fmaf(px, px, __builtin_fmaf(py, py, pz * pz));
+    if (o2 > 0.0f) {
+        float inv = 1.0f / fsqrt(o2);
+        gr[0] = sg[0] * px * inv; gr[1] = sg[1] * py * inv; gr[2] = sg[2] * pz * inv;
+    } else {
+        int am = 0;
+        if (qv[1] > qv[am]) am = 1;
+        if (qv[2] > qv[am]) am = 2;
+        gr[0] = am == 0 ? sg[0] : 0.0f;
+        gr[1] = am == 1 ? sg[1] : 0.0f;
+        gr[2] = am == 2 ? sg[2] : 0.0f;
+    }
+    return sd;
+}
+
+// d cost_k / d q for the collision term through the tape's pair (s, o):
+// recomputes the chain, the sphere centre and the pair's signed distance.
+__device__ __forceinline__ void collision_grad(const PlanView &P, const float (&q)[CP_MAX_JOINTS], int s_orig,
+                                               uint32_t o, float (&gq)[CP_MAX_JOINTS]) {
+    // locate the sphere (table sorted by frame; `orig` is the caller's index)
+    int si = 0;
+    for (int i = 0; i < P.n_spheres; ++i)
+        if (P.spheres[i].orig == s_orig) si = i;
+    const SphereDev sp = P.spheres[si];
+    float aw[CP_MAX_JOINTS][3], pj[CP_MAX_JOINTS][3];
+    float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+    Xf T;
+    xf_identity(T);
+    if (sp.frame == 0) xf_point(T, sp.lx, sp.ly, sp.lz, cx, cy, cz);
+#pragma unroll
+    for (int f = 1; f <= CP_MAX_JOINTS; ++f) {
+        if (f <= P.n_joints) {
+            const JointDev J = P.joints[f - 1];
+            // world axis of joint f-1: R_{f-1} a (unchanged by its own rotation)
+            aw[f - 1][0] = __builtin_fmaf(T.r[0], J.ax, __builtin_fmaf(T.r[1], J.ay, T.r[2] * J.az));
+            aw[f - 1][1] = __builtin_fmaf(T.r[3], J.ax, __builtin_fmaf(T.r[4], J.ay, T.r[5] * J.az));
+            aw[f - 1][2] = __builtin_fmaf(T.r[6], J.ax, __builtin_fmaf(T.r[7], J.ay, T.r[8] * J.az));
+            xf_joint(T, J, q[f - 1]);
+            pj[f - 1][0] = T.p[0]; pj[f - 1][1] = T.p[1]; pj[f - 1][2] = T.p[2];
+            if (sp.frame == f) xf_point(T, sp.lx, sp.ly, sp.lz, cx, cy, cz);
+        }
+    }
+    // a tape entry that names no obstacle of this plan contributes nothing
+    const bool valid = (o == CP_OBS_SDF) ? (P.sdf != nullptr)
+                                          : (o == 0 ? P.has_ground != 0 : (int)o <= P.n_cyl + P.n_box);
+    if (!valid || s_orig >= P.n_spheres) return;
+    float gr[3];
+    float sd = obstacle_sd_grad(P, o, cx, cy, cz, gr);
+    float dphi;
+    hinge_value(P, sd - sp.r, dphi);
+    float scale = P.w_c * dphi;
+#pragma unroll
+    for (int jj = 0; jj < CP_MAX_JOINTS; ++jj) {
+        if (jj < P.n_joints && jj < sp.frame && scale != 0.0f) {
+            float jx, jy, jz;
+            if (P.joints[jj].type == CP_REVOLUTE) {
+                float rx = cx - pj[jj][0], ry = cy - pj[jj][1], rz = cz - pj[jj][2];
+                jx = aw[jj][1] * rz - aw[jj][2] * ry;
+                jy = aw[jj][2] * rx - aw[jj][0] * rz;
+                jz = aw[jj][0] * ry - aw[jj][1] * rx;
+            } else {
+                jx = aw[jj][0]; jy = aw[jj][1]; jz = aw[jj][2];
+            }
+            gq[jj] += scale * __builtin_fmaf(gr[0], jx, __builtin_fmaf(gr[1], jy, gr[2] * jz));
+        }
+    }
+}
+
+constexpr int kBwdThreads = 256;
+constexpr int kMaxCtrl = CP_MAX_K + 6;
+
+template <bool TAPE>
+__global__ __launch_bounds__(kBwdThreads) void k_eval_bwd(PlanView P, const float *__restrict__ W, int B,
+                                                          const uint32_t *__restrict__ tape,
+                                                          const float *__restrict__ grad_cost,
+                                                          float *__restrict__ grad_W) {
+    __shared__ float contrib[kBwdThreads][4][CP_MAX_JOINTS];
+    __shared__ int jwin[kBwdThreads];
+    __shared__ double acc[kMaxCtrl * CP_MAX_JOINTS];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int n = P.n_joints;
+    const int nc = n_ctrl_points(P);
+    for (int i = tid; i < nc * n; i += kBwdThreads) acc[i] = 0.0;
+    const float *Wb = W + (size_t)b * P.K * n;
+    for (int k0 = 1; k0 <= P.ns; k0 += kBwdThreads) {
+        const int k = k0 + tid;
+        const bool active = k <= P.ns;
+        const int kk = active ? k : P.ns;
+        float q[CP_MAX_JOINTS], dq[CP_MAX_JOINTS], bw[4], db[4];
+        int j;
+        interpolate(P, Wb, kk, q, dq, j, bw, db);
+        float gq[CP_MAX_JOINTS], gd[CP_MAX_JOINTS];
+        float sq = 0.0f;
+#pragma unroll
+        for (int i = 0; i < CP_MAX_JOINTS; ++i) sq = __builtin_fmaf(dq[i], dq[i], sq);
+        float len = fsqrt(sq);
+        float inv = len > 0.0f ? 1.0f / len : 0.0f;
+#pragma unroll
+        for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+            gd[i] = P.jp_mode == CP_JP_SQUARED ? 2.0f * dq[i] : dq[i] * inv;
+            gq[i] = 0.0f;
+            if (i < n) {
+                const JointDev J = P.joints[i];
+                float hi = fmaxf(q[i] - J.qmax, 0.0f), lo = fmaxf(J.qmin - q[i], 0.0f);
+                gq[i] = P.w_l * (2.0f * hi - 2.0f * lo);
+            }
+        }
+        int s_orig;
+        uint32_t o;
+        if (TAPE) {
+            uint32_t t = tape[(size_t)b * P.ns + (kk - 1)];
+            s_orig = (int)(t >> 16);
+            o = t & 0xFFFFu;
+        } else {
+            Best best = config_distance<true>(P, q);
+            s_orig = best.s;
+            o = argmin_obstacle(P, best.cx, best.cy, best.cz);
+        }
+        collision_grad(P, q, s_orig, o, gq);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < CP_MAX_JOINTS; ++i)
+                contrib[tid][t][i] = active ? __builtin_fmaf(bw[t], gq[i], db[t] * gd[i]) : 0.0f;
+        jwin[tid] = active ? j : -100;
+        __syncthreads();
+        // control points touched by this chunk, each summed over lanes in order
+        const int last = min(kBwdThreads, P.ns - k0 + 1);
+        const int jlo = jwin[0], jhi = jwin[last - 1] + 3;
+        const int cnt = (jhi - jlo + 1) * n;
+        for (int idx = tid; idx < cnt; idx += kBwdThreads) {
+            const int cpi = jlo + idx / n, jj = idx % n;
+            float s = 0.0f;
+            for (int l = 0; l < last; ++l) {
+                const int t = cpi - jwin[l];
+                if (t >= 0 && t < 4) s += contrib[l][t][jj];
+            }
+            acc[cpi * n + jj] += (double)s;
+        }
+        __syncthreads();
+    }
+    const float gc = grad_cost[b];
+    const int lead = P.interp == CP_INTERP_BSPLINE ? 3 : 1;
+    for (int idx = tid; idx < P.K * n; idx += kBwdThreads) {
+        const int i = idx / n, jj = idx % n;
+        grad_W[(size_t)b * P.K * n + idx] = gc * (float)acc[(i + lead) * n + jj];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// test exports
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_debug_fk(PlanView P, const float *__restrict__ Q, int N,
+                                                  float *__restrict__ centers, float *__restrict__ frames) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    float q[CP_MAX_JOINTS];
+#pragma unroll
+    for (int jj = 0; jj < CP_MAX_JOINTS; ++jj) q[jj] = jj < P.n_joints ? Q[(size_t)i * P.n_joints + jj] : 0.0f;
+    Xf T;
+    xf_identity(T);
+    for (int f = 0; f <= P.n_joints; ++f) {
+        if (f > 0) xf_joint(T, P.joints[f - 1], pick(q, f - 1));
+        if (frames) {
+            float *fr = frames + ((size_t)i * (P.n_joints + 1) + f) * 12;
+            for (int e = 0; e < 9; ++e) fr[e] = T.r[e];
+            for (int e = 0; e < 3; ++e) fr[9 + e] = T.p[e];
+        }
+        if (centers) {
+            for (int s = P.frame_start[f]; s < P.frame_start[f + 1]; ++s) {
+                const SphereDev sp = P.spheres[s];
+                float cx, cy, cz;
+                xf_point(T, sp.lx, sp.ly, sp.lz, cx, cy, cz);
+                float *c = centers + ((size_t)i * P.n_spheres + sp.orig) * 3;
+                c[0] = cx; c[1] = cy; c[2] = cz;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_debug_configs(PlanView P, const float *__restrict__ Q, int N,
+                                                       float *__restrict__ dist, uint32_t *__restrict__ arg) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ii = i < N ? i : N - 1;
+    float q[CP_MAX_JOINTS];
+#pragma unroll
+    for (int jj = 0; jj < CP_MAX_JOINTS; ++jj) q[jj] = jj < P.n_joints ? Q[(size_t)ii * P.n_joints + jj] : 0.0f;
+    Best best = config_distance<true>(P, q);
+    uint32_t o = argmin_obstacle(P, best.cx, best.cy, best.cz);
+    if (i < N) {
+        dist[i] = best.d;
+        if (arg) arg[i] = ((uint32_t)best.s << 16) | o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+int eval_slots(int ns) { return kWave / ns + 2; }
+
+size_t eval_partial_count(int B, int ns) {
+    const int64_t N = (int64_t)B * ns;
+    return (size_t)((N + kWave - 1) / kWave) * eval_slots(ns);
+}
+
+hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *partial, uint32_t *tape,
+                           float *cost, float *min_dist, uint8_t *flags, hipStream_t st) {
+    const int64_t N = (int64_t)B * P.ns;
+    const int slots = eval_slots(P.ns);
+    const dim3 grid((unsigned)((N + 255) / 256));
+    if (tape)
+        hipLaunchKernelGGL(k_eval_fwd<true>, grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
+    else
+        hipLaunchKernelGGL(k_eval_fwd<false>, grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eval_reduce, dim3((B + 255) / 256), dim3(256), 0, st, partial, slots, B, P.ns, P.margin,
+                       cost, min_dist, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_bwd(const PlanView &P, const float *W, int B, const uint32_t *tape, const float *grad_cost,
+                           float *grad_W, hipStream_t st) {
+    if (tape)
+        hipLaunchKernelGGL(k_eval_bwd<true>, dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost, grad_W);
+    else
+        hipLaunchKernelGGL(k_eval_bwd<false>, dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost, grad_W);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_fk(const PlanView &P, const float *Q, int N, float *centers, float *frames, hipStream_t st) {
+    hipLaunchKernelGGL(k_debug_fk, dim3((N + 255) / 256), dim3(256), 0, st, P, Q, N, centers, frames);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_configs(const PlanView &P, const float *Q, int N, float *dist, uint32_t *arg, hipStream_t st) {
+    hipLaunchKernelGGL(k_debug_configs, dim3((N + 255) / 256), dim3(256), 0, st, P, Q, N, dist, arg);
+    return hipGetLastError();
+}
+
+}  // namespace cp

@@ -1,0 +1,292 @@
+// Internal device-side tables and helpers of the craneplan library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "craneplan.h"
+
+namespace cp {
+
+constexpr int kWave = 64;
+constexpr float kInf = __builtin_huge_valf();
+
+// One joint: fixed offset, then motion about / along a unit axis.
+struct JointDev {
+    int32_t type;
+    float ax, ay, az;
+    float ox, oy, oz;
+    float qmin, qmax, qhold;
+    int32_t active;
+    int32_t pad;
+};
+
+// Spheres are stored sorted by frame; `orig` is the caller's sphere index.
+struct SphereDev {
+    float lx, ly, lz, r;
+    int32_t frame, orig, pad0, pad1;
+};
+
+// Cylinders that share one vertical extent form a group.  Within a group the
+// minimum over cylinders of (radial distance - R) is taken first and the
+// height term applied once (the cylinder SDF is non-decreasing in the radial
+// term for a fixed height offset, so this equals the minimum of the SDFs).
+struct GroupDev {
+    int32_t start, count;  // into the sorted cylinder table; count is a multiple of 4
+    float zc, hz;          // centre and half height of the shared extent
+};
+
+// Everything a kernel needs about a plan, passed by value.
+struct PlanView {
+    int32_t n_joints, n_spheres, n_groups, n_box, n_cyl, has_ground;
+    float ground_z;
+    int32_t K, M, ns, interp, jp_mode, hinge;
+    float margin, lambda_c, w_c, w_l;
+    const JointDev *joints;       // [n_joints]
+    const SphereDev *spheres;     // [n_spheres], sorted by frame
+    const int32_t *frame_start;   // [n_joints + 2]: spheres of frame f are [frame_start[f], frame_start[f+1])
+    const float4 *cyl;            // [sum of group counts] (x, y, R, unused), grouped
+    const GroupDev *groups;       // [n_groups]
+    const float4 *cyl_orig;       // [n_cyl] (x, y, R, group) in the caller's order
+    const float4 *box;            // [n_box][2]: (cx, cy, cz, hx), (hy, hz, -, -)
+    const float *qs, *qg;         // [n_joints]
+    const float *sdf;             // [nz][ny][nx] or null
+    int32_t sdf_n[3];
+    float sdf_o[3], sdf_inv_h, sdf_h;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// signed distance of a vertical cylinder with radial term a and height term b
+// (exact Euclidean SDF of the solid: inside part + outside part)
+__device__ __forceinline__ float cyl_combine(float a, float b) {
+    float ap = fmaxf(a, 0.0f), bp = fmaxf(b, 0.0f);
+    return fminf(fmaxf(a, b), 0.0f) + fsqrt(__builtin_fmaf(ap, ap, bp * bp));
+}
+
+__device__ __forceinline__ float cyl_radial(float cx, float cy, float4 c) {
+    float dx = cx - c.x, dy = cy - c.y;
+    return fsqrt(__builtin_fmaf(dx, dx, dy * dy)) - c.z;
+}
+
+__device__ __forceinline__ float box_sd(float cx, float cy, float cz, float4 b0, float4 b1) {
+    float qx = fabsf(cx - b0.x) - b0.w;
+    float qy = fabsf(cy - b0.y) - b1.x;
+    float qz = fabsf(cz - b0.z) - b1.y;
+    float px = fmaxf(qx, 0.0f), py = fmaxf(qy, 0.0f), pz = fmaxf(qz, 0.0f);
+    float o2 = __builtin_fmaf(px, px, __builtin_fmaf(py, py, pz * pz));
+    return fsqrt(o2) + fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f);
+}
+
+// trilinear signed-distance lookup (voxel-centre samples, clamped coordinates)
+__device__ __forceinline__ float sdf_query(const PlanView &P, float cx, float cy, float cz, float *grad) {
+    float g[3] = {(cx - P.sdf_o[0]) * P.sdf_inv_h - 0.5f, (cy - P.sdf_o[1]) * P.sdf_inv_h - 0.5f,
+                  (cz - P.sdf_o[2]) * P.sdf_inv_h - 0.5f};
+    int i0[3];
+    float f[3], dg[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float fl = floorf(g[a]);
+        float hi = (float)(P.sdf_n[a] - 2);
+        float il = fminf(fmaxf(fl, 0.0f), hi);
+        float fr = g[a] - il;
+        dg[a] = (fr >= 0.0f && fr <= 1.0f) ? 1.0f : 0.0f;
+        fr = fminf(fmaxf(fr, 0.0f), 1.0f);
+        i0[a] = (int)il;
+        f[a] = fr;
+    }
+    const int nx = P.sdf_n[0], ny = P.sdf_n[1];
+    const float *base = P.sdf + ((size_t)i0[2] * ny + i0[1]) * nx + i0[0];
+    const size_t sy = nx, sz = (size_t)nx * ny;
+    float v000 = base[0], v001 = base[1], v010 = base[sy], v011 = base[sy + 1];
+    float v100 = base[sz], v101 = base[sz + 1], v110 = base[sz + sy], v111 = base[sz + sy + 1];
+    // interpolate along x, then y, then z
+    float c00 = __builtin_fmaf(f[0], v001 - v000, v000);
+    float c01 = __builtin_fmaf(f[0], v011 - v010, v010);
+    float c10 = __builtin_fmaf(f[0], v101 - v100, v100);
+    float c11 = __builtin_fmaf(f[0], v111 - v110, v110);
+    float c0 = __builtin_fmaf(f[1], c01 - c00, c00);
+    float c1 = __builtin_fmaf(f[1], c11 - c10, c10);
+    float phi = __builtin_fmaf(f[2], c1 - c0, c0);
+    if (grad) {
+        float dx0 = __builtin_fmaf(f[1], (v011 - v010) - (v001 - v000), v001 - v000);
+        float dx1 = __builtin_fmaf(f[1], (v111 - v110) - (v101 - v100), v101 - v100);
+        float gx = __builtin_fmaf(f[2], dx1 - dx0, dx0);
+        float gy = __builtin_fmaf(f[2], c11 - c10 - (c01 - c00), c01 - c00);
+        float gz = c1 - c0;
+        grad[0] = gx * dg[0] * P.sdf_inv_h;
+        grad[1] = gy * dg[1] * P.sdf_inv_h;
+        grad[2] = gz * dg[2] * P.sdf_inv_h;
+    }
+    return phi;
+}
+
+// ---------------------------------------------------------------------------
+// uniform cubic B-spline blend on one span (closed form of the degree-3 basis
+// on uniform knots) and its backward difference over one checkpoint step h,
+// written without cancellation: db_t(u) = b_t(u) - b_t(u - h)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void bspline_blend(float u, float h, float b[4], float db[4]) {
+    float v = 1.0f - u;
+    float u2 = u * u, v2 = v * v;
+    b[0] = v2 * v * (1.0f / 6.0f);
+    b[1] = __builtin_fmaf(u2, __builtin_fmaf(0.5f, u, -1.0f), 2.0f / 3.0f);
+    b[2] = __builtin_fmaf(v2, __builtin_fmaf(0.5f, v, -1.0f), 2.0f / 3.0f);
+    b[3] = u2 * u * (1.0f / 6.0f);
+    // cube differences: u^3 - (u-h)^3 = h (3u^2 - 3uh + h^2); v^3 - (v+h)^3 = -h (3v^2 + 3vh + h^2)
+    float h2 = h * h;
+    float Au = __builtin_fmaf(3.0f * u, u - h, h2);
+    float Av = __builtin_fmaf(3.0f * v, v + h, h2);
+    float du2 = h * (2.0f * u - h);   // u^2 - (u-h)^2
+    db[0] = -h * Av * (1.0f / 6.0f);
+    db[3] = h * Au * (1.0f / 6.0f);
+    // b1 = u^3/2 - u^2 + 2/3 ; b2 = v^3/2 - v^2 + 2/3 with v = 1 - u
+    db[1] = __builtin_fmaf(0.5f * h, Au, -du2);
+    float dv2 = -h * (2.0f * v + h);  // v^2 - (v+h)^2
+    db[2] = __builtin_fmaf(-0.5f * h, Av, -dv2);
+}
+
+// Control point i of path b (B-spline polygon: 3 x start, W, 3 x goal;
+// linear polygon: start, W, goal).
+__device__ __forceinline__ const float *control_point(const PlanView &P, const float *Wb, int i) {
+    const int lead = P.interp == CP_INTERP_BSPLINE ? 3 : 1;
+    if (i < lead) return P.qs;
+    if (i < lead + P.K) return Wb + (size_t)(i - lead) * P.n_joints;
+    return P.qg;
+}
+
+// Position of checkpoint k (1..n_s): first control point j of its span
+// window, blend weights b[4] and difference weights db[4] so that
+//   q_k = sum_t b_t P_{j+t},  q_k - q_{k-1} = sum_t db_t P_{j+t}.
+__device__ __forceinline__ void checkpoint_weights(const PlanView &P, int k, int &j, float b[4], float db[4]) {
+    j = (k - 1) / P.M;
+    int i = k - j * P.M;  // 1..M
+    float h = 1.0f / (float)P.M;
+    float u = (float)i * h;
+    if (P.interp == CP_INTERP_BSPLINE) {
+        bspline_blend(u, h, b, db);
+    } else {
+        b[0] = 1.0f - u; b[1] = u; b[2] = 0.0f; b[3] = 0.0f;
+        db[0] = -h; db[1] = h; db[2] = 0.0f; db[3] = 0.0f;
+    }
+}
+
+__device__ __forceinline__ int n_ctrl_points(const PlanView &P) {
+    return P.interp == CP_INTERP_BSPLINE ? P.K + 6 : P.K + 2;
+}
+
+// Rigid transform in registers: R row-major, p.
+struct Xf {
+    float r[9];
+    float p[3];
+};
+
+__device__ __forceinline__ void xf_identity(Xf &T) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) T.r[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+    T.p[0] = T.p[1] = T.p[2] = 0.0f;
+}
+
+// T <- T * Trans(origin) * Motion(q) for joint J
+__device__ __forceinline__ void xf_joint(Xf &T, const JointDev &J, float q) {
+    float ox = J.ox, oy = J.oy, oz = J.oz;
+    if (J.type == CP_PRISMATIC) {
+        ox = __builtin_fmaf(q, J.ax, ox);
+        oy = __builtin_fmaf(q, J.ay, oy);
+        oz = __builtin_fmaf(q, J.az, oz);
+    }
+    float np[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        np[i] = __builtin_fmaf(T.r[3 * i], ox, __builtin_fmaf(T.r[3 * i + 1], oy, __builtin_fmaf(T.r[3 * i + 2], oz, T.p[i])));
+    T.p[0] = np[0]; T.p[1] = np[1]; T.p[2] = np[2];
+    if (J.type == CP_REVOLUTE) {
+        float s, c;
+        sincosf(q, &s, &c);
+        float v = 1.0f - c;
+        float x = J.ax, y = J.ay, z = J.az;
+        float R[9];
+        R[0] = __builtin_fmaf(x * x, v, c);
+        R[1] = __builtin_fmaf(x * y, v, -z * s);
+        R[2] = __builtin_fmaf(x * z, v, y * s);
+        R[3] = __builtin_fmaf(y * x, v, z * s);
+        R[4] = __builtin_fmaf(y * y, v, c);
+        R[5] = __builtin_fmaf(y * z, v, -x * s);
+        R[6] = __builtin_fmaf(z * x, v, -y * s);
+        R[7] = __builtin_fmaf(z * y, v, x * s);
+        R[8] = __builtin_fmaf(z * z, v, c);
+        float nr[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                nr[3 * i + k] = __builtin_fmaf(T.r[3 * i], R[k], __builtin_fmaf(T.r[3 * i + 1], R[3 + k], T.r[3 * i + 2] * R[6 + k]));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) T.r[i] = nr[i];
+    }
+}
+
+__device__ __forceinline__ void xf_point(const Xf &T, float lx, float ly, float lz, float &cx, float &cy, float &cz) {
+    cx = __builtin_fmaf(T.r[0], lx, __builtin_fmaf(T.r[1], ly, __builtin_fmaf(T.r[2], lz, T.p[0])));
+    cy = __builtin_fmaf(T.r[3], lx, __builtin_fmaf(T.r[4], ly, __builtin_fmaf(T.r[5], lz, T.p[1])));
+    cz = __builtin_fmaf(T.r[6], lx, __builtin_fmaf(T.r[7], ly, __builtin_fmaf(T.r[8], lz, T.p[2])));
+}
+
+// q[j] with a wave-uniform index j (avoids dynamic register indexing)
+__device__ __forceinline__ float pick(const float q[CP_MAX_JOINTS], int j) {
+    float v = q[0];
+#pragma unroll
+    for (int i = 1; i < CP_MAX_JOINTS; ++i) v = (j == i) ? q[i] : v;
+    return v;
+}
+
+__device__ __forceinline__ float hinge_value(const PlanView &P, float d, float &dphi) {
+    float m = P.margin, lam = P.lambda_c;
+    if (P.hinge == CP_HINGE_HARD) {
+        dphi = d < m ? -lam : 0.0f;
+        return d < m ? lam * (m - d) : 0.0f;
+    }
+    if (d < 0.0f) {
+        dphi = -lam;
+        return lam * (0.5f * m - d);
+    }
+    if (d < m) {
+        float e = m - d;
+        dphi = -lam * e / m;
+        return lam * e * e / (2.0f * m);
+    }
+    dphi = 0.0f;
+    return 0.0f;
+}
+
+// total order key of a cost: increasing in the cost, NaN after everything
+__device__ __forceinline__ uint32_t cost_key(float c) {
+    if (c != c) return 0xFFFFFFFFu;
+    if (c == 0.0f) c = 0.0f;
+    uint32_t u = __float_as_uint(c);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// wave reductions (butterfly over all 64 lanes; fixed order, so deterministic)
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+}  // namespace cp

@@ -1,0 +1,61 @@
+// Host-side launchers of the craneplan kernels (internal).
+#pragma once
+
+#include "internal.h"
+
+namespace cp {
+
+// evaluation (eval.hip)
+int eval_slots(int ns);
+size_t eval_partial_count(int B, int ns);
+hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *partial, uint32_t *tape, float *cost,
+                           float *min_dist, uint8_t *flags, hipStream_t st);
+hipError_t launch_eval_bwd(const PlanView &P, const float *W, int B, const uint32_t *tape, const float *grad_cost,
+                           float *grad_W, hipStream_t st);
+hipError_t launch_debug_fk(const PlanView &P, const float *Q, int N, float *centers, float *frames, hipStream_t st);
+hipError_t launch_debug_configs(const PlanView &P, const float *Q, int N, float *dist, uint32_t *arg,
+                                hipStream_t st);
+
+// optimizer state on the device (opt.hip)
+struct OptView {
+    int32_t B, nu, D, n_act, npol;
+    int32_t act[CP_MAX_JOINTS];  // sampled joint ids
+    double eps;
+    uint64_t seed;
+    uint32_t problem_id;
+    float eta, clip;
+    double *mu;        // [D]
+    double *C;         // [D][D]
+    double *L;         // [D][D] lower Cholesky factor used for sampling
+    double *xi;        // [B][D] samples
+    float *W;          // [B][K][n] samples as waypoints
+    float *cost;       // [B]
+    float *min_dist;   // [B]
+    int32_t *elite;    // [nu] elite indices in rank order (>= B: polished slot)
+    int32_t *elite0;   // [nu] elite indices before polish
+    float *Wp;         // [npol][K][n] polished elites
+    float *cost_p;     // [npol]
+    float *grad_p;     // [npol][K][n]
+    float *ones;       // [npol] 1.0
+    double *w;         // [nu] log-rank weights
+    int64_t *t;        // iteration counter
+    int32_t *status;   // 0 ok, 1 covariance not positive definite
+    float *best_cost;  // [1]
+    float *best_W;     // [K][n]
+};
+
+hipError_t launch_sample(const PlanView &P, const OptView &O, hipStream_t st);
+hipError_t launch_select(const OptView &O, hipStream_t st);
+hipError_t launch_polish_gather(const PlanView &P, const OptView &O, hipStream_t st);
+hipError_t launch_polish_gd(const PlanView &P, const OptView &O, hipStream_t st);
+hipError_t launch_rerank(const OptView &O, hipStream_t st);
+hipError_t launch_update(const PlanView &P, const OptView &O, hipStream_t st);
+hipError_t launch_chol(const OptView &O, hipStream_t st);
+hipError_t launch_init_state(const PlanView &P, const OptView &O, float sigma0, hipStream_t st);
+
+// signed-distance grid (sdf.hip)
+hipError_t launch_sdf_build(const float *points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
+                            float *sdf, uint8_t *occ, int32_t *edt_occ, int32_t *edt_free, int32_t *work_a,
+                            int32_t *work_b, hipStream_t st);
+
+}  // namespace cp

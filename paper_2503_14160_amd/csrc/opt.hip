@@ -1,0 +1,466 @@
+// Algorithm 1 steps other than evaluation: sampling (1), selection (3),
+// log-rank weights (4), mean (5) and covariance (6) updates, the Cholesky
+// factor used for sampling, and the gradient polish of the elites.
+// All state lives on the device; no step needs the host, so the loop can be
+// captured into a graph.  Reductions run in a fixed order (deterministic).
+#include "launch.h"
+
+namespace cp {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller normals
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+        const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ double uniform01(uint32_t x) {
+    return (2.0 * (double)(x >> 9) + 1.0) * (1.0 / 16777216.0);
+}
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &z0, double &z1) {
+    const double two_pi = 6.283185307179586476925286766559;
+    const double r = sqrt(-2.0 * log(uniform01(a)));
+    const double th = two_pi * uniform01(b);
+    z0 = r * cos(th);
+    z1 = r * sin(th);
+}
+
+// ---------------------------------------------------------------------------
+// state initialisation: mu_0 evenly spaced on the start-goal segment,
+// C_0 = sigma0^2 I, log-rank weights
+// ---------------------------------------------------------------------------
+
+__global__ void k_init_state(PlanView P, OptView O, float sigma0) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int D = O.D;
+    if (tid < D) {
+        const int k = tid / O.n_act, a = tid % O.n_act;
+        const int jj = O.act[a];
+        const double qs = P.qs[jj], qg = P.qg[jj];
+        O.mu[tid] = qs + (double)(k + 1) / (double)(P.K + 1) * (qg - qs);
+    }
+    for (int i = tid; i < D * D; i += gridDim.x * blockDim.x) {
+        const double s = (double)sigma0;
+        O.C[i] = (i / D == i % D) ? s * s : 0.0;
+    }
+    if (tid == 0) {
+        // w_j = (ln(nu + 1/2) - ln j) / sum_k (ln(nu + 1/2) - ln k), summed in rank order
+        const double lmax = log((double)O.nu + 0.5);
+        double s = 0.0;
+        for (int j = 1; j <= O.nu; ++j) s += lmax - log((double)j);
+        for (int j = 1; j <= O.nu; ++j) O.w[j - 1] = (lmax - log((double)j)) / s;
+        *O.t = 0;
+        *O.status = 0;
+        *O.best_cost = kInf;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sampling: xi_b = mu + L z_b (double), waypoints W_b (float)
+// ---------------------------------------------------------------------------
+
+constexpr int kSampleTile = 16;  // paths per block
+
+__global__ __launch_bounds__(256) void k_sample(PlanView P, OptView O) {
+    __shared__ double z[kSampleTile][CP_MAX_DIM];
+    const int D = O.D;
+    const int b0 = blockIdx.x * kSampleTile;
+    const uint32_t t = (uint32_t)*O.t;
+    const uint32_t k0 = (uint32_t)O.seed, k1 = (uint32_t)(O.seed >> 32);
+    const int G = (D + 3) / 4;
+    for (int idx = threadIdx.x; idx < kSampleTile * G; idx += blockDim.x) {
+        const int bl = idx / G, g = idx % G, b = b0 + bl;
+        if (b >= O.B) continue;
+        const uint4 x = philox4x32_10(make_uint4((uint32_t)g, (uint32_t)b, t, O.problem_id), k0, k1);
+        double zz[4];
+        box_muller(x.x, x.y, zz[0], zz[1]);
+        box_muller(x.z, x.w, zz[2], zz[3]);
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+            if (4 * g + h < D) z[bl][4 * g + h] = zz[h];
+    }
+    __syncthreads();
+    const int n = P.n_joints;
+    for (int idx = threadIdx.x; idx < kSampleTile * D; idx += blockDim.x) {
+        const int bl = idx / D, e = idx % D, b = b0 + bl;
+        if (b >= O.B) continue;
+        const double *Lr = O.L + (size_t)e * D;
+        double s = O.mu[e];
+        for (int e2 = 0; e2 <= e; ++e2) s = fma(Lr[e2], z[bl][e2], s);
+        O.xi[(size_t)b * D + e] = s;
+        const int k = e / O.n_act, a = e % O.n_act;
+        O.W[((size_t)b * P.K + k) * n + O.act[a]] = (float)s;
+    }
+    // joints that are not sampled take their hold value
+    for (int idx = threadIdx.x; idx < kSampleTile * P.K * n; idx += blockDim.x) {
+        const int bl = idx / (P.K * n), r = idx % (P.K * n), b = b0 + bl;
+        if (b >= O.B) continue;
+        const int jj = r % n;
+        const JointDev J = P.joints[jj];
+        if (!J.active) O.W[(size_t)b * P.K * n + r] = J.qhold;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// selection: the nu smallest (cost, index) pairs, in rank order
+// ---------------------------------------------------------------------------
+
+constexpr int kSelThreads = 1024;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *buf, uint32_t &total) {
+    const int tid = threadIdx.x;
+    buf[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < kSelThreads; o <<= 1) {
+        uint32_t a = tid >= o ? buf[tid - o] : 0u;
+        __syncthreads();
+        buf[tid] += a;
+        __syncthreads();
+    }
+    total = buf[kSelThreads - 1];
+    uint32_t incl = buf[tid];
+    __syncthreads();
+    return incl - v;
+}
+
+// bitonic sort of n (power of two) 64-bit keys in shared memory, ascending
+__device__ __forceinline__ void bitonic_sort(uint64_t *a, int n) {
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int jx = i ^ stride;
+                if (jx > i) {
+                    const bool up = (i & size) == 0;
+                    const uint64_t x = a[i], y = a[jx];
+                    if ((x > y) == up) { a[i] = y; a[jx] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_select(const float *__restrict__ cost, int B, int nu,
+                                                        int32_t *__restrict__ elite) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t scanbuf[kSelThreads];
+    __shared__ uint64_t sorted[CP_MAX_ELITES];
+    __shared__ uint32_t s_digit, s_rem;
+    const int tid = threadIdx.x;
+    uint32_t prefix = 0, mask = 0, remaining = (uint32_t)nu;
+    // radix select on the 32-bit order key, most significant byte first
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        if (tid < 256) hist[tid] = 0;
+        __syncthreads();
+        for (int i = tid; i < B; i += kSelThreads) {
+            const uint32_t key = cost_key(cost[i]);
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t cum = 0;
+            for (int d = 0; d < 256; ++d) {
+                if (cum + hist[d] >= remaining) { s_digit = (uint32_t)d; s_rem = remaining - cum; break; }
+                cum += hist[d];
+            }
+        }
+        __syncthreads();
+        prefix |= s_digit << shift;
+        mask |= 255u << shift;
+        remaining = s_rem;
+        __syncthreads();
+    }
+    // keys below the threshold, plus the `remaining` lowest-index keys equal to it
+    const int chunk = (B + kSelThreads - 1) / kSelThreads;
+    const int i0 = min(B, tid * chunk), i1 = min(B, i0 + chunk);
+    uint32_t n_less = 0, n_eq = 0;
+    for (int i = i0; i < i1; ++i) {
+        const uint32_t key = cost_key(cost[i]);
+        n_less += key < prefix;
+        n_eq += key == prefix;
+    }
+    uint32_t tot;
+    const uint32_t eq_before = block_exclusive_scan(n_eq, scanbuf, tot);
+    const uint32_t take_eq = eq_before >= remaining ? 0u : min(n_eq, remaining - eq_before);
+    const uint32_t off = block_exclusive_scan(n_less + take_eq, scanbuf, tot);
+    uint32_t pos = off, eq_seen = 0;
+    for (int i = i0; i < i1; ++i) {
+        const uint32_t key = cost_key(cost[i]);
+        bool sel = key < prefix;
+        if (key == prefix) { sel = eq_seen < take_eq; ++eq_seen; }
+        if (sel) sorted[pos++] = ((uint64_t)key << 32) | (uint32_t)i;
+    }
+    int np = 1;
+    while (np < nu) np <<= 1;
+    for (int i = nu + tid; i < np; i += kSelThreads) sorted[i] = ~0ull;
+    __syncthreads();
+    bitonic_sort(sorted, np);
+    for (int r = tid; r < nu; r += kSelThreads) elite[r] = (int32_t)(uint32_t)(sorted[r] & 0xFFFFFFFFu);
+}
+
+// ---------------------------------------------------------------------------
+// gradient polish of the elites
+// ---------------------------------------------------------------------------
+
+__global__ void k_polish_gather(PlanView P, OptView O) {
+    const int per = P.K * P.n_joints;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < O.npol * per; idx += gridDim.x * blockDim.x) {
+        const int i = idx / per, r = idx % per;
+        O.Wp[idx] = O.W[(size_t)O.elite0[i] * per + r];
+    }
+}
+
+// W <- W - eta g / max(1, |g| / g_max) on the sampled joints; one wave per path
+__global__ __launch_bounds__(64) void k_polish_step(PlanView P, OptView O) {
+    const int i = blockIdx.x;
+    const int n = P.n_joints;
+    float *Wi = O.Wp + (size_t)i * P.K * n;
+    const float *gi = O.grad_p + (size_t)i * P.K * n;
+    float s = 0.0f;
+    for (int e = threadIdx.x; e < O.D; e += 64) {
+        const float g = gi[(e / O.n_act) * n + O.act[e % O.n_act]];
+        s = __builtin_fmaf(g, g, s);
+    }
+    s = wave_sum(s);
+    const float scale = O.eta / fmaxf(1.0f, fsqrt(s) / O.clip);
+    for (int e = threadIdx.x; e < O.D; e += 64) {
+        const int off = (e / O.n_act) * n + O.act[e % O.n_act];
+        Wi[off] = Wi[off] - scale * gi[off];
+    }
+}
+
+// elites re-ranked after polish: polished slots (index B + i) carry their new
+// cost, the rest keep theirs; ties keep the earlier rank
+__global__ __launch_bounds__(kSelThreads) void k_rerank(OptView O) {
+    __shared__ uint64_t keys[CP_MAX_ELITES];
+    const int nu = O.nu;
+    int np = 1;
+    while (np < nu) np <<= 1;
+    for (int r = threadIdx.x; r < np; r += kSelThreads) {
+        if (r < nu) {
+            const float c = r < O.npol ? O.cost_p[r] : O.cost[O.elite0[r]];
+            keys[r] = ((uint64_t)cost_key(c) << 32) | (uint32_t)r;
+        } else {
+            keys[r] = ~0ull;
+        }
+    }
+    __syncthreads();
+    bitonic_sort(keys, np);
+    for (int r = threadIdx.x; r < nu; r += kSelThreads) {
+        const int src = (int)(keys[r] & 0xFFFFFFFFu);
+        O.elite[r] = src < O.npol ? O.B + src : O.elite0[src];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// mean and covariance update (steps 4-6) and best-so-far
+// ---------------------------------------------------------------------------
+
+constexpr int kUpdThreads = 512;
+constexpr int kEliteChunk = 32;
+
+__device__ __forceinline__ double elite_value(const PlanView &P, const OptView &O, int idx, int e) {
+    if (idx < O.B) return O.xi[(size_t)idx * O.D + e];
+    const int k = e / O.n_act, a = e % O.n_act;
+    return (double)O.Wp[((size_t)(idx - O.B) * P.K + k) * P.n_joints + O.act[a]];
+}
+
+__device__ __forceinline__ const float *elite_waypoints(const PlanView &P, const OptView &O, int idx) {
+    const size_t per = (size_t)P.K * P.n_joints;
+    return idx < O.B ? O.W + (size_t)idx * per : O.Wp + (size_t)(idx - O.B) * per;
+}
+
+__device__ __forceinline__ float elite_cost(const OptView &O, int idx) {
+    return idx < O.B ? O.cost[idx] : O.cost_p[idx - O.B];
+}
+
+__global__ __launch_bounds__(kUpdThreads) void k_update(PlanView P, OptView O) {
+    const double *w = O.w;
+    __shared__ double mu[CP_MAX_DIM];
+    __shared__ double xs[kEliteChunk][CP_MAX_DIM];
+    __shared__ int s_improved;
+    const int D = O.D, tid = threadIdx.x;
+    // mean: sum_j w_j x_(j), in rank order
+    for (int e = tid; e < D; e += kUpdThreads) {
+        double s = 0.0;
+        for (int j = 0; j < O.nu; ++j) s = fma(w[j], elite_value(P, O, O.elite[j], e), s);
+        mu[e] = s;
+        O.mu[e] = s;
+    }
+    __syncthreads();
+    // covariance about the new mean: sum_j w_j (x_(j) - mu)(x_(j) - mu)^T + eps I
+    const int n_ent = D * (D + 1) / 2;
+    constexpr int kPer = (CP_MAX_DIM * (CP_MAX_DIM + 1) / 2 + kUpdThreads - 1) / kUpdThreads;
+    double acc[kPer];
+    int e1s[kPer], e2s[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        acc[r] = 0.0;
+        int idx = tid + r * kUpdThreads;
+        int e1 = 0;
+        if (idx < n_ent) {
+            e1 = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+            while ((e1 + 1) * (e1 + 2) / 2 <= idx) ++e1;
+            while (e1 * (e1 + 1) / 2 > idx) --e1;
+        }
+        e1s[r] = e1;
+        e2s[r] = idx < n_ent ? idx - e1 * (e1 + 1) / 2 : 0;
+    }
+    for (int j0 = 0; j0 < O.nu; j0 += kEliteChunk) {
+        const int nj = min(kEliteChunk, O.nu - j0);
+        for (int idx = tid; idx < nj * D; idx += kUpdThreads) {
+            const int jj = idx / D, e = idx % D;
+            xs[jj][e] = elite_value(P, O, O.elite[j0 + jj], e) - mu[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            if (tid + r * kUpdThreads < n_ent) {
+                const int e1 = e1s[r], e2 = e2s[r];
+                double a = acc[r];
+                for (int jj = 0; jj < nj; ++jj) a = fma(w[j0 + jj] * xs[jj][e1], xs[jj][e2], a);
+                acc[r] = a;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        if (tid + r * kUpdThreads < n_ent) {
+            const int e1 = e1s[r], e2 = e2s[r];
+            const double v = acc[r] + (e1 == e2 ? O.eps : 0.0);
+            O.C[(size_t)e1 * D + e2] = v;
+            O.C[(size_t)e2 * D + e1] = v;
+        }
+    }
+    // best-so-far: the iteration's best sample, then the best polished elite
+    if (tid == 0) {
+        int imp = -1;
+        float bc = *O.best_cost;
+        const float c0 = O.cost[O.elite0[0]];
+        if (c0 < bc) { bc = c0; imp = O.elite0[0]; }
+        if (O.npol > 0) {
+            const float c1 = elite_cost(O, O.elite[0]);
+            if (c1 < bc) { bc = c1; imp = O.elite[0]; }
+        }
+        if (imp >= 0) *O.best_cost = bc;
+        s_improved = imp;
+        *O.t = *O.t + 1;
+    }
+    __syncthreads();
+    if (s_improved >= 0) {
+        const float *src = elite_waypoints(P, O, s_improved);
+        for (int i = tid; i < P.K * P.n_joints; i += kUpdThreads) O.best_W[i] = src[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// lower Cholesky factor of C (double, in shared memory, packed lower
+// triangle); if a pivot is not positive, retry with C + 10^k eps I, k = 1..3
+// ---------------------------------------------------------------------------
+
+constexpr int kCholThreads = 256;
+
+__global__ __launch_bounds__(kCholThreads) void k_chol(OptView O) {
+    __shared__ double A[CP_MAX_DIM * (CP_MAX_DIM + 1) / 2];
+    __shared__ int s_fail;
+    const int D = O.D, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = kCholThreads / 64;
+    auto at = [](int i, int j) { return i * (i + 1) / 2 + j; };
+    bool ok = false;
+    for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+        const double jitter = attempt == 0 ? 0.0 : O.eps * (attempt == 1 ? 10.0 : attempt == 2 ? 100.0 : 1000.0);
+        for (int idx = tid; idx < D * D; idx += kCholThreads) {
+            const int i = idx / D, j = idx % D;
+            if (j <= i) A[at(i, j)] = O.C[idx] + (i == j ? jitter : 0.0);
+        }
+        if (tid == 0) s_fail = 0;
+        __syncthreads();
+        for (int k = 0; k < D; ++k) {
+            if (tid == 0) {
+                const double piv = A[at(k, k)];
+                if (!(piv > 0.0)) s_fail = 1;
+                A[at(k, k)] = sqrt(piv > 0.0 ? piv : 1.0);
+            }
+            __syncthreads();
+            if (s_fail) break;
+            const double dk = A[at(k, k)];
+            for (int i = k + 1 + tid; i < D; i += kCholThreads) A[at(i, k)] /= dk;
+            __syncthreads();
+            for (int i = k + 1 + wv; i < D; i += nw) {
+                const double lik = A[at(i, k)];
+                for (int j = k + 1 + lane; j <= i; j += 64) A[at(i, j)] -= lik * A[at(j, k)];
+            }
+            __syncthreads();
+        }
+        ok = !s_fail;
+        __syncthreads();
+    }
+    if (!ok) {
+        if (tid == 0) *O.status = 1;
+        return;  // keep the previous factor
+    }
+    for (int idx = tid; idx < D * D; idx += kCholThreads) {
+        const int i = idx / D, j = idx % D;
+        O.L[idx] = j <= i ? A[at(i, j)] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_init_state(const PlanView &P, const OptView &O, float sigma0, hipStream_t st) {
+    const int n = O.D * O.D;
+    hipLaunchKernelGGL(k_init_state, dim3((n + 255) / 256), dim3(256), 0, st, P, O, sigma0);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const PlanView &P, const OptView &O, hipStream_t st) {
+    hipLaunchKernelGGL(k_sample, dim3((O.B + kSampleTile - 1) / kSampleTile), dim3(256), 0, st, P, O);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const OptView &O, hipStream_t st) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(kSelThreads), 0, st, O.cost, O.B, O.nu, O.elite0);
+    return hipGetLastError();
+}
+
+hipError_t launch_polish_gather(const PlanView &P, const OptView &O, hipStream_t st) {
+    const int n = O.npol * P.K * P.n_joints;
+    hipLaunchKernelGGL(k_polish_gather, dim3((n + 255) / 256), dim3(256), 0, st, P, O);
+    return hipGetLastError();
+}
+
+hipError_t launch_polish_gd(const PlanView &P, const OptView &O, hipStream_t st) {
+    hipLaunchKernelGGL(k_polish_step, dim3(O.npol), dim3(64), 0, st, P, O);
+    return hipGetLastError();
+}
+
+hipError_t launch_rerank(const OptView &O, hipStream_t st) {
+    hipLaunchKernelGGL(k_rerank, dim3(1), dim3(kSelThreads), 0, st, O);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const PlanView &P, const OptView &O, hipStream_t st) {
+    hipLaunchKernelGGL(k_update, dim3(1), dim3(kUpdThreads), 0, st, P, O);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol(const OptView &O, hipStream_t st) {
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), 0, st, O);
+    return hipGetLastError();
+}
+
+}  // namespace cp

@@ -1,0 +1,50 @@
+"""The C-ABI library loads on a machine without a GPU and exports every entry
+point that include/craneplan.h declares (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "craneplan.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("cp_plan_create", "cp_eval_paths", "cp_eval_paths_backward", "cp_optimizer_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2503_14160_amd import craneplan
+    if not os.path.exists(craneplan.LIB_PATH):
+        from paper_2503_14160_amd import build
+        build.build()
+    L = ctypes.CDLL(craneplan.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(craneplan.EXPORTS) == _declared()
+
+
+def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
+    from paper_2503_14160_amd import craneplan
+    monkeypatch.setattr(craneplan, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(craneplan, "_lib", None)
+    with pytest.raises(ImportError):
+        craneplan.lib()
+
+
+def test_product_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_2503_14160_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "oracle.c" not in txt, f
