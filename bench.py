@@ -35,7 +35,7 @@ def flops_per_config(n_spheres, n_cyl, n_box):
     return n_spheres * (n_cyl * F_CYL + n_box * F_BOX + F_SPHERE) + F_CONFIG
 
 
-def cpu_baseline(prob, n_paths=32, seed=7):
+def cpu_baseline(prob, n_paths=1536, seed=7):
     import oracle
     oracle.build()
     rng = np.random.default_rng(seed)
@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eval-reps", type=int, default=10)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU in this build",
@@ -65,6 +67,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n}))
+        return
     from paper_2503_14160_amd import craneplan as cp
     from paper_2503_14160_amd import synth
 
