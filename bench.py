@@ -29,6 +29,10 @@ sys.path.insert(0, ROOT)
 # the ground), interpolation + forward kinematics 1500
 F_CYL, F_BOX, F_SPHERE, F_CONFIG = 15, 20, 7, 1500
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+# HBM bytes per k_eval_fwd launch on c1_full from rocprofv3 FETCH_SIZE / WRITE_SIZE, each
+# scaled by the same counter on a plain 1 GiB copy (profiles/k_eval_fwd_c1_full_hbm_bytes.md);
+# None once the kernel has changed since the counters were taken
+TRAFFIC_BYTES = None
 
 
 def flops_per_config(n_spheres, n_cyl, n_box):
@@ -120,6 +124,22 @@ def main():
     flops = fpc * B * ns
     achieved = flops / (eval_ms * 1e-3)
 
+    # the same evaluation with every pair in full (no square-root skipping):
+    # identical results, the brute-force reference for the roofline
+    plain = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, pair_filter=False)
+    plain.set_endpoints(prob.q_start, prob.q_goal)
+    c_plain = torch.empty_like(cost)
+    plain.eval_into(W, c_plain, md)
+    torch.cuda.synchronize()
+    reps_plain = max(1, args.eval_reps // 3)
+    ev0.record()
+    for _ in range(reps_plain):
+        plain.eval_into(W, c_plain, md)
+    ev1.record()
+    torch.cuda.synchronize()
+    plain_ms = ev0.elapsed_time(ev1) / reps_plain
+    same = bool(torch.equal(c_plain, cost))
+
     configs = B * ns
     out = {
         "metric": "configs checked/s (FK+collision)",
@@ -143,8 +163,14 @@ def main():
                    "checkpoints": ns, "spheres": prob.robot.n_spheres, "cylinders": prob.scene.n_cyl,
                    "boxes": prob.scene.n_box, "elites": prob.opt.nu},
         "roofline": {"bound": "alu", "kernel": "k_eval_fwd", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "flops_per_config": fpc},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": TRAFFIC_BYTES,
+                     "flops_per_config": fpc,
+                     "note": "algorithmic flops of the all-pairs definition; the kernel skips the square root of "
+                             "pairs that cannot lower the minimum (bitwise-identical results), so this rate can "
+                             "exceed the hardware peak; all_pairs_kernel is the same launch evaluating every pair",
+                     "all_pairs_kernel": {"ms": plain_ms, "achieved": flops / (plain_ms * 1e-3) / 1e12,
+                                          "frac": flops / (plain_ms * 1e-3) / PEAK_FP32,
+                                          "identical_costs": same}},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

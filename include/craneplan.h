@@ -136,6 +136,10 @@ typedef struct {
     float lambda_c;
     float w_c, w_l;
     int32_t max_B;    /* largest batch any call on this plan will pass */
+    /* 1: a sphere-cylinder pair whose squared axis distance shows it cannot
+     * lower the running minimum skips its square root (results are bitwise
+     * those of 0); 0: every pair is evaluated in full. */
+    int32_t pair_filter;
 } cp_cost_params;
 
 /* Algorithm 1 settings.  C_0 = sigma0^2 I; samples are xi ~ N(mu, C).  The

@@ -52,7 +52,8 @@ class _Scene(ctypes.Structure):
 
 class _Cost(ctypes.Structure):
     _fields_ = [("K", _c_i32), ("M", _c_i32), ("interp", _c_i32), ("jp_mode", _c_i32), ("hinge", _c_i32),
-                ("margin", _c_f32), ("lambda_c", _c_f32), ("w_c", _c_f32), ("w_l", _c_f32), ("max_B", _c_i32)]
+                ("margin", _c_f32), ("lambda_c", _c_f32), ("w_c", _c_f32), ("w_l", _c_f32), ("max_B", _c_i32),
+                ("pair_filter", _c_i32)]
 
 
 class _Opt(ctypes.Structure):
@@ -120,7 +121,7 @@ class Plan:
     """A crane, a scene and a path cost on one device (cp_plan_create)."""
 
     def __init__(self, robot, scene, cost, max_B: int, device: int = 0, sdf: Optional[torch.Tensor] = None,
-                 sdf_spec=None):
+                 sdf_spec=None, pair_filter: bool = True):
         L = lib()
         self._keep = []
 
@@ -160,6 +161,7 @@ class Plan:
         c.K, c.M, c.interp, c.jp_mode, c.hinge = cost.K, cost.M, cost.interp, cost.jp_mode, cost.hinge
         c.margin, c.lambda_c, c.w_c, c.w_l = cost.margin, cost.lambda_c, cost.w_c, cost.w_l
         c.max_B = int(max_B)
+        c.pair_filter = 1 if pair_filter else 0
         h = ctypes.c_void_p()
         _check(L.cp_plan_create(ctypes.byref(r), ctypes.byref(s), ctypes.byref(c), int(device), ctypes.byref(h)))
         self._h = h

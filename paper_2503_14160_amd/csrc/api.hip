@@ -2,6 +2,7 @@
 // objects and their device tables, and the step sequencing of Algorithm 1.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -71,6 +72,7 @@ struct cp_plan {
     int32_t *d_frame_start = nullptr;
     float4 *d_cyl = nullptr;
     GroupDev *d_groups = nullptr;
+    int32_t *d_angle_start = nullptr;
     float4 *d_cyl_orig = nullptr;
     float4 *d_box = nullptr;
     float *d_qs = nullptr, *d_qg = nullptr;
@@ -79,7 +81,8 @@ struct cp_plan {
 
     ~cp_plan() {
         DeviceGuard g(device);
-        void *bufs[] = {d_joints, d_spheres, d_frame_start, d_cyl, d_groups, d_cyl_orig, d_box, d_qs, d_qg, d_partial};
+        void *bufs[] = {d_joints, d_spheres, d_frame_start, d_cyl, d_groups, d_angle_start, d_cyl_orig, d_box, d_qs, d_qg,
+                        d_partial};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
     }
@@ -249,21 +252,44 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         std::memcpy(&gf, &gbits, sizeof(float));
         cyl_orig[o] = make_float4(y[0], y[1], y[2], gf);
     }
+    // within a group, cylinders sorted by polar angle about the z axis, with a
+    // per-azimuth-bin scan start (one bin behind, aligned to the chunk of 4)
     std::vector<float4> cyl;
     std::vector<GroupDev> groups;
+    std::vector<int32_t> angle_start;
+    const double kPi = 3.14159265358979323846;
     for (size_t g = 0; g < ext.size(); ++g) {
         GroupDev G{};
         G.start = (int)cyl.size();
+        std::vector<std::pair<double, int>> by_angle;
+        float rmax = 0.0f;
         for (int o : members[g]) {
             const float *y = scene->cyl + 5 * o;
+            by_angle.emplace_back(std::atan2((double)y[1], (double)y[0]), o);
+            rmax = std::max(rmax, y[2]);
+        }
+        std::stable_sort(by_angle.begin(), by_angle.end(),
+                         [](const std::pair<double, int> &a, const std::pair<double, int> &b) { return a.first < b.first; });
+        for (const auto &ao : by_angle) {
+            const float *y = scene->cyl + 5 * ao.second;
             cyl.push_back(make_float4(y[0], y[1], y[2], 0.0f));
         }
         while ((cyl.size() - G.start) % 4) cyl.push_back(make_float4(1e15f, 1e15f, 0.0f, 0.0f));
         G.count = (int)cyl.size() - G.start;
         G.zc = (float)(0.5 * ((double)ext[g].first + (double)ext[g].second));
         G.hz = (float)(0.5 * ((double)ext[g].second - (double)ext[g].first));
+        G.rmax = rmax;
         groups.push_back(G);
+        for (int b = 0; b < kAngleBins; ++b) {
+            const double lo = -kPi + (b - 1) * (2.0 * kPi / kAngleBins);
+            int first = 0;
+            while (first < (int)by_angle.size() && by_angle[first].first < lo) ++first;
+            if (first >= (int)by_angle.size()) first = 0;
+            angle_start.push_back(first & ~3);
+        }
     }
+    if (angle_start.empty()) angle_start.assign(kAngleBins, 0);
+    const int pair_filter = cost->pair_filter ? 1 : 0;
     std::vector<float4> box;
     for (int o = 0; o < p->n_box; ++o) {
         const float *y = scene->box + 6 * o;
@@ -274,7 +300,8 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     hipError_t e;
     if ((e = upload(&p->d_joints, p->joints)) != hipSuccess || (e = upload(&p->d_spheres, spheres)) != hipSuccess ||
         (e = upload(&p->d_frame_start, frame_start)) != hipSuccess || (e = upload(&p->d_cyl, cyl)) != hipSuccess ||
-        (e = upload(&p->d_groups, groups)) != hipSuccess || (e = upload(&p->d_cyl_orig, cyl_orig)) != hipSuccess ||
+        (e = upload(&p->d_groups, groups)) != hipSuccess || (e = upload(&p->d_angle_start, angle_start)) != hipSuccess ||
+        (e = upload(&p->d_cyl_orig, cyl_orig)) != hipSuccess ||
         (e = upload(&p->d_box, box)) != hipSuccess || (e = upload(&p->d_qs, hold)) != hipSuccess ||
         (e = upload(&p->d_qg, hold)) != hipSuccess)
         return bail(hip_fail(e, "plan tables"));
@@ -294,6 +321,8 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     v.margin = cost->margin; v.lambda_c = cost->lambda_c; v.w_c = cost->w_c; v.w_l = cost->w_l;
     v.joints = p->d_joints; v.spheres = p->d_spheres; v.frame_start = p->d_frame_start;
     v.cyl = p->d_cyl; v.groups = p->d_groups; v.cyl_orig = p->d_cyl_orig; v.box = p->d_box;
+    v.angle_start = p->d_angle_start;
+    v.pair_filter = pair_filter;
     v.qs = p->d_qs; v.qg = p->d_qg;
     v.sdf = scene->d_sdf;
     for (int a = 0; a < 3; ++a) {

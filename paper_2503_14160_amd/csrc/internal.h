@@ -34,7 +34,14 @@ struct SphereDev {
 struct GroupDev {
     int32_t start, count;  // into the sorted cylinder table; count is a multiple of 4
     float zc, hz;          // centre and half height of the shared extent
+    float rmax;            // largest radius in the group
+    int32_t pad[3];
 };
+
+// Within a group, cylinders are sorted by polar angle about the world z axis;
+// kAngleBins start offsets per group let a wave begin its scan at the
+// cylinders nearest its own azimuth.
+constexpr int kAngleBins = 64;
 
 // Everything a kernel needs about a plan, passed by value.
 struct PlanView {
@@ -47,6 +54,8 @@ struct PlanView {
     const int32_t *frame_start;   // [n_joints + 2]: spheres of frame f are [frame_start[f], frame_start[f+1])
     const float4 *cyl;            // [sum of group counts] (x, y, R, unused), grouped
     const GroupDev *groups;       // [n_groups]
+    const int32_t *angle_start;   // [n_groups][kAngleBins] scan start (multiple of 4) per azimuth bin
+    int32_t pair_filter;          // 1: skip the square root of pairs that cannot lower the minimum
     const float4 *cyl_orig;       // [n_cyl] (x, y, R, group) in the caller's order
     const float4 *box;            // [n_box][2]: (cx, cy, cz, hx), (hy, hz, -, -)
     const float *qs, *qg;         // [n_joints]
