@@ -1,16 +1,20 @@
-"""Benchmark: one optimizer iteration of the crane path planner per step.
+"""Benchmark of the crane path planner on one MI355X.
 
-A step is one pass of the whole hot path on the c1_full workload (16384
-sampled paths x 16 waypoints x 32 checkpoints per span = 608 checkpoints,
-64 link spheres, 512 trees + 16 boxes + ground, 819 elites): sampling,
-evaluation (interpolation, forward kinematics, sphere-obstacle distances,
-cost), elite selection, mean/covariance update and the Cholesky factor.
-Inputs are seeded synthetic data already resident on the GPU.
-
-Prints one JSON line: configurations checked per second over the timed
-optimizer iterations, planner iterations per second, the evaluation kernel
+Default (``--workload c1_full``): a step is one optimizer iteration of the
+whole hot path on the 16384-path workload (16 waypoints, 32 checkpoints per
+span = 608 checkpoints, 64 link spheres, 512 trees + 16 boxes + ground,
+819 elites): sampling, evaluation (interpolation, forward kinematics,
+sphere-obstacle distances, cost), elite selection, mean/covariance update and
+the Cholesky factor.  Inputs are seeded synthetic data already resident on
+the GPU.  Prints one JSON line: configurations checked per second over the
+timed iterations, planner iterations per second, the evaluation kernel
 against the FP32 vector roofline, and the CPU oracle's rate on a bounded
 sample of the same workload.
+
+Other workloads print their own line: c0_plain (small single problem),
+c2_diff (adjoint: fwd+bwd vs fwd, gradient error, polished iterations),
+c3_batch (many problems: batched graph launch vs one problem at a time),
+c4_sdf (lidar -> signed-distance grid, trilinear queries, fwd+bwd).
 """
 import argparse
 import json
@@ -29,20 +33,33 @@ sys.path.insert(0, ROOT)
 # the ground), interpolation + forward kinematics 1500
 F_CYL, F_BOX, F_SPHERE, F_CONFIG = 15, 20, 7, 1500
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+PEAK_HBM = 8.0e12     # MI355X HBM3E bytes/s
 # HBM bytes per k_eval_fwd launch on c1_full from rocprofv3 FETCH_SIZE / WRITE_SIZE, each
 # scaled by the same counter on a plain 1 GiB copy (profiles/k_eval_fwd_c1_full_hbm_bytes.md);
 # None once the kernel has changed since the counters were taken
 TRAFFIC_BYTES = None
+# algorithmic bytes of one trilinear signed-distance query: 8 FP32 corners
+SDF_QUERY_BYTES = 32
 
 
 def flops_per_config(n_spheres, n_cyl, n_box):
     return n_spheres * (n_cyl * F_CYL + n_box * F_BOX + F_SPHERE) + F_CONFIG
 
 
-def cpu_baseline(prob, n_paths=1536, seed=7):
+def _timed(torch, fn, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(prob, n_paths=1536):
     import oracle
     oracle.build()
-    rng = np.random.default_rng(seed)
     W = oracle.expand(prob.robot, oracle.Optimizer(prob).sample()[:n_paths], prob.cost.K)
     m = oracle.Model(prob.robot, prob.scene, prob.cost)
     t0 = time.perf_counter()
@@ -51,8 +68,246 @@ def cpu_baseline(prob, n_paths=1536, seed=7):
     n_cfg = n_paths * prob.cost.n_s
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n_cfg / dt, "unit": "configs/s", "cores": min(threads, n_paths), "kind": "oracle",
-            "sample": f"{n_paths} of {prob.opt.B} sampled paths of the first c1_full iteration "
+            "sample": f"{n_paths} of {prob.opt.B} sampled paths of the first {prob.name} iteration "
                       f"({n_cfg} configurations, evaluation only), FP64, {dt:.1f} s"}
+
+
+def base_line(args, metric, value, unit, ms_step, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# c1_full / c0_plain: optimizer iterations
+# ----------------------------------------------------------------------------
+
+def bench_iterations(args, torch, cp, prob, with_roofline):
+    B, ns = prob.opt.B, prob.cost.n_s
+    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B)
+    plan.set_endpoints(prob.q_start, prob.q_goal)
+    opt = cp.Optimizer(plan, prob.opt)
+    torch.cuda.synchronize()
+    print(f"[bench] {prob.name} warmup {args.warmup}", file=sys.stderr, flush=True)
+    opt.step(args.warmup)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} iterations", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ms = _timed(torch, lambda: opt.step(args.steps), 1)
+    wall = time.perf_counter() - t0
+    ms_step = ms / args.steps
+    st = opt.get_state()
+    configs = B * ns
+    config = {"workload": prob.name, "paths": B, "waypoints": prob.cost.K, "points_per_span": prob.cost.M,
+              "checkpoints": ns, "spheres": prob.robot.n_spheres, "cylinders": prob.scene.n_cyl,
+              "boxes": prob.scene.n_box, "elites": prob.opt.nu, "iterations_timed": args.steps}
+    out = base_line(args, "configs checked/s (FK+collision)", configs * args.steps / (ms * 1e-3), "configs/s",
+                    ms_step, config, planner_iters_per_s=1e3 / ms_step, best_cost=st["best_cost"], wall_s=wall)
+    if not with_roofline:
+        return out, plan, opt
+
+    # evaluation kernel alone, on the same stream, on the last population
+    W, cost, _ = opt.last()
+    md = torch.empty_like(cost)
+    plan.eval_into(W, cost, md)
+    torch.cuda.synchronize()
+    print(f"[bench] eval kernel x{args.eval_reps}", file=sys.stderr, flush=True)
+    eval_ms = _timed(torch, lambda: plan.eval_into(W, cost, md), args.eval_reps)
+    fpc = flops_per_config(prob.robot.n_spheres, prob.scene.n_cyl, prob.scene.n_box)
+    flops = fpc * B * ns
+    achieved = flops / (eval_ms * 1e-3)
+    # the same evaluation with every pair in full (no square-root skipping):
+    # identical results, the brute-force reference for the roofline
+    plain = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, pair_filter=False)
+    plain.set_endpoints(prob.q_start, prob.q_goal)
+    c_plain = torch.empty_like(cost)
+    plain.eval_into(W, c_plain, md)
+    torch.cuda.synchronize()
+    plain_ms = _timed(torch, lambda: plain.eval_into(W, c_plain, md), max(1, args.eval_reps // 3))
+    out.update({
+        "eval_ms": eval_ms,
+        "eval_configs_per_s": configs / (eval_ms * 1e-3),
+        "roofline": {"bound": "alu", "kernel": "k_eval_fwd", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": TRAFFIC_BYTES, "flops_per_config": fpc,
+                     "note": "algorithmic flops of the all-pairs definition; the kernel skips the square root of "
+                             "pairs that cannot lower the minimum (bitwise-identical results), so this rate can "
+                             "exceed the hardware peak; all_pairs_kernel is the same launch evaluating every pair",
+                     "all_pairs_kernel": {"ms": plain_ms, "achieved": flops / (plain_ms * 1e-3) / 1e12,
+                                          "frac": flops / (plain_ms * 1e-3) / PEAK_FP32,
+                                          "identical_costs": bool(torch.equal(c_plain, cost))}},
+    })
+    return out, plan, opt
+
+
+# ----------------------------------------------------------------------------
+# c2_diff: adjoint
+# ----------------------------------------------------------------------------
+
+def bench_diff(args, torch, cp, prob):
+    import oracle
+    B = prob.opt.B
+    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B)
+    plan.set_endpoints(prob.q_start, prob.q_goal)
+    opt = cp.Optimizer(plan, synth_opt_no_polish(prob))
+    opt.step(1)
+    W, _, _ = opt.last()
+    cost = torch.empty(B, device="cuda")
+    md = torch.empty_like(cost)
+    tape = torch.empty((B, plan.n_s), dtype=torch.int32, device="cuda")
+    g = torch.empty_like(W)
+    ones = torch.ones(B, device="cuda")
+    plan.eval_into(W, cost, md)
+    plan.eval_into(W, cost, md, tape=tape)
+    plan.backward_into(W, ones, g, tape)
+    torch.cuda.synchronize()
+    print("[bench] c2_diff fwd / fwd+bwd", file=sys.stderr, flush=True)
+    reps = args.eval_reps
+    fwd_ms = _timed(torch, lambda: plan.eval_into(W, cost, md), reps)
+    fwd_tape_ms = _timed(torch, lambda: plan.eval_into(W, cost, md, tape=tape), reps)
+
+    def fb():
+        plan.eval_into(W, cost, md, tape=tape)
+        plan.backward_into(W, ones, g, tape)
+    fb_ms = _timed(torch, fb, reps)
+
+    def fb_nt():
+        plan.eval_into(W, cost, md)
+        plan.backward_into(W, ones, g, None)
+    fb_nt_ms = _timed(torch, fb_nt, max(1, reps // 3))
+    # gradient error of 8 paths against the oracle's analytic FP64 gradient
+    Wn = W[:8].cpu().numpy().astype(np.float64)
+    m = oracle.Model(prob.robot, prob.scene, prob.cost)
+    _, gref = oracle.grad_paths(m, prob.q_start, prob.q_goal, Wn)
+    gg = g[:8].cpu().numpy().astype(np.float64)
+    rel = [float(np.linalg.norm(gg[b] - gref[b]) / max(np.linalg.norm(gref[b]), 1e-12)) for b in range(8)]
+    # optimizer iterations with the gradient polish of the elites
+    popt = cp.Optimizer(plan, prob.opt)
+    popt.step(1)
+    torch.cuda.synchronize()
+    it_ms = _timed(torch, lambda: popt.step(args.steps), 1) / args.steps
+    ns = plan.n_s
+    config = {"workload": prob.name, "paths": B, "waypoints": prob.cost.K, "checkpoints": ns,
+              "spheres": prob.robot.n_spheres, "cylinders": prob.scene.n_cyl, "boxes": prob.scene.n_box,
+              "hinge": "smooth", "margin": prob.cost.margin, "polish": [prob.opt.polish_elites, prob.opt.polish_steps]}
+    return base_line(args, "fwd+bwd time / fwd time", fb_ms / fwd_ms, "ratio", it_ms, config,
+                     higher_is_better=False, fwd_ms=fwd_ms, fwd_with_tape_ms=fwd_tape_ms, fwd_bwd_ms=fb_ms,
+                     fwd_bwd_without_tape_ms=fb_nt_ms, grad_rel_err_max=max(rel),
+                     fwd_configs_per_s=B * ns / (fwd_ms * 1e-3), polished_iters_per_s=1e3 / it_ms)
+
+
+def synth_opt_no_polish(prob):
+    from paper_2503_14160_amd import synth
+    o = prob.opt
+    return synth.OptParams(B=o.B, nu=o.nu, sigma0=o.sigma0, eps=o.eps, seed=o.seed, T=o.T)
+
+
+# ----------------------------------------------------------------------------
+# c3_batch: many problems in one launch vs one at a time
+# ----------------------------------------------------------------------------
+
+def bench_batch(args, torch, cp, probs):
+    n = len(probs)
+    T = args.batch_iters
+    work = np.array([p.opt.B * p.cost.n_s for p in probs], np.float64)
+    print(f"[bench] c3_batch: {n} problems, building", file=sys.stderr, flush=True)
+    batch = cp.Batch(probs)
+    cache = os.path.join(ROOT, "gpurun_out", "c3_tune_cache.txt") if os.path.isdir(
+        os.path.join(ROOT, "gpurun_out")) else None
+    t0 = time.perf_counter()
+    tuning = batch.tune(cache)
+    tune_s = time.perf_counter() - t0
+    print(f"[bench] tuned {tuning} in {tune_s:.1f} s; graph of {T} iterations", file=sys.stderr, flush=True)
+    batch.run(1)  # warm-up iteration (its own small graph)
+    torch.cuda.synchronize()
+    ms_b = _timed(torch, lambda: batch.run(T), 1)  # captures the T-iteration graph, then launches it
+    print(f"[bench] batched {ms_b:.1f} ms; sequential", file=sys.stderr, flush=True)
+    # one problem at a time: same kernels, eager launches, synchronised per problem
+    per = np.zeros(n)
+    for i, p in enumerate(probs):
+        plan = cp.Plan(p.robot, p.scene, p.cost, max_B=p.opt.B)
+        plan.set_endpoints(p.q_start, p.q_goal)
+        opt = cp.Optimizer(plan, p.opt, problem_id=i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        opt.step(T)
+        torch.cuda.synchronize()
+        per[i] = (time.perf_counter() - t0) * 1e3
+        if i % 32 == 0:
+            print(f"[bench] sequential {i}/{n}", file=sys.stderr, flush=True)
+    ms_s = per.sum()
+    total_cfg = work.sum() * T
+    # per-size buckets: ratio of the bucket's sequential time to its share of the batched time
+    order = np.argsort(work)
+    buckets = {}
+    for name, idx in (("small", order[: n // 3]), ("medium", order[n // 3: 2 * n // 3]), ("large", order[2 * n // 3:])):
+        share = ms_b * work[idx].sum() / work.sum()
+        buckets[name] = {"problems": int(len(idx)), "sequential_ms": float(per[idx].sum()),
+                         "batched_share_ms": float(share), "ratio": float(per[idx].sum() / share)}
+    config = {"workload": "c3_batch", "problems": n, "iterations": T,
+              "paths": [int(min(p.opt.B for p in probs)), int(max(p.opt.B for p in probs))],
+              "waypoints": [int(min(p.cost.K for p in probs)), int(max(p.cost.K for p in probs))],
+              "obstacles": [int(min(p.scene.n_cyl + p.scene.n_box for p in probs)),
+                            int(max(p.scene.n_cyl + p.scene.n_box for p in probs))],
+              "tuning": {"rounds": tuning[0], "wg_per_cu": tuning[1]}}
+    return base_line(args, "configs checked/s (FK+collision), batched", total_cfg / (ms_b * 1e-3), "configs/s",
+                     ms_b / T, config, batched_ms=ms_b, sequential_ms=ms_s, batched_over_sequential=ms_s / ms_b,
+                     sequential_configs_per_s=total_cfg / (ms_s * 1e-3), planner_iters_per_s=T * n / (ms_b * 1e-3),
+                     buckets=buckets, tune_s=tune_s)
+
+
+# ----------------------------------------------------------------------------
+# c4_sdf: lidar -> signed-distance grid, trilinear queries
+# ----------------------------------------------------------------------------
+
+def bench_sdf(args, torch, cp, prob):
+    spec = prob.sdf
+    pts = torch.from_numpy(prob.lidar).cuda()
+    cp.sdf_build(pts, spec)
+    torch.cuda.synchronize()
+    print("[bench] c4_sdf build", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    sdf = cp.sdf_build(pts, spec)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    B = prob.opt.B
+    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, sdf=sdf, sdf_spec=spec)
+    plan.set_endpoints(prob.q_start, prob.q_goal)
+    opt = cp.Optimizer(plan, prob.opt)
+    opt.step(args.warmup)
+    torch.cuda.synchronize()
+    ms = _timed(torch, lambda: opt.step(args.steps), 1)
+    ms_step = ms / args.steps
+    W, cost, _ = opt.last()
+    md = torch.empty_like(cost)
+    tape = torch.empty((B, plan.n_s), dtype=torch.int32, device="cuda")
+    g = torch.empty_like(W)
+    ones = torch.ones(B, device="cuda")
+    plan.eval_into(W, cost, md, tape=tape)
+    plan.backward_into(W, ones, g, tape)
+    torch.cuda.synchronize()
+    fwd_ms = _timed(torch, lambda: plan.eval_into(W, cost, md), args.eval_reps)
+
+    def fb():
+        plan.eval_into(W, cost, md, tape=tape)
+        plan.backward_into(W, ones, g, tape)
+    fb_ms = _timed(torch, fb, args.eval_reps)
+    ns = plan.n_s
+    queries = B * ns * prob.robot.n_spheres
+    config = {"workload": "c4_sdf", "points": int(prob.lidar.shape[0]), "grid": list(spec.dims),
+              "voxel": spec.voxel, "paths": B, "waypoints": prob.cost.K, "checkpoints": ns,
+              "spheres": prob.robot.n_spheres}
+    return base_line(args, "configs checked/s (FK+collision)", B * ns * args.steps / (ms * 1e-3), "configs/s",
+                     ms_step, config, planner_iters_per_s=1e3 / ms_step, sdf_build_ms=build_ms, fwd_ms=fwd_ms,
+                     fwd_bwd_ms=fb_ms, fwd_bwd_over_fwd=fb_ms / fwd_ms,
+                     roofline={"bound": "hbm", "kernel": "k_eval_fwd", "unit": "GB/s",
+                               "achieved": queries * SDF_QUERY_BYTES / (fwd_ms * 1e-3) / 1e9,
+                               "peak": PEAK_HBM / 1e9,
+                               "frac": queries * SDF_QUERY_BYTES / (fwd_ms * 1e-3) / PEAK_HBM, "traffic": None,
+                               "note": "algorithmic bytes: 8 FP32 corners per sphere query; the 32 MiB grid is "
+                                       "cache resident, so the rate can exceed HBM bandwidth"})
 
 
 def main():
@@ -60,8 +315,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c1_full", choices=["c1_full", "c0_plain", "c2_diff", "c3_batch", "c4_sdf"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eval-reps", type=int, default=10)
+    ap.add_argument("--batch-problems", type=int, default=256)
+    ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -83,98 +341,20 @@ def main():
     from paper_2503_14160_amd import craneplan as cp
     from paper_2503_14160_amd import synth
 
-    prob = synth.c1_full()
-    B, ns = prob.opt.B, prob.cost.n_s
-    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B)
-    plan.set_endpoints(prob.q_start, prob.q_goal)
-    opt = cp.Optimizer(plan, prob.opt)
-    torch.cuda.synchronize()
-
-    print(f"[bench] c1_full warmup {args.warmup}", file=sys.stderr, flush=True)
-    opt.step(args.warmup)
-    torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} iterations", file=sys.stderr, flush=True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    opt.step(args.steps)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    ms_step = ms / args.steps
-    st = opt.get_state()
-
-    # evaluation kernel alone, on the same stream, on the last population
-    W, cost, _ = opt.last()
-    md = torch.empty_like(cost)
-    plan.eval_into(W, cost, md)
-    torch.cuda.synchronize()
-    print(f"[bench] eval kernel x{args.eval_reps}", file=sys.stderr, flush=True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.eval_reps):
-        plan.eval_into(W, cost, md)
-    ev1.record()
-    torch.cuda.synchronize()
-    eval_ms = ev0.elapsed_time(ev1) / args.eval_reps
-    fpc = flops_per_config(prob.robot.n_spheres, prob.scene.n_cyl, prob.scene.n_box)
-    flops = fpc * B * ns
-    achieved = flops / (eval_ms * 1e-3)
-
-    # the same evaluation with every pair in full (no square-root skipping):
-    # identical results, the brute-force reference for the roofline
-    plain = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, pair_filter=False)
-    plain.set_endpoints(prob.q_start, prob.q_goal)
-    c_plain = torch.empty_like(cost)
-    plain.eval_into(W, c_plain, md)
-    torch.cuda.synchronize()
-    reps_plain = max(1, args.eval_reps // 3)
-    ev0.record()
-    for _ in range(reps_plain):
-        plain.eval_into(W, c_plain, md)
-    ev1.record()
-    torch.cuda.synchronize()
-    plain_ms = ev0.elapsed_time(ev1) / reps_plain
-    same = bool(torch.equal(c_plain, cost))
-
-    configs = B * ns
-    out = {
-        "metric": "configs checked/s (FK+collision)",
-        "value": configs * args.steps / (ms * 1e-3),
-        "unit": "configs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "planner_iters_per_s": 1e3 / ms_step,
-        "eval_ms": eval_ms,
-        "eval_configs_per_s": configs / (eval_ms * 1e-3),
-        "best_cost": st["best_cost"],
-        "wall_s": wall,
-        "config": {"workload": "c1_full", "paths": B, "waypoints": prob.cost.K, "points_per_span": prob.cost.M,
-                   "checkpoints": ns, "spheres": prob.robot.n_spheres, "cylinders": prob.scene.n_cyl,
-                   "boxes": prob.scene.n_box, "elites": prob.opt.nu},
-        "roofline": {"bound": "alu", "kernel": "k_eval_fwd", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": TRAFFIC_BYTES,
-                     "flops_per_config": fpc,
-                     "note": "algorithmic flops of the all-pairs definition; the kernel skips the square root of "
-                             "pairs that cannot lower the minimum (bitwise-identical results), so this rate can "
-                             "exceed the hardware peak; all_pairs_kernel is the same launch evaluating every pair",
-                     "all_pairs_kernel": {"ms": plain_ms, "achieved": flops / (plain_ms * 1e-3) / 1e12,
-                                          "frac": flops / (plain_ms * 1e-3) / PEAK_FP32,
-                                          "identical_costs": same}},
-    }
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob)
+    if args.workload == "c1_full":
+        prob = synth.c1_full()
+        out, _, _ = bench_iterations(args, torch, cp, prob, with_roofline=True)
+        if not args.no_cpu_baseline:
+            print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline(prob)
+    elif args.workload == "c0_plain":
+        out, _, _ = bench_iterations(args, torch, cp, synth.c0_plain(), with_roofline=False)
+    elif args.workload == "c2_diff":
+        out = bench_diff(args, torch, cp, synth.c2_diff())
+    elif args.workload == "c3_batch":
+        out = bench_batch(args, torch, cp, synth.c3_batch(args.batch_problems))
+    else:
+        out = bench_sdf(args, torch, cp, synth.c4_sdf())
     print(json.dumps(out))
 
 

@@ -221,6 +221,58 @@ int cp_optimizer_set_state(cp_opt *opt, const double *mu, const double *C, int64
  * polish: indices >= B denote polished elite slots).  Any may be NULL. */
 int cp_optimizer_last(cp_opt *opt, float *d_waypoints, float *d_cost, int32_t *d_elite, cp_stream_t stream);
 
+/*
+ * Batches of independent planning problems (the paper's batch generation of
+ * trajectories, Sec. 1).  Every problem has its own crane, scene, cost and
+ * optimizer settings and sizes; an iteration of all of them is one sampling
+ * launch, ONE persistent evaluation launch (workgroups pull work items of
+ * consecutive configurations from a device queue ordered costliest problem
+ * first), and one selection / update / factor launch each, with a workgroup
+ * per problem.  Results are bitwise those of running each problem alone
+ * through cp_optimizer_step.
+ */
+typedef struct cp_batch cp_batch;
+
+/* Launch shape of the batched evaluation: configurations per work item
+ * (rounds x 256) and persistent workgroups per compute unit. */
+typedef struct {
+    int32_t rounds;     /* 1..64 */
+    int32_t wg_per_cu;  /* 1..16 */
+} cp_batch_tuning;
+
+/* Create n problems on `device` (SYNC).  robots, scenes, costs, opts are
+ * arrays of n descriptors (as for cp_plan_create / cp_optimizer_create; the
+ * cost's max_B must be >= the opt's B; polish is not supported in a batch);
+ * q_start and q_goal hold the n endpoint vectors back to back (host). */
+int cp_batch_create(int32_t n, const cp_robot_desc *robots, const cp_scene_desc *scenes, const cp_cost_params *costs,
+                    const cp_opt_params *opts, const float *q_start, const float *q_goal, int device,
+                    cp_batch **out);
+int cp_batch_destroy(cp_batch *batch); /* SYNC; NULL is a no-op */
+
+/* Run n_iters iterations of every problem.  The first call for a given
+ * n_iters (and tuning) captures the sequence into a HIP graph on an internal
+ * stream; every call replays the graph on `stream`. */
+int cp_batch_run(cp_batch *batch, int32_t n_iters, cp_stream_t stream);
+
+/* The persistent evaluation launch alone on the current populations
+ * (enqueued on stream; used for tuning and timing). */
+int cp_batch_eval(cp_batch *batch, cp_stream_t stream);
+
+/* State of problem p, as cp_optimizer_get_state (SYNC). */
+int cp_batch_get_state(cp_batch *batch, int32_t p, double *mu, double *C, int64_t *iter, float *best_cost,
+                       float *best_waypoints);
+
+/* Set / read the launch shape (setting drops captured graphs). */
+int cp_batch_set_tuning(cp_batch *batch, const cp_batch_tuning *tuning);
+int cp_batch_get_tuning(const cp_batch *batch, cp_batch_tuning *tuning);
+
+/* Autotune the launch shape (SYNC): reuse the entry for this batch's shape
+ * and device from the text cache at cache_path if there is one, else time
+ * every candidate shape on this batch, keep the fastest and append it to the
+ * cache (cache_path may be NULL: no cache).  The chosen shape is applied
+ * and returned in *chosen (may be NULL). */
+int cp_batch_tune(cp_batch *batch, const char *cache_path, cp_batch_tuning *chosen);
+
 /* Signed-distance grid from a point cloud (for scenes given as lidar):
  * voxels holding at least one point are occupied (index floor((p - o) / h) in
  * double precision; points outside the grid are dropped); exact squared

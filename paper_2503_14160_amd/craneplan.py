@@ -29,7 +29,9 @@ CP_OBS_SDF = 0xFFFF
 EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_endpoints", "cp_plan_n_checkpoints",
            "cp_eval_paths", "cp_eval_paths_backward", "cp_optimizer_create", "cp_optimizer_destroy",
            "cp_optimizer_step", "cp_optimizer_get_state", "cp_optimizer_set_state", "cp_optimizer_last",
-           "cp_sdf_build", "cp_debug_fk", "cp_debug_eval_configs", "cp_debug_select"]
+           "cp_sdf_build", "cp_debug_fk", "cp_debug_eval_configs", "cp_debug_select", "cp_batch_create",
+           "cp_batch_destroy", "cp_batch_run", "cp_batch_eval", "cp_batch_get_state", "cp_batch_set_tuning",
+           "cp_batch_get_tuning", "cp_batch_tune"]
 
 
 class CranePlanError(RuntimeError):
@@ -90,6 +92,14 @@ def lib():
         L.cp_debug_fk.argtypes = [_vp, _vp, i32, _vp, _vp, _vp]
         L.cp_debug_eval_configs.argtypes = [_vp, _vp, i32, _vp, _vp, _vp]
         L.cp_debug_select.argtypes = [_vp, i32, i32, _vp, _vp]
+        L.cp_batch_create.argtypes = [i32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]
+        L.cp_batch_destroy.argtypes = [_vp]
+        L.cp_batch_run.argtypes = [_vp, i32, _vp]
+        L.cp_batch_eval.argtypes = [_vp, _vp]
+        L.cp_batch_get_state.argtypes = [_vp, i32, _vp, _vp, _vp, _vp, _vp]
+        L.cp_batch_set_tuning.argtypes = [_vp, _vp]
+        L.cp_batch_get_tuning.argtypes = [_vp, _vp]
+        L.cp_batch_tune.argtypes = [_vp, ctypes.c_char_p, _vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -117,6 +127,58 @@ def _host(a, dt):
     return np.ascontiguousarray(np.asarray(a), dtype=dt)
 
 
+def _keep_ptr(keep, a, dt):
+    a = _host(a, dt)
+    keep.append(a)
+    return a.ctypes.data
+
+
+def _fill_robot(r, robot, keep):
+    r.n_joints = int(len(robot.joint_type))
+    r.type = _keep_ptr(keep, robot.joint_type, np.int32)
+    r.axis = _keep_ptr(keep, robot.axis, np.float32)
+    r.origin = _keep_ptr(keep, robot.origin, np.float32)
+    r.q_min = _keep_ptr(keep, robot.q_min, np.float32)
+    r.q_max = _keep_ptr(keep, robot.q_max, np.float32)
+    r.q_hold = _keep_ptr(keep, robot.q_hold, np.float32)
+    r.active = _keep_ptr(keep, robot.active, np.uint8)
+    r.n_spheres = int(len(robot.sphere_radius))
+    r.sphere_frame = _keep_ptr(keep, robot.sphere_frame, np.int32)
+    r.sphere_center = _keep_ptr(keep, robot.sphere_center, np.float32)
+    r.sphere_radius = _keep_ptr(keep, robot.sphere_radius, np.float32)
+
+
+def _fill_scene(s, scene, keep, sdf=None, sdf_spec=None):
+    s.has_ground = int(scene.has_ground)
+    s.ground_z = float(scene.ground_z)
+    s.n_cyl = int(scene.cyl.shape[0])
+    s.cyl = _keep_ptr(keep, scene.cyl, np.float32) if s.n_cyl else None
+    s.n_box = int(scene.box.shape[0])
+    s.box = _keep_ptr(keep, scene.box, np.float32) if s.n_box else None
+    if sdf is not None:
+        s.d_sdf = sdf.data_ptr()
+        for a in range(3):
+            s.sdf_dims[a] = int(sdf_spec.dims[a])
+            s.sdf_origin[a] = float(sdf_spec.origin[a])
+        s.voxel = float(sdf_spec.voxel)
+
+
+def _fill_cost(c, cost, max_B, pair_filter=True):
+    c.K, c.M, c.interp, c.jp_mode, c.hinge = cost.K, cost.M, cost.interp, cost.jp_mode, cost.hinge
+    c.margin, c.lambda_c, c.w_c, c.w_l = cost.margin, cost.lambda_c, cost.w_c, cost.w_l
+    c.max_B = int(max_B)
+    c.pair_filter = 1 if pair_filter else 0
+
+
+def _fill_opt(o, opt, problem_id=0):
+    o.B, o.nu, o.sigma0, o.eps, o.seed = int(opt.B), int(opt.nu), float(opt.sigma0), float(opt.eps), int(opt.seed)
+    o.problem_id = int(problem_id)
+    o.polish_elites = int(getattr(opt, "polish_elites", 0))
+    o.polish_steps = int(getattr(opt, "polish_steps", 0))
+    o.polish_eta = float(getattr(opt, "polish_eta", 0.0))
+    o.polish_clip = float(getattr(opt, "polish_clip", 1.0))
+
+
 class Plan:
     """A crane, a scene and a path cost on one device (cp_plan_create)."""
 
@@ -124,44 +186,11 @@ class Plan:
                  sdf_spec=None, pair_filter: bool = True):
         L = lib()
         self._keep = []
-
-        def keep(a, dt):
-            a = _host(a, dt)
-            self._keep.append(a)
-            return a.ctypes.data
-
-        r = _Robot()
-        r.n_joints = int(len(robot.joint_type))
-        r.type = keep(robot.joint_type, np.int32)
-        r.axis = keep(robot.axis, np.float32)
-        r.origin = keep(robot.origin, np.float32)
-        r.q_min = keep(robot.q_min, np.float32)
-        r.q_max = keep(robot.q_max, np.float32)
-        r.q_hold = keep(robot.q_hold, np.float32)
-        r.active = keep(robot.active, np.uint8)
-        r.n_spheres = int(len(robot.sphere_radius))
-        r.sphere_frame = keep(robot.sphere_frame, np.int32)
-        r.sphere_center = keep(robot.sphere_center, np.float32)
-        r.sphere_radius = keep(robot.sphere_radius, np.float32)
-        s = _Scene()
-        s.has_ground = int(scene.has_ground)
-        s.ground_z = float(scene.ground_z)
-        s.n_cyl = int(scene.cyl.shape[0])
-        s.cyl = keep(scene.cyl, np.float32) if s.n_cyl else None
-        s.n_box = int(scene.box.shape[0])
-        s.box = keep(scene.box, np.float32) if s.n_box else None
+        r, s, c = _Robot(), _Scene(), _Cost()
+        _fill_robot(r, robot, self._keep)
+        _fill_scene(s, scene, self._keep, sdf, sdf_spec)
+        _fill_cost(c, cost, max_B, pair_filter)
         self.sdf = sdf
-        if sdf is not None:
-            s.d_sdf = sdf.data_ptr()
-            for a in range(3):
-                s.sdf_dims[a] = int(sdf_spec.dims[a])
-                s.sdf_origin[a] = float(sdf_spec.origin[a])
-            s.voxel = float(sdf_spec.voxel)
-        c = _Cost()
-        c.K, c.M, c.interp, c.jp_mode, c.hinge = cost.K, cost.M, cost.interp, cost.jp_mode, cost.hinge
-        c.margin, c.lambda_c, c.w_c, c.w_l = cost.margin, cost.lambda_c, cost.w_c, cost.w_l
-        c.max_B = int(max_B)
-        c.pair_filter = 1 if pair_filter else 0
         h = ctypes.c_void_p()
         _check(L.cp_plan_create(ctypes.byref(r), ctypes.byref(s), ctypes.byref(c), int(device), ctypes.byref(h)))
         self._h = h
@@ -264,12 +293,7 @@ class Optimizer:
 
     def __init__(self, plan: Plan, opt, problem_id: int = 0):
         o = _Opt()
-        o.B, o.nu, o.sigma0, o.eps, o.seed = int(opt.B), int(opt.nu), float(opt.sigma0), float(opt.eps), int(opt.seed)
-        o.problem_id = int(problem_id)
-        o.polish_elites = int(getattr(opt, "polish_elites", 0))
-        o.polish_steps = int(getattr(opt, "polish_steps", 0))
-        o.polish_eta = float(getattr(opt, "polish_eta", 0.0))
-        o.polish_clip = float(getattr(opt, "polish_clip", 1.0))
+        _fill_opt(o, opt, problem_id)
         h = ctypes.c_void_p()
         _check(lib().cp_optimizer_create(plan._h, ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -315,6 +339,81 @@ class Optimizer:
         elite = torch.empty(self.nu, dtype=torch.int32, device=dev)
         _check(lib().cp_optimizer_last(self._h, _ptr(W), _ptr(cost), _ptr(elite), _stream()))
         return W, cost, elite
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("rounds", _c_i32), ("wg_per_cu", _c_i32)]
+
+
+class Batch:
+    """Independent problems run together (cp_batch_create): one persistent
+    evaluation launch per iteration, iterations replayed from a HIP graph.
+    ``problems`` are objects with robot, scene, cost, opt, q_start, q_goal;
+    problem i uses Philox problem id i."""
+
+    def __init__(self, problems, device: int = 0, pair_filter: bool = True):
+        L = lib()
+        n = len(problems)
+        self._keep = []
+        robots, scenes = (_Robot * n)(), (_Scene * n)()
+        costs, opts = (_Cost * n)(), (_Opt * n)()
+        for i, p in enumerate(problems):
+            _fill_robot(robots[i], p.robot, self._keep)
+            _fill_scene(scenes[i], p.scene, self._keep)
+            _fill_cost(costs[i], p.cost, p.opt.B, pair_filter)
+            _fill_opt(opts[i], p.opt, i)
+        qs = _host(np.concatenate([np.asarray(p.q_start, np.float32) for p in problems]), np.float32)
+        qg = _host(np.concatenate([np.asarray(p.q_goal, np.float32) for p in problems]), np.float32)
+        h = ctypes.c_void_p()
+        _check(L.cp_batch_create(n, robots, scenes, costs, opts, qs.ctypes.data, qg.ctypes.data, int(device),
+                                 ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.shapes = [(p.cost.K, p.robot.n_joints, int(p.cost.K * int(np.count_nonzero(p.robot.active))))
+                       for p in problems]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, n_iters: int):
+        _check(lib().cp_batch_run(self._h, int(n_iters), _stream()))
+
+    def eval(self):
+        _check(lib().cp_batch_eval(self._h, _stream()))
+
+    def get_state(self, p: int):
+        K, n, D = self.shapes[p]
+        mu = np.zeros(D)
+        C = np.zeros((D, D))
+        t = ctypes.c_int64()
+        bc = ctypes.c_float()
+        bw = np.zeros((K, n), np.float32)
+        _check(lib().cp_batch_get_state(self._h, int(p), mu.ctypes.data, C.ctypes.data, ctypes.byref(t),
+                                        ctypes.byref(bc), bw.ctypes.data))
+        return dict(mu=mu, C=C, t=t.value, best_cost=bc.value, best_W=bw)
+
+    def set_tuning(self, rounds: int, wg_per_cu: int):
+        t = _Tuning(int(rounds), int(wg_per_cu))
+        _check(lib().cp_batch_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = _Tuning()
+        _check(lib().cp_batch_get_tuning(self._h, ctypes.byref(t)))
+        return t.rounds, t.wg_per_cu
+
+    def tune(self, cache_path: Optional[str] = None):
+        t = _Tuning()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().cp_batch_tune(self._h, path, ctypes.byref(t)))
+        return t.rounds, t.wg_per_cu
 
 
 def select(cost: torch.Tensor, nu: int) -> torch.Tensor:

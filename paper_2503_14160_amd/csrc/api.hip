@@ -2,6 +2,7 @@
 // objects and their device tables, and the step sequencing of Algorithm 1.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -582,6 +583,292 @@ int cp_optimizer_last(cp_opt *opt, float *d_waypoints, float *d_cost, int32_t *d
         CP_HIP(hipMemcpyAsync(d_waypoints, v.W, v.B * per * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
     if (d_cost) CP_HIP(hipMemcpyAsync(d_cost, v.cost, v.B * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
     if (d_elite) CP_HIP(hipMemcpyAsync(d_elite, v.elite, v.nu * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "copy");
+    return CP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of problems
+// ---------------------------------------------------------------------------
+
+struct cp_batch {
+    int device = 0, n = 0, max_B = 0, n_cu = 0;
+    std::vector<cp_plan *> plans;
+    std::vector<cp_opt *> opts;
+    std::vector<int> order;           // problems, costliest configuration first
+    BatchProblem *d_probs = nullptr;
+    int2 *d_items = nullptr;
+    size_t items_cap = 0;
+    int n_items = 0;
+    int *d_counter = nullptr;
+    BatchTuning tune{4, 4};
+    hipStream_t capture_stream = nullptr;
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+
+    void drop_graphs() {
+        for (auto &kv : graphs) {
+            (void)hipGraphExecDestroy(kv.second.second);
+            (void)hipGraphDestroy(kv.second.first);
+        }
+        graphs.clear();
+    }
+    ~cp_batch() {
+        DeviceGuard g(device);
+        (void)hipDeviceSynchronize();
+        drop_graphs();
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        if (d_probs) (void)hipFree(d_probs);
+        if (d_items) (void)hipFree(d_items);
+        if (d_counter) (void)hipFree(d_counter);
+        for (cp_opt *o : opts) delete o;
+        for (cp_plan *p : plans) delete p;
+    }
+    // work items (problem, first configuration) for the current tuning
+    hipError_t build_items() {
+        std::vector<int2> items;
+        const int64_t chunk = 256 * (int64_t)tune.rounds;
+        for (int p : order) {
+            const int64_t N = (int64_t)opts[p]->prm.B * plans[p]->ns;
+            for (int64_t g0 = 0; g0 < N; g0 += chunk) items.push_back(make_int2(p, (int)g0));
+        }
+        n_items = (int)items.size();
+        if (items.size() > items_cap) {
+            if (d_items) (void)hipFree(d_items);
+            d_items = nullptr;
+            hipError_t e = hipMalloc((void **)&d_items, items.size() * sizeof(int2));
+            if (e != hipSuccess) return e;
+            items_cap = items.size();
+        }
+        return hipMemcpy(d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+    }
+    int grid() const { return n_cu * tune.wg_per_cu; }
+};
+
+extern "C" {
+
+int cp_batch_create(int32_t n, const cp_robot_desc *robots, const cp_scene_desc *scenes, const cp_cost_params *costs,
+                    const cp_opt_params *opts, const float *q_start, const float *q_goal, int device,
+                    cp_batch **out) {
+    if (!out) return fail(CP_ERR_INVALID_ARG, "null out");
+    *out = nullptr;
+    if (n < 1) return fail(CP_ERR_SIZE, "n must be >= 1");
+    if (!robots || !scenes || !costs || !opts || !q_start || !q_goal) return fail(CP_ERR_INVALID_ARG, "null argument");
+    for (int i = 0; i < n; ++i) {
+        if (opts[i].polish_steps > 0 && opts[i].polish_elites > 0)
+            return fail(CP_ERR_INVALID_ARG, "polish is not supported in a batch");
+        if (costs[i].max_B < opts[i].B) return fail(CP_ERR_SIZE, "cost max_B below opt B");
+    }
+    cp_batch *b = new (std::nothrow) cp_batch();
+    if (!b) return fail(CP_ERR_NOMEM, "host allocation");
+    b->device = device;
+    b->n = n;
+    size_t qoff = 0;
+    for (int i = 0; i < n; ++i) {
+        cp_plan *p = nullptr;
+        int rc = cp_plan_create(robots + i, scenes + i, costs + i, device, &p);
+        if (rc) {
+            delete b;
+            return fail(rc, "problem " + std::to_string(i) + ": " + g_err);
+        }
+        b->plans.push_back(p);
+        rc = cp_plan_set_endpoints(p, q_start + qoff, q_goal + qoff);
+        qoff += robots[i].n_joints;
+        cp_opt *o = nullptr;
+        if (!rc) rc = cp_optimizer_create(p, opts + i, &o);
+        if (rc) {
+            delete b;
+            return fail(rc, "problem " + std::to_string(i) + ": " + g_err);
+        }
+        b->opts.push_back(o);
+        b->max_B = std::max(b->max_B, opts[i].B);
+    }
+    DeviceGuard guard(device);
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "device properties");
+    }
+    b->n_cu = prop.multiProcessorCount;
+    std::vector<BatchProblem> probs(n);
+    std::vector<std::pair<double, int>> cost_of(n);
+    for (int i = 0; i < n; ++i) {
+        probs[i].P = b->plans[i]->view;
+        probs[i].O = b->opts[i]->view;
+        probs[i].O.elite0 = probs[i].O.elite;  // no polish: selection writes the final ranking
+        probs[i].partial = b->plans[i]->d_partial;
+        probs[i].slots = eval_slots(b->plans[i]->ns);
+        cost_of[i] = {-(double)b->plans[i]->S * (b->plans[i]->n_cyl + b->plans[i]->n_box + 1), i};
+    }
+    std::stable_sort(cost_of.begin(), cost_of.end());
+    for (auto &c : cost_of) b->order.push_back(c.second);
+    if ((e = upload(&b->d_probs, probs)) != hipSuccess || (e = hipMalloc((void **)&b->d_counter, sizeof(int))) != hipSuccess ||
+        (e = b->build_items()) != hipSuccess || (e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch tables");
+    }
+    *out = b;
+    return CP_OK;
+}
+
+int cp_batch_destroy(cp_batch *batch) {
+    delete batch;
+    return CP_OK;
+}
+
+int cp_batch_run(cp_batch *b, int32_t n_iters, cp_stream_t stream) {
+    if (!b) return fail(CP_ERR_INVALID_ARG, "null batch");
+    if (n_iters < 0) return fail(CP_ERR_SIZE, "n_iters must be >= 0");
+    if (n_iters == 0) return CP_OK;
+    DeviceGuard g(b->device);
+    auto it = b->graphs.find(n_iters);
+    if (it == b->graphs.end()) {
+        hipStream_t cs = b->capture_stream;
+        CP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "graph capture");
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < n_iters && e == hipSuccess; ++i)
+            e = launch_batch_iteration(b->d_probs, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds, b->grid(),
+                                       b->d_counter, cs);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e, "graph capture");
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "graph capture end");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "graph instantiate");
+        }
+        it = b->graphs.emplace(n_iters, std::make_pair(graph, exec)).first;
+    }
+    CP_HIP(hipGraphLaunch(it->second.second, (hipStream_t)stream), "graph launch");
+    return CP_OK;
+}
+
+int cp_batch_eval(cp_batch *b, cp_stream_t stream) {
+    if (!b) return fail(CP_ERR_INVALID_ARG, "null batch");
+    DeviceGuard g(b->device);
+    CP_HIP(launch_batch_eval(b->d_probs, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds, b->grid(),
+                             b->d_counter, (hipStream_t)stream),
+           "batch eval");
+    return CP_OK;
+}
+
+int cp_batch_get_state(cp_batch *b, int32_t p, double *mu, double *C, int64_t *iter, float *best_cost,
+                       float *best_waypoints) {
+    if (!b) return fail(CP_ERR_INVALID_ARG, "null batch");
+    if (p < 0 || p >= b->n) return fail(CP_ERR_SIZE, "problem index out of range");
+    return cp_optimizer_get_state(b->opts[p], mu, C, iter, best_cost, best_waypoints);
+}
+
+int cp_batch_set_tuning(cp_batch *b, const cp_batch_tuning *t) {
+    if (!b || !t) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (t->rounds < 1 || t->rounds > 64 || t->wg_per_cu < 1 || t->wg_per_cu > 16)
+        return fail(CP_ERR_SIZE, "tuning out of range");
+    DeviceGuard g(b->device);
+    CP_HIP(hipDeviceSynchronize(), "sync");
+    b->drop_graphs();
+    b->tune.rounds = t->rounds;
+    b->tune.wg_per_cu = t->wg_per_cu;
+    CP_HIP(b->build_items(), "work items");
+    return CP_OK;
+}
+
+int cp_batch_get_tuning(const cp_batch *b, cp_batch_tuning *t) {
+    if (!b || !t) return fail(CP_ERR_INVALID_ARG, "null argument");
+    t->rounds = b->tune.rounds;
+    t->wg_per_cu = b->tune.wg_per_cu;
+    return CP_OK;
+}
+
+int cp_batch_tune(cp_batch *b, const char *cache_path, cp_batch_tuning *chosen) {
+    if (!b) return fail(CP_ERR_INVALID_ARG, "null batch");
+    DeviceGuard g(b->device);
+    // signature of the batch shape and the device (FNV-1a)
+    hipDeviceProp_t prop;
+    CP_HIP(hipGetDeviceProperties(&prop, b->device), "device properties");
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xFF;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)b->n);
+    for (int i = 0; i < b->n; ++i) {
+        mix((uint64_t)b->opts[i]->prm.B);
+        mix((uint64_t)b->plans[i]->ns);
+        mix((uint64_t)b->plans[i]->S);
+        mix((uint64_t)b->plans[i]->n_cyl);
+        mix((uint64_t)b->plans[i]->n_box);
+    }
+    for (const char *c = prop.gcnArchName; *c; ++c) mix((uint64_t)(unsigned char)*c);
+    mix((uint64_t)prop.multiProcessorCount);
+    char key[32];
+    std::snprintf(key, sizeof(key), "%016llx", (unsigned long long)h);
+    cp_batch_tuning best{0, 0};
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char k[64];
+            int r, w;
+            double ms;
+            while (std::fscanf(f, "%63s %d %d %lf", k, &r, &w, &ms) == 4)
+                if (std::strcmp(k, key) == 0) best = {r, w};
+            std::fclose(f);
+        }
+    }
+    if (best.rounds == 0) {
+        // current populations for timing: one sampling pass (does not advance t)
+        hipStream_t st = b->capture_stream;
+        CP_HIP(launch_batch_sample(b->d_probs, b->n, b->max_B, st), "tune sample");
+        hipEvent_t e0, e1;
+        CP_HIP(hipEventCreate(&e0), "event");
+        CP_HIP(hipEventCreate(&e1), "event");
+        double best_ms = 1e300;
+        const int rounds_c[] = {1, 4, 16};
+        const int wg_c[] = {2, 4, 8};
+        bool warm = false;
+        for (int r : rounds_c)
+            for (int w : wg_c) {
+                cp_batch_tuning t{r, w};
+                int rc = cp_batch_set_tuning(b, &t);
+                if (rc) return rc;
+                hipError_t e = hipSuccess;
+                if (!warm) {
+                    e = launch_batch_eval(b->d_probs, b->n, b->max_B, b->d_items, b->n_items, r, b->grid(),
+                                          b->d_counter, st);
+                    warm = true;
+                }
+                if (e == hipSuccess) e = hipEventRecord(e0, st);
+                if (e == hipSuccess)
+                    e = launch_batch_eval(b->d_probs, b->n, b->max_B, b->d_items, b->n_items, r, b->grid(),
+                                          b->d_counter, st);
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) return hip_fail(e, "tune timing");
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (cache_path) {
+            if (FILE *f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "%s %d %d %.4f\n", key, best.rounds, best.wg_per_cu, best_ms);
+                std::fclose(f);
+            }
+        }
+    }
+    int rc = cp_batch_set_tuning(b, &best);
+    if (rc) return rc;
+    if (chosen) *chosen = best;
     return CP_OK;
 }
 

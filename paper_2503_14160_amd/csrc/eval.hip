@@ -227,11 +227,13 @@ __device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[C
     jl = lim;
 }
 
+// One configuration per lane: g is the flattened (path, checkpoint) index;
+// all 64 lanes of a wave hold consecutive g (some may lie past the end).
 template <bool TAPE>
-__global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__restrict__ W, int B,
-                                                  double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape) {
+__device__ __forceinline__ void eval_one(const PlanView &P, const float *__restrict__ W, int B,
+                                         double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape,
+                                         int64_t g) {
     const int64_t N = (int64_t)B * P.ns;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = g < N;
     const int b = active ? (int)(g / P.ns) : B - 1;
     const int k = active ? (int)(g - (int64_t)b * P.ns) + 1 : 1;
@@ -266,11 +268,40 @@ __global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__res
     }
 }
 
-__global__ __launch_bounds__(256) void k_eval_reduce(const double2 *__restrict__ partial, int slots, int B, int ns,
-                                                     float margin, float *__restrict__ cost,
-                                                     float *__restrict__ min_dist, uint8_t *__restrict__ flags) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+template <bool TAPE>
+__global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__restrict__ W, int B,
+                                                  double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape) {
+    eval_one<TAPE>(P, W, B, partial, slots, tape, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Many problems in one persistent launch: workgroups pull work items (problem,
+// first configuration) from a queue ordered costliest-problem first; an item
+// covers `rounds` x 256 consecutive configurations of one problem.  Every
+// configuration runs exactly the single-problem code, so results are bitwise
+// those of k_eval_fwd on each problem.  The counter is zeroed before launch.
+__global__ __launch_bounds__(256) void k_eval_persistent(const BatchProblem *__restrict__ probs,
+                                                         const int2 *__restrict__ items, int n_items, int rounds,
+                                                         int *__restrict__ counter) {
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        const BatchProblem &bp = probs[item.x];
+        const PlanView P = bp.P;
+        const float *W = bp.O.W;
+        const int B = bp.O.B;
+        for (int r = 0; r < rounds; ++r)
+            eval_one<false>(P, W, B, bp.partial, bp.slots, nullptr, (int64_t)item.y + r * 256 + threadIdx.x);
+    }
+}
+
+__device__ __forceinline__ void reduce_one(const double2 *__restrict__ partial, int slots, int ns, float margin,
+                                           float *__restrict__ cost, float *__restrict__ min_dist,
+                                           uint8_t *__restrict__ flags, int b) {
     const int64_t g0 = (int64_t)b * ns, g1 = g0 + ns - 1;
     double s = 0.0;
     float m = kInf;
@@ -283,6 +314,20 @@ __global__ __launch_bounds__(256) void k_eval_reduce(const double2 *__restrict__
     cost[b] = (float)s;
     if (min_dist) min_dist[b] = m;
     if (flags) flags[b] = (uint8_t)(m < margin);
+}
+
+__global__ __launch_bounds__(256) void k_eval_reduce(const double2 *__restrict__ partial, int slots, int B, int ns,
+                                                     float margin, float *__restrict__ cost,
+                                                     float *__restrict__ min_dist, uint8_t *__restrict__ flags) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) reduce_one(partial, slots, ns, margin, cost, min_dist, flags, b);
+}
+
+// per-problem path sums of a batch: blockIdx.y = problem
+__global__ __launch_bounds__(256) void k_reduce_batched(const BatchProblem *__restrict__ probs) {
+    const BatchProblem &bp = probs[blockIdx.y];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < bp.O.B) reduce_one(bp.partial, bp.slots, bp.P.ns, bp.P.margin, bp.O.cost, bp.O.min_dist, nullptr, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -547,6 +592,21 @@ hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *pa
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_eval_reduce, dim3((B + 255) / 256), dim3(256), 0, st, partial, slots, B, P.ns, P.margin,
                        cost, min_dist, flags);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_counter(int *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+hipError_t launch_batch_eval(const BatchProblem *probs, int n, int max_B, const int2 *items, int n_items, int rounds,
+                             int grid, int *counter, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eval_persistent, dim3(grid), dim3(256), 0, st, probs, items, n_items, rounds, counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_batched, dim3((max_B + 255) / 256, n), dim3(256), 0, st, probs);
     return hipGetLastError();
 }
 

@@ -71,10 +71,10 @@ __global__ void k_init_state(PlanView P, OptView O, float sigma0) {
 
 constexpr int kSampleTile = 16;  // paths per block
 
-__global__ __launch_bounds__(256) void k_sample(PlanView P, OptView O) {
+__device__ __forceinline__ void sample_body(const PlanView &P, const OptView &O, int tile) {
     __shared__ double z[kSampleTile][CP_MAX_DIM];
     const int D = O.D;
-    const int b0 = blockIdx.x * kSampleTile;
+    const int b0 = tile * kSampleTile;
     const uint32_t t = (uint32_t)*O.t;
     const uint32_t k0 = (uint32_t)O.seed, k1 = (uint32_t)(O.seed >> 32);
     const int G = (D + 3) / 4;
@@ -109,6 +109,15 @@ __global__ __launch_bounds__(256) void k_sample(PlanView P, OptView O) {
         const JointDev J = P.joints[jj];
         if (!J.active) O.W[(size_t)b * P.K * n + r] = J.qhold;
     }
+}
+
+__global__ __launch_bounds__(256) void k_sample(PlanView P, OptView O) { sample_body(P, O, blockIdx.x); }
+
+// batch: blockIdx.y = problem, blockIdx.x = tile of 16 paths
+__global__ __launch_bounds__(256) void k_sample_batched(const BatchProblem *__restrict__ probs) {
+    const BatchProblem &bp = probs[blockIdx.y];
+    if ((int)blockIdx.x * kSampleTile >= bp.O.B) return;
+    sample_body(bp.P, bp.O, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -150,8 +159,8 @@ __device__ __forceinline__ void bitonic_sort(uint64_t *a, int n) {
     }
 }
 
-__global__ __launch_bounds__(kSelThreads) void k_select(const float *__restrict__ cost, int B, int nu,
-                                                        int32_t *__restrict__ elite) {
+__device__ __forceinline__ void select_body(const float *__restrict__ cost, int B, int nu,
+                                            int32_t *__restrict__ elite) {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t scanbuf[kSelThreads];
     __shared__ uint64_t sorted[CP_MAX_ELITES];
@@ -207,6 +216,17 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const float *__restrict_
     __syncthreads();
     bitonic_sort(sorted, np);
     for (int r = tid; r < nu; r += kSelThreads) elite[r] = (int32_t)(uint32_t)(sorted[r] & 0xFFFFFFFFu);
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_select(const float *__restrict__ cost, int B, int nu,
+                                                        int32_t *__restrict__ elite) {
+    select_body(cost, B, nu, elite);
+}
+
+// batch: one workgroup per problem
+__global__ __launch_bounds__(kSelThreads) void k_select_batched(const BatchProblem *__restrict__ probs) {
+    const OptView &O = probs[blockIdx.x].O;
+    select_body(O.cost, O.B, O.nu, O.elite0);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,7 +305,7 @@ __device__ __forceinline__ float elite_cost(const OptView &O, int idx) {
     return idx < O.B ? O.cost[idx] : O.cost_p[idx - O.B];
 }
 
-__global__ __launch_bounds__(kUpdThreads) void k_update(PlanView P, OptView O) {
+__device__ __forceinline__ void update_body(const PlanView &P, const OptView &O) {
     const double *w = O.w;
     __shared__ double mu[CP_MAX_DIM];
     __shared__ double xs[kEliteChunk][CP_MAX_DIM];
@@ -365,6 +385,13 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(PlanView P, OptView O) {
     }
 }
 
+__global__ __launch_bounds__(kUpdThreads) void k_update(PlanView P, OptView O) { update_body(P, O); }
+
+__global__ __launch_bounds__(kUpdThreads) void k_update_batched(const BatchProblem *__restrict__ probs) {
+    const BatchProblem &bp = probs[blockIdx.x];
+    update_body(bp.P, bp.O);
+}
+
 // ---------------------------------------------------------------------------
 // lower Cholesky factor of C (double, in shared memory, packed lower
 // triangle); if a pivot is not positive, retry with C + 10^k eps I, k = 1..3
@@ -372,7 +399,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(PlanView P, OptView O) {
 
 constexpr int kCholThreads = 256;
 
-__global__ __launch_bounds__(kCholThreads) void k_chol(OptView O) {
+__device__ __forceinline__ void chol_body(const OptView &O) {
     __shared__ double A[CP_MAX_DIM * (CP_MAX_DIM + 1) / 2];
     __shared__ int s_fail;
     const int D = O.D, tid = threadIdx.x;
@@ -415,6 +442,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(OptView O) {
         const int i = idx / D, j = idx % D;
         O.L[idx] = j <= i ? A[at(i, j)] : 0.0;
     }
+}
+
+__global__ __launch_bounds__(kCholThreads) void k_chol(OptView O) { chol_body(O); }
+
+__global__ __launch_bounds__(kCholThreads) void k_chol_batched(const BatchProblem *__restrict__ probs) {
+    chol_body(probs[blockIdx.x].O);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,6 +493,24 @@ hipError_t launch_update(const PlanView &P, const OptView &O, hipStream_t st) {
 
 hipError_t launch_chol(const OptView &O, hipStream_t st) {
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholThreads), 0, st, O);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sample(const BatchProblem *probs, int n, int max_B, hipStream_t st) {
+    hipLaunchKernelGGL(k_sample_batched, dim3((max_B + kSampleTile - 1) / kSampleTile, n), dim3(256), 0, st, probs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_iteration(const BatchProblem *probs, int n, int max_B, const int2 *items, int n_items,
+                                  int rounds, int grid, int *counter, hipStream_t st) {
+    hipError_t e = launch_batch_sample(probs, n, max_B, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_batch_eval(probs, n, max_B, items, n_items, rounds, grid, counter, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_select_batched, dim3(n), dim3(kSelThreads), 0, st, probs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_update_batched, dim3(n), dim3(kUpdThreads), 0, st, probs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chol_batched, dim3(n), dim3(kCholThreads), 0, st, probs);
     return hipGetLastError();
 }
 

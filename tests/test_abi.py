@@ -48,3 +48,35 @@ def test_product_does_not_import_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "oracle.c" not in txt, f
+
+
+def test_batch_rejects_polish_before_touching_the_device():
+    """Argument checks run before any device work (no GPU needed)."""
+    import numpy as np
+
+    from paper_2503_14160_amd import craneplan, synth
+    p = synth.c0_plain()
+    p.opt = synth.OptParams(B=16, nu=2, sigma0=0.2, eps=1e-6, seed=1, T=1, polish_elites=2, polish_steps=3)
+    with pytest.raises(craneplan.CranePlanError) as ei:
+        craneplan.Batch([p])
+    assert ei.value.code == -1
+
+
+def test_plan_argument_errors_without_device():
+    import numpy as np
+
+    from paper_2503_14160_amd import craneplan, synth
+    p = synth.c0_plain()
+    bad = synth.CostParams(K=0, M=16)
+    with pytest.raises(craneplan.CranePlanError) as ei:
+        craneplan.Plan(p.robot, p.scene, bad, max_B=4)
+    assert ei.value.code == -2
+    smooth0 = synth.CostParams(K=4, M=4, hinge=synth.HINGE_SMOOTH, margin=0.0)
+    with pytest.raises(craneplan.CranePlanError) as ei:
+        craneplan.Plan(p.robot, p.scene, smooth0, max_B=4)
+    assert ei.value.code == -1
+    rb = synth.make_robot(3, 8)
+    rb.axis = rb.axis * 2.0
+    with pytest.raises(craneplan.CranePlanError) as ei:
+        craneplan.Plan(rb, p.scene, p.cost, max_B=4)
+    assert "unit" in str(ei.value)
