@@ -601,7 +601,7 @@ struct cp_batch {
     int2 *d_items = nullptr;
     size_t items_cap = 0;
     int n_items = 0;
-    int *d_counter = nullptr;
+    double2 *d_partial = nullptr;     // per-wave partial sums of every problem, back to back
     BatchTuning tune{4, 4};
     hipStream_t capture_stream = nullptr;
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
@@ -620,7 +620,7 @@ struct cp_batch {
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
         if (d_probs) (void)hipFree(d_probs);
         if (d_items) (void)hipFree(d_items);
-        if (d_counter) (void)hipFree(d_counter);
+        if (d_partial) (void)hipFree(d_partial);
         for (cp_opt *o : opts) delete o;
         for (cp_plan *p : plans) delete p;
     }
@@ -693,17 +693,23 @@ int cp_batch_create(int32_t n, const cp_robot_desc *robots, const cp_scene_desc 
     b->n_cu = prop.multiProcessorCount;
     std::vector<BatchProblem> probs(n);
     std::vector<std::pair<double, int>> cost_of(n);
+    int64_t partial_total = 0;
     for (int i = 0; i < n; ++i) {
         probs[i].P = b->plans[i]->view;
         probs[i].O = b->opts[i]->view;
         probs[i].O.elite0 = probs[i].O.elite;  // no polish: selection writes the final ranking
-        probs[i].partial = b->plans[i]->d_partial;
+        probs[i].partial_off = partial_total;
         probs[i].slots = eval_slots(b->plans[i]->ns);
+        partial_total += (int64_t)eval_partial_count(opts[i].B, b->plans[i]->ns);
         cost_of[i] = {-(double)b->plans[i]->S * (b->plans[i]->n_cyl + b->plans[i]->n_box + 1), i};
     }
     std::stable_sort(cost_of.begin(), cost_of.end());
     for (auto &c : cost_of) b->order.push_back(c.second);
-    if ((e = upload(&b->d_probs, probs)) != hipSuccess || (e = hipMalloc((void **)&b->d_counter, sizeof(int))) != hipSuccess ||
+    if ((e = hipMalloc((void **)&b->d_partial, (size_t)partial_total * sizeof(double2))) != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch workspace");
+    }
+    if ((e = upload(&b->d_probs, probs)) != hipSuccess ||
         (e = b->build_items()) != hipSuccess || (e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
         delete b;
         return hip_fail(e, "batch tables");
@@ -728,8 +734,8 @@ int cp_batch_run(cp_batch *b, int32_t n_iters, cp_stream_t stream) {
         CP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "graph capture");
         hipError_t e = hipSuccess;
         for (int i = 0; i < n_iters && e == hipSuccess; ++i)
-            e = launch_batch_iteration(b->d_probs, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds, b->grid(),
-                                       b->d_counter, cs);
+            e = launch_batch_iteration(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds, b->grid(),
+                                       cs);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         if (e != hipSuccess) {
@@ -752,8 +758,8 @@ int cp_batch_run(cp_batch *b, int32_t n_iters, cp_stream_t stream) {
 int cp_batch_eval(cp_batch *b, cp_stream_t stream) {
     if (!b) return fail(CP_ERR_INVALID_ARG, "null batch");
     DeviceGuard g(b->device);
-    CP_HIP(launch_batch_eval(b->d_probs, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds, b->grid(),
-                             b->d_counter, (hipStream_t)stream),
+    CP_HIP(launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds, b->grid(),
+                             (hipStream_t)stream),
            "batch eval");
     return CP_OK;
 }
@@ -839,14 +845,14 @@ int cp_batch_tune(cp_batch *b, const char *cache_path, cp_batch_tuning *chosen) 
                 if (rc) return rc;
                 hipError_t e = hipSuccess;
                 if (!warm) {
-                    e = launch_batch_eval(b->d_probs, b->n, b->max_B, b->d_items, b->n_items, r, b->grid(),
-                                          b->d_counter, st);
+                    e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r, b->grid(),
+                                          st);
                     warm = true;
                 }
                 if (e == hipSuccess) e = hipEventRecord(e0, st);
                 if (e == hipSuccess)
-                    e = launch_batch_eval(b->d_probs, b->n, b->max_B, b->d_items, b->n_items, r, b->grid(),
-                                          b->d_counter, st);
+                    e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r, b->grid(),
+                                          st);
                 if (e == hipSuccess) e = hipEventRecord(e1, st);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.0f;

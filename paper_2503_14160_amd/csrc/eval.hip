@@ -16,7 +16,7 @@ namespace cp {
 // Four cylinders against G spheres: running minimum of (radial distance - R).
 template <int G>
 __device__ __forceinline__ void cyl_chunk(const float (&cx)[G], const float (&cy)[G], const float4 *c, float (&a)[G]) {
-    const float4 c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+    const float4 c0 = ldg(c, 0), c1 = ldg(c, 1), c2 = ldg(c, 2), c3 = ldg(c, 3);
 #pragma unroll
     for (int s = 0; s < G; ++s) {
         float r0 = cyl_radial(cx[s], cy[s], c0);
@@ -41,7 +41,7 @@ __device__ __forceinline__ void cyl_chunk(const float (&cx)[G], const float (&cy
 template <int G>
 __device__ __forceinline__ void cyl_chunk_filtered(const float (&cx)[G], const float (&cy)[G], const float4 *c,
                                                    float (&a)[G], float (&thr)[G], float reach) {
-    const float4 cc[4] = {c[0], c[1], c[2], c[3]};
+    const float4 cc[4] = {ldg(c, 0), ldg(c, 1), ldg(c, 2), ldg(c, 3)};
     float d2[G][4];
     uint64_t need = 0;
 #pragma unroll
@@ -76,7 +76,7 @@ __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&
 #pragma unroll
     for (int s = 0; s < G; ++s) v[s] = P.has_ground ? cz[s] - P.ground_z : kInf;
     for (int g = 0; g < P.n_groups; ++g) {
-        const GroupDev gr = P.groups[g];
+        const GroupDev gr = ldg(P.groups, g);
         const float4 *c = P.cyl + gr.start;
         float a[G];
 #pragma unroll
@@ -86,7 +86,7 @@ __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&
             const float ang = atan2f(first_lane(cy[0]), first_lane(cx[0]));
             int bin = (int)((ang + 3.14159265f) * (kAngleBins / 6.28318531f));
             bin = min(max(bin, 0), kAngleBins - 1);
-            const int start = P.angle_start[g * kAngleBins + bin];
+            const int start = ldg(P.angle_start, g * kAngleBins + bin);
             const float reach = gr.rmax + 1e-4f;
             float thr[G];
 #pragma unroll
@@ -100,7 +100,7 @@ __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&
         for (int s = 0; s < G; ++s) v[s] = fminf(v[s], cyl_combine(a[s], fabsf(cz[s] - gr.zc) - gr.hz));
     }
     for (int o = 0; o < P.n_box; ++o) {
-        const float4 b0 = P.box[2 * o], b1 = P.box[2 * o + 1];
+        const float4 b0 = ldg(P.box, 2 * o), b1 = ldg(P.box, 2 * o + 1);
 #pragma unroll
         for (int s = 0; s < G; ++s) v[s] = fminf(v[s], box_sd(cx[s], cy[s], cz[s], b0, b1));
     }
@@ -123,13 +123,13 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
     float cx[G], cy[G], cz[G], v[G];
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-        const SphereDev sp = P.spheres[s0 + i];
+        const SphereDev sp = ldg(P.spheres, s0 + i);
         xf_point(T, sp.lx, sp.ly, sp.lz, cx[i], cy[i], cz[i]);
     }
     spheres_min_sd<G>(P, cx, cy, cz, v);
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-        const SphereDev sp = P.spheres[s0 + i];
+        const SphereDev sp = ldg(P.spheres, s0 + i);
         float d = v[i] - sp.r;
         if (ARG) {
             if (d < best.d || (d == best.d && sp.orig < best.s)) {
@@ -151,9 +151,9 @@ __device__ __forceinline__ Best config_distance(const PlanView &P, const float (
     Xf T;
     xf_identity(T);
     for (int f = 0; f <= P.n_joints; ++f) {
-        if (f > 0) xf_joint(T, P.joints[f - 1], pick(q, f - 1));
-        const int s1 = P.frame_start[f + 1];
-        int s = P.frame_start[f];
+        if (f > 0) xf_joint(T, ldg(P.joints, f - 1), pick(q, f - 1));
+        const int s1 = ldg(P.frame_start, f + 1);
+        int s = ldg(P.frame_start, f);
         for (; s + 4 <= s1; s += 4) sphere_group<4, ARG>(P, T, s, best);
         switch (s1 - s) {
             case 3: sphere_group<3, ARG>(P, T, s, best); break;
@@ -173,13 +173,13 @@ __device__ __forceinline__ uint32_t argmin_obstacle(const PlanView &P, float cx,
     uint32_t bo = 0;
     if (P.has_ground) { bv = cz - P.ground_z; bo = 0; }
     for (int o = 0; o < P.n_cyl; ++o) {
-        const float4 c = P.cyl_orig[o];
-        const GroupDev gr = P.groups[__float_as_int(c.w)];
+        const float4 c = ldg(P.cyl_orig, o);
+        const GroupDev gr = ldg(P.groups, __float_as_int(c.w));
         float val = cyl_combine(cyl_radial(cx, cy, c), fabsf(cz - gr.zc) - gr.hz);
         if (val < bv) { bv = val; bo = 1u + (uint32_t)o; }
     }
     for (int o = 0; o < P.n_box; ++o) {
-        float val = box_sd(cx, cy, cz, P.box[2 * o], P.box[2 * o + 1]);
+        float val = box_sd(cx, cy, cz, ldg(P.box, 2 * o), ldg(P.box, 2 * o + 1));
         if (val < bv) { bv = val; bo = 1u + (uint32_t)(P.n_cyl + o); }
     }
     if (P.sdf) {
@@ -199,7 +199,7 @@ __device__ __forceinline__ void interpolate(const PlanView &P, const float *Wb, 
 #pragma unroll
     for (int i = 0; i < CP_MAX_JOINTS; ++i) {
         if (i < P.n_joints) {
-            float a0 = p0[i], a1 = p1[i], a2 = p2[i], a3 = p3[i];
+            float a0 = ldg(p0, i), a1 = ldg(p1, i), a2 = ldg(p2, i), a3 = ldg(p3, i);
             q[i] = __builtin_fmaf(bw[0], a0, __builtin_fmaf(bw[1], a1, __builtin_fmaf(bw[2], a2, bw[3] * a3)));
             // differences centred on the second control point (the db sum to zero)
             dq[i] = __builtin_fmaf(db[0], a0 - a1, __builtin_fmaf(db[2], a2 - a1, db[3] * (a3 - a1)));
@@ -218,7 +218,7 @@ __device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[C
     for (int i = 0; i < CP_MAX_JOINTS; ++i) {
         if (i < P.n_joints) {
             sq = __builtin_fmaf(dq[i], dq[i], sq);
-            const JointDev J = P.joints[i];
+            const JointDev J = ldg(P.joints, i);
             float hi = fmaxf(q[i] - J.qmax, 0.0f), lo = fmaxf(J.qmin - q[i], 0.0f);
             lim = __builtin_fmaf(hi, hi, __builtin_fmaf(lo, lo, lim));
         }
@@ -244,6 +244,12 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     interpolate(P, Wb, k, q, dq, j, bw, db);
     float jp, jl;
     step_terms(P, q, dq, jp, jl);
+
+    // paths p0..p1 of this wave (contiguous)
+    const int64_t w = g / kWave;
+    const int64_t g_first = w * kWave;
+    const int64_t g_last = min(g_first + kWave - 1, N - 1);
+    const int p0 = (int)(g_first / P.ns), p1 = (int)(g_last / P.ns);
     Best best = config_distance<TAPE>(P, q);
     float dphi;
     float phi = hinge_value(P, best.d, dphi);
@@ -255,11 +261,7 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     float dk = best.d;
     if (!active) { c = 0.0f; dk = kInf; }
 
-    // per-path sums of this wave: paths p0..p1 are contiguous
-    const int64_t w = g / kWave;
-    const int64_t g_first = w * kWave;
-    const int64_t g_last = min(g_first + kWave - 1, N - 1);
-    const int p0 = (int)(g_first / P.ns), p1 = (int)(g_last / P.ns);
+    // per-path sums of this wave
     const int bl = active ? b : -1;
     for (int p = p0; p <= p1; ++p) {
         double s = wave_sum_d(bl == p ? (double)c : 0.0);
@@ -274,28 +276,31 @@ __global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__res
     eval_one<TAPE>(P, W, B, partial, slots, tape, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Many problems in one persistent launch: workgroups pull work items (problem,
-// first configuration) from a queue ordered costliest-problem first; an item
-// covers `rounds` x 256 consecutive configurations of one problem.  Every
-// configuration runs exactly the single-problem code, so results are bitwise
-// those of k_eval_fwd on each problem.  The counter is zeroed before launch.
-__global__ __launch_bounds__(256) void k_eval_persistent(const BatchProblem *__restrict__ probs,
-                                                         const int2 *__restrict__ items, int n_items, int rounds,
-                                                         int *__restrict__ counter) {
-    __shared__ int s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = s_item;
-        __syncthreads();
-        if (it >= n_items) break;
-        const int2 item = items[it];
-        const BatchProblem &bp = probs[item.x];
-        const PlanView P = bp.P;
-        const float *W = bp.O.W;
-        const int B = bp.O.B;
+// Many problems in one persistent launch: the work items (problem, first
+// configuration) are listed costliest problem first and dealt to the resident
+// workgroups round robin (workgroup w takes items w, w + G, w + 2G, ...); an
+// item covers `rounds` x 256 consecutive configurations of one problem.  With
+// hundreds of items per workgroup the deal balances to within one item.
+// Every configuration runs exactly the single-problem code, so results are
+// bitwise those of k_eval_fwd on each problem.  (The kernel has no atomics and
+// stores only through the restrict-qualified partial-sum base pointer, so the
+// compiler can prove the tables unchanged and keeps their wave-uniform reads
+// in scalar loads; a global work counter would turn them into vector loads.)
+__global__ __launch_bounds__(256, 6) void k_eval_persistent(const BatchProblem *__restrict__ probs,
+                                                         double2 *__restrict__ partial,
+                                                         const int2 *__restrict__ items, int n_items, int rounds) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = ldg(items, it);
+        const int p = item.x, g0 = item.y;
+        // only what the evaluation needs (the optimizer state stays in memory)
+        const BatchProblem *bp = probs + p;
+        const PlanView P = ldg(&bp->P);
+        const float *W = ldg(&bp->O.W);
+        const int B = ldg(&bp->O.B);
+        const int slots = ldg(&bp->slots);
+        double2 *part = partial + ldg(&bp->partial_off);
         for (int r = 0; r < rounds; ++r)
-            eval_one<false>(P, W, B, bp.partial, bp.slots, nullptr, (int64_t)item.y + r * 256 + threadIdx.x);
+            eval_one<false>(P, W, B, part, slots, nullptr, (int64_t)g0 + r * 256 + threadIdx.x);
     }
 }
 
@@ -324,10 +329,12 @@ __global__ __launch_bounds__(256) void k_eval_reduce(const double2 *__restrict__
 }
 
 // per-problem path sums of a batch: blockIdx.y = problem
-__global__ __launch_bounds__(256) void k_reduce_batched(const BatchProblem *__restrict__ probs) {
+__global__ __launch_bounds__(256) void k_reduce_batched(const BatchProblem *__restrict__ probs,
+                                                        const double2 *__restrict__ partial) {
     const BatchProblem &bp = probs[blockIdx.y];
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < bp.O.B) reduce_one(bp.partial, bp.slots, bp.P.ns, bp.P.margin, bp.O.cost, bp.O.min_dist, nullptr, b);
+    if (b < bp.O.B)
+        reduce_one(partial + bp.partial_off, bp.slots, bp.P.ns, bp.P.margin, bp.O.cost, bp.O.min_dist, nullptr, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -474,7 +481,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_eval_bwd(PlanView P, const floa
             gd[i] = P.jp_mode == CP_JP_SQUARED ? 2.0f * dq[i] : dq[i] * inv;
             gq[i] = 0.0f;
             if (i < n) {
-                const JointDev J = P.joints[i];
+                const JointDev J = ldg(P.joints, i);
                 float hi = fmaxf(q[i] - J.qmax, 0.0f), lo = fmaxf(J.qmin - q[i], 0.0f);
                 gq[i] = P.w_l * (2.0f * hi - 2.0f * lo);
             }
@@ -535,7 +542,7 @@ __global__ __launch_bounds__(256) void k_debug_fk(PlanView P, const float *__res
     Xf T;
     xf_identity(T);
     for (int f = 0; f <= P.n_joints; ++f) {
-        if (f > 0) xf_joint(T, P.joints[f - 1], pick(q, f - 1));
+        if (f > 0) xf_joint(T, ldg(P.joints, f - 1), pick(q, f - 1));
         if (frames) {
             float *fr = frames + ((size_t)i * (P.n_joints + 1) + f) * 12;
             for (int e = 0; e < 9; ++e) fr[e] = T.r[e];
@@ -595,18 +602,12 @@ hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *pa
     return hipGetLastError();
 }
 
-__global__ void k_zero_counter(int *counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
-}
-
-hipError_t launch_batch_eval(const BatchProblem *probs, int n, int max_B, const int2 *items, int n_items, int rounds,
-                             int grid, int *counter, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, counter);
+hipError_t launch_batch_eval(const BatchProblem *probs, double2 *partial, int n, int max_B, const int2 *items,
+                             int n_items, int rounds, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_eval_persistent, dim3(grid), dim3(256), 0, st, probs, partial, items, n_items, rounds);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_eval_persistent, dim3(grid), dim3(256), 0, st, probs, items, n_items, rounds, counter);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_batched, dim3((max_B + 255) / 256, n), dim3(256), 0, st, probs);
+    hipLaunchKernelGGL(k_reduce_batched, dim3((max_B + 255) / 256, n), dim3(256), 0, st, probs, partial);
     return hipGetLastError();
 }
 

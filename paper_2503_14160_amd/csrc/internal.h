@@ -70,6 +70,23 @@ struct PlanView {
 
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Load through a global-address-space pointer.  Table pointers that reach a
+// kernel through device memory (the batched launch) lose their address space,
+// which would turn wave-uniform table reads into vector flat loads; loading
+// through this helper keeps them scalar (and lane-varying ones global).
+// (The host compilation pass also instantiates these templates; it only needs
+// a well-formed body, so it gets the plain load.)
+template <class T>
+__device__ __forceinline__ T ldg(const T *p, int64_t i = 0) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    T v;
+    __builtin_memcpy(&v, (const __attribute__((address_space(1))) T *)p + i, sizeof(T));
+    return v;
+#else
+    return p[i];
+#endif
+}
+
 // signed distance of a vertical cylinder with radial term a and height term b
 // (exact Euclidean SDF of the solid: inside part + outside part)
 __device__ __forceinline__ float cyl_combine(float a, float b) {

@@ -48,7 +48,7 @@ struct OptView {
 struct BatchProblem {
     PlanView P;
     OptView O;
-    double2 *partial;  // per-wave partial sums of this problem
+    int64_t partial_off;  // this problem's per-wave partial sums in the batch's shared buffer
     int32_t slots;
     int32_t pad;
 };
@@ -59,14 +59,14 @@ struct BatchTuning {
     int32_t wg_per_cu;    // persistent workgroups per compute unit
 };
 
-// zero the work counter, persistent evaluation of every problem, per-problem path sums
-hipError_t launch_batch_eval(const BatchProblem *probs, int n, int max_B, const int2 *items, int n_items, int rounds,
-                             int grid, int *counter, hipStream_t st);
+// persistent evaluation of every problem, then per-problem path sums
+hipError_t launch_batch_eval(const BatchProblem *probs, double2 *partial, int n, int max_B, const int2 *items,
+                             int n_items, int rounds, int grid, hipStream_t st);
 // sampling of every problem (iteration counters unchanged)
 hipError_t launch_batch_sample(const BatchProblem *probs, int n, int max_B, hipStream_t st);
 // one optimizer iteration of every problem: sampling, evaluation, selection, update, factor
-hipError_t launch_batch_iteration(const BatchProblem *probs, int n, int max_B, const int2 *items, int n_items,
-                                  int rounds, int grid, int *counter, hipStream_t st);
+hipError_t launch_batch_iteration(const BatchProblem *probs, double2 *partial, int n, int max_B, const int2 *items,
+                                  int n_items, int rounds, int grid, hipStream_t st);
 
 hipError_t launch_sample(const PlanView &P, const OptView &O, hipStream_t st);
 hipError_t launch_select(const OptView &O, hipStream_t st);
