@@ -120,7 +120,7 @@ def bench_iterations(args, torch, cp, prob, with_roofline):
     achieved = flops / (eval_ms * 1e-3)
     # the same evaluation with every pair in full (no square-root skipping):
     # identical results, the brute-force reference for the roofline
-    plain = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, pair_filter=False)
+    plain = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, pair_filter=cp.PAIRS_ALL)
     plain.set_endpoints(prob.q_start, prob.q_goal)
     c_plain = torch.empty_like(cost)
     plain.eval_into(W, c_plain, md)

@@ -70,6 +70,9 @@ enum { CP_REVOLUTE = 0, CP_PRISMATIC = 1 };
 enum { CP_INTERP_BSPLINE = 0, CP_INTERP_LINEAR = 1 };
 enum { CP_JP_SQUARED = 0, CP_JP_L2 = 1 };
 enum { CP_HINGE_HARD = 0, CP_HINGE_SMOOTH = 1 };
+/* How much of the sphere-obstacle pair work is skipped; every mode returns
+ * bitwise the same distances (see cp_cost_params.pair_filter). */
+enum { CP_PAIRS_ALL = 0, CP_PAIRS_LANE = 1, CP_PAIRS_WAVE = 2 };
 
 /* tape entry of a checkpoint: (sphere << 16) | obstacle, where obstacle 0 is
  * the ground, 1..n_cyl the cylinders, n_cyl+1..n_cyl+n_box the boxes, and
@@ -136,9 +139,16 @@ typedef struct {
     float lambda_c;
     float w_c, w_l;
     int32_t max_B;    /* largest batch any call on this plan will pass */
-    /* 1: a sphere-cylinder pair whose squared axis distance shows it cannot
-     * lower the running minimum skips its square root (results are bitwise
-     * those of 0); 0: every pair is evaluated in full. */
+    /* CP_PAIRS_ALL: every sphere-obstacle pair is evaluated in full.
+     * CP_PAIRS_LANE: a sphere-cylinder pair whose squared axis distance shows
+     * that it cannot lower the running minimum skips its square root.
+     * CP_PAIRS_WAVE: the configurations of one hardware wave that belong to
+     * one path are bounded by a box per sphere; cylinders and boxes that no
+     * configuration in the box can come closer to than an upper bound of its
+     * minimum are skipped for the whole wave (waves that hold more than two
+     * paths use the lane filter).  Skipped pairs cannot lower any minimum, so
+     * distances, costs and argmin records are bitwise those of CP_PAIRS_ALL
+     * for any input whose coordinates stay within +-1e4 m. */
     int32_t pair_filter;
 } cp_cost_params;
 

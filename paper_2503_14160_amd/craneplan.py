@@ -26,6 +26,8 @@ _c_i32, _c_f32, _c_f64, _c_u64, _c_u32, _vp = (ctypes.c_int32, ctypes.c_float, c
                                                ctypes.c_uint32, ctypes.c_void_p)
 
 CP_OBS_SDF = 0xFFFF
+# cp_cost_params.pair_filter: every pair / lane-level square-root skip / wave-level culling
+PAIRS_ALL, PAIRS_LANE, PAIRS_WAVE = 0, 1, 2
 EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_endpoints", "cp_plan_n_checkpoints",
            "cp_eval_paths", "cp_eval_paths_backward", "cp_optimizer_create", "cp_optimizer_destroy",
            "cp_optimizer_step", "cp_optimizer_get_state", "cp_optimizer_set_state", "cp_optimizer_last",
@@ -163,11 +165,11 @@ def _fill_scene(s, scene, keep, sdf=None, sdf_spec=None):
         s.voxel = float(sdf_spec.voxel)
 
 
-def _fill_cost(c, cost, max_B, pair_filter=True):
+def _fill_cost(c, cost, max_B, pair_filter=PAIRS_WAVE):
     c.K, c.M, c.interp, c.jp_mode, c.hinge = cost.K, cost.M, cost.interp, cost.jp_mode, cost.hinge
     c.margin, c.lambda_c, c.w_c, c.w_l = cost.margin, cost.lambda_c, cost.w_c, cost.w_l
     c.max_B = int(max_B)
-    c.pair_filter = 1 if pair_filter else 0
+    c.pair_filter = int(pair_filter)
 
 
 def _fill_opt(o, opt, problem_id=0):
@@ -183,7 +185,7 @@ class Plan:
     """A crane, a scene and a path cost on one device (cp_plan_create)."""
 
     def __init__(self, robot, scene, cost, max_B: int, device: int = 0, sdf: Optional[torch.Tensor] = None,
-                 sdf_spec=None, pair_filter: bool = True):
+                 sdf_spec=None, pair_filter: int = PAIRS_WAVE):
         L = lib()
         self._keep = []
         r, s, c = _Robot(), _Scene(), _Cost()
@@ -351,7 +353,7 @@ class Batch:
     ``problems`` are objects with robot, scene, cost, opt, q_start, q_goal;
     problem i uses Philox problem id i."""
 
-    def __init__(self, problems, device: int = 0, pair_filter: bool = True):
+    def __init__(self, problems, device: int = 0, pair_filter: int = PAIRS_WAVE):
         L = lib()
         n = len(problems)
         self._keep = []

@@ -163,6 +163,8 @@ static int validate_plan_args(const cp_robot_desc *r, const cp_scene_desc *s, co
     if (c->interp != CP_INTERP_BSPLINE && c->interp != CP_INTERP_LINEAR) return fail(CP_ERR_INVALID_ARG, "bad interp");
     if (c->jp_mode != CP_JP_SQUARED && c->jp_mode != CP_JP_L2) return fail(CP_ERR_INVALID_ARG, "bad jp_mode");
     if (c->hinge != CP_HINGE_HARD && c->hinge != CP_HINGE_SMOOTH) return fail(CP_ERR_INVALID_ARG, "bad hinge");
+    if (c->pair_filter < CP_PAIRS_ALL || c->pair_filter > CP_PAIRS_WAVE)
+        return fail(CP_ERR_INVALID_ARG, "bad pair_filter");
     if (!(c->margin >= 0.0f) || (c->hinge == CP_HINGE_SMOOTH && !(c->margin > 0.0f)))
         return fail(CP_ERR_INVALID_ARG, "bad margin");
     if (!finite(c->lambda_c) || !finite(c->w_c) || !finite(c->w_l)) return fail(CP_ERR_INVALID_ARG, "bad weights");
@@ -290,7 +292,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         }
     }
     if (angle_start.empty()) angle_start.assign(kAngleBins, 0);
-    const int pair_filter = cost->pair_filter ? 1 : 0;
+    const int pair_filter = cost->pair_filter;
     std::vector<float4> box;
     for (int o = 0; o < p->n_box; ++o) {
         const float *y = scene->box + 6 * o;
@@ -603,6 +605,7 @@ struct cp_batch {
     int n_items = 0;
     double2 *d_partial = nullptr;     // per-wave partial sums of every problem, back to back
     BatchTuning tune{4, 4};
+    bool cull = false;                // wave-level culling (CP_PAIRS_WAVE)
     hipStream_t capture_stream = nullptr;
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 
@@ -658,11 +661,14 @@ int cp_batch_create(int32_t n, const cp_robot_desc *robots, const cp_scene_desc 
         if (opts[i].polish_steps > 0 && opts[i].polish_elites > 0)
             return fail(CP_ERR_INVALID_ARG, "polish is not supported in a batch");
         if (costs[i].max_B < opts[i].B) return fail(CP_ERR_SIZE, "cost max_B below opt B");
+        if (costs[i].pair_filter != costs[0].pair_filter)
+            return fail(CP_ERR_INVALID_ARG, "every problem of a batch needs the same pair_filter");
     }
     cp_batch *b = new (std::nothrow) cp_batch();
     if (!b) return fail(CP_ERR_NOMEM, "host allocation");
     b->device = device;
     b->n = n;
+    b->cull = costs[0].pair_filter == CP_PAIRS_WAVE;
     size_t qoff = 0;
     for (int i = 0; i < n; ++i) {
         cp_plan *p = nullptr;
@@ -734,8 +740,8 @@ int cp_batch_run(cp_batch *b, int32_t n_iters, cp_stream_t stream) {
         CP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "graph capture");
         hipError_t e = hipSuccess;
         for (int i = 0; i < n_iters && e == hipSuccess; ++i)
-            e = launch_batch_iteration(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds, b->grid(),
-                                       cs);
+            e = launch_batch_iteration(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items,
+                                       b->tune.rounds, b->grid(), b->cull, cs);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         if (e != hipSuccess) {
@@ -758,8 +764,8 @@ int cp_batch_run(cp_batch *b, int32_t n_iters, cp_stream_t stream) {
 int cp_batch_eval(cp_batch *b, cp_stream_t stream) {
     if (!b) return fail(CP_ERR_INVALID_ARG, "null batch");
     DeviceGuard g(b->device);
-    CP_HIP(launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds, b->grid(),
-                             (hipStream_t)stream),
+    CP_HIP(launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, b->tune.rounds,
+                             b->grid(), b->cull, (hipStream_t)stream),
            "batch eval");
     return CP_OK;
 }
@@ -845,14 +851,14 @@ int cp_batch_tune(cp_batch *b, const char *cache_path, cp_batch_tuning *chosen) 
                 if (rc) return rc;
                 hipError_t e = hipSuccess;
                 if (!warm) {
-                    e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r, b->grid(),
-                                          st);
+                    e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r,
+                                          b->grid(), b->cull, st);
                     warm = true;
                 }
                 if (e == hipSuccess) e = hipEventRecord(e0, st);
                 if (e == hipSuccess)
-                    e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r, b->grid(),
-                                          st);
+                    e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r,
+                                          b->grid(), b->cull, st);
                 if (e == hipSuccess) e = hipEventRecord(e1, st);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.0f;

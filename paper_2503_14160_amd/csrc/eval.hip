@@ -29,15 +29,19 @@ __device__ __forceinline__ void cyl_chunk(const float (&cx)[G], const float (&cy
 
 // Same result with the square root taken only where it can matter: a pair
 // lowers the running minimum a only if rho - R < a, which needs
-// rho^2 < (a + R_max)^2.  The threshold carries 1e-4 m of slack so that
-// rounding never hides a pair that would lower a; pairs that are skipped
-// cannot change the minimum, so the result is bitwise that of cyl_chunk.
+// rho^2 < (a + R_max)^2.  The threshold carries 1e-4 m plus a relative 1e-6
+// of slack, far above the rounding of the threshold and of the square root
+// (both a few 1e-7 relative), so rounding never hides a pair that would lower
+// a; pairs that are skipped cannot change the minimum, so the result is
+// bitwise that of cyl_chunk.
 // The test is a wave-wide ballot (compares OR-ed in scalar registers) and the
 // candidate block runs for the whole wave when any lane has a candidate:
 // lanes without one only recompute values that cannot lower their minimum.
 // Per skipped pair this costs two subtractions, a multiply, a multiply-add and
 // a compare, all in 32-bit (VOP2/VOPC) encodings, instead of the same four
 // operations plus a square root, a subtraction and a minimum.
+constexpr float kRelSlack = 1.000001f;
+
 template <int G>
 __device__ __forceinline__ void cyl_chunk_filtered(const float (&cx)[G], const float (&cy)[G], const float4 *c,
                                                    float (&a)[G], float (&thr)[G], float reach) {
@@ -59,7 +63,7 @@ __device__ __forceinline__ void cyl_chunk_filtered(const float (&cx)[G], const f
             float r0 = fsqrt(d2[s][0]) - cc[0].z, r1 = fsqrt(d2[s][1]) - cc[1].z;
             float r2 = fsqrt(d2[s][2]) - cc[2].z, r3 = fsqrt(d2[s][3]) - cc[3].z;
             a[s] = fminf(a[s], fminf(fminf(r0, r1), fminf(r2, r3)));
-            float t = fmaxf(a[s] + reach, 0.0f);
+            float t = fmaxf(a[s] + reach, 0.0f) * kRelSlack;
             thr[s] = t * t;
         }
     }
@@ -110,6 +114,134 @@ __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&
     }
 }
 
+// Wave-level culling.  The configurations of a wave are consecutive
+// checkpoints of at most NS paths, so each sphere's centres over the lanes of
+// one path (a segment) lie in a small box.  Per sphere and segment:
+//  1. the box [xl, xh] x [yl, yh] (wave reductions);
+//  2. U = min over cylinders o of (farthest box point to o's axis - R_o), an
+//     upper bound of every segment lane's final minimum a;
+//  3. a cylinder is a candidate only if the nearest box point comes within
+//     U + R_o (+ slack) of its axis; the others cannot lower any lane's a.
+// Steps 2 and 3 put one cylinder on each lane (64 per pass), and the
+// candidates are then evaluated by every lane with the same arithmetic as the
+// all-pairs loop.  Boxes are culled the same way against the wave maximum of
+// the running minimum v, with the 3-D gap between the two boxes as the lower
+// bound.  The per-axis bounds are exact in floating point (rounding is
+// monotone, so the nearest box point's squared distance never exceeds a
+// lane's and the farthest one's is never below it); only the square roots and
+// the threshold carry rounding, covered by 1e-4 m plus 1e-6 relative slack.
+// Results are therefore bitwise those of the all-pairs evaluation.
+constexpr float kCullAbs = 1e-4f;
+constexpr float kCullRel = 1e-6f;
+
+// The minima are exact for the lanes with `in` set (one segment); the other
+// lanes' results are unspecified.  With `all` set (a non-finite centre in the
+// segment, where the box bounds do not hold) every obstacle is a candidate.
+template <int G>
+__device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const float (&cx)[G], const float (&cy)[G],
+                                                      const float (&cz)[G], bool in, bool all, float (&v)[G]) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    float xl[G], xh[G], yl[G], yh[G];
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+        xl[s] = wave_min_u(in ? cx[s] : kInf);
+        xh[s] = wave_max_u(in ? cx[s] : -kInf);
+        yl[s] = wave_min_u(in ? cy[s] : kInf);
+        yh[s] = wave_max_u(in ? cy[s] : -kInf);
+    }
+#pragma unroll
+    for (int s = 0; s < G; ++s) v[s] = P.has_ground ? cz[s] - P.ground_z : kInf;
+    const float4 kFar = make_float4(1e15f, 1e15f, 0.0f, 0.0f);
+    for (int g = 0; g < P.n_groups; ++g) {
+        const GroupDev gr = ldg(P.groups, g);
+        const float4 *c = P.cyl + gr.start;
+        // upper bounds U
+        float u[G];
+#pragma unroll
+        for (int s = 0; s < G; ++s) u[s] = kInf;
+        for (int o0 = 0; o0 < (all ? 0 : gr.count); o0 += kWave) {
+            float4 cc = ldg(c, min(o0 + lane, gr.count - 1));
+            if (o0 + lane >= gr.count) cc = kFar;
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                const float fx = fmaxf(fabsf(xl[s] - cc.x), fabsf(xh[s] - cc.x));
+                const float fy = fmaxf(fabsf(yl[s] - cc.y), fabsf(yh[s] - cc.y));
+                u[s] = fminf(u[s], fsqrt(__builtin_fmaf(fx, fx, fy * fy)) - cc.z);
+            }
+        }
+        float us[G];  // U + slack
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
+            const float U = wave_min_u(u[s]);
+            us[s] = U + (kCullAbs + kCullRel * (fabsf(U) + 2.0f * gr.rmax));
+        }
+        // candidates, evaluated exactly
+        float a[G];
+#pragma unroll
+        for (int s = 0; s < G; ++s) a[s] = kInf;
+        for (int o0 = 0; o0 < gr.count; o0 += kWave) {
+            float4 cc = ldg(c, min(o0 + lane, gr.count - 1));
+            if (o0 + lane >= gr.count) cc = kFar;
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                const float ex = fmaxf(fmaxf(xl[s] - cc.x, cc.x - xh[s]), 0.0f);
+                const float ey = fmaxf(fmaxf(yl[s] - cc.y, cc.y - yh[s]), 0.0f);
+                const float n2 = __builtin_fmaf(ex, ex, ey * ey);
+                const float th = fmaxf(us[s] + cc.z, 0.0f);
+                const bool cand = all || n2 < th * th;
+                uint64_t m = __builtin_amdgcn_ballot_w64(cand);
+                while (m) {
+                    const int l = (int)__builtin_ctzll(m);
+                    m &= m - 1;
+                    const float ox = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cc.x), l));
+                    const float oy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cc.y), l));
+                    const float R = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cc.z), l));
+                    const float dx = cx[s] - ox, dy = cy[s] - oy;
+                    a[s] = fmin_q(a[s], fsqrt(__builtin_fmaf(dx, dx, dy * dy)) - R);
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], cyl_combine(a[s], fabsf(cz[s] - gr.zc) - gr.hz));
+    }
+    if (P.n_box > 0) {
+        float zl[G], zh[G], vs[G];  // vs: wave maximum of v + slack
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
+            zl[s] = wave_min_u(in ? cz[s] : kInf);
+            zh[s] = wave_max_u(in ? cz[s] : -kInf);
+            const float V = wave_max_u(in ? v[s] : -kInf);
+            vs[s] = V + (kCullAbs + kCullRel * fabsf(V));
+        }
+        for (int o0 = 0; o0 < P.n_box; o0 += kWave) {
+            const int ob = min(o0 + lane, P.n_box - 1);
+            const float4 b0 = ldg(P.box, 2 * ob), b1 = ldg(P.box, 2 * ob + 1);
+            const bool real = o0 + lane < P.n_box;
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                // per axis: distance of the box of centres from the obstacle's slab
+                const float gx = fmaxf(fmaxf(fmaxf(xl[s] - b0.x, b0.x - xh[s]), 0.0f) - b0.w, 0.0f);
+                const float gy = fmaxf(fmaxf(fmaxf(yl[s] - b0.y, b0.y - yh[s]), 0.0f) - b1.x, 0.0f);
+                const float gz = fmaxf(fmaxf(fmaxf(zl[s] - b0.z, b0.z - zh[s]), 0.0f) - b1.y, 0.0f);
+                const float g2 = __builtin_fmaf(gx, gx, __builtin_fmaf(gy, gy, gz * gz));
+                const float th = fmaxf(vs[s], 0.0f);
+                const bool cand = all || g2 <= 0.0f || g2 < th * th;
+                uint64_t m = __builtin_amdgcn_ballot_w64(cand && real);
+                while (m) {
+                    const int o = o0 + (int)__builtin_ctzll(m);
+                    m &= m - 1;
+                    const float4 c0 = ldg(P.box, 2 * o), c1 = ldg(P.box, 2 * o + 1);
+                    v[s] = fminf(v[s], box_sd(cx[s], cy[s], cz[s], c0, c1));
+                }
+            }
+        }
+    }
+    if (P.sdf) {
+#pragma unroll
+        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], sdf_query(P, cx[s], cy[s], cz[s], nullptr));
+    }
+}
+
 // Lane state of the running minimum over spheres.
 struct Best {
     float d;
@@ -118,15 +250,39 @@ struct Best {
     float cx, cy, cz;
 };
 
-template <int G, bool ARG>
-__device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int s0, Best &best) {
+// How the lanes of a wave split into paths for the wave-level culling: n
+// segments (1 or 2) and this lane's segment (-1: result unused).
+struct WaveSeg {
+    int n;
+    int lane;
+};
+
+template <int G, bool ARG, bool CULL>
+__device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int s0, Best &best, WaveSeg ws) {
     float cx[G], cy[G], cz[G], v[G];
+    bool finite = true;
 #pragma unroll
     for (int i = 0; i < G; ++i) {
         const SphereDev sp = ldg(P.spheres, s0 + i);
         xf_point(T, sp.lx, sp.ly, sp.lz, cx[i], cy[i], cz[i]);
+        finite = finite && fabsf(cx[i]) < kInf && fabsf(cy[i]) < kInf && fabsf(cz[i]) < kInf;
     }
-    spheres_min_sd<G>(P, cx, cy, cz, v);
+    if (CULL) {
+        // the box bounds hold only for finite centres: a wave with a
+        // non-finite one (from non-finite waypoints) evaluates every pair
+        const bool all = __builtin_amdgcn_ballot_w64(ws.lane >= 0 && !finite) != 0;
+        // one pass per path segment (a wave holding the end of one path and
+        // the start of the next bounds the two separately)
+        spheres_min_sd_culled<G>(P, cx, cy, cz, ws.n == 2 ? ws.lane == 0 : ws.lane >= 0, all, v);
+        if (ws.n == 2) {
+            float vt[G];
+            spheres_min_sd_culled<G>(P, cx, cy, cz, ws.lane == 1, all, vt);
+#pragma unroll
+            for (int i = 0; i < G; ++i) v[i] = ws.lane == 1 ? vt[i] : v[i];
+        }
+    } else {
+        spheres_min_sd<G>(P, cx, cy, cz, v);
+    }
 #pragma unroll
     for (int i = 0; i < G; ++i) {
         const SphereDev sp = ldg(P.spheres, s0 + i);
@@ -143,8 +299,8 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
 }
 
 // d(q) for one configuration; with ARG also the minimising sphere and its centre.
-template <bool ARG>
-__device__ __forceinline__ Best config_distance(const PlanView &P, const float (&q)[CP_MAX_JOINTS]) {
+template <bool ARG, bool CULL>
+__device__ __forceinline__ Best config_distance(const PlanView &P, const float (&q)[CP_MAX_JOINTS], WaveSeg ws) {
     Best best;
     best.d = kInf; best.s = 0x7fffffff; best.r = 0.0f;
     best.cx = best.cy = best.cz = 0.0f;
@@ -154,11 +310,11 @@ __device__ __forceinline__ Best config_distance(const PlanView &P, const float (
         if (f > 0) xf_joint(T, ldg(P.joints, f - 1), pick(q, f - 1));
         const int s1 = ldg(P.frame_start, f + 1);
         int s = ldg(P.frame_start, f);
-        for (; s + 4 <= s1; s += 4) sphere_group<4, ARG>(P, T, s, best);
+        for (; s + 4 <= s1; s += 4) sphere_group<4, ARG, CULL>(P, T, s, best, ws);
         switch (s1 - s) {
-            case 3: sphere_group<3, ARG>(P, T, s, best); break;
-            case 2: sphere_group<2, ARG>(P, T, s, best); break;
-            case 1: sphere_group<1, ARG>(P, T, s, best); break;
+            case 3: sphere_group<3, ARG, CULL>(P, T, s, best, ws); break;
+            case 2: sphere_group<2, ARG, CULL>(P, T, s, best, ws); break;
+            case 1: sphere_group<1, ARG, CULL>(P, T, s, best, ws); break;
             default: break;
         }
     }
@@ -229,7 +385,7 @@ __device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[C
 
 // One configuration per lane: g is the flattened (path, checkpoint) index;
 // all 64 lanes of a wave hold consecutive g (some may lie past the end).
-template <bool TAPE>
+template <bool TAPE, bool CULL>
 __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restrict__ W, int B,
                                          double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape,
                                          int64_t g) {
@@ -245,12 +401,17 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     float jp, jl;
     step_terms(P, q, dq, jp, jl);
 
-    // paths p0..p1 of this wave (contiguous)
-    const int64_t w = g / kWave;
-    const int64_t g_first = w * kWave;
+    // paths p0..p1 of this wave (contiguous; wave-uniform, kept in scalar registers)
+    const int64_t g_first = uniform_i64(g & ~(int64_t)(kWave - 1));
+    const int64_t w = g_first / kWave;
     const int64_t g_last = min(g_first + kWave - 1, N - 1);
     const int p0 = (int)(g_first / P.ns), p1 = (int)(g_last / P.ns);
-    Best best = config_distance<TAPE>(P, q);
+    // (a wave over more than two paths, only when a path has fewer than 64
+    // checkpoints, is bounded as one segment: still exact, culls less)
+    WaveSeg ws;
+    ws.n = p1 - p0 == 1 ? 2 : 1;
+    ws.lane = active ? (ws.n == 2 ? b - p0 : 0) : -1;
+    Best best = config_distance<TAPE, CULL>(P, q, ws);
     float dphi;
     float phi = hinge_value(P, best.d, dphi);
     float c = __builtin_fmaf(P.w_c, phi, __builtin_fmaf(P.w_l, jl, jp));
@@ -270,10 +431,10 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     }
 }
 
-template <bool TAPE>
+template <bool TAPE, bool CULL>
 __global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__restrict__ W, int B,
                                                   double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape) {
-    eval_one<TAPE>(P, W, B, partial, slots, tape, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    eval_one<TAPE, CULL>(P, W, B, partial, slots, tape, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Many problems in one persistent launch: the work items (problem, first
@@ -286,7 +447,8 @@ __global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__res
 // stores only through the restrict-qualified partial-sum base pointer, so the
 // compiler can prove the tables unchanged and keeps their wave-uniform reads
 // in scalar loads; a global work counter would turn them into vector loads.)
-__global__ __launch_bounds__(256, 6) void k_eval_persistent(const BatchProblem *__restrict__ probs,
+template <bool CULL>
+__global__ __launch_bounds__(256, CULL ? 4 : 6) void k_eval_persistent(const BatchProblem *__restrict__ probs,
                                                          double2 *__restrict__ partial,
                                                          const int2 *__restrict__ items, int n_items, int rounds) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -300,7 +462,7 @@ __global__ __launch_bounds__(256, 6) void k_eval_persistent(const BatchProblem *
         const int slots = ldg(&bp->slots);
         double2 *part = partial + ldg(&bp->partial_off);
         for (int r = 0; r < rounds; ++r)
-            eval_one<false>(P, W, B, part, slots, nullptr, (int64_t)g0 + r * 256 + threadIdx.x);
+            eval_one<false, CULL>(P, W, B, part, slots, nullptr, (int64_t)g0 + r * 256 + threadIdx.x);
     }
 }
 
@@ -449,7 +611,7 @@ __device__ __forceinline__ void collision_grad(const PlanView &P, const float (&
 constexpr int kBwdThreads = 256;
 constexpr int kMaxCtrl = CP_MAX_K + 6;
 
-template <bool TAPE>
+template <bool TAPE, bool CULL>
 __global__ __launch_bounds__(kBwdThreads) void k_eval_bwd(PlanView P, const float *__restrict__ W, int B,
                                                           const uint32_t *__restrict__ tape,
                                                           const float *__restrict__ grad_cost,
@@ -493,7 +655,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_eval_bwd(PlanView P, const floa
             s_orig = (int)(t >> 16);
             o = t & 0xFFFFu;
         } else {
-            Best best = config_distance<true>(P, q);
+            // a block's lanes all hold checkpoints of path b (inactive ones repeat the last)
+            WaveSeg ws;
+            ws.n = 1;
+            ws.lane = 0;
+            Best best = config_distance<true, CULL>(P, q, ws);
             s_orig = best.s;
             o = argmin_obstacle(P, best.cx, best.cy, best.cz);
         }
@@ -560,6 +726,7 @@ __global__ __launch_bounds__(256) void k_debug_fk(PlanView P, const float *__res
     }
 }
 
+template <bool CULL>
 __global__ __launch_bounds__(256) void k_debug_configs(PlanView P, const float *__restrict__ Q, int N,
                                                        float *__restrict__ dist, uint32_t *__restrict__ arg) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -567,7 +734,11 @@ __global__ __launch_bounds__(256) void k_debug_configs(PlanView P, const float *
     float q[CP_MAX_JOINTS];
 #pragma unroll
     for (int jj = 0; jj < CP_MAX_JOINTS; ++jj) q[jj] = jj < P.n_joints ? Q[(size_t)ii * P.n_joints + jj] : 0.0f;
-    Best best = config_distance<true>(P, q);
+    // unrelated configurations: one segment (culling still exact, rarely useful)
+    WaveSeg ws;
+    ws.n = 1;
+    ws.lane = 0;
+    Best best = config_distance<true, CULL>(P, q, ws);
     uint32_t o = argmin_obstacle(P, best.cx, best.cy, best.cz);
     if (i < N) {
         dist[i] = best.d;
@@ -591,10 +762,15 @@ hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *pa
     const int64_t N = (int64_t)B * P.ns;
     const int slots = eval_slots(P.ns);
     const dim3 grid((unsigned)((N + 255) / 256));
-    if (tape)
-        hipLaunchKernelGGL(k_eval_fwd<true>, grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
+    const bool cull = P.pair_filter == CP_PAIRS_WAVE;
+    if (tape && cull)
+        hipLaunchKernelGGL((k_eval_fwd<true, true>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
+    else if (tape)
+        hipLaunchKernelGGL((k_eval_fwd<true, false>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
+    else if (cull)
+        hipLaunchKernelGGL((k_eval_fwd<false, true>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
     else
-        hipLaunchKernelGGL(k_eval_fwd<false>, grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
+        hipLaunchKernelGGL((k_eval_fwd<false, false>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_eval_reduce, dim3((B + 255) / 256), dim3(256), 0, st, partial, slots, B, P.ns, P.margin,
@@ -603,8 +779,13 @@ hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *pa
 }
 
 hipError_t launch_batch_eval(const BatchProblem *probs, double2 *partial, int n, int max_B, const int2 *items,
-                             int n_items, int rounds, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_eval_persistent, dim3(grid), dim3(256), 0, st, probs, partial, items, n_items, rounds);
+                             int n_items, int rounds, int grid, bool cull, hipStream_t st) {
+    if (cull)
+        hipLaunchKernelGGL(k_eval_persistent<true>, dim3(grid), dim3(256), 0, st, probs, partial, items, n_items,
+                           rounds);
+    else
+        hipLaunchKernelGGL(k_eval_persistent<false>, dim3(grid), dim3(256), 0, st, probs, partial, items, n_items,
+                           rounds);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_batched, dim3((max_B + 255) / 256, n), dim3(256), 0, st, probs, partial);
@@ -614,9 +795,14 @@ hipError_t launch_batch_eval(const BatchProblem *probs, double2 *partial, int n,
 hipError_t launch_eval_bwd(const PlanView &P, const float *W, int B, const uint32_t *tape, const float *grad_cost,
                            float *grad_W, hipStream_t st) {
     if (tape)
-        hipLaunchKernelGGL(k_eval_bwd<true>, dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost, grad_W);
+        hipLaunchKernelGGL((k_eval_bwd<true, false>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
+                           grad_W);
+    else if (P.pair_filter == CP_PAIRS_WAVE)
+        hipLaunchKernelGGL((k_eval_bwd<false, true>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
+                           grad_W);
     else
-        hipLaunchKernelGGL(k_eval_bwd<false>, dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost, grad_W);
+        hipLaunchKernelGGL((k_eval_bwd<false, false>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
+                           grad_W);
     return hipGetLastError();
 }
 
@@ -626,7 +812,10 @@ hipError_t launch_debug_fk(const PlanView &P, const float *Q, int N, float *cent
 }
 
 hipError_t launch_debug_configs(const PlanView &P, const float *Q, int N, float *dist, uint32_t *arg, hipStream_t st) {
-    hipLaunchKernelGGL(k_debug_configs, dim3((N + 255) / 256), dim3(256), 0, st, P, Q, N, dist, arg);
+    if (P.pair_filter == CP_PAIRS_WAVE)
+        hipLaunchKernelGGL(k_debug_configs<true>, dim3((N + 255) / 256), dim3(256), 0, st, P, Q, N, dist, arg);
+    else
+        hipLaunchKernelGGL(k_debug_configs<false>, dim3((N + 255) / 256), dim3(256), 0, st, P, Q, N, dist, arg);
     return hipGetLastError();
 }
 

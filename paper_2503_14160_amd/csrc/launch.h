@@ -59,14 +59,15 @@ struct BatchTuning {
     int32_t wg_per_cu;    // persistent workgroups per compute unit
 };
 
-// persistent evaluation of every problem, then per-problem path sums
+// persistent evaluation of every problem, then per-problem path sums (cull:
+// every problem uses the wave-level culling)
 hipError_t launch_batch_eval(const BatchProblem *probs, double2 *partial, int n, int max_B, const int2 *items,
-                             int n_items, int rounds, int grid, hipStream_t st);
+                             int n_items, int rounds, int grid, bool cull, hipStream_t st);
 // sampling of every problem (iteration counters unchanged)
 hipError_t launch_batch_sample(const BatchProblem *probs, int n, int max_B, hipStream_t st);
 // one optimizer iteration of every problem: sampling, evaluation, selection, update, factor
 hipError_t launch_batch_iteration(const BatchProblem *probs, double2 *partial, int n, int max_B, const int2 *items,
-                                  int n_items, int rounds, int grid, hipStream_t st);
+                                  int n_items, int rounds, int grid, bool cull, hipStream_t st);
 
 hipError_t launch_sample(const PlanView &P, const OptView &O, hipStream_t st);
 hipError_t launch_select(const OptView &O, hipStream_t st);

@@ -502,10 +502,11 @@ hipError_t launch_batch_sample(const BatchProblem *probs, int n, int max_B, hipS
 }
 
 hipError_t launch_batch_iteration(const BatchProblem *probs, double2 *partial, int n, int max_B, const int2 *items,
-                                  int n_items, int rounds, int grid, hipStream_t st) {
+                                  int n_items, int rounds, int grid, bool cull, hipStream_t st) {
     hipError_t e = launch_batch_sample(probs, n, max_B, st);
     if (e != hipSuccess) return e;
-    if ((e = launch_batch_eval(probs, partial, n, max_B, items, n_items, rounds, grid, st)) != hipSuccess) return e;
+    if ((e = launch_batch_eval(probs, partial, n, max_B, items, n_items, rounds, grid, cull, st)) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_select_batched, dim3(n), dim3(kSelThreads), 0, st, probs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_update_batched, dim3(n), dim3(kUpdThreads), 0, st, probs);
