@@ -72,6 +72,8 @@ struct cp_plan {
     SphereDev *d_spheres = nullptr;
     int32_t *d_frame_start = nullptr;
     float4 *d_cyl = nullptr;
+    float4 *d_cyl_cell = nullptr;
+    int32_t *d_cell_start = nullptr;
     GroupDev *d_groups = nullptr;
     int32_t *d_angle_start = nullptr;
     float4 *d_cyl_orig = nullptr;
@@ -82,8 +84,8 @@ struct cp_plan {
 
     ~cp_plan() {
         DeviceGuard g(device);
-        void *bufs[] = {d_joints, d_spheres, d_frame_start, d_cyl, d_groups, d_angle_start, d_cyl_orig, d_box, d_qs, d_qg,
-                        d_partial};
+        void *bufs[] = {d_joints, d_spheres, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_groups,
+                        d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
     }
@@ -257,9 +259,9 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     }
     // within a group, cylinders sorted by polar angle about the z axis, with a
     // per-azimuth-bin scan start (one bin behind, aligned to the chunk of 4)
-    std::vector<float4> cyl;
+    std::vector<float4> cyl, cyl_cell;
     std::vector<GroupDev> groups;
-    std::vector<int32_t> angle_start;
+    std::vector<int32_t> angle_start, cell_start;
     const double kPi = 3.14159265358979323846;
     for (size_t g = 0; g < ext.size(); ++g) {
         GroupDev G{};
@@ -282,6 +284,40 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         G.zc = (float)(0.5 * ((double)ext[g].first + (double)ext[g].second));
         G.hz = (float)(0.5 * ((double)ext[g].second - (double)ext[g].first));
         G.rmax = rmax;
+        // the grid: about three cylinder centres per cell, at most 256 cells per axis
+        double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+        for (int o : members[g]) {
+            const float *y = scene->cyl + 5 * o;
+            x0 = std::min(x0, (double)y[0]); x1 = std::max(x1, (double)y[0]);
+            y0 = std::min(y0, (double)y[1]); y1 = std::max(y1, (double)y[1]);
+        }
+        const double gw = x1 - x0, gd = y1 - y0;
+        double h = std::sqrt(std::max(gw * gd, 1e-6) * 3.0 / (double)members[g].size());
+        h = std::max({h, 1e-3, gw / 255.0, gd / 255.0});
+        const int nx = std::min(256, (int)std::floor(gw / h) + 1), ny = std::min(256, (int)std::floor(gd / h) + 1);
+        std::vector<std::pair<int, int>> by_cell;  // (cell, caller index), stable in caller order
+        for (int o : members[g]) {
+            const float *y = scene->cyl + 5 * o;
+            const int ix = std::min(nx - 1, std::max(0, (int)std::floor(((double)y[0] - x0) / h)));
+            const int iy = std::min(ny - 1, std::max(0, (int)std::floor(((double)y[1] - y0) / h)));
+            by_cell.emplace_back(iy * nx + ix, o);
+        }
+        std::stable_sort(by_cell.begin(), by_cell.end(),
+                         [](const std::pair<int, int> &a, const std::pair<int, int> &b) { return a.first < b.first; });
+        G.gx0 = (float)x0; G.gy0 = (float)y0;
+        G.gh = (float)h; G.ginv = (float)(1.0 / h);
+        G.gnx = nx; G.gny = ny;
+        G.gcell = (int)cell_start.size();
+        size_t next = 0;
+        for (int c = 0; c <= nx * ny; ++c) {
+            while (next < by_cell.size() && by_cell[next].first < c) ++next;
+            cell_start.push_back(G.start + (int)next);
+        }
+        for (const auto &co : by_cell) {
+            const float *y = scene->cyl + 5 * co.second;
+            cyl_cell.push_back(make_float4(y[0], y[1], y[2], 0.0f));
+        }
+        while (cyl_cell.size() < cyl.size()) cyl_cell.push_back(make_float4(1e15f, 1e15f, 0.0f, 0.0f));
         groups.push_back(G);
         for (int b = 0; b < kAngleBins; ++b) {
             const double lo = -kPi + (b - 1) * (2.0 * kPi / kAngleBins);
@@ -292,6 +328,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         }
     }
     if (angle_start.empty()) angle_start.assign(kAngleBins, 0);
+    if (cell_start.empty()) cell_start.assign(1, 0);
     const int pair_filter = cost->pair_filter;
     std::vector<float4> box;
     for (int o = 0; o < p->n_box; ++o) {
@@ -303,6 +340,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     hipError_t e;
     if ((e = upload(&p->d_joints, p->joints)) != hipSuccess || (e = upload(&p->d_spheres, spheres)) != hipSuccess ||
         (e = upload(&p->d_frame_start, frame_start)) != hipSuccess || (e = upload(&p->d_cyl, cyl)) != hipSuccess ||
+        (e = upload(&p->d_cyl_cell, cyl_cell)) != hipSuccess || (e = upload(&p->d_cell_start, cell_start)) != hipSuccess ||
         (e = upload(&p->d_groups, groups)) != hipSuccess || (e = upload(&p->d_angle_start, angle_start)) != hipSuccess ||
         (e = upload(&p->d_cyl_orig, cyl_orig)) != hipSuccess ||
         (e = upload(&p->d_box, box)) != hipSuccess || (e = upload(&p->d_qs, hold)) != hipSuccess ||
@@ -325,6 +363,8 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     v.joints = p->d_joints; v.spheres = p->d_spheres; v.frame_start = p->d_frame_start;
     v.cyl = p->d_cyl; v.groups = p->d_groups; v.cyl_orig = p->d_cyl_orig; v.box = p->d_box;
     v.angle_start = p->d_angle_start;
+    v.cyl_cell = p->d_cyl_cell;
+    v.cell_start = p->d_cell_start;
     v.pair_filter = pair_filter;
     v.qs = p->d_qs; v.qg = p->d_qg;
     v.sdf = scene->d_sdf;

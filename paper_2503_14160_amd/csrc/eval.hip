@@ -134,6 +134,49 @@ __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&
 constexpr float kCullAbs = 1e-4f;
 constexpr float kCullRel = 1e-6f;
 
+// Grid cell range [c0, c1] along one axis covering the interval [x0, x1]
+// (clamped to the grid; widened by a hair so that a centre on a cell border,
+// binned in double precision on the host, is never missed).
+__device__ __forceinline__ void cell_span(float x0, float x1, float g0, float ginv, int n, int &c0, int &c1) {
+    const float slack = 1e-3f + 4e-7f * (fabsf(x0) + fabsf(x1) + fabsf(g0)) * ginv;
+    const float f0 = floorf((x0 - g0) * ginv - slack), f1 = floorf((x1 - g0) * ginv + slack);
+    c0 = (int)fminf(fmaxf(f0, 0.0f), (float)(n - 1));
+    c1 = (int)fminf(fmaxf(f1, 0.0f), (float)(n - 1));
+}
+
+// Calls f(idx) once per 64 cylinders of the cells overlapping
+// [x0, x1] x [y0, y1] (every cell when `whole` is set or a bound is not
+// finite); on each call lane l holds the cyl_cell index of one cylinder or -1.
+// A row's cells are contiguous in cyl_cell, so the region is a list of row
+// runs, packed onto the lanes in order.
+template <class F>
+__device__ __forceinline__ void for_cells(const PlanView &P, const GroupDev &gr, float x0, float x1, float y0,
+                                          float y1, bool whole, int lane, F &&f) {
+    int cx0 = 0, cx1 = gr.gnx - 1, cy0 = 0, cy1 = gr.gny - 1;
+    if (!whole && fabsf(x0) < 1e30f && fabsf(x1) < 1e30f && fabsf(y0) < 1e30f && fabsf(y1) < 1e30f) {
+        cell_span(x0, x1, gr.gx0, gr.ginv, gr.gnx, cx0, cx1);
+        cell_span(y0, y1, gr.gy0, gr.ginv, gr.gny, cy0, cy1);
+    }
+    cx0 = __builtin_amdgcn_readfirstlane(cx0);
+    cx1 = __builtin_amdgcn_readfirstlane(cx1);
+    cy0 = __builtin_amdgcn_readfirstlane(cy0);
+    cy1 = __builtin_amdgcn_readfirstlane(cy1);
+    const int32_t *cs = P.cell_start + gr.gcell;
+    const int nx = gr.gnx;
+    int total = 0;
+    for (int iy = cy0; iy <= cy1; ++iy) total += ldg(cs, iy * nx + cx1 + 1) - ldg(cs, iy * nx + cx0);
+    for (int t0 = 0; t0 < total; t0 += kWave) {
+        int idx = -1, acc = 0;
+        for (int iy = cy0; iy <= cy1 && acc < t0 + kWave; ++iy) {
+            const int s0 = ldg(cs, iy * nx + cx0), len = ldg(cs, iy * nx + cx1 + 1) - s0;
+            const int t = t0 + lane - acc;
+            if (t >= 0 && t < len) idx = s0 + t;
+            acc += len;
+        }
+        f(idx);
+    }
+}
+
 // The minima are exact for the lanes with `in` set (one segment); the other
 // lanes' results are unspecified.  With `all` set (a non-finite centre in the
 // segment, where the box bounds do not hold) every obstacle is a candidate.
@@ -151,44 +194,57 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
     }
 #pragma unroll
     for (int s = 0; s < G; ++s) v[s] = P.has_ground ? cz[s] - P.ground_z : kInf;
+    // union of the spheres' boxes: the grid region is taken around it
+    float bxl = xl[0], bxh = xh[0], byl = yl[0], byh = yh[0];
+#pragma unroll
+    for (int s = 1; s < G; ++s) {
+        bxl = fminf(bxl, xl[s]); bxh = fmaxf(bxh, xh[s]);
+        byl = fminf(byl, yl[s]); byh = fmaxf(byh, yh[s]);
+    }
     const float4 kFar = make_float4(1e15f, 1e15f, 0.0f, 0.0f);
     for (int g = 0; g < P.n_groups; ++g) {
         const GroupDev gr = ldg(P.groups, g);
-        const float4 *c = P.cyl + gr.start;
-        // upper bounds U
+        // upper bounds U from the cylinders of the cells within one cell edge
         float u[G];
 #pragma unroll
         for (int s = 0; s < G; ++s) u[s] = kInf;
-        for (int o0 = 0; o0 < (all ? 0 : gr.count); o0 += kWave) {
-            float4 cc = ldg(c, min(o0 + lane, gr.count - 1));
-            if (o0 + lane >= gr.count) cc = kFar;
+        if (!all) {
+            const float e1 = gr.gh;
+            for_cells(P, gr, bxl - e1, bxh + e1, byl - e1, byh + e1, false, lane, [&](int idx) {
+                float4 cc = ldg(P.cyl_cell, max(idx, 0));
+                if (idx < 0) cc = kFar;
 #pragma unroll
-            for (int s = 0; s < G; ++s) {
-                const float fx = fmaxf(fabsf(xl[s] - cc.x), fabsf(xh[s] - cc.x));
-                const float fy = fmaxf(fabsf(yl[s] - cc.y), fabsf(yh[s] - cc.y));
-                u[s] = fminf(u[s], fsqrt(__builtin_fmaf(fx, fx, fy * fy)) - cc.z);
-            }
+                for (int s = 0; s < G; ++s) {
+                    const float fx = fmaxf(fabsf(xl[s] - cc.x), fabsf(xh[s] - cc.x));
+                    const float fy = fmaxf(fabsf(yl[s] - cc.y), fabsf(yh[s] - cc.y));
+                    u[s] = fminf(u[s], fsqrt(__builtin_fmaf(fx, fx, fy * fy)) - cc.z);
+                }
+            });
         }
         float us[G];  // U + slack
+        float e2 = 0.0f;
 #pragma unroll
         for (int s = 0; s < G; ++s) {
             const float U = wave_min_u(u[s]);
             us[s] = U + (kCullAbs + kCullRel * (fabsf(U) + 2.0f * gr.rmax));
+            e2 = fmaxf(e2, us[s] + gr.rmax);
         }
-        // candidates, evaluated exactly
+        // candidates: a cylinder can be one only if its centre lies within
+        // U + R (+ slack) of a sphere's box, so within e2 of the union box;
+        // they are evaluated exactly
         float a[G];
 #pragma unroll
         for (int s = 0; s < G; ++s) a[s] = kInf;
-        for (int o0 = 0; o0 < gr.count; o0 += kWave) {
-            float4 cc = ldg(c, min(o0 + lane, gr.count - 1));
-            if (o0 + lane >= gr.count) cc = kFar;
+        for_cells(P, gr, bxl - e2, bxh + e2, byl - e2, byh + e2, all, lane, [&](int idx) {
+            float4 cc = ldg(P.cyl_cell, max(idx, 0));
+            if (idx < 0) cc = kFar;
 #pragma unroll
             for (int s = 0; s < G; ++s) {
                 const float ex = fmaxf(fmaxf(xl[s] - cc.x, cc.x - xh[s]), 0.0f);
                 const float ey = fmaxf(fmaxf(yl[s] - cc.y, cc.y - yh[s]), 0.0f);
                 const float n2 = __builtin_fmaf(ex, ex, ey * ey);
                 const float th = fmaxf(us[s] + cc.z, 0.0f);
-                const bool cand = all || n2 < th * th;
+                const bool cand = idx >= 0 && (all || n2 < th * th);
                 uint64_t m = __builtin_amdgcn_ballot_w64(cand);
                 while (m) {
                     const int l = (int)__builtin_ctzll(m);
@@ -200,7 +256,7 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
                     a[s] = fmin_q(a[s], fsqrt(__builtin_fmaf(dx, dx, dy * dy)) - R);
                 }
             }
-        }
+        });
 #pragma unroll
         for (int s = 0; s < G; ++s) v[s] = fminf(v[s], cyl_combine(a[s], fabsf(cz[s] - gr.zc) - gr.hz));
     }

@@ -31,11 +31,19 @@ struct SphereDev {
 // minimum over cylinders of (radial distance - R) is taken first and the
 // height term applied once (the cylinder SDF is non-decreasing in the radial
 // term for a fixed height offset, so this equals the minimum of the SDFs).
+// A uniform 2-D grid over the group's cylinder centres (about three per cell)
+// lets a wave visit only the cylinders near its own spheres: the group's
+// cylinders are also stored sorted by cell (row-major), so the cylinders of a
+// run of cells in one row are contiguous.
 struct GroupDev {
-    int32_t start, count;  // into the sorted cylinder table; count is a multiple of 4
+    int32_t start, count;  // into the sorted cylinder tables; count is a multiple of 4
     float zc, hz;          // centre and half height of the shared extent
     float rmax;            // largest radius in the group
-    int32_t pad[3];
+    float gx0, gy0;        // grid: lower corner,
+    float gh, ginv;        //       cell edge and its reciprocal,
+    int32_t gnx, gny;      //       cells per axis,
+    int32_t gcell;         //       offset of the group's first cell in cell_start
+    int32_t pad[4];
 };
 
 // Within a group, cylinders are sorted by polar angle about the world z axis;
@@ -56,6 +64,8 @@ struct PlanView {
     const GroupDev *groups;       // [n_groups]
     const int32_t *angle_start;   // [n_groups][kAngleBins] scan start (multiple of 4) per azimuth bin
     int32_t pair_filter;          // 1: skip the square root of pairs that cannot lower the minimum
+    const float4 *cyl_cell;       // same entries as cyl, sorted by grid cell within each group
+    const int32_t *cell_start;    // per group [gny * gnx + 1]: first cyl_cell index of each cell
     const float4 *cyl_orig;       // [n_cyl] (x, y, R, group) in the caller's order
     const float4 *box;            // [n_box][2]: (cx, cy, cz, hx), (hy, hz, -, -)
     const float *qs, *qg;         // [n_joints]
