@@ -125,8 +125,8 @@ __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&
 // Steps 2 and 3 put one cylinder on each lane (64 per pass), and the
 // candidates are then evaluated by every lane with the same arithmetic as the
 // all-pairs loop.  Boxes are culled the same way against the wave maximum of
-// the running minimum v, with the 3-D gap between the two boxes as the lower
-// bound.  The per-axis bounds are exact in floating point (rounding is
+// the running minimum v, with the 3-D gap between the obstacle and the union
+// of the group's sphere boxes as the lower bound.  The per-axis bounds are exact in floating point (rounding is
 // monotone, so the nearest box point's squared distance never exceeds a
 // lane's and the farthest one's is never below it); only the square roots and
 // the threshold carry rounding, covered by 1e-4 m plus 1e-6 relative slack.
@@ -187,10 +187,11 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
     float xl[G], xh[G], yl[G], yh[G];
 #pragma unroll
     for (int s = 0; s < G; ++s) {
-        xl[s] = wave_min_u(in ? cx[s] : kInf);
-        xh[s] = wave_max_u(in ? cx[s] : -kInf);
-        yl[s] = wave_min_u(in ? cy[s] : kInf);
-        yh[s] = wave_max_u(in ? cy[s] : -kInf);
+        xl[s] = in ? cx[s] : kInf;
+        xh[s] = in ? cx[s] : -kInf;
+        yl[s] = in ? cy[s] : kInf;
+        yh[s] = in ? cy[s] : -kInf;
+        wave_box(xl[s], xh[s], yl[s], yh[s]);
     }
 #pragma unroll
     for (int s = 0; s < G; ++s) v[s] = P.has_ground ? cz[s] - P.ground_z : kInf;
@@ -209,7 +210,7 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
 #pragma unroll
         for (int s = 0; s < G; ++s) u[s] = kInf;
         if (!all) {
-            const float e1 = gr.gh;
+            const float e1 = 0.5f * gr.gh;
             for_cells(P, gr, bxl - e1, bxh + e1, byl - e1, byh + e1, false, lane, [&](int idx) {
                 float4 cc = ldg(P.cyl_cell, max(idx, 0));
                 if (idx < 0) cc = kFar;
@@ -223,11 +224,15 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
         }
         float us[G];  // U + slack
         float e2 = 0.0f;
+        {
+            float r[4] = {u[0], u[G > 1 ? 1 : 0], u[G > 2 ? 2 : 0], u[G > 3 ? 3 : 0]};
+            wave_min4(r[0], r[1], r[2], r[3]);
 #pragma unroll
-        for (int s = 0; s < G; ++s) {
-            const float U = wave_min_u(u[s]);
-            us[s] = U + (kCullAbs + kCullRel * (fabsf(U) + 2.0f * gr.rmax));
-            e2 = fmaxf(e2, us[s] + gr.rmax);
+            for (int s = 0; s < G; ++s) {
+                const float U = r[s];
+                us[s] = U + (kCullAbs + kCullRel * (fabsf(U) + 2.0f * gr.rmax));
+                e2 = fmaxf(e2, us[s] + gr.rmax);
+            }
         }
         // candidates: a cylinder can be one only if its centre lies within
         // U + R (+ slack) of a sphere's box, so within e2 of the union box;
@@ -261,34 +266,39 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
         for (int s = 0; s < G; ++s) v[s] = fminf(v[s], cyl_combine(a[s], fabsf(cz[s] - gr.zc) - gr.hz));
     }
     if (P.n_box > 0) {
-        float zl[G], zh[G], vs[G];  // vs: wave maximum of v + slack
+        // one test per obstacle box for the whole sphere group: the gap between
+        // the union of the spheres' boxes and the obstacle, against the wave
+        // maximum of the running minima (obstacle boxes that pass are
+        // evaluated for every sphere of the group)
+        float zlo = cz[0], zhi = cz[0], vmax = v[0], unused = 0.0f;
 #pragma unroll
-        for (int s = 0; s < G; ++s) {
-            zl[s] = wave_min_u(in ? cz[s] : kInf);
-            zh[s] = wave_max_u(in ? cz[s] : -kInf);
-            const float V = wave_max_u(in ? v[s] : -kInf);
-            vs[s] = V + (kCullAbs + kCullRel * fabsf(V));
+        for (int s = 1; s < G; ++s) {
+            zlo = fminf(zlo, cz[s]);
+            zhi = fmaxf(zhi, cz[s]);
+            vmax = fmaxf(vmax, v[s]);
         }
+        zlo = in ? zlo : kInf;
+        zhi = in ? zhi : -kInf;
+        vmax = in ? vmax : -kInf;
+        wave_box(zlo, zhi, unused, vmax);
+        const float th = fmaxf(vmax + (kCullAbs + kCullRel * fabsf(vmax)), 0.0f);
         for (int o0 = 0; o0 < P.n_box; o0 += kWave) {
             const int ob = min(o0 + lane, P.n_box - 1);
             const float4 b0 = ldg(P.box, 2 * ob), b1 = ldg(P.box, 2 * ob + 1);
             const bool real = o0 + lane < P.n_box;
+            // per axis: distance of the box of centres from the obstacle's slab
+            const float gx = fmaxf(fmaxf(fmaxf(bxl - b0.x, b0.x - bxh), 0.0f) - b0.w, 0.0f);
+            const float gy = fmaxf(fmaxf(fmaxf(byl - b0.y, b0.y - byh), 0.0f) - b1.x, 0.0f);
+            const float gz = fmaxf(fmaxf(fmaxf(zlo - b0.z, b0.z - zhi), 0.0f) - b1.y, 0.0f);
+            const float g2 = __builtin_fmaf(gx, gx, __builtin_fmaf(gy, gy, gz * gz));
+            const bool cand = all || g2 <= 0.0f || g2 < th * th;
+            uint64_t m = __builtin_amdgcn_ballot_w64(cand && real);
+            while (m) {
+                const int o = o0 + (int)__builtin_ctzll(m);
+                m &= m - 1;
+                const float4 c0 = ldg(P.box, 2 * o), c1 = ldg(P.box, 2 * o + 1);
 #pragma unroll
-            for (int s = 0; s < G; ++s) {
-                // per axis: distance of the box of centres from the obstacle's slab
-                const float gx = fmaxf(fmaxf(fmaxf(xl[s] - b0.x, b0.x - xh[s]), 0.0f) - b0.w, 0.0f);
-                const float gy = fmaxf(fmaxf(fmaxf(yl[s] - b0.y, b0.y - yh[s]), 0.0f) - b1.x, 0.0f);
-                const float gz = fmaxf(fmaxf(fmaxf(zl[s] - b0.z, b0.z - zh[s]), 0.0f) - b1.y, 0.0f);
-                const float g2 = __builtin_fmaf(gx, gx, __builtin_fmaf(gy, gy, gz * gz));
-                const float th = fmaxf(vs[s], 0.0f);
-                const bool cand = all || g2 <= 0.0f || g2 < th * th;
-                uint64_t m = __builtin_amdgcn_ballot_w64(cand && real);
-                while (m) {
-                    const int o = o0 + (int)__builtin_ctzll(m);
-                    m &= m - 1;
-                    const float4 c0 = ldg(P.box, 2 * o), c1 = ldg(P.box, 2 * o + 1);
-                    v[s] = fminf(v[s], box_sd(cx[s], cy[s], cz[s], c0, c1));
-                }
+                for (int s = 0; s < G; ++s) v[s] = fminf(v[s], box_sd(cx[s], cy[s], cz[s], c0, c1));
             }
         }
     }
@@ -487,8 +497,11 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     }
 }
 
+// The culling path holds more state than the plain pair loop; five waves per
+// SIMD (at most 96 registers per lane) measured faster than the compiler's
+// unconstrained four, and six spill.
 template <bool TAPE, bool CULL>
-__global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__restrict__ W, int B,
+__global__ __launch_bounds__(256, CULL ? 5 : 1) void k_eval_fwd(PlanView P, const float *__restrict__ W, int B,
                                                   double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape) {
     eval_one<TAPE, CULL>(P, W, B, partial, slots, tape, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
@@ -504,7 +517,7 @@ __global__ __launch_bounds__(256) void k_eval_fwd(PlanView P, const float *__res
 // compiler can prove the tables unchanged and keeps their wave-uniform reads
 // in scalar loads; a global work counter would turn them into vector loads.)
 template <bool CULL>
-__global__ __launch_bounds__(256, CULL ? 4 : 6) void k_eval_persistent(const BatchProblem *__restrict__ probs,
+__global__ __launch_bounds__(256, CULL ? 5 : 6) void k_eval_persistent(const BatchProblem *__restrict__ probs,
                                                          double2 *__restrict__ partial,
                                                          const int2 *__restrict__ items, int n_items, int rounds) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {

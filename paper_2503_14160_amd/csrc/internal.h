@@ -375,6 +375,44 @@ __device__ __forceinline__ float wave_max_u(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1));
 }
 
+// Four independent wave reductions in one sequence: the four chains are
+// interleaved, so consecutive DPP reads of one register are four instructions
+// apart and need no wait states of their own.  OPn is "min" or "max".
+#define CP_DPP4(OA, OB, OC, OD, CTRL)                  \
+    "v_" OA "_f32_dpp %0, %0, %0 " CTRL "\n\t"       \
+    "v_" OB "_f32_dpp %1, %1, %1 " CTRL "\n\t"       \
+    "v_" OC "_f32_dpp %2, %2, %2 " CTRL "\n\t"       \
+    "v_" OD "_f32_dpp %3, %3, %3 " CTRL "\n\t"
+#define CP_WAVE_REDUCE4(OA, OB, OC, OD, a, b, c, d)                                         \
+    asm("s_nop 1\n\t"                                                                    \
+        CP_DPP4(OA, OB, OC, OD, "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf")           \
+        CP_DPP4(OA, OB, OC, OD, "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf")           \
+        CP_DPP4(OA, OB, OC, OD, "row_half_mirror row_mask:0xf bank_mask:0xf")               \
+        CP_DPP4(OA, OB, OC, OD, "row_mirror row_mask:0xf bank_mask:0xf")                    \
+        CP_DPP4(OA, OB, OC, OD, "row_bcast:15 row_mask:0xa bank_mask:0xf")                  \
+        CP_DPP4(OA, OB, OC, OD, "row_bcast:31 row_mask:0xc bank_mask:0xf")                  \
+        "s_nop 1"                                                                           \
+        : "+v"(a), "+v"(b), "+v"(c), "+v"(d))
+
+__device__ __forceinline__ float lane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1));
+}
+
+// wave-uniform (min a, max b, min c, max d)
+__device__ __forceinline__ void wave_box(float &a, float &b, float &c, float &d) {
+    CP_WAVE_REDUCE4("min", "max", "min", "max", a, b, c, d);
+    a = lane63(a); b = lane63(b); c = lane63(c); d = lane63(d);
+}
+// wave-uniform minima / maxima of four values
+__device__ __forceinline__ void wave_min4(float &a, float &b, float &c, float &d) {
+    CP_WAVE_REDUCE4("min", "min", "min", "min", a, b, c, d);
+    a = lane63(a); b = lane63(b); c = lane63(c); d = lane63(d);
+}
+__device__ __forceinline__ void wave_max4(float &a, float &b, float &c, float &d) {
+    CP_WAVE_REDUCE4("max", "max", "max", "max", a, b, c, d);
+    a = lane63(a); b = lane63(b); c = lane63(c); d = lane63(d);
+}
+
 // min(a, b) as one v_min_f32, for operands known not to be signalling NaNs
 // (fminf adds a canonicalising instruction when it cannot prove that).
 __device__ __forceinline__ float fmin_q(float a, float b) {
