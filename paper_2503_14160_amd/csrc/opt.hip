@@ -287,8 +287,16 @@ __global__ __launch_bounds__(kSelThreads) void k_rerank(OptView O) {
 // mean and covariance update (steps 4-6) and best-so-far
 // ---------------------------------------------------------------------------
 
-constexpr int kUpdThreads = 512;
-constexpr int kEliteChunk = 32;
+// One workgroup per 16 x 16 tile of the lower triangle of C.  Every workgroup
+// first forms the means of its tile's rows and columns (each a sum over the
+// elites in rank order, the same arithmetic in every workgroup, so all hold
+// identical values; diagonal tiles store theirs), then accumulates its
+// entries about those means.  Elites are staged through LDS 256 at a time.
+constexpr int kUpdTile = 16;
+constexpr int kUpdThreads = kUpdTile * kUpdTile;
+constexpr int kUpdChunk = 256;
+constexpr int kUpdTilesPerDim = (CP_MAX_DIM + kUpdTile - 1) / kUpdTile;
+constexpr int kUpdTiles = kUpdTilesPerDim * (kUpdTilesPerDim + 1) / 2;
 
 __device__ __forceinline__ double elite_value(const PlanView &P, const OptView &O, int idx, int e) {
     if (idx < O.B) return O.xi[(size_t)idx * O.D + e];
@@ -305,71 +313,78 @@ __device__ __forceinline__ float elite_cost(const OptView &O, int idx) {
     return idx < O.B ? O.cost[idx] : O.cost_p[idx - O.B];
 }
 
-__device__ __forceinline__ void update_body(const PlanView &P, const OptView &O) {
-    const double *w = O.w;
-    __shared__ double mu[CP_MAX_DIM];
-    __shared__ double xs[kEliteChunk][CP_MAX_DIM];
+__device__ __forceinline__ void update_tile(const PlanView &P, const OptView &O, int t) {
+    const int D = O.D, nu = O.nu, tid = threadIdx.x;
+    const int nt = (D + kUpdTile - 1) / kUpdTile;
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    const int tj = t - ti * (ti + 1) / 2;
+    if (ti >= nt) return;  // whole workgroup
+    const int r0 = ti * kUpdTile, c0 = tj * kUpdTile;
+    const int r = tid / kUpdTile, c = tid % kUpdTile;
+    __shared__ double xr[kUpdChunk][kUpdTile], xc[kUpdChunk][kUpdTile];
+    __shared__ double wch[kUpdChunk];
+    __shared__ int ech[kUpdChunk];
+    __shared__ double mr[kUpdTile], mc[kUpdTile];
     __shared__ int s_improved;
-    const int D = O.D, tid = threadIdx.x;
-    // mean: sum_j w_j x_(j), in rank order
-    for (int e = tid; e < D; e += kUpdThreads) {
-        double s = 0.0;
-        for (int j = 0; j < O.nu; ++j) s = fma(w[j], elite_value(P, O, O.elite[j], e), s);
-        mu[e] = s;
-        O.mu[e] = s;
+    // stage elites j0 .. j0 + nj - 1 of the tile's rows and columns (minus the
+    // means once they are known)
+    auto stage = [&](int j0, int nj, bool centred) {
+        for (int i = tid; i < nj; i += kUpdThreads) {
+            ech[i] = O.elite[j0 + i];
+            wch[i] = O.w[j0 + i];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < nj * 2 * kUpdTile; idx += kUpdThreads) {
+            const int jj = idx / (2 * kUpdTile), q = idx % (2 * kUpdTile);
+            const bool row = q < kUpdTile;
+            const int qq = row ? q : q - kUpdTile;
+            const int e = (row ? r0 : c0) + qq;
+            double v = e < D ? elite_value(P, O, ech[jj], e) : 0.0;
+            if (centred) v -= row ? mr[qq] : mc[qq];
+            if (row) xr[jj][qq] = v;
+            else xc[jj][qq] = v;
+        }
+        __syncthreads();
+    };
+    // means: sum_j w_j x_(j), in rank order
+    double m = 0.0;
+    for (int j0 = 0; j0 < nu; j0 += kUpdChunk) {
+        const int nj = min(kUpdChunk, nu - j0);
+        stage(j0, nj, false);
+        if (tid < 2 * kUpdTile) {
+            for (int jj = 0; jj < nj; ++jj)
+                m = fma(wch[jj], tid < kUpdTile ? xr[jj][tid] : xc[jj][tid - kUpdTile], m);
+        }
+        __syncthreads();
     }
+    if (tid < kUpdTile) mr[tid] = m;
+    else if (tid < 2 * kUpdTile) mc[tid - kUpdTile] = m;
     __syncthreads();
+    if (ti == tj && tid < kUpdTile && r0 + tid < D) O.mu[r0 + tid] = mr[tid];
     // covariance about the new mean: sum_j w_j (x_(j) - mu)(x_(j) - mu)^T + eps I
-    const int n_ent = D * (D + 1) / 2;
-    constexpr int kPer = (CP_MAX_DIM * (CP_MAX_DIM + 1) / 2 + kUpdThreads - 1) / kUpdThreads;
-    double acc[kPer];
-    int e1s[kPer], e2s[kPer];
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        acc[r] = 0.0;
-        int idx = tid + r * kUpdThreads;
-        int e1 = 0;
-        if (idx < n_ent) {
-            e1 = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-            while ((e1 + 1) * (e1 + 2) / 2 <= idx) ++e1;
-            while (e1 * (e1 + 1) / 2 > idx) --e1;
-        }
-        e1s[r] = e1;
-        e2s[r] = idx < n_ent ? idx - e1 * (e1 + 1) / 2 : 0;
-    }
-    for (int j0 = 0; j0 < O.nu; j0 += kEliteChunk) {
-        const int nj = min(kEliteChunk, O.nu - j0);
-        for (int idx = tid; idx < nj * D; idx += kUpdThreads) {
-            const int jj = idx / D, e = idx % D;
-            xs[jj][e] = elite_value(P, O, O.elite[j0 + jj], e) - mu[e];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            if (tid + r * kUpdThreads < n_ent) {
-                const int e1 = e1s[r], e2 = e2s[r];
-                double a = acc[r];
-                for (int jj = 0; jj < nj; ++jj) a = fma(w[j0 + jj] * xs[jj][e1], xs[jj][e2], a);
-                acc[r] = a;
-            }
-        }
+    const int e1 = r0 + r, e2 = c0 + c;
+    const bool mine = e1 < D && e2 < D && e2 <= e1;
+    double acc = 0.0;
+    for (int j0 = 0; j0 < nu; j0 += kUpdChunk) {
+        const int nj = min(kUpdChunk, nu - j0);
+        stage(j0, nj, true);
+        if (mine)
+            for (int jj = 0; jj < nj; ++jj) acc = fma(wch[jj] * xr[jj][r], xc[jj][c], acc);
         __syncthreads();
     }
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        if (tid + r * kUpdThreads < n_ent) {
-            const int e1 = e1s[r], e2 = e2s[r];
-            const double v = acc[r] + (e1 == e2 ? O.eps : 0.0);
-            O.C[(size_t)e1 * D + e2] = v;
-            O.C[(size_t)e2 * D + e1] = v;
-        }
+    if (mine) {
+        const double v = acc + (e1 == e2 ? O.eps : 0.0);
+        O.C[(size_t)e1 * D + e2] = v;
+        O.C[(size_t)e2 * D + e1] = v;
     }
+    if (t != 0) return;
     // best-so-far: the iteration's best sample, then the best polished elite
     if (tid == 0) {
         int imp = -1;
         float bc = *O.best_cost;
-        const float c0 = O.cost[O.elite0[0]];
-        if (c0 < bc) { bc = c0; imp = O.elite0[0]; }
+        const float cb = O.cost[O.elite0[0]];
+        if (cb < bc) { bc = cb; imp = O.elite0[0]; }
         if (O.npol > 0) {
             const float c1 = elite_cost(O, O.elite[0]);
             if (c1 < bc) { bc = c1; imp = O.elite[0]; }
@@ -385,11 +400,11 @@ __device__ __forceinline__ void update_body(const PlanView &P, const OptView &O)
     }
 }
 
-__global__ __launch_bounds__(kUpdThreads) void k_update(PlanView P, OptView O) { update_body(P, O); }
+__global__ __launch_bounds__(kUpdThreads) void k_update(PlanView P, OptView O) { update_tile(P, O, blockIdx.x); }
 
 __global__ __launch_bounds__(kUpdThreads) void k_update_batched(const BatchProblem *__restrict__ probs) {
-    const BatchProblem &bp = probs[blockIdx.x];
-    update_body(bp.P, bp.O);
+    const BatchProblem &bp = probs[blockIdx.y];
+    update_tile(bp.P, bp.O, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -397,13 +412,15 @@ __global__ __launch_bounds__(kUpdThreads) void k_update_batched(const BatchProbl
 // triangle); if a pivot is not positive, retry with C + 10^k eps I, k = 1..3
 // ---------------------------------------------------------------------------
 
-constexpr int kCholThreads = 256;
+// One wave: the factorisation is a chain of D small steps, so a single wave
+// (whose barriers cost nothing) beats a larger workgroup whose barriers
+// dominate.  Lane l owns rows l, l + 64; each row's entries are updated in
+// the same order as any right-looking factorisation (k ascending).
+constexpr int kCholThreads = 64;
 
 __device__ __forceinline__ void chol_body(const OptView &O) {
     __shared__ double A[CP_MAX_DIM * (CP_MAX_DIM + 1) / 2];
-    __shared__ int s_fail;
     const int D = O.D, tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6, nw = kCholThreads / 64;
     auto at = [](int i, int j) { return i * (i + 1) / 2 + j; };
     bool ok = false;
     for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
@@ -412,26 +429,27 @@ __device__ __forceinline__ void chol_body(const OptView &O) {
             const int i = idx / D, j = idx % D;
             if (j <= i) A[at(i, j)] = O.C[idx] + (i == j ? jitter : 0.0);
         }
-        if (tid == 0) s_fail = 0;
         __syncthreads();
+        bool fail = false;
         for (int k = 0; k < D; ++k) {
-            if (tid == 0) {
-                const double piv = A[at(k, k)];
-                if (!(piv > 0.0)) s_fail = 1;
-                A[at(k, k)] = sqrt(piv > 0.0 ? piv : 1.0);
+            // every lane takes the pivot itself (identical values, no broadcast)
+            const double piv = A[at(k, k)];
+            if (!(piv > 0.0)) {
+                fail = true;
+                break;  // uniform: every lane read the same pivot
             }
+            const double dk = sqrt(piv);
             __syncthreads();
-            if (s_fail) break;
-            const double dk = A[at(k, k)];
+            if (tid == 0) A[at(k, k)] = dk;
             for (int i = k + 1 + tid; i < D; i += kCholThreads) A[at(i, k)] /= dk;
             __syncthreads();
-            for (int i = k + 1 + wv; i < D; i += nw) {
+            for (int i = k + 1 + tid; i < D; i += kCholThreads) {
                 const double lik = A[at(i, k)];
-                for (int j = k + 1 + lane; j <= i; j += 64) A[at(i, j)] -= lik * A[at(j, k)];
+                for (int j = k + 1; j <= i; ++j) A[at(i, j)] -= lik * A[at(j, k)];
             }
             __syncthreads();
         }
-        ok = !s_fail;
+        ok = !fail;
         __syncthreads();
     }
     if (!ok) {
@@ -487,7 +505,7 @@ hipError_t launch_rerank(const OptView &O, hipStream_t st) {
 }
 
 hipError_t launch_update(const PlanView &P, const OptView &O, hipStream_t st) {
-    hipLaunchKernelGGL(k_update, dim3(1), dim3(kUpdThreads), 0, st, P, O);
+    hipLaunchKernelGGL(k_update, dim3(kUpdTiles), dim3(kUpdThreads), 0, st, P, O);
     return hipGetLastError();
 }
 
@@ -509,7 +527,7 @@ hipError_t launch_batch_iteration(const BatchProblem *probs, double2 *partial, i
         return e;
     hipLaunchKernelGGL(k_select_batched, dim3(n), dim3(kSelThreads), 0, st, probs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_update_batched, dim3(n), dim3(kUpdThreads), 0, st, probs);
+    hipLaunchKernelGGL(k_update_batched, dim3(kUpdTiles, n), dim3(kUpdThreads), 0, st, probs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_chol_batched, dim3(n), dim3(kCholThreads), 0, st, probs);
     return hipGetLastError();
