@@ -72,7 +72,7 @@ enum { CP_JP_SQUARED = 0, CP_JP_L2 = 1 };
 enum { CP_HINGE_HARD = 0, CP_HINGE_SMOOTH = 1 };
 /* How much of the sphere-obstacle pair work is skipped; every mode returns
  * bitwise the same distances (see cp_cost_params.pair_filter). */
-enum { CP_PAIRS_ALL = 0, CP_PAIRS_LANE = 1, CP_PAIRS_WAVE = 2 };
+enum { CP_PAIRS_ALL = 0, CP_PAIRS_LANE = 1, CP_PAIRS_WAVE = 2, CP_PAIRS_AUTO = 3 };
 
 /* tape entry of a checkpoint: (sphere << 16) | obstacle, where obstacle 0 is
  * the ground, 1..n_cyl the cylinders, n_cyl+1..n_cyl+n_box the boxes, and
@@ -146,9 +146,12 @@ typedef struct {
      * one path are bounded by a box per sphere; cylinders and boxes that no
      * configuration in the box can come closer to than an upper bound of its
      * minimum are skipped for the whole wave (waves that hold more than two
-     * paths use the lane filter).  Skipped pairs cannot lower any minimum, so
-     * distances, costs and argmin records are bitwise those of CP_PAIRS_ALL
-     * for any input whose coordinates stay within +-1e4 m. */
+     * paths are bounded as one box).  CP_PAIRS_AUTO: CP_PAIRS_WAVE for
+     * scenes of at least 48 cylinders and boxes, else CP_PAIRS_LANE (the
+     * culling's fixed cost per wave outweighs its savings on small scenes;
+     * in a batch, CP_PAIRS_WAVE if any problem qualifies).  Skipped pairs
+     * cannot lower any minimum, so distances, costs and argmin records are
+     * bitwise those of CP_PAIRS_ALL in every mode. */
     int32_t pair_filter;
 } cp_cost_params;
 

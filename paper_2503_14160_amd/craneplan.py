@@ -26,8 +26,9 @@ _c_i32, _c_f32, _c_f64, _c_u64, _c_u32, _vp = (ctypes.c_int32, ctypes.c_float, c
                                                ctypes.c_uint32, ctypes.c_void_p)
 
 CP_OBS_SDF = 0xFFFF
-# cp_cost_params.pair_filter: every pair / lane-level square-root skip / wave-level culling
-PAIRS_ALL, PAIRS_LANE, PAIRS_WAVE = 0, 1, 2
+# cp_cost_params.pair_filter: every pair / lane-level square-root skip / wave-level culling /
+# culling for scenes of at least 48 obstacles, else the lane filter
+PAIRS_ALL, PAIRS_LANE, PAIRS_WAVE, PAIRS_AUTO = 0, 1, 2, 3
 EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_endpoints", "cp_plan_n_checkpoints",
            "cp_eval_paths", "cp_eval_paths_backward", "cp_optimizer_create", "cp_optimizer_destroy",
            "cp_optimizer_step", "cp_optimizer_get_state", "cp_optimizer_set_state", "cp_optimizer_last",
@@ -165,7 +166,7 @@ def _fill_scene(s, scene, keep, sdf=None, sdf_spec=None):
         s.voxel = float(sdf_spec.voxel)
 
 
-def _fill_cost(c, cost, max_B, pair_filter=PAIRS_WAVE):
+def _fill_cost(c, cost, max_B, pair_filter=PAIRS_AUTO):
     c.K, c.M, c.interp, c.jp_mode, c.hinge = cost.K, cost.M, cost.interp, cost.jp_mode, cost.hinge
     c.margin, c.lambda_c, c.w_c, c.w_l = cost.margin, cost.lambda_c, cost.w_c, cost.w_l
     c.max_B = int(max_B)
@@ -185,7 +186,7 @@ class Plan:
     """A crane, a scene and a path cost on one device (cp_plan_create)."""
 
     def __init__(self, robot, scene, cost, max_B: int, device: int = 0, sdf: Optional[torch.Tensor] = None,
-                 sdf_spec=None, pair_filter: int = PAIRS_WAVE):
+                 sdf_spec=None, pair_filter: int = PAIRS_AUTO):
         L = lib()
         self._keep = []
         r, s, c = _Robot(), _Scene(), _Cost()
@@ -353,7 +354,7 @@ class Batch:
     ``problems`` are objects with robot, scene, cost, opt, q_start, q_goal;
     problem i uses Philox problem id i."""
 
-    def __init__(self, problems, device: int = 0, pair_filter: int = PAIRS_WAVE):
+    def __init__(self, problems, device: int = 0, pair_filter: int = PAIRS_AUTO):
         L = lib()
         n = len(problems)
         self._keep = []

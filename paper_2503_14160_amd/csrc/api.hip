@@ -60,6 +60,14 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 
 bool finite(float x) { return std::isfinite(x); }
 
+// CP_PAIRS_AUTO: the wave-level culling pays off from a few dozen obstacles on
+// (measured crossover between 32 and 64 for a 64-sphere crane)
+constexpr int kAutoCullObstacles = 48;
+int resolve_pairs(int mode, int n_obstacles) {
+    if (mode != CP_PAIRS_AUTO) return mode;
+    return n_obstacles >= kAutoCullObstacles ? CP_PAIRS_WAVE : CP_PAIRS_LANE;
+}
+
 }  // namespace
 
 struct cp_plan {
@@ -165,7 +173,7 @@ static int validate_plan_args(const cp_robot_desc *r, const cp_scene_desc *s, co
     if (c->interp != CP_INTERP_BSPLINE && c->interp != CP_INTERP_LINEAR) return fail(CP_ERR_INVALID_ARG, "bad interp");
     if (c->jp_mode != CP_JP_SQUARED && c->jp_mode != CP_JP_L2) return fail(CP_ERR_INVALID_ARG, "bad jp_mode");
     if (c->hinge != CP_HINGE_HARD && c->hinge != CP_HINGE_SMOOTH) return fail(CP_ERR_INVALID_ARG, "bad hinge");
-    if (c->pair_filter < CP_PAIRS_ALL || c->pair_filter > CP_PAIRS_WAVE)
+    if (c->pair_filter < CP_PAIRS_ALL || c->pair_filter > CP_PAIRS_AUTO)
         return fail(CP_ERR_INVALID_ARG, "bad pair_filter");
     if (!(c->margin >= 0.0f) || (c->hinge == CP_HINGE_SMOOTH && !(c->margin > 0.0f)))
         return fail(CP_ERR_INVALID_ARG, "bad margin");
@@ -329,7 +337,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     }
     if (angle_start.empty()) angle_start.assign(kAngleBins, 0);
     if (cell_start.empty()) cell_start.assign(1, 0);
-    const int pair_filter = cost->pair_filter;
+    const int pair_filter = resolve_pairs(cost->pair_filter, p->n_cyl + p->n_box);
     std::vector<float4> box;
     for (int o = 0; o < p->n_box; ++o) {
         const float *y = scene->box + 6 * o;
@@ -709,6 +717,8 @@ int cp_batch_create(int32_t n, const cp_robot_desc *robots, const cp_scene_desc 
     b->device = device;
     b->n = n;
     b->cull = costs[0].pair_filter == CP_PAIRS_WAVE;
+    for (int i = 0; i < n && costs[0].pair_filter == CP_PAIRS_AUTO; ++i)
+        if (resolve_pairs(CP_PAIRS_AUTO, scenes[i].n_cyl + scenes[i].n_box) == CP_PAIRS_WAVE) b->cull = true;
     size_t qoff = 0;
     for (int i = 0; i < n; ++i) {
         cp_plan *p = nullptr;

@@ -821,6 +821,10 @@ __global__ __launch_bounds__(256) void k_debug_configs(PlanView P, const float *
 
 int eval_slots(int ns) { return kWave / ns + 2; }
 
+// the wave-level culling runs when asked for and there is something to cull
+// (a grid-only scene has neither cylinders nor boxes)
+static bool use_cull(const PlanView &P) { return P.pair_filter == CP_PAIRS_WAVE && (P.n_groups > 0 || P.n_box > 0); }
+
 size_t eval_partial_count(int B, int ns) {
     const int64_t N = (int64_t)B * ns;
     return (size_t)((N + kWave - 1) / kWave) * eval_slots(ns);
@@ -831,7 +835,7 @@ hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *pa
     const int64_t N = (int64_t)B * P.ns;
     const int slots = eval_slots(P.ns);
     const dim3 grid((unsigned)((N + 255) / 256));
-    const bool cull = P.pair_filter == CP_PAIRS_WAVE;
+    const bool cull = use_cull(P);
     if (tape && cull)
         hipLaunchKernelGGL((k_eval_fwd<true, true>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
     else if (tape)
@@ -866,7 +870,7 @@ hipError_t launch_eval_bwd(const PlanView &P, const float *W, int B, const uint3
     if (tape)
         hipLaunchKernelGGL((k_eval_bwd<true, false>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
                            grad_W);
-    else if (P.pair_filter == CP_PAIRS_WAVE)
+    else if (use_cull(P))
         hipLaunchKernelGGL((k_eval_bwd<false, true>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
                            grad_W);
     else
@@ -881,7 +885,7 @@ hipError_t launch_debug_fk(const PlanView &P, const float *Q, int N, float *cent
 }
 
 hipError_t launch_debug_configs(const PlanView &P, const float *Q, int N, float *dist, uint32_t *arg, hipStream_t st) {
-    if (P.pair_filter == CP_PAIRS_WAVE)
+    if (use_cull(P))
         hipLaunchKernelGGL(k_debug_configs<true>, dim3((N + 255) / 256), dim3(256), 0, st, P, Q, N, dist, arg);
     else
         hipLaunchKernelGGL(k_debug_configs<false>, dim3((N + 255) / 256), dim3(256), 0, st, P, Q, N, dist, arg);

@@ -80,3 +80,7 @@ def test_plan_argument_errors_without_device():
     with pytest.raises(craneplan.CranePlanError) as ei:
         craneplan.Plan(rb, p.scene, p.cost, max_B=4)
     assert "unit" in str(ei.value)
+    for mode in (-1, 4):
+        with pytest.raises(craneplan.CranePlanError) as ei:
+            craneplan.Plan(p.robot, p.scene, p.cost, max_B=4, pair_filter=mode)
+        assert "pair_filter" in str(ei.value)

@@ -33,7 +33,7 @@ def _eval_modes(cp, prob, W, label, backward=False):
     print(f"[pairs] {label} B={W.shape[0]} K={prob.cost.K} M={prob.cost.M}", flush=True)
     Wt = torch.from_numpy(np.ascontiguousarray(W, dtype=np.float32)).cuda()
     out = {}
-    for mode in (cp.PAIRS_ALL, cp.PAIRS_LANE, cp.PAIRS_WAVE):
+    for mode in (cp.PAIRS_ALL, cp.PAIRS_LANE, cp.PAIRS_WAVE, cp.PAIRS_AUTO):
         plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=W.shape[0], pair_filter=mode)
         plan.set_endpoints(prob.q_start, prob.q_goal)
         cost, md, fl, tape = plan.eval(Wt, tape=True)
@@ -43,7 +43,7 @@ def _eval_modes(cp, prob, W, label, backward=False):
             res.append(_bits(plan.backward(Wt, gc, None)))
         torch.cuda.synchronize()
         out[mode] = res
-    for mode in (cp.PAIRS_LANE, cp.PAIRS_WAVE):
+    for mode in (cp.PAIRS_LANE, cp.PAIRS_WAVE, cp.PAIRS_AUTO):
         for name, a, b in zip(("cost", "min_dist", "flags", "tape", "grad"), out[cp.PAIRS_ALL], out[mode]):
             np.testing.assert_array_equal(a, b, err_msg=f"{label}: {name} differs in mode {mode}")
     return out[cp.PAIRS_ALL]
@@ -190,4 +190,4 @@ def test_pairs_batch(cp):
 def test_pair_filter_validated(cp):
     prob = synth.c0_plain()
     with pytest.raises(cp.CranePlanError):
-        cp.Plan(prob.robot, prob.scene, prob.cost, max_B=1, pair_filter=3)
+        cp.Plan(prob.robot, prob.scene, prob.cost, max_B=1, pair_filter=4)
