@@ -37,7 +37,7 @@ PEAK_HBM = 8.0e12     # MI355X HBM3E bytes/s
 # HBM bytes per k_eval_fwd launch on c1_full from rocprofv3 FETCH_SIZE / WRITE_SIZE, each
 # scaled by the same counter on a plain 1 GiB copy (profiles/k_eval_fwd_c1_full_hbm_bytes.md);
 # None once the kernel has changed since the counters were taken
-TRAFFIC_BYTES = None
+TRAFFIC_BYTES = 27.8e6
 # algorithmic bytes of one trilinear signed-distance query: 8 FP32 corners
 SDF_QUERY_BYTES = 32
 
@@ -132,9 +132,9 @@ def bench_iterations(args, torch, cp, prob, with_roofline):
         "roofline": {"bound": "alu", "kernel": "k_eval_fwd", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
                      "traffic": TRAFFIC_BYTES, "flops_per_config": fpc,
-                     "note": "algorithmic flops of the all-pairs definition; the kernel skips the square root of "
-                             "pairs that cannot lower the minimum (bitwise-identical results), so this rate can "
-                             "exceed the hardware peak; all_pairs_kernel is the same launch evaluating every pair",
+                     "note": "algorithmic flops of the all-pairs definition; the kernel culls sphere-obstacle "
+                             "pairs that cannot lower any minimum (bitwise-identical results), so this rate exceeds "
+                             "the hardware peak; all_pairs_kernel is the same evaluation with every pair in full",
                      "all_pairs_kernel": {"ms": plain_ms, "achieved": flops / (plain_ms * 1e-3) / 1e12,
                                           "frac": flops / (plain_ms * 1e-3) / PEAK_FP32,
                                           "identical_costs": bool(torch.equal(c_plain, cost))}},

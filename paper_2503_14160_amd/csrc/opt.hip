@@ -412,15 +412,13 @@ __global__ __launch_bounds__(kUpdThreads) void k_update_batched(const BatchProbl
 // triangle); if a pivot is not positive, retry with C + 10^k eps I, k = 1..3
 // ---------------------------------------------------------------------------
 
-// One wave: the factorisation is a chain of D small steps, so a single wave
-// (whose barriers cost nothing) beats a larger workgroup whose barriers
-// dominate.  Lane l owns rows l, l + 64; each row's entries are updated in
-// the same order as any right-looking factorisation (k ascending).
-constexpr int kCholThreads = 64;
+constexpr int kCholThreads = 256;
 
 __device__ __forceinline__ void chol_body(const OptView &O) {
     __shared__ double A[CP_MAX_DIM * (CP_MAX_DIM + 1) / 2];
+    __shared__ int s_fail;
     const int D = O.D, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = kCholThreads / 64;
     auto at = [](int i, int j) { return i * (i + 1) / 2 + j; };
     bool ok = false;
     for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
@@ -429,27 +427,26 @@ __device__ __forceinline__ void chol_body(const OptView &O) {
             const int i = idx / D, j = idx % D;
             if (j <= i) A[at(i, j)] = O.C[idx] + (i == j ? jitter : 0.0);
         }
+        if (tid == 0) s_fail = 0;
         __syncthreads();
-        bool fail = false;
         for (int k = 0; k < D; ++k) {
-            // every lane takes the pivot itself (identical values, no broadcast)
-            const double piv = A[at(k, k)];
-            if (!(piv > 0.0)) {
-                fail = true;
-                break;  // uniform: every lane read the same pivot
+            if (tid == 0) {
+                const double piv = A[at(k, k)];
+                if (!(piv > 0.0)) s_fail = 1;
+                A[at(k, k)] = sqrt(piv > 0.0 ? piv : 1.0);
             }
-            const double dk = sqrt(piv);
             __syncthreads();
-            if (tid == 0) A[at(k, k)] = dk;
+            if (s_fail) break;
+            const double dk = A[at(k, k)];
             for (int i = k + 1 + tid; i < D; i += kCholThreads) A[at(i, k)] /= dk;
             __syncthreads();
-            for (int i = k + 1 + tid; i < D; i += kCholThreads) {
+            for (int i = k + 1 + wv; i < D; i += nw) {
                 const double lik = A[at(i, k)];
-                for (int j = k + 1; j <= i; ++j) A[at(i, j)] -= lik * A[at(j, k)];
+                for (int j = k + 1 + lane; j <= i; j += 64) A[at(i, j)] -= lik * A[at(j, k)];
             }
             __syncthreads();
         }
-        ok = !fail;
+        ok = !s_fail;
         __syncthreads();
     }
     if (!ok) {
