@@ -82,6 +82,7 @@ struct cp_plan {
     float4 *d_cyl = nullptr;
     float4 *d_cyl_cell = nullptr;
     int32_t *d_cell_start = nullptr;
+    int32_t *d_hint = nullptr;
     GroupDev *d_groups = nullptr;
     int32_t *d_angle_start = nullptr;
     float4 *d_cyl_orig = nullptr;
@@ -92,7 +93,7 @@ struct cp_plan {
 
     ~cp_plan() {
         DeviceGuard g(device);
-        void *bufs[] = {d_joints, d_spheres, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_groups,
+        void *bufs[] = {d_joints, d_spheres, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_hint, d_groups,
                         d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
@@ -269,7 +270,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     // per-azimuth-bin scan start (one bin behind, aligned to the chunk of 4)
     std::vector<float4> cyl, cyl_cell;
     std::vector<GroupDev> groups;
-    std::vector<int32_t> angle_start, cell_start;
+    std::vector<int32_t> angle_start, cell_start, hint;
     const double kPi = 3.14159265358979323846;
     for (size_t g = 0; g < ext.size(); ++g) {
         GroupDev G{};
@@ -325,6 +326,42 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
             const float *y = scene->cyl + 5 * co.second;
             cyl_cell.push_back(make_float4(y[0], y[1], y[2], 0.0f));
         }
+        // hints: a square grid over the cylinders' extent plus 10 m on every
+        // side, about four cells per cylinder cell edge (at most 128 per axis);
+        // per cell the cylinder minimising (distance to the centre - R), found
+        // among the 5 x 5 cylinder cells around it, else among all
+        {
+            const double span = std::max(gw, gd) + 20.0;
+            const double hh = std::max(h / 4.0, span / 128.0);
+            const int hn = std::min(128, (int)std::ceil(span / hh));
+            const double hx0 = 0.5 * (x0 + x1) - 0.5 * hn * hh, hy0 = 0.5 * (y0 + y1) - 0.5 * hn * hh;
+            G.hx0 = (float)hx0; G.hy0 = (float)hy0;
+            G.hinv = (float)(1.0 / hh);
+            G.hn = hn;
+            G.hoff = (int)hint.size();
+            const int n_mem = (int)by_cell.size();
+            for (int iy = 0; iy < hn; ++iy)
+                for (int ix = 0; ix < hn; ++ix) {
+                    const double px = hx0 + (ix + 0.5) * hh, py = hy0 + (iy + 0.5) * hh;
+                    const int cx = std::min(nx - 1, std::max(0, (int)std::floor((px - x0) / h)));
+                    const int cy = std::min(ny - 1, std::max(0, (int)std::floor((py - y0) / h)));
+                    double best = HUGE_VAL;
+                    int arg = 0;
+                    auto visit = [&](int c) {
+                        const float *y = scene->cyl + 5 * by_cell[c].second;
+                        const double d = std::hypot(px - y[0], py - y[1]) - y[2];
+                        if (d < best) { best = d; arg = c; }
+                    };
+                    for (int jy = std::max(0, cy - 2); jy <= std::min(ny - 1, cy + 2); ++jy)
+                        for (int jx = std::max(0, cx - 2); jx <= std::min(nx - 1, cx + 2); ++jx)
+                            for (int c = cell_start[G.gcell + jy * nx + jx] - G.start;
+                                 c < cell_start[G.gcell + jy * nx + jx + 1] - G.start; ++c)
+                                visit(c);
+                    if (best == HUGE_VAL)
+                        for (int c = 0; c < n_mem; ++c) visit(c);
+                    hint.push_back(G.start + arg);
+                }
+        }
         while (cyl_cell.size() < cyl.size()) cyl_cell.push_back(make_float4(1e15f, 1e15f, 0.0f, 0.0f));
         groups.push_back(G);
         for (int b = 0; b < kAngleBins; ++b) {
@@ -337,6 +374,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     }
     if (angle_start.empty()) angle_start.assign(kAngleBins, 0);
     if (cell_start.empty()) cell_start.assign(1, 0);
+    if (hint.empty()) hint.assign(1, 0);
     const int pair_filter = resolve_pairs(cost->pair_filter, p->n_cyl + p->n_box);
     std::vector<float4> box;
     for (int o = 0; o < p->n_box; ++o) {
@@ -349,6 +387,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     if ((e = upload(&p->d_joints, p->joints)) != hipSuccess || (e = upload(&p->d_spheres, spheres)) != hipSuccess ||
         (e = upload(&p->d_frame_start, frame_start)) != hipSuccess || (e = upload(&p->d_cyl, cyl)) != hipSuccess ||
         (e = upload(&p->d_cyl_cell, cyl_cell)) != hipSuccess || (e = upload(&p->d_cell_start, cell_start)) != hipSuccess ||
+        (e = upload(&p->d_hint, hint)) != hipSuccess ||
         (e = upload(&p->d_groups, groups)) != hipSuccess || (e = upload(&p->d_angle_start, angle_start)) != hipSuccess ||
         (e = upload(&p->d_cyl_orig, cyl_orig)) != hipSuccess ||
         (e = upload(&p->d_box, box)) != hipSuccess || (e = upload(&p->d_qs, hold)) != hipSuccess ||
@@ -373,6 +412,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     v.angle_start = p->d_angle_start;
     v.cyl_cell = p->d_cyl_cell;
     v.cell_start = p->d_cell_start;
+    v.hint = p->d_hint;
     v.pair_filter = pair_filter;
     v.qs = p->d_qs; v.qg = p->d_qg;
     v.sdf = scene->d_sdf;

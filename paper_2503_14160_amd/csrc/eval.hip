@@ -205,28 +205,30 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
     const float4 kFar = make_float4(1e15f, 1e15f, 0.0f, 0.0f);
     for (int g = 0; g < P.n_groups; ++g) {
         const GroupDev gr = ldg(P.groups, g);
-        // upper bounds U from the cylinders of the cells within one cell edge
-        float u[G];
-#pragma unroll
-        for (int s = 0; s < G; ++s) u[s] = kInf;
-        if (!all) {
-            const float e1 = 0.5f * gr.gh;
-            for_cells(P, gr, bxl - e1, bxh + e1, byl - e1, byh + e1, false, lane, [&](int idx) {
-                float4 cc = ldg(P.cyl_cell, max(idx, 0));
-                if (idx < 0) cc = kFar;
-#pragma unroll
-                for (int s = 0; s < G; ++s) {
-                    const float fx = fmaxf(fabsf(xl[s] - cc.x), fabsf(xh[s] - cc.x));
-                    const float fy = fmaxf(fabsf(yl[s] - cc.y), fabsf(yh[s] - cc.y));
-                    u[s] = fminf(u[s], fsqrt(__builtin_fmaf(fx, fx, fy * fy)) - cc.z);
-                }
-            });
-        }
+        // upper bounds U: every lane's distance to one near cylinder (the
+        // hint at the centre of the sphere's box), maximised over the
+        // segment's lanes.  Each lane's final minimum a is at most its own
+        // value for that cylinder, computed with the same arithmetic.
         float us[G];  // U + slack
         float e2 = 0.0f;
         {
-            float r[4] = {u[0], u[G > 1 ? 1 : 0], u[G > 2 ? 2 : 0], u[G > 3 ? 3 : 0]};
-            wave_min4(r[0], r[1], r[2], r[3]);
+            float r[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int i = s < G ? s : 0;
+                r[s] = kInf;
+                if (!all) {
+                    const float hx = (0.5f * (xl[i] + xh[i]) - gr.hx0) * gr.hinv;
+                    const float hy = (0.5f * (yl[i] + yh[i]) - gr.hy0) * gr.hinv;
+                    const int ix = (int)fminf(fmaxf(hx, 0.0f), (float)(gr.hn - 1));
+                    const int iy = (int)fminf(fmaxf(hy, 0.0f), (float)(gr.hn - 1));
+                    const int h = ldg(P.hint, gr.hoff + __builtin_amdgcn_readfirstlane(iy * gr.hn + ix));
+                    const float4 c = ldg(P.cyl_cell, h);
+                    const float dx = cx[i] - c.x, dy = cy[i] - c.y;
+                    r[s] = in ? fsqrt(__builtin_fmaf(dx, dx, dy * dy)) - c.z : -kInf;
+                }
+            }
+            wave_max4(r[0], r[1], r[2], r[3]);
 #pragma unroll
             for (int s = 0; s < G; ++s) {
                 const float U = r[s];

@@ -43,8 +43,16 @@ struct GroupDev {
     float gh, ginv;        //       cell edge and its reciprocal,
     int32_t gnx, gny;      //       cells per axis,
     int32_t gcell;         //       offset of the group's first cell in cell_start
-    int32_t pad[4];
+    // A finer square grid of hints: per cell, the cyl_cell index of the
+    // cylinder nearest to the cell's centre (in the radial term); any one
+    // cylinder gives an upper bound of a minimum, a near one a tight bound.
+    float hx0, hy0;        // lower corner
+    float hinv;            // reciprocal of the cell edge
+    int32_t hn;            // cells per axis
+    int32_t hoff;          // offset of the group's first cell in hint
+    int32_t pad[3];
 };
+static_assert(sizeof(GroupDev) == 80, "GroupDev layout");
 
 // Within a group, cylinders are sorted by polar angle about the world z axis;
 // kAngleBins start offsets per group let a wave begin its scan at the
@@ -66,6 +74,7 @@ struct PlanView {
     int32_t pair_filter;          // 1: skip the square root of pairs that cannot lower the minimum
     const float4 *cyl_cell;       // same entries as cyl, sorted by grid cell within each group
     const int32_t *cell_start;    // per group [gny * gnx + 1]: first cyl_cell index of each cell
+    const int32_t *hint;          // per group [hn * hn]: cyl_cell index of a near cylinder per cell
     const float4 *cyl_orig;       // [n_cyl] (x, y, R, group) in the caller's order
     const float4 *box;            // [n_box][2]: (cx, cy, cz, hx), (hy, hz, -, -)
     const float *qs, *qg;         // [n_joints]
