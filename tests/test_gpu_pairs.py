@@ -191,3 +191,51 @@ def test_pair_filter_validated(cp):
     prob = synth.c0_plain()
     with pytest.raises(cp.CranePlanError):
         cp.Plan(prob.robot, prob.scene, prob.cost, max_B=1, pair_filter=4)
+
+
+def _scene_variants():
+    rng = np.random.default_rng(730)
+    out = {}
+    # several vertical extents: one cylinder group (and grid) per extent
+    n = 200
+    ext = np.array([[0.0, 15.0], [0.0, 4.0], [2.0, 9.0], [-1.0, 30.0], [5.0, 6.0]])[rng.integers(0, 5, n)]
+    r = rng.uniform(2.0, 14.0, n)
+    a = rng.uniform(-np.pi, np.pi, n)
+    out["groups"] = np.stack([r * np.cos(a), r * np.sin(a), rng.uniform(0.1, 0.5, n), ext[:, 0], ext[:, 1]], 1)
+    # every cylinder on one line (a grid of one row)
+    xs = rng.uniform(-15, 15, 120)
+    out["line"] = np.stack([xs, np.full(120, 4.0), rng.uniform(0.1, 0.4, 120), np.zeros(120), np.full(120, 15.0)], 1)
+    # duplicated centres with different radii
+    base = np.stack([rng.uniform(-12, 12, 40), rng.uniform(-12, 12, 40)], 1)
+    dup = np.concatenate([base, base, base])
+    out["duplicates"] = np.concatenate([dup, rng.uniform(0.1, 0.6, (120, 1)), np.zeros((120, 1)),
+                                        np.full((120, 1), 15.0)], 1)
+    # a single tree
+    out["single"] = np.array([[3.0, 2.0, 0.3, 0.0, 15.0]])
+    # a huge trunk around part of the sweep (centres inside it) among ordinary trees
+    big = np.array([[6.0, 0.0, 4.0, 0.0, 15.0]])
+    r = rng.uniform(3.0, 14.0, 80)
+    a = rng.uniform(-np.pi, np.pi, 80)
+    small = np.stack([r * np.cos(a), r * np.sin(a), rng.uniform(0.1, 0.4, 80), np.zeros(80), np.full(80, 15.0)], 1)
+    out["huge"] = np.concatenate([big, small])
+    # everything far away but one tree close to the base
+    far = np.stack([rng.uniform(200, 260, 100), rng.uniform(-30, 30, 100), rng.uniform(0.1, 0.5, 100), np.zeros(100),
+                    np.full(100, 15.0)], 1)
+    out["far_and_one"] = np.concatenate([far, np.array([[2.5, -3.0, 0.4, 0.0, 15.0]])])
+    return out
+
+
+@pytest.mark.parametrize("name", ["groups", "line", "duplicates", "single", "huge", "far_and_one"])
+def test_pairs_degenerate_scenes(cp, name):
+    """Scenes that stress the cell and hint grids: several cylinder groups,
+    one-row grids, duplicated centres, a single cylinder, centres inside a
+    huge trunk, and nearly everything out of reach."""
+    base = synth.c1_full()
+    cyl = _scene_variants()[name].astype(np.float32)
+    box = np.array([[4.0, -6.0, 1.0, 1.0, 1.0, 1.0]], np.float32) if name in ("groups", "huge") else \
+        np.zeros((0, 6), np.float32)
+    scene = synth.Scene(cyl=cyl, box=box, has_ground=1, ground_z=0.0)
+    prob = dataclasses.replace(base, scene=scene, cost=synth.CostParams(K=6, M=12))
+    rng = np.random.default_rng(731)
+    W = synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, 96, prob.cost.K, sigma=0.4)
+    _eval_modes(cp, prob, W, f"degenerate {name}")
