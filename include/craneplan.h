@@ -292,9 +292,11 @@ int cp_batch_tune(cp_batch *batch, const char *cache_path, cp_batch_tuning *chos
  * distances (voxel units) to the nearest occupied / free voxel; field
  * h (sqrt(EDT_occ) - 1/2) on free voxels, -h (sqrt(EDT_free) - 1/2) on
  * occupied ones.  With no occupied (free) voxel the squared distance is
- * nx^2 + ny^2 + nz^2.  d_points [N][3]; outputs [nz][ny][nx]; the three
- * optional outputs may be NULL.  Needs 8 bytes of device workspace per voxel,
- * allocated and freed by the call (which therefore synchronises the stream). */
+ * nx^2 + ny^2 + nz^2.  d_points [N][3]; outputs [nz][ny][nx]; d_sdf also
+ * serves as scratch until the last pass writes it.  The three optional
+ * outputs may be NULL: the call then allocates them (1, 4 and 4 bytes per
+ * voxel), frees them and synchronises the stream; with all three given it
+ * allocates nothing and returns without waiting. */
 int cp_sdf_build(const float *d_points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
                  float *d_sdf, uint8_t *d_occ, int32_t *d_edt_occ, int32_t *d_edt_free, cp_stream_t stream);
 

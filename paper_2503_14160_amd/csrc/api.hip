@@ -993,7 +993,10 @@ int cp_sdf_build(const float *d_points, int64_t N, const int32_t dims[3], const 
     CP_HIP(hipGetDevice(&dev), "device");
     hipStream_t st = (hipStream_t)stream;
     uint8_t *occ = d_occ;
-    int32_t *eo = d_edt_occ, *ef = d_edt_free, *wa = nullptr, *wb = nullptr;
+    int32_t *eo = d_edt_occ, *ef = d_edt_free;
+    // the output grid doubles as the transforms' scratch (the sign pass, which
+    // writes it, runs last)
+    int32_t *work = reinterpret_cast<int32_t *>(d_sdf);
     std::vector<void *> owned;
     auto cleanup = [&]() {
         for (void *q : owned) (void)hipFree(q);
@@ -1007,10 +1010,8 @@ int cp_sdf_build(const float *d_points, int64_t N, const int32_t dims[3], const 
     if (!occ) e = get((void **)&occ, n);
     if (e == hipSuccess && !eo) e = get((void **)&eo, n * 4);
     if (e == hipSuccess && !ef) e = get((void **)&ef, n * 4);
-    if (e == hipSuccess) e = get((void **)&wa, n * 4);
-    if (e == hipSuccess) e = get((void **)&wb, n * 4);
-    if (e == hipSuccess) e = launch_sdf_build(d_points, N, dims, origin, voxel, d_sdf, occ, eo, ef, wa, wb, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = launch_sdf_build(d_points, N, dims, origin, voxel, d_sdf, occ, eo, ef, work, st);
+    if (e == hipSuccess && !owned.empty()) e = hipStreamSynchronize(st);
     cleanup();
     if (e != hipSuccess) return hip_fail(e, "sdf build");
     return CP_OK;

@@ -80,7 +80,7 @@ hipError_t launch_init_state(const PlanView &P, const OptView &O, float sigma0, 
 
 // signed-distance grid (sdf.hip)
 hipError_t launch_sdf_build(const float *points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
-                            float *sdf, uint8_t *occ, int32_t *edt_occ, int32_t *edt_free, int32_t *work_a,
-                            int32_t *work_b, hipStream_t st);
+                            float *sdf, uint8_t *occ, int32_t *edt_occ, int32_t *edt_free, int32_t *work,
+                            hipStream_t st);
 
 }  // namespace cp

@@ -111,8 +111,8 @@ static hipError_t edt3(const uint8_t *occ, uint8_t target, int nx, int ny, int n
 }
 
 hipError_t launch_sdf_build(const float *points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
-                            float *sdf, uint8_t *occ, int32_t *edt_occ, int32_t *edt_free, int32_t *work_a,
-                            int32_t *work_b, hipStream_t st) {
+                            float *sdf, uint8_t *occ, int32_t *edt_occ, int32_t *edt_free, int32_t *work,
+                            hipStream_t st) {
     const int nx = dims[0], ny = dims[1], nz = dims[2];
     const size_t n = (size_t)nx * ny * nz;
     hipLaunchKernelGGL(k_fill_u8, dim3(1024), dim3(256), 0, st, occ, n, (uint8_t)0);
@@ -124,8 +124,8 @@ hipError_t launch_sdf_build(const float *points, int64_t N, const int32_t dims[3
                            (double)origin[1], (double)origin[2], (double)voxel, occ);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = edt3(occ, 1, nx, ny, nz, edt_occ, work_a, st)) != hipSuccess) return e;
-    if ((e = edt3(occ, 0, nx, ny, nz, edt_free, work_b, st)) != hipSuccess) return e;
+    if ((e = edt3(occ, 1, nx, ny, nz, edt_occ, work, st)) != hipSuccess) return e;
+    if ((e = edt3(occ, 0, nx, ny, nz, edt_free, work, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sdf_sign, dim3(1024), dim3(256), 0, st, occ, edt_occ, edt_free, n, voxel, sdf);
     return hipGetLastError();
 }
