@@ -247,10 +247,11 @@ int cp_optimizer_last(cp_opt *opt, float *d_waypoints, float *d_cost, int32_t *d
 typedef struct cp_batch cp_batch;
 
 /* Launch shape of the batched evaluation: configurations per work item
- * (rounds x 256) and persistent workgroups per compute unit. */
+ * (rounds x 256) and persistent workgroups per compute unit, or 0 for one
+ * workgroup per work item (the hardware dispatcher then balances the load). */
 typedef struct {
     int32_t rounds;     /* 1..64 */
-    int32_t wg_per_cu;  /* 1..16 */
+    int32_t wg_per_cu;  /* 0..16 */
 } cp_batch_tuning;
 
 /* Create n problems on `device` (SYNC).  robots, scenes, costs, opts are

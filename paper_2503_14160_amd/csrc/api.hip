@@ -733,7 +733,7 @@ struct cp_batch {
         }
         return hipMemcpy(d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
     }
-    int grid() const { return n_cu * tune.wg_per_cu; }
+    int grid() const { return tune.wg_per_cu > 0 ? n_cu * tune.wg_per_cu : std::max(1, n_items); }
 };
 
 extern "C" {
@@ -869,7 +869,7 @@ int cp_batch_get_state(cp_batch *b, int32_t p, double *mu, double *C, int64_t *i
 
 int cp_batch_set_tuning(cp_batch *b, const cp_batch_tuning *t) {
     if (!b || !t) return fail(CP_ERR_INVALID_ARG, "null argument");
-    if (t->rounds < 1 || t->rounds > 64 || t->wg_per_cu < 1 || t->wg_per_cu > 16)
+    if (t->rounds < 1 || t->rounds > 64 || t->wg_per_cu < 0 || t->wg_per_cu > 16)
         return fail(CP_ERR_SIZE, "tuning out of range");
     DeviceGuard g(b->device);
     CP_HIP(hipDeviceSynchronize(), "sync");
@@ -932,7 +932,7 @@ int cp_batch_tune(cp_batch *b, const char *cache_path, cp_batch_tuning *chosen) 
         CP_HIP(hipEventCreate(&e1), "event");
         double best_ms = 1e300;
         const int rounds_c[] = {1, 4, 16};
-        const int wg_c[] = {2, 4, 8};
+        const int wg_c[] = {0, 2, 4, 8};
         bool warm = false;
         for (int r : rounds_c)
             for (int w : wg_c) {

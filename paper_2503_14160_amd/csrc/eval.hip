@@ -508,11 +508,13 @@ __global__ __launch_bounds__(256, CULL ? 5 : 1) void k_eval_fwd(PlanView P, cons
     eval_one<TAPE, CULL>(P, W, B, partial, slots, tape, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Many problems in one persistent launch: the work items (problem, first
-// configuration) are listed costliest problem first and dealt to the resident
-// workgroups round robin (workgroup w takes items w, w + G, w + 2G, ...); an
-// item covers `rounds` x 256 consecutive configurations of one problem.  With
-// hundreds of items per workgroup the deal balances to within one item.
+// Many problems in one launch: the work items (problem, first configuration)
+// are listed costliest problem first and dealt to the workgroups round robin
+// (workgroup w takes items w, w + G, w + 2G, ...); an item covers `rounds` x
+// 256 consecutive configurations of one problem.  With a grid of a few
+// workgroups per compute unit the workgroups are persistent and the deal
+// balances to within one item; with one workgroup per item the hardware
+// dispatcher hands items out in order as compute units free up.
 // Every configuration runs exactly the single-problem code, so results are
 // bitwise those of k_eval_fwd on each problem.  (The kernel has no atomics and
 // stores only through the restrict-qualified partial-sum base pointer, so the

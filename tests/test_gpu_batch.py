@@ -90,7 +90,7 @@ def test_batch_graph_replays_with_eager_work_between(cp):
 def test_batch_result_does_not_depend_on_tuning(cp):
     probs = _problems(n=5, seed=540)
     ref = None
-    for rounds, wg in ((1, 2), (8, 8), (3, 5)):
+    for rounds, wg in ((1, 2), (8, 8), (3, 5), (2, 0)):
         batch = cp.Batch(probs)
         batch.set_tuning(rounds, wg)
         assert batch.get_tuning() == (rounds, wg)
