@@ -78,6 +78,7 @@ struct cp_plan {
     std::vector<JointDev> joints;
     JointDev *d_joints = nullptr;
     SphereDev *d_spheres = nullptr;
+    int32_t *d_sphere_slot = nullptr;
     int32_t *d_frame_start = nullptr;
     float4 *d_cyl = nullptr;
     float4 *d_cyl_cell = nullptr;
@@ -93,7 +94,7 @@ struct cp_plan {
 
     ~cp_plan() {
         DeviceGuard g(device);
-        void *bufs[] = {d_joints, d_spheres, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_hint, d_groups,
+        void *bufs[] = {d_joints, d_spheres, d_sphere_slot, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_hint, d_groups,
                         d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
@@ -237,6 +238,8 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         s.orig = i;
         spheres.push_back(s);
     }
+    std::vector<int32_t> sphere_slot(p->S);
+    for (int k = 0; k < p->S; ++k) sphere_slot[spheres[k].orig] = k;
     std::vector<int32_t> frame_start(p->n + 2, 0);
     for (int f = 0; f <= p->n + 1; ++f) {
         int c = 0;
@@ -385,6 +388,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     std::vector<float> hold(robot->q_hold, robot->q_hold + p->n);
     hipError_t e;
     if ((e = upload(&p->d_joints, p->joints)) != hipSuccess || (e = upload(&p->d_spheres, spheres)) != hipSuccess ||
+        (e = upload(&p->d_sphere_slot, sphere_slot)) != hipSuccess ||
         (e = upload(&p->d_frame_start, frame_start)) != hipSuccess || (e = upload(&p->d_cyl, cyl)) != hipSuccess ||
         (e = upload(&p->d_cyl_cell, cyl_cell)) != hipSuccess || (e = upload(&p->d_cell_start, cell_start)) != hipSuccess ||
         (e = upload(&p->d_hint, hint)) != hipSuccess ||
@@ -408,6 +412,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     v.interp = cost->interp; v.jp_mode = cost->jp_mode; v.hinge = cost->hinge;
     v.margin = cost->margin; v.lambda_c = cost->lambda_c; v.w_c = cost->w_c; v.w_l = cost->w_l;
     v.joints = p->d_joints; v.spheres = p->d_spheres; v.frame_start = p->d_frame_start;
+    v.sphere_slot = p->d_sphere_slot;
     v.cyl = p->d_cyl; v.groups = p->d_groups; v.cyl_orig = p->d_cyl_orig; v.box = p->d_box;
     v.angle_start = p->d_angle_start;
     v.cyl_cell = p->d_cyl_cell;

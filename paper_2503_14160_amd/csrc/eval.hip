@@ -633,10 +633,8 @@ __device__ __forceinline__ float obstacle_sd_grad(const PlanView &P, uint32_t o,
 __device__ __forceinline__ void collision_grad(const PlanView &P, const float (&q)[CP_MAX_JOINTS], int s_orig,
                                                uint32_t o, float (&gq)[CP_MAX_JOINTS]) {
     // locate the sphere (table sorted by frame; `orig` is the caller's index)
-    int si = 0;
-    for (int i = 0; i < P.n_spheres; ++i)
-        if (P.spheres[i].orig == s_orig) si = i;
-    const SphereDev sp = P.spheres[si];
+    const int si = (s_orig >= 0 && s_orig < P.n_spheres) ? ldg(P.sphere_slot, s_orig) : 0;
+    const SphereDev sp = ldg(P.spheres, si);
     float aw[CP_MAX_JOINTS][3], pj[CP_MAX_JOINTS][3];
     float cx = 0.0f, cy = 0.0f, cz = 0.0f;
     Xf T;
@@ -645,7 +643,7 @@ __device__ __forceinline__ void collision_grad(const PlanView &P, const float (&
 #pragma unroll
     for (int f = 1; f <= CP_MAX_JOINTS; ++f) {
         if (f <= P.n_joints) {
-            const JointDev J = P.joints[f - 1];
+            const JointDev J = ldg(P.joints, f - 1);
             // world axis of joint f-1: R_{f-1} a (unchanged by its own rotation)
             aw[f - 1][0] = __builtin_fmaf(T.r[0], J.ax, __builtin_fmaf(T.r[1], J.ay, T.r[2] * J.az));
             aw[f - 1][1] = __builtin_fmaf(T.r[3], J.ax, __builtin_fmaf(T.r[4], J.ay, T.r[5] * J.az));
@@ -682,21 +680,30 @@ __device__ __forceinline__ void collision_grad(const PlanView &P, const float (&
 }
 
 constexpr int kBwdThreads = 256;
+constexpr int kBwdWaves = kBwdThreads / kWave;
 constexpr int kMaxCtrl = CP_MAX_K + 6;
+// control points one wave can touch: 64 checkpoints span at most 64 windows
+// of four consecutive control points
+constexpr int kWaveCtrl = kWave + 3;
 
+// One workgroup per path.  Each lane takes one checkpoint and forms its
+// contribution to the four control points of its span window; per wave and
+// control point the contributions are summed by DPP reductions (fixed order)
+// and the wave sums are added in wave order in double precision.
 template <bool TAPE, bool CULL>
 __global__ __launch_bounds__(kBwdThreads) void k_eval_bwd(PlanView P, const float *__restrict__ W, int B,
                                                           const uint32_t *__restrict__ tape,
                                                           const float *__restrict__ grad_cost,
                                                           float *__restrict__ grad_W) {
-    __shared__ float contrib[kBwdThreads][4][CP_MAX_JOINTS];
-    __shared__ int jwin[kBwdThreads];
+    __shared__ float part[kBwdWaves][kWaveCtrl][CP_MAX_JOINTS];
+    __shared__ int wlo[kBwdWaves], whi[kBwdWaves];
     __shared__ double acc[kMaxCtrl * CP_MAX_JOINTS];
     const int b = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int n = P.n_joints;
-    const int nc = n_ctrl_points(P);
-    for (int i = tid; i < nc * n; i += kBwdThreads) acc[i] = 0.0;
+    // (the windows of the linear mode reach past its last control point: those
+    // entries receive zero weights and are never read out)
+    for (int i = tid; i < kMaxCtrl * CP_MAX_JOINTS; i += kBwdThreads) acc[i] = 0.0;
     const float *Wb = W + (size_t)b * P.K * n;
     for (int k0 = 1; k0 <= P.ns; k0 += kBwdThreads) {
         const int k = k0 + tid;
@@ -737,25 +744,39 @@ __global__ __launch_bounds__(kBwdThreads) void k_eval_bwd(PlanView P, const floa
             o = argmin_obstacle(P, best.cx, best.cy, best.cz);
         }
         collision_grad(P, q, s_orig, o, gq);
+        float c[4][CP_MAX_JOINTS];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int i = 0; i < CP_MAX_JOINTS; ++i)
-                contrib[tid][t][i] = active ? __builtin_fmaf(bw[t], gq[i], db[t] * gd[i]) : 0.0f;
-        jwin[tid] = active ? j : -100;
-        __syncthreads();
-        // control points touched by this chunk, each summed over lanes in order
-        const int last = min(kBwdThreads, P.ns - k0 + 1);
-        const int jlo = jwin[0], jhi = jwin[last - 1] + 3;
-        const int cnt = (jhi - jlo + 1) * n;
-        for (int idx = tid; idx < cnt; idx += kBwdThreads) {
-            const int cpi = jlo + idx / n, jj = idx % n;
-            float s = 0.0f;
-            for (int l = 0; l < last; ++l) {
-                const int t = cpi - jwin[l];
-                if (t >= 0 && t < 4) s += contrib[l][t][jj];
+            for (int i = 0; i < CP_MAX_JOINTS; ++i) c[t][i] = active ? __builtin_fmaf(bw[t], gq[i], db[t] * gd[i]) : 0.0f;
+        // this wave's control points: windows are non-decreasing along the lanes
+        const int jlo = __builtin_amdgcn_readfirstlane(j);
+        const int jhi = __builtin_amdgcn_readlane(j, kWave - 1);
+        for (int cp = jlo; cp <= jhi + 3; ++cp) {
+            const int t = cp - j;
+#pragma unroll
+            for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+                if (i < n) {
+                    const float v = t == 0 ? c[0][i] : t == 1 ? c[1][i] : t == 2 ? c[2][i] : t == 3 ? c[3][i] : 0.0f;
+                    const float sum = wave_sum_u(v);
+                    if (lane == 0) part[wv][cp - jlo][i] = sum;
+                }
             }
-            acc[cpi * n + jj] += (double)s;
+        }
+        if (lane == 0) {
+            wlo[wv] = jlo;
+            whi[wv] = jhi + 3;
+        }
+        __syncthreads();
+        // each control point: the waves' sums in wave order
+        const int lo = wlo[0], hi = whi[kBwdWaves - 1];
+        for (int idx = tid; idx < (hi - lo + 1) * n; idx += kBwdThreads) {
+            const int cp = lo + idx / n, i = idx % n;
+            double s = acc[cp * n + i];
+#pragma unroll
+            for (int w = 0; w < kBwdWaves; ++w)
+                if (cp >= wlo[w] && cp <= whi[w]) s += (double)part[w][cp - wlo[w]][i];
+            acc[cp * n + i] = s;
         }
         __syncthreads();
     }

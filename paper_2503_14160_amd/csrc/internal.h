@@ -67,6 +67,7 @@ struct PlanView {
     float margin, lambda_c, w_c, w_l;
     const JointDev *joints;       // [n_joints]
     const SphereDev *spheres;     // [n_spheres], sorted by frame
+    const int32_t *sphere_slot;   // [n_spheres]: position in spheres of the caller's sphere i
     const int32_t *frame_start;   // [n_joints + 2]: spheres of frame f are [frame_start[f], frame_start[f+1])
     const float4 *cyl;            // [sum of group counts] (x, y, R, unused), grouped
     const GroupDev *groups;       // [n_groups]
@@ -405,6 +406,25 @@ __device__ __forceinline__ float wave_max_u(float v) {
 
 __device__ __forceinline__ float lane63(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1));
+}
+
+// wave-uniform sum of one value (fixed order, so deterministic)
+__device__ __forceinline__ float wave_sum_u(float v) {
+    asm("s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "s_nop 1"
+        : "+v"(v));
+    return lane63(v);
 }
 
 // wave-uniform (min a, max b, min c, max d)
