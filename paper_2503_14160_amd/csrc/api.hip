@@ -327,7 +327,9 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         }
         for (const auto &co : by_cell) {
             const float *y = scene->cyl + 5 * co.second;
-            cyl_cell.push_back(make_float4(y[0], y[1], y[2], 0.0f));
+            float idx_bits;  // the caller's index, as integer bits
+            std::memcpy(&idx_bits, &co.second, sizeof(float));
+            cyl_cell.push_back(make_float4(y[0], y[1], y[2], idx_bits));
         }
         // hints: a square grid over the cylinders' extent plus 10 m on every
         // side, about four cells per cylinder cell edge (at most 128 per axis);

@@ -315,6 +315,7 @@ struct Best {
     float d;
     int s;           // caller's sphere index
     float r;         // its radius
+    float v;         // its minimum signed distance over the obstacles (d = v - r)
     float cx, cy, cz;
 };
 
@@ -357,7 +358,7 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
         float d = v[i] - sp.r;
         if (ARG) {
             if (d < best.d || (d == best.d && sp.orig < best.s)) {
-                best.d = d; best.s = sp.orig; best.r = sp.r;
+                best.d = d; best.s = sp.orig; best.r = sp.r; best.v = v[i];
                 best.cx = cx[i]; best.cy = cy[i]; best.cz = cz[i];
             }
         } else {
@@ -370,7 +371,7 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
 template <bool ARG, bool CULL>
 __device__ __forceinline__ Best config_distance(const PlanView &P, const float (&q)[CP_MAX_JOINTS], WaveSeg ws) {
     Best best;
-    best.d = kInf; best.s = 0x7fffffff; best.r = 0.0f;
+    best.d = kInf; best.s = 0x7fffffff; best.r = 0.0f; best.v = kInf;
     best.cx = best.cy = best.cz = 0.0f;
     Xf T;
     xf_identity(T);
@@ -401,6 +402,48 @@ __device__ __forceinline__ uint32_t argmin_obstacle(const PlanView &P, float cx,
         const GroupDev gr = ldg(P.groups, __float_as_int(c.w));
         float val = cyl_combine(cyl_radial(cx, cy, c), fabsf(cz - gr.zc) - gr.hz);
         if (val < bv) { bv = val; bo = 1u + (uint32_t)o; }
+    }
+    for (int o = 0; o < P.n_box; ++o) {
+        float val = box_sd(cx, cy, cz, ldg(P.box, 2 * o), ldg(P.box, 2 * o + 1));
+        if (val < bv) { bv = val; bo = 1u + (uint32_t)(P.n_cyl + o); }
+    }
+    if (P.sdf) {
+        float val = sdf_query(P, cx, cy, cz, nullptr);
+        if (val < bv) { bv = val; bo = CP_OBS_SDF; }
+    }
+    return bo;
+}
+
+// The same choice as argmin_obstacle when v is the minimum over the
+// obstacles at c (the value the evaluation found): a cylinder's signed
+// distance is never below its radial term, so only cylinders whose axis lies
+// within v + R_max (+ slack) of c can attain v, and those are read from the
+// cell grid; ties keep the lowest obstacle number, as in the full scan.
+__device__ __forceinline__ uint32_t argmin_obstacle_near(const PlanView &P, float cx, float cy, float cz, float v) {
+    if (!(fabsf(cx) < kInf && fabsf(cy) < kInf && fabsf(cz) < kInf && fabsf(v) < kInf))
+        return argmin_obstacle(P, cx, cy, cz);
+    float bv = kInf;
+    uint32_t bo = 0;
+    if (P.has_ground) { bv = cz - P.ground_z; bo = 0; }
+    for (int g = 0; g < P.n_groups; ++g) {
+        const GroupDev gr = ldg(P.groups, g);
+        const float E = fmaxf(v + gr.rmax + kCullAbs +
+                                  kCullRel * (fabsf(v) + 2.0f * gr.rmax + fabsf(cx) + fabsf(cy)),
+                              0.0f);
+        int cx0, cx1, cy0, cy1;
+        cell_span(cx - E, cx + E, gr.gx0, gr.ginv, gr.gnx, cx0, cx1);
+        cell_span(cy - E, cy + E, gr.gy0, gr.ginv, gr.gny, cy0, cy1);
+        const int32_t *cs = P.cell_start + gr.gcell;
+        const float bz = fabsf(cz - gr.zc) - gr.hz;
+        for (int iy = cy0; iy <= cy1; ++iy) {
+            const int e1 = ldg(cs, iy * gr.gnx + cx1 + 1);
+            for (int e = ldg(cs, iy * gr.gnx + cx0); e < e1; ++e) {
+                const float4 c = ldg(P.cyl_cell, e);
+                const float val = cyl_combine(cyl_radial(cx, cy, c), bz);
+                const uint32_t id = 1u + (uint32_t)__float_as_int(c.w);
+                if (val < bv || (val == bv && id < bo)) { bv = val; bo = id; }
+            }
+        }
     }
     for (int o = 0; o < P.n_box; ++o) {
         float val = box_sd(cx, cy, cz, ldg(P.box, 2 * o), ldg(P.box, 2 * o + 1));
@@ -484,7 +527,8 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     float phi = hinge_value(P, best.d, dphi);
     float c = __builtin_fmaf(P.w_c, phi, __builtin_fmaf(P.w_l, jl, jp));
     if (TAPE && active) {
-        uint32_t o = argmin_obstacle(P, best.cx, best.cy, best.cz);
+        uint32_t o = CULL ? argmin_obstacle_near(P, best.cx, best.cy, best.cz, best.v)
+                          : argmin_obstacle(P, best.cx, best.cy, best.cz);
         tape[g] = ((uint32_t)best.s << 16) | o;
     }
     float dk = best.d;
@@ -741,7 +785,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_eval_bwd(PlanView P, const floa
             ws.lane = 0;
             Best best = config_distance<true, CULL>(P, q, ws);
             s_orig = best.s;
-            o = argmin_obstacle(P, best.cx, best.cy, best.cz);
+            o = CULL ? argmin_obstacle_near(P, best.cx, best.cy, best.cz, best.v)
+                     : argmin_obstacle(P, best.cx, best.cy, best.cz);
         }
         collision_grad(P, q, s_orig, o, gq);
         float c[4][CP_MAX_JOINTS];

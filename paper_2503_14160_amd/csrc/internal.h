@@ -73,7 +73,7 @@ struct PlanView {
     const GroupDev *groups;       // [n_groups]
     const int32_t *angle_start;   // [n_groups][kAngleBins] scan start (multiple of 4) per azimuth bin
     int32_t pair_filter;          // 1: skip the square root of pairs that cannot lower the minimum
-    const float4 *cyl_cell;       // same entries as cyl, sorted by grid cell within each group
+    const float4 *cyl_cell;       // (x, y, R, caller index as int bits), sorted by grid cell within each group
     const int32_t *cell_start;    // per group [gny * gnx + 1]: first cyl_cell index of each cell
     const int32_t *hint;          // per group [hn * hn]: cyl_cell index of a near cylinder per cell
     const float4 *cyl_orig;       // [n_cyl] (x, y, R, group) in the caller's order

@@ -111,7 +111,7 @@ def test_batch_autotune_and_cache(cp, tmp_path):
     batch = cp.Batch(probs)
     print("[batch] autotune", flush=True)
     chosen = batch.tune(cache)
-    assert chosen[0] >= 1 and chosen[1] >= 1
+    assert chosen[0] >= 1 and chosen[1] >= 0  # 0: one workgroup per work item
     assert batch.get_tuning() == chosen
     lines = open(cache).read().split("\n")
     assert len([l for l in lines if l.strip()]) == 1
