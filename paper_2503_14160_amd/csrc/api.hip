@@ -565,6 +565,7 @@ int cp_optimizer_create(cp_plan *plan, const cp_opt_params *prm, cp_opt **out) {
         delete o;
         return hip_fail(e, "optimizer buffers");
     }
+    if (o->npol == 0) v.elite0 = v.elite;  // no polish: selection writes the final ranking
     std::vector<float> ones(np, 1.0f);
     e = hipMemcpy(v.ones, ones.data(), np * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_init_state(plan->view, v, prm->sigma0, nullptr);
@@ -612,8 +613,6 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
             CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, nullptr, v.cost_p, v.min_dist, nullptr, st),
                    "polish eval");
             CP_HIP(launch_rerank(v, st), "rerank");
-        } else {
-            CP_HIP(hipMemcpyAsync(v.elite, v.elite0, v.nu * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "elite copy");
         }
         CP_HIP(launch_update(P, v, st), "update");
         CP_HIP(launch_chol(v, st), "cholesky");

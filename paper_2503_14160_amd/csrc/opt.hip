@@ -166,6 +166,20 @@ __device__ __forceinline__ void select_body(const float *__restrict__ cost, int 
     __shared__ uint64_t sorted[CP_MAX_ELITES];
     __shared__ uint32_t s_digit, s_rem;
     const int tid = threadIdx.x;
+    if (B <= kSelThreads) {
+        // small populations: every path's rank in the (cost, index) order is
+        // the number of smaller 64-bit keys, counted directly (broadcast LDS
+        // reads); the first nu ranks are the elites
+        if (tid < B) sorted[tid] = ((uint64_t)cost_key(cost[tid]) << 32) | (uint32_t)tid;
+        __syncthreads();
+        if (tid < B) {
+            const uint64_t mine = sorted[tid];
+            int rank = 0;
+            for (int j = 0; j < B; ++j) rank += sorted[j] < mine ? 1 : 0;
+            if (rank < nu) elite[rank] = tid;
+        }
+        return;
+    }
     uint32_t prefix = 0, mask = 0, remaining = (uint32_t)nu;
     // radix select on the 32-bit order key, most significant byte first
     for (int pass = 0; pass < 4; ++pass) {
@@ -177,11 +191,24 @@ __device__ __forceinline__ void select_body(const float *__restrict__ cost, int 
             if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (tid == 0) {
-            uint32_t cum = 0;
-            for (int d = 0; d < 256; ++d) {
-                if (cum + hist[d] >= remaining) { s_digit = (uint32_t)d; s_rem = remaining - cum; break; }
-                cum += hist[d];
+        if (tid < 64) {
+            // the digit where the running count first reaches `remaining`:
+            // four bins per lane, an inclusive scan of the lane sums across
+            // the wave, then the one lane whose bins cross it
+            uint32_t h[4], sum = 0;
+            for (int d = 0; d < 4; ++d) sum += h[d] = hist[4 * tid + d];
+            uint32_t incl = sum;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t up = __shfl_up(incl, o, 64);
+                if (tid >= o) incl += up;
+            }
+            uint32_t cum = incl - sum;
+            for (int d = 0; d < 4; ++d) {
+                if (cum < remaining && cum + h[d] >= remaining) {
+                    s_digit = (uint32_t)(4 * tid + d);
+                    s_rem = remaining - cum;
+                }
+                cum += h[d];
             }
         }
         __syncthreads();
@@ -416,10 +443,19 @@ constexpr int kCholThreads = 256;
 
 __device__ __forceinline__ void chol_body(const OptView &O) {
     __shared__ double A[CP_MAX_DIM * (CP_MAX_DIM + 1) / 2];
+    __shared__ double dg[CP_MAX_DIM];
     __shared__ int s_fail;
     const int D = O.D, tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6, nw = kCholThreads / 64;
     auto at = [](int i, int j) { return i * (i + 1) / 2 + j; };
+    // Right-looking factorisation with one barrier per column: the phase that
+    // applies column k to the trailing triangle also completes column k + 1
+    // (its pivot, square root and division), since those entries receive
+    // their last update in that phase.  Each entry keeps the order of its
+    // updates, k ascending.  Pivots go to dg[], so no entry is read and
+    // written by different threads within a phase.  A failed pivot (taken as
+    // 1 to keep the arithmetic finite) is acted on once the attempt ends, so
+    // every thread passes the same barriers.
     bool ok = false;
     for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
         const double jitter = attempt == 0 ? 0.0 : O.eps * (attempt == 1 ? 10.0 : attempt == 2 ? 100.0 : 1000.0);
@@ -429,20 +465,55 @@ __device__ __forceinline__ void chol_body(const OptView &O) {
         }
         if (tid == 0) s_fail = 0;
         __syncthreads();
-        for (int k = 0; k < D; ++k) {
+        {
+            const double piv = A[0];
+            const double d = sqrt(piv > 0.0 ? piv : 1.0);
             if (tid == 0) {
-                const double piv = A[at(k, k)];
+                dg[0] = d;
                 if (!(piv > 0.0)) s_fail = 1;
-                A[at(k, k)] = sqrt(piv > 0.0 ? piv : 1.0);
             }
-            __syncthreads();
-            if (s_fail) break;
-            const double dk = A[at(k, k)];
-            for (int i = k + 1 + tid; i < D; i += kCholThreads) A[at(i, k)] /= dk;
-            __syncthreads();
-            for (int i = k + 1 + wv; i < D; i += nw) {
-                const double lik = A[at(i, k)];
-                for (int j = k + 1 + lane; j <= i; j += 64) A[at(i, j)] -= lik * A[at(j, k)];
+            for (int i = 1 + tid; i < D; i += kCholThreads) A[at(i, 0)] /= d;
+        }
+        __syncthreads();
+        for (int k = 0; k + 1 < D; ++k) {
+            const int c = k + 1, m = D - c;
+            // pivot of column c from its last update; every thread forms it
+            const double lck = A[at(c, k)];
+            const double piv = __builtin_fma(-lck, lck, A[at(c, c)]);
+            const double d = sqrt(piv > 0.0 ? piv : 1.0);
+            if (tid == 0) {
+                dg[c] = d;
+                if (!(piv > 0.0)) s_fail = 1;
+            }
+            // the trailing triangle rows c..D-1, columns c..i, flattened
+            // row by row and dealt to threads four entries at a time; all
+            // loads of a batch precede its stores
+            const int T = m * (m + 1) / 2;
+            for (int e0 = tid; e0 < T; e0 += 4 * kCholThreads) {
+                double a[4], li[4], lj[4];
+                int pos[4];
+                bool col[4], act[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * kCholThreads;
+                    act[u] = e > 0 && e < T;  // e == 0 is the pivot itself
+                    if (!act[u]) continue;
+                    int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+                    if (r * (r + 1) / 2 > e) --r;
+                    if ((r + 1) * (r + 2) / 2 <= e) ++r;
+                    const int i = c + r, j = c + (e - r * (r + 1) / 2);
+                    li[u] = A[at(i, k)];
+                    lj[u] = A[at(j, k)];
+                    pos[u] = at(i, j);
+                    a[u] = A[pos[u]];
+                    col[u] = j == c;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!act[u]) continue;
+                    const double v = __builtin_fma(-li[u], lj[u], a[u]);
+                    A[pos[u]] = col[u] ? v / d : v;
+                }
             }
             __syncthreads();
         }
@@ -455,7 +526,7 @@ __device__ __forceinline__ void chol_body(const OptView &O) {
     }
     for (int idx = tid; idx < D * D; idx += kCholThreads) {
         const int i = idx / D, j = idx % D;
-        O.L[idx] = j <= i ? A[at(i, j)] : 0.0;
+        O.L[idx] = j < i ? A[at(i, j)] : j == i ? dg[i] : 0.0;
     }
 }
 
