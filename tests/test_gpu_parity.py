@@ -268,7 +268,8 @@ def test_autograd_function(cp):
 # selection and optimizer
 # ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("B,nu", [(1, 1), (256, 25), (1000, 999), (16384, 819), (65536, 3276), (5000, 4096)])
+@pytest.mark.parametrize("B,nu", [(1, 1), (256, 25), (1000, 999), (1024, 1024), (1024, 100), (1025, 100),
+                                  (16384, 819), (65536, 3276), (5000, 4096)])
 def test_select_parity(cp, B, nu):
     rng = np.random.default_rng(110 + B)
     cost = np.round(rng.normal(size=B) * 3, 2).astype(np.float32)  # many ties
@@ -324,6 +325,40 @@ def test_optimizer_one_step_parity(cp):
     if set(e.tolist()) == set(step["elite"].tolist()) and np.array_equal(e, step["elite"]):
         np.testing.assert_allclose(st["mu"], step["mu"], rtol=1e-5, atol=1e-7)
         np.testing.assert_allclose(st["C"], step["C"], rtol=1e-4, atol=1e-8)
+
+
+@pytest.mark.parametrize("kind", ["spd", "zero_variance"])
+def test_sampling_parity_full_dim(cp, kind):
+    """Step (1) at the largest sampled dimension the library takes (c1_full's
+    crane with K = 24 waypoints of 4 sampled joints, D = 96, the largest batched
+    problems' size) from a given mean and covariance: the device Cholesky factor and the
+    samples it draws equal the oracle's.  'zero_variance' gives one sampled
+    joint of one waypoint no variance, so the first factorisation meets a zero
+    pivot and the jittered retry C + 10 eps I is the one used."""
+    import dataclasses
+    base = synth.c1_full()
+    prob = dataclasses.replace(base, cost=dataclasses.replace(base.cost, K=24),
+                               opt=synth.OptParams(B=256, nu=25, sigma0=0.2, eps=1e-6, seed=21, T=1))
+    D = prob.cost.K * prob.robot.n_active
+    assert D == 96
+    rng = np.random.default_rng(33)
+    X = rng.normal(size=(D, 2 * D)) * 0.05
+    C = X @ X.T / (2 * D) + 1e-4 * np.eye(D)
+    if kind == "zero_variance":
+        C[37, :] = 0.0
+        C[:, 37] = 0.0
+    mu = oracle.initial_mean(prob.robot, prob.q_start, prob.q_goal, prob.cost.K) + rng.normal(size=D) * 0.01
+    orc = oracle.Optimizer(prob)
+    orc.set_state(mu, C, 4)
+    Wref = oracle.expand(prob.robot, orc.sample(), prob.cost.K)
+    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=prob.opt.B)
+    plan.set_endpoints(prob.q_start, prob.q_goal)
+    opt = cp.Optimizer(plan, prob.opt)
+    print(f"[sampling full dim] D={D} kind={kind}", flush=True)
+    opt.set_state(mu, C, 4)
+    opt.step(1)
+    W = opt.last()[0].cpu().numpy()
+    np.testing.assert_allclose(W, Wref, rtol=0, atol=2e-6 * np.maximum(1, np.abs(Wref)).max())
 
 
 def test_optimizer_runs_and_is_deterministic(cp):
