@@ -368,23 +368,30 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
 }
 
 // d(q) for one configuration; with ARG also the minimising sphere and its centre.
+// With split > 1 only the sphere groups numbered part, part + split, ... are
+// taken (their minimum is merged with the other parts' by the caller).
 template <bool ARG, bool CULL>
-__device__ __forceinline__ Best config_distance(const PlanView &P, const float (&q)[CP_MAX_JOINTS], WaveSeg ws) {
+__device__ __forceinline__ Best config_distance(const PlanView &P, const float (&q)[CP_MAX_JOINTS], WaveSeg ws,
+                                                int part = 0, int split = 1) {
     Best best;
     best.d = kInf; best.s = 0x7fffffff; best.r = 0.0f; best.v = kInf;
     best.cx = best.cy = best.cz = 0.0f;
     Xf T;
     xf_identity(T);
+    int gi = 0;
     for (int f = 0; f <= P.n_joints; ++f) {
         if (f > 0) xf_joint(T, ldg(P.joints, f - 1), pick(q, f - 1));
         const int s1 = ldg(P.frame_start, f + 1);
         int s = ldg(P.frame_start, f);
-        for (; s + 4 <= s1; s += 4) sphere_group<4, ARG, CULL>(P, T, s, best, ws);
-        switch (s1 - s) {
-            case 3: sphere_group<3, ARG, CULL>(P, T, s, best, ws); break;
-            case 2: sphere_group<2, ARG, CULL>(P, T, s, best, ws); break;
-            case 1: sphere_group<1, ARG, CULL>(P, T, s, best, ws); break;
-            default: break;
+        for (; s + 4 <= s1; s += 4, ++gi)
+            if (gi % split == part) sphere_group<4, ARG, CULL>(P, T, s, best, ws);
+        if (s < s1 && gi++ % split == part) {
+            switch (s1 - s) {
+                case 3: sphere_group<3, ARG, CULL>(P, T, s, best, ws); break;
+                case 2: sphere_group<2, ARG, CULL>(P, T, s, best, ws); break;
+                case 1: sphere_group<1, ARG, CULL>(P, T, s, best, ws); break;
+                default: break;
+            }
         }
     }
     return best;
@@ -494,12 +501,22 @@ __device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[C
     jl = lim;
 }
 
+// Per-lane minima of the waves of a workgroup, for merging split parts.
+struct MergeBuf {
+    float d[4][kWave], r[4][kWave], v[4][kWave], cx[4][kWave], cy[4][kWave], cz[4][kWave];
+    int s[4][kWave];
+};
+
 // One configuration per lane: g is the flattened (path, checkpoint) index;
 // all 64 lanes of a wave hold consecutive g (some may lie past the end).
-template <bool TAPE, bool CULL>
+// SPLIT: `split` consecutive waves of the workgroup hold the same
+// configurations and share out the sphere groups; the first of them merges
+// the others' minima (the minimum over all pairs, and with the tape the
+// lowest sphere among equal minima, do not depend on the order) and finishes.
+template <bool TAPE, bool CULL, bool SPLIT = false>
 __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restrict__ W, int B,
                                          double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape,
-                                         int64_t g) {
+                                         int64_t g, int part = 0, int split = 1, MergeBuf *mb = nullptr) {
     const int64_t N = (int64_t)B * P.ns;
     const bool active = g < N;
     const int b = active ? (int)(g / P.ns) : B - 1;
@@ -522,7 +539,31 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     WaveSeg ws;
     ws.n = p1 - p0 == 1 ? 2 : 1;
     ws.lane = active ? (ws.n == 2 ? b - p0 : 0) : -1;
-    Best best = config_distance<TAPE, CULL>(P, q, ws);
+    Best best = config_distance<TAPE, CULL>(P, q, ws, part, split);
+    if (SPLIT) {
+        const int wv = threadIdx.x >> 6, ln = threadIdx.x & (kWave - 1);
+        if (part != 0) {
+            mb->d[wv][ln] = best.d;
+            if (TAPE) {
+                mb->s[wv][ln] = best.s; mb->r[wv][ln] = best.r; mb->v[wv][ln] = best.v;
+                mb->cx[wv][ln] = best.cx; mb->cy[wv][ln] = best.cy; mb->cz[wv][ln] = best.cz;
+            }
+        }
+        __syncthreads();
+        if (part != 0) return;
+        for (int u = 1; u < split; ++u) {
+            const float d = mb->d[wv + u][ln];
+            if (TAPE) {
+                const int so = mb->s[wv + u][ln];
+                if (d < best.d || (d == best.d && so < best.s)) {
+                    best.d = d; best.s = so; best.r = mb->r[wv + u][ln]; best.v = mb->v[wv + u][ln];
+                    best.cx = mb->cx[wv + u][ln]; best.cy = mb->cy[wv + u][ln]; best.cz = mb->cz[wv + u][ln];
+                }
+            } else {
+                best.d = fminf(best.d, d);
+            }
+        }
+    }
     float dphi;
     float phi = hinge_value(P, best.d, dphi);
     float c = __builtin_fmaf(P.w_c, phi, __builtin_fmaf(P.w_l, jl, jp));
@@ -550,6 +591,20 @@ template <bool TAPE, bool CULL>
 __global__ __launch_bounds__(256, CULL ? 5 : 1) void k_eval_fwd(PlanView P, const float *__restrict__ W, int B,
                                                   double2 *__restrict__ partial, int slots, uint32_t *__restrict__ tape) {
     eval_one<TAPE, CULL>(P, W, B, partial, slots, tape, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Small launches (too few waves to fill the chip): each group of `split`
+// waves (2 or 4) of a workgroup takes one wave's 64 configurations and shares
+// out their sphere groups, so the per-wave chain is up to `split` times shorter.
+template <bool TAPE, bool CULL>
+__global__ __launch_bounds__(256, CULL ? 5 : 1) void k_eval_fwd_split(PlanView P, const float *__restrict__ W, int B,
+                                                                     double2 *__restrict__ partial, int slots,
+                                                                     uint32_t *__restrict__ tape, int split) {
+    __shared__ MergeBuf mb;
+    const int wv = threadIdx.x >> 6;
+    const int64_t cw = (int64_t)blockIdx.x * (4 / split) + wv / split;
+    eval_one<TAPE, CULL, true>(P, W, B, partial, slots, tape, cw * kWave + (threadIdx.x & (kWave - 1)), wv % split,
+                               split, &mb);
 }
 
 // Many problems in one launch: the work items (problem, first configuration)
@@ -895,6 +950,14 @@ int eval_slots(int ns) { return kWave / ns + 2; }
 // (a grid-only scene has neither cylinders nor boxes)
 static bool use_cull(const PlanView &P) { return P.pair_filter == CP_PAIRS_WAVE && (P.n_groups > 0 || P.n_box > 0); }
 
+// Waves per configuration wave: launches of fewer than about four waves per
+// SIMD (1024 SIMDs) share each wave's sphere groups out over 4 or 2 waves.
+static int eval_split(int64_t waves) {
+    if (waves <= 1024) return 4;
+    if (waves <= 4096) return 2;
+    return 1;
+}
+
 size_t eval_partial_count(int B, int ns) {
     const int64_t N = (int64_t)B * ns;
     return (size_t)((N + kWave - 1) / kWave) * eval_slots(ns);
@@ -906,7 +969,23 @@ hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *pa
     const int slots = eval_slots(P.ns);
     const dim3 grid((unsigned)((N + 255) / 256));
     const bool cull = use_cull(P);
-    if (tape && cull)
+    const int64_t waves = (N + kWave - 1) / kWave;
+    const int split = eval_split(waves);
+    if (split > 1) {
+        const dim3 sg((unsigned)((waves * split + 3) / 4));
+        if (tape && cull)
+            hipLaunchKernelGGL((k_eval_fwd_split<true, true>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+                               split);
+        else if (tape)
+            hipLaunchKernelGGL((k_eval_fwd_split<true, false>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+                               split);
+        else if (cull)
+            hipLaunchKernelGGL((k_eval_fwd_split<false, true>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+                               split);
+        else
+            hipLaunchKernelGGL((k_eval_fwd_split<false, false>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+                               split);
+    } else if (tape && cull)
         hipLaunchKernelGGL((k_eval_fwd<true, true>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
     else if (tape)
         hipLaunchKernelGGL((k_eval_fwd<true, false>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
