@@ -501,10 +501,10 @@ __device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[C
     jl = lim;
 }
 
-// Per-lane minima of the waves of a workgroup, for merging split parts.
+// Per-lane minima of the waves of a workgroup (up to 8), for merging split parts.
 struct MergeBuf {
-    float d[4][kWave], r[4][kWave], v[4][kWave], cx[4][kWave], cy[4][kWave], cz[4][kWave];
-    int s[4][kWave];
+    float d[8][kWave], r[8][kWave], v[8][kWave], cx[8][kWave], cy[8][kWave], cz[8][kWave];
+    int s[8][kWave];
 };
 
 // One configuration per lane: g is the flattened (path, checkpoint) index;
@@ -594,15 +594,17 @@ __global__ __launch_bounds__(256, CULL ? 5 : 1) void k_eval_fwd(PlanView P, cons
 }
 
 // Small launches (too few waves to fill the chip): each group of `split`
-// waves (2 or 4) of a workgroup takes one wave's 64 configurations and shares
-// out their sphere groups, so the per-wave chain is up to `split` times shorter.
-template <bool TAPE, bool CULL>
-__global__ __launch_bounds__(256, CULL ? 5 : 1) void k_eval_fwd_split(PlanView P, const float *__restrict__ W, int B,
-                                                                     double2 *__restrict__ partial, int slots,
-                                                                     uint32_t *__restrict__ tape, int split) {
+// waves (2, 4 or 8) of a workgroup of NW waves takes one wave's 64
+// configurations and shares out their sphere groups, so the per-wave chain is
+// up to `split` times shorter.  With the tape, four waves per SIMD (128
+// registers): at five the merge state spills heavily.
+template <bool TAPE, bool CULL, int NW>
+__global__ __launch_bounds__(NW * 64, NW == 4 ? (CULL ? (TAPE ? 4 : 5) : 1) : (CULL ? 2 : 1)) void k_eval_fwd_split(
+    PlanView P, const float *__restrict__ W, int B, double2 *__restrict__ partial, int slots,
+    uint32_t *__restrict__ tape, int split) {
     __shared__ MergeBuf mb;
     const int wv = threadIdx.x >> 6;
-    const int64_t cw = (int64_t)blockIdx.x * (4 / split) + wv / split;
+    const int64_t cw = (int64_t)blockIdx.x * (NW / split) + wv / split;
     eval_one<TAPE, CULL, true>(P, W, B, partial, slots, tape, cw * kWave + (threadIdx.x & (kWave - 1)), wv % split,
                                split, &mb);
 }
@@ -950,11 +952,13 @@ int eval_slots(int ns) { return kWave / ns + 2; }
 // (a grid-only scene has neither cylinders nor boxes)
 static bool use_cull(const PlanView &P) { return P.pair_filter == CP_PAIRS_WAVE && (P.n_groups > 0 || P.n_box > 0); }
 
-// Waves per configuration wave: launches of fewer than about four waves per
-// SIMD (1024 SIMDs) share each wave's sphere groups out over 4 or 2 waves.
+// Waves per configuration wave: launches of fewer than about twelve waves
+// per SIMD (1024 SIMDs) share each wave's sphere groups out over 8, 4 or 2
+// waves (measured on the polish, c0 and c2 launches).
 static int eval_split(int64_t waves) {
-    if (waves <= 1024) return 4;
-    if (waves <= 4096) return 2;
+    if (waves <= 1024) return 8;
+    if (waves <= 2048) return 4;
+    if (waves <= 12288) return 2;
     return 1;
 }
 
@@ -971,20 +975,34 @@ hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *pa
     const bool cull = use_cull(P);
     const int64_t waves = (N + kWave - 1) / kWave;
     const int split = eval_split(waves);
-    if (split > 1) {
-        const dim3 sg((unsigned)((waves * split + 3) / 4));
+    if (split == 8) {
+        const dim3 sg((unsigned)waves);
         if (tape && cull)
-            hipLaunchKernelGGL((k_eval_fwd_split<true, true>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+            hipLaunchKernelGGL((k_eval_fwd_split<true, true, 8>), sg, dim3(512), 0, st, P, W, B, partial, slots, tape,
                                split);
         else if (tape)
-            hipLaunchKernelGGL((k_eval_fwd_split<true, false>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+            hipLaunchKernelGGL((k_eval_fwd_split<true, false, 8>), sg, dim3(512), 0, st, P, W, B, partial, slots, tape,
                                split);
         else if (cull)
-            hipLaunchKernelGGL((k_eval_fwd_split<false, true>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+            hipLaunchKernelGGL((k_eval_fwd_split<false, true, 8>), sg, dim3(512), 0, st, P, W, B, partial, slots, tape,
                                split);
         else
-            hipLaunchKernelGGL((k_eval_fwd_split<false, false>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+            hipLaunchKernelGGL((k_eval_fwd_split<false, false, 8>), sg, dim3(512), 0, st, P, W, B, partial, slots,
+                               tape, split);
+    } else if (split > 1) {
+        const dim3 sg((unsigned)((waves * split + 3) / 4));
+        if (tape && cull)
+            hipLaunchKernelGGL((k_eval_fwd_split<true, true, 4>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
                                split);
+        else if (tape)
+            hipLaunchKernelGGL((k_eval_fwd_split<true, false, 4>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+                               split);
+        else if (cull)
+            hipLaunchKernelGGL((k_eval_fwd_split<false, true, 4>), sg, dim3(256), 0, st, P, W, B, partial, slots, tape,
+                               split);
+        else
+            hipLaunchKernelGGL((k_eval_fwd_split<false, false, 4>), sg, dim3(256), 0, st, P, W, B, partial, slots,
+                               tape, split);
     } else if (tape && cull)
         hipLaunchKernelGGL((k_eval_fwd<true, true>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
     else if (tape)
