@@ -205,10 +205,12 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
     const float4 kFar = make_float4(1e15f, 1e15f, 0.0f, 0.0f);
     for (int g = 0; g < P.n_groups; ++g) {
         const GroupDev gr = ldg(P.groups, g);
-        // upper bounds U: every lane's distance to one near cylinder (the
-        // hint at the centre of the sphere's box), maximised over the
-        // segment's lanes.  Each lane's final minimum a is at most its own
-        // value for that cylinder, computed with the same arithmetic.
+        // upper bounds U: every lane's distance to a cylinder near its own
+        // centre (the hint of the hint-grid cell the centre falls in),
+        // maximised over the segment's lanes.  Each lane's final minimum a is
+        // at most its own value for that cylinder, computed with the same
+        // arithmetic.  (A hint per lane rather than one for the wave keeps U
+        // close to the largest of the lanes' true minima.)
         float us[G];  // U + slack
         float e2 = 0.0f;
         {
@@ -218,11 +220,11 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
                 const int i = s < G ? s : 0;
                 r[s] = kInf;
                 if (!all) {
-                    const float hx = (0.5f * (xl[i] + xh[i]) - gr.hx0) * gr.hinv;
-                    const float hy = (0.5f * (yl[i] + yh[i]) - gr.hy0) * gr.hinv;
+                    const float hx = (cx[i] - gr.hx0) * gr.hinv;
+                    const float hy = (cy[i] - gr.hy0) * gr.hinv;
                     const int ix = (int)fminf(fmaxf(hx, 0.0f), (float)(gr.hn - 1));
                     const int iy = (int)fminf(fmaxf(hy, 0.0f), (float)(gr.hn - 1));
-                    const int h = ldg(P.hint, gr.hoff + __builtin_amdgcn_readfirstlane(iy * gr.hn + ix));
+                    const int h = ldg(P.hint, gr.hoff + iy * gr.hn + ix);
                     const float4 c = ldg(P.cyl_cell, h);
                     const float dx = cx[i] - c.x, dy = cy[i] - c.y;
                     r[s] = in ? fsqrt(__builtin_fmaf(dx, dx, dy * dy)) - c.z : -kInf;
