@@ -530,10 +530,75 @@ __device__ __forceinline__ void chol_body(const OptView &O) {
     }
 }
 
-__global__ __launch_bounds__(kCholThreads) void k_chol(OptView O) { chol_body(O); }
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The same factorisation for D <= DM <= 64 in one wave and its registers:
+// lane i holds row i, padded to DM with identity rows (the factor of
+// diag(C, I) is diag(L, I)); column k's entries l_jk reach the other lanes
+// by v_readlane into scalar registers.  Every entry receives the same
+// operations in the same order as in chol_body (updates k ascending as
+// fused multiply-adds, then the division by its column's pivot root), so the
+// two give identical factors.
+template <int DM>
+__device__ __forceinline__ void chol_reg(const OptView &O) {
+    const int D = O.D, lane = threadIdx.x & 63;
+    double a[DM];
+    double mydiag = 1.0;
+    bool ok = false;
+    for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+        const double jitter = attempt == 0 ? 0.0 : O.eps * (attempt == 1 ? 10.0 : attempt == 2 ? 100.0 : 1000.0);
+#pragma unroll
+        for (int j = 0; j < DM; ++j) {
+            // lower triangle of row `lane` (C is symmetric: column reads coalesce)
+            a[j] = lane < D && j < D ? (j <= lane ? O.C[(size_t)j * D + lane] + (j == lane ? jitter : 0.0) : 0.0)
+                                     : (j == lane ? 1.0 : 0.0);
+        }
+        bool fail = false;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            const double piv = readlane_f64(a[k], k);
+            fail = fail || !(piv > 0.0);
+            const double d = sqrt(piv > 0.0 ? piv : 1.0);
+            if (lane == k) mydiag = d;
+            a[k] = a[k] / d;
+#pragma unroll
+            for (int j = k + 1; j < DM; ++j) a[j] = __builtin_fma(-a[k], readlane_f64(a[k], j), a[j]);
+        }
+        ok = !fail;
+    }
+    if (!ok) {
+        if (lane == 0) *O.status = 1;
+        return;  // keep the previous factor
+    }
+    if (lane < D) {
+#pragma unroll
+        for (int j = 0; j < DM; ++j)
+            if (j < D) O.L[(size_t)lane * D + j] = j < lane ? a[j] : j == lane ? mydiag : 0.0;
+    }
+}
+
+// one workgroup per factorisation; D <= 32 and D <= 64 in the first wave's
+// registers, larger D in shared memory
+__device__ __forceinline__ void chol_any(const OptView &O) {
+    if (O.D <= 64) {
+        if (threadIdx.x >= 64) return;
+        if (O.D <= 32)
+            chol_reg<32>(O);
+        else
+            chol_reg<64>(O);
+        return;
+    }
+    chol_body(O);
+}
+
+__global__ __launch_bounds__(kCholThreads) void k_chol(OptView O) { chol_any(O); }
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_batched(const BatchProblem *__restrict__ probs) {
-    chol_body(probs[blockIdx.x].O);
+    chol_any(probs[blockIdx.x].O);
 }
 
 // ---------------------------------------------------------------------------

@@ -327,26 +327,30 @@ def test_optimizer_one_step_parity(cp):
         np.testing.assert_allclose(st["C"], step["C"], rtol=1e-4, atol=1e-8)
 
 
+@pytest.mark.parametrize("K", [24, 16, 9, 8, 5])
 @pytest.mark.parametrize("kind", ["spd", "zero_variance"])
-def test_sampling_parity_full_dim(cp, kind):
-    """Step (1) at the largest sampled dimension the library takes (c1_full's
-    crane with K = 24 waypoints of 4 sampled joints, D = 96, the largest batched
-    problems' size) from a given mean and covariance: the device Cholesky factor and the
-    samples it draws equal the oracle's.  'zero_variance' gives one sampled
-    joint of one waypoint no variance, so the first factorisation meets a zero
-    pivot and the jittered retry C + 10 eps I is the one used."""
+def test_sampling_parity_dims(cp, kind, K):
+    """Step (1) from a given mean and covariance at several dimensions
+    D = 4K (c1_full's crane, 4 sampled joints): 96, the largest the library
+    takes (the largest batched problems), 64 (c1), 36, 32 (c0) and 20 (the
+    factorisation runs in shared memory above 64, in one wave's registers up
+    to 32 and up to 64).  The device Cholesky factor and the samples it draws
+    equal the oracle's.  'zero_variance' gives one sampled joint of one
+    waypoint no variance, so the first factorisation meets a zero pivot and
+    the jittered retry C + 10 eps I is the one used."""
     import dataclasses
     base = synth.c1_full()
-    prob = dataclasses.replace(base, cost=dataclasses.replace(base.cost, K=24),
+    prob = dataclasses.replace(base, cost=dataclasses.replace(base.cost, K=K),
                                opt=synth.OptParams(B=256, nu=25, sigma0=0.2, eps=1e-6, seed=21, T=1))
     D = prob.cost.K * prob.robot.n_active
-    assert D == 96
+    assert D == 4 * K
     rng = np.random.default_rng(33)
     X = rng.normal(size=(D, 2 * D)) * 0.05
     C = X @ X.T / (2 * D) + 1e-4 * np.eye(D)
     if kind == "zero_variance":
-        C[37, :] = 0.0
-        C[:, 37] = 0.0
+        z = (37 * D) // 96
+        C[z, :] = 0.0
+        C[:, z] = 0.0
     mu = oracle.initial_mean(prob.robot, prob.q_start, prob.q_goal, prob.cost.K) + rng.normal(size=D) * 0.01
     orc = oracle.Optimizer(prob)
     orc.set_state(mu, C, 4)
@@ -354,7 +358,7 @@ def test_sampling_parity_full_dim(cp, kind):
     plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=prob.opt.B)
     plan.set_endpoints(prob.q_start, prob.q_goal)
     opt = cp.Optimizer(plan, prob.opt)
-    print(f"[sampling full dim] D={D} kind={kind}", flush=True)
+    print(f"[sampling] D={D} kind={kind}", flush=True)
     opt.set_state(mu, C, 4)
     opt.step(1)
     W = opt.last()[0].cpu().numpy()
