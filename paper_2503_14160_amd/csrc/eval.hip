@@ -202,31 +202,38 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
     const float4 kFar = make_float4(1e15f, 1e15f, 0.0f, 0.0f);
     for (int g = 0; g < P.n_groups; ++g) {
         const GroupDev gr = ldg(P.groups, g);
-        // upper bounds U: every lane's distance to a cylinder near its own
-        // centre (the hint of the hint-grid cell the centre falls in),
-        // maximised over the segment's lanes.  Each lane's final minimum a is
-        // at most its own value for that cylinder, computed with the same
-        // arithmetic.  (A hint per lane rather than one for the wave keeps U
-        // close to the largest of the lanes' true minima.)
+        // upper bounds U_s: every lane's distance from sphere s to one
+        // cylinder near that lane's spheres (the hint of the hint-grid cell
+        // holding the centre of the group's middle sphere), maximised over the
+        // segment's lanes.  Each lane's final minimum a_s is at most its own
+        // value for that cylinder, computed with the same arithmetic.  (A hint
+        // per lane rather than one for the wave keeps U close to the largest
+        // of the lanes' true minima; one per group of spheres rather than per
+        // sphere measured faster.)
         float umax = -kInf;  // max over the spheres of U + slack
         {
             float r[4];
+            float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (!all) {
+                const int m = G / 2;
+                const float hx = (cx[m] - gr.hx0) * gr.hinv;
+                const float hy = (cy[m] - gr.hy0) * gr.hinv;
+                const int ix = (int)fminf(fmaxf(hx, 0.0f), (float)(gr.hn - 1));
+                const int iy = (int)fminf(fmaxf(hy, 0.0f), (float)(gr.hn - 1));
+                c = ldg(P.cyl_cell, ldg(P.hint, gr.hoff + iy * gr.hn + ix));
+            }
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const int i = s < G ? s : 0;
-                r[s] = kInf;
-                if (!all) {
-                    const float hx = (cx[i] - gr.hx0) * gr.hinv;
-                    const float hy = (cy[i] - gr.hy0) * gr.hinv;
-                    const int ix = (int)fminf(fmaxf(hx, 0.0f), (float)(gr.hn - 1));
-                    const int iy = (int)fminf(fmaxf(hy, 0.0f), (float)(gr.hn - 1));
-                    const int h = ldg(P.hint, gr.hoff + iy * gr.hn + ix);
-                    const float4 c = ldg(P.cyl_cell, h);
-                    const float dx = cx[i] - c.x, dy = cy[i] - c.y;
+                r[s] = s < G ? kInf : -kInf;
+                if (s < G && !all) {
+                    const float dx = cx[s] - c.x, dy = cy[s] - c.y;
                     r[s] = in ? fsqrt(__builtin_fmaf(dx, dx, dy * dy)) - c.z : -kInf;
                 }
             }
-            wave_max4(r[0], r[1], r[2], r[3]);
+            if (G == 1)
+                r[0] = wave_max_u(r[0]);
+            else
+                wave_max4(r[0], r[1], r[2], r[3]);
 #pragma unroll
             for (int s = 0; s < G; ++s) {
                 const float U = r[s];
