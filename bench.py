@@ -37,7 +37,7 @@ PEAK_HBM = 8.0e12     # MI355X HBM3E bytes/s
 # HBM bytes per k_eval_fwd launch on c1_full from rocprofv3 FETCH_SIZE / WRITE_SIZE, each
 # scaled by the same counter on a plain 1 GiB copy (profiles/k_eval_fwd_c1_full_hbm_bytes.md);
 # None once the kernel has changed since the counters were taken
-TRAFFIC_BYTES = None
+TRAFFIC_BYTES = 19.7e6
 # algorithmic bytes of one trilinear signed-distance query: 8 FP32 corners
 SDF_QUERY_BYTES = 32
 
