@@ -267,3 +267,21 @@ def test_small_launch_split_matches_full_launch(cp, wl, n_big, n_small):
             small = [_bits(t) for t in plan.eval(Wt[:n].contiguous(), tape=True)]
             for name, a, b in zip(("cost", "min_dist", "flags", "tape"), big, small):
                 np.testing.assert_array_equal(a[:n], b, err_msg=f"{wl} mode {mode} n={n}: {name}")
+
+
+@pytest.mark.parametrize("counts", [(1, 5, 6, 7, 2, 3, 9), (0, 4, 0, 13, 1, 0, 8), (3, 3, 3, 3, 3, 3, 3)])
+def test_pairs_sphere_group_sizes(cp, counts):
+    """Frames holding 0 to 13 spheres, so that sphere groups of every size
+    from 1 to 4 and frames without spheres occur: the crane of c1_full with
+    its spheres reassigned to frames in the given counts."""
+    base = synth.c1_full()
+    rb = base.robot
+    S = sum(counts)
+    frame = np.repeat(np.arange(len(counts)), counts).astype(np.int32)
+    robot = dataclasses.replace(rb, sphere_frame=frame, sphere_center=rb.sphere_center[:S].copy(),
+                                sphere_radius=rb.sphere_radius[:S].copy())
+    cost = synth.CostParams(K=6, M=12, hinge=synth.HINGE_SMOOTH, margin=0.1)
+    prob = dataclasses.replace(base, robot=robot, cost=cost)
+    rng = np.random.default_rng(740 + S)
+    W = synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, 80, cost.K, sigma=0.4)
+    _eval_modes(cp, prob, W, f"sphere counts {counts}", backward=True)
