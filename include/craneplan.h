@@ -139,7 +139,12 @@ typedef struct {
     float lambda_c;
     float w_c, w_l;
     int32_t max_B;    /* largest batch any call on this plan will pass */
-    /* CP_PAIRS_ALL: every sphere-obstacle pair is evaluated in full.
+    /* CP_PAIRS_ALL: every sphere-obstacle pair and every grid lookup is
+     * evaluated in full.  In the other modes a sphere's grid lookup is
+     * skipped where a lower bound of the grid over its 4 x 4 x 4 block of
+     * cells (refreshed from the grid by each evaluation call, so the borrowed
+     * grid may change between calls) shows that it cannot bring the sphere
+     * below the configuration's running minimum.
      * CP_PAIRS_LANE: a sphere-cylinder pair whose squared axis distance shows
      * that it cannot lower the running minimum skips its square root.
      * CP_PAIRS_WAVE: the configurations of one hardware wave that belong to
@@ -149,9 +154,10 @@ typedef struct {
      * paths are bounded as one box).  CP_PAIRS_AUTO: CP_PAIRS_WAVE for
      * scenes of at least 48 cylinders and boxes, else CP_PAIRS_LANE (the
      * culling's fixed cost per wave outweighs its savings on small scenes;
-     * in a batch, CP_PAIRS_WAVE if any problem qualifies).  Skipped pairs
-     * cannot lower any minimum, so distances, costs and argmin records are
-     * bitwise those of CP_PAIRS_ALL in every mode. */
+     * in a batch, CP_PAIRS_WAVE if any problem qualifies; batched launches
+     * do not skip grid lookups).  Skipped pairs and lookups cannot lower any
+     * minimum, so distances, costs and argmin records are bitwise those of
+     * CP_PAIRS_ALL in every mode. */
     int32_t pair_filter;
 } cp_cost_params;
 

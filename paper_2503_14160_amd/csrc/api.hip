@@ -90,12 +90,13 @@ struct cp_plan {
     float4 *d_box = nullptr;
     float *d_qs = nullptr, *d_qg = nullptr;
     double2 *d_partial = nullptr;
+    float *d_sdf_lb = nullptr;
     PlanView view{};
 
     ~cp_plan() {
         DeviceGuard g(device);
         void *bufs[] = {d_joints, d_spheres, d_sphere_slot, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_hint, d_groups,
-                        d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial};
+                        d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial, d_sdf_lb};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
     }
@@ -429,6 +430,17 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     }
     v.sdf_h = scene->d_sdf ? scene->voxel : 1.0f;
     v.sdf_inv_h = 1.0f / v.sdf_h;
+    // block lower bounds of the grid, refreshed from the grid by every launch
+    // that uses them (the grid is borrowed and may change between calls)
+    v.sdf_lb = nullptr;
+    v.sdf_lb_buf = nullptr;
+    if (scene->d_sdf) {
+        size_t nb = 1;
+        for (int a = 0; a < 3; ++a) nb *= (size_t)(v.sdf_lbn[a] = ((v.sdf_n[a] - 2) >> 2) + 1);
+        e = hipMalloc((void **)&p->d_sdf_lb, nb * sizeof(float));
+        if (e != hipSuccess) return bail(hip_fail(e, "plan workspace"));
+        v.sdf_lb_buf = p->d_sdf_lb;
+    }
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return bail(hip_fail(e, "plan create"));
     *out = p;

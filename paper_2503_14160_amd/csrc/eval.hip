@@ -73,7 +73,8 @@ __device__ __forceinline__ float first_lane(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Minimum signed distance over every obstacle for G sphere centres.
+// Minimum signed distance over the primitive obstacles (ground, cylinders,
+// boxes) for G sphere centres; the grid term is taken by the caller.
 template <int G>
 __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&cx)[G], const float (&cy)[G],
                                                const float (&cz)[G], float (&v)[G]) {
@@ -107,10 +108,6 @@ __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&
         const float4 b0 = ldg(P.box, 2 * o), b1 = ldg(P.box, 2 * o + 1);
 #pragma unroll
         for (int s = 0; s < G; ++s) v[s] = fminf(v[s], box_sd(cx[s], cy[s], cz[s], b0, b1));
-    }
-    if (P.sdf) {
-#pragma unroll
-        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], sdf_query(P, cx[s], cy[s], cz[s], nullptr));
     }
 }
 
@@ -177,8 +174,8 @@ __device__ __forceinline__ void for_cells(const PlanView &P, const GroupDev &gr,
     }
 }
 
-// The minima are exact for the lanes with `in` set (one segment); the other
-// lanes' results are unspecified.  With `all` set (a non-finite centre in the
+// The minima over the primitive obstacles are exact for the lanes with `in`
+// set (one segment); the other lanes' results are unspecified.  With `all` set (a non-finite centre in the
 // segment, where the box bounds do not hold) every obstacle is a candidate.
 template <int G>
 __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const float (&cx)[G], const float (&cy)[G],
@@ -312,10 +309,6 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
             }
         }
     }
-    if (P.sdf) {
-#pragma unroll
-        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], sdf_query(P, cx[s], cy[s], cz[s], nullptr));
-    }
 }
 
 // Lane state of the running minimum over spheres.
@@ -363,6 +356,15 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
 #pragma unroll
     for (int i = 0; i < G; ++i) {
         const SphereDev sp = ldg(P.spheres, s0 + i);
+        if (P.sdf) {
+            // the grid term; skipped where the block's lower bound shows it
+            // cannot bring this sphere below the lane's running minimum
+            // (strictly, so ties keep their order)
+            int i0[3];
+            float f[3], dg[3];
+            sdf_cell(P, cx[i], cy[i], cz[i], i0, f, dg);
+            if (!P.sdf_lb || !(sdf_cell_bound(P, i0) - sp.r > best.d)) v[i] = fminf(v[i], sdf_interp(P, i0, f, dg, nullptr));
+        }
         float d = v[i] - sp.r;
         if (ARG) {
             if (d < best.d || (d == best.d && sp.orig < best.s)) {
@@ -975,8 +977,45 @@ size_t eval_partial_count(int B, int ns) {
     return (size_t)((N + kWave - 1) / kWave) * eval_slots(ns);
 }
 
-hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *partial, uint32_t *tape,
+// Per block of 4 x 4 x 4 cells, the smallest grid sample any of its cells
+// interpolates, less a margin for the rounding of the three interpolation
+// steps (each loses at most 3 units in the last place of the largest sample
+// magnitude A; the margin is 1e-6 (A + 1)): a lower bound of every value
+// sdf_interp computes in the block.
+__global__ __launch_bounds__(256) void k_sdf_bound(PlanView P) {
+    const int nbx = P.sdf_lbn[0], nby = P.sdf_lbn[1], nbz = P.sdf_lbn[2];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbx * nby * nbz) return;
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int nx = P.sdf_n[0], ny = P.sdf_n[1], nz = P.sdf_n[2];
+    float mn = kInf, mx = 0.0f;
+    for (int z = 4 * bz; z <= min(4 * bz + 4, nz - 1); ++z)
+        for (int y = 4 * by; y <= min(4 * by + 4, ny - 1); ++y)
+            for (int x = 4 * bx; x <= min(4 * bx + 4, nx - 1); ++x) {
+                const float val = P.sdf[((size_t)z * ny + y) * nx + x];
+                mn = fminf(mn, val);
+                mx = fmaxf(mx, fabsf(val));
+            }
+    P.sdf_lb_buf[b] = mn - (1e-6f + 1e-6f * mx);
+}
+
+// The view the evaluation kernels get: with a grid, its block bounds are
+// refreshed from the current grid first and switched on (not in the
+// every-pair mode, which takes every grid lookup too).
+static hipError_t view_with_sdf_bound(const PlanView &P, PlanView &Q, hipStream_t st) {
+    Q = P;
+    if (!P.sdf || !P.sdf_lb_buf || P.pair_filter == CP_PAIRS_ALL) return hipSuccess;
+    const int nb = P.sdf_lbn[0] * P.sdf_lbn[1] * P.sdf_lbn[2];
+    hipLaunchKernelGGL(k_sdf_bound, dim3((nb + 255) / 256), dim3(256), 0, st, P);
+    Q.sdf_lb = P.sdf_lb_buf;
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_fwd(const PlanView &P0, const float *W, int B, double2 *partial, uint32_t *tape,
                            float *cost, float *min_dist, uint8_t *flags, hipStream_t st) {
+    PlanView P;
+    const hipError_t eb = view_with_sdf_bound(P0, P, st);
+    if (eb != hipSuccess) return eb;
     const int64_t N = (int64_t)B * P.ns;
     const int slots = eval_slots(P.ns);
     const dim3 grid((unsigned)((N + 255) / 256));
@@ -1040,8 +1079,14 @@ hipError_t launch_batch_eval(const BatchProblem *probs, double2 *partial, int n,
     return hipGetLastError();
 }
 
-hipError_t launch_eval_bwd(const PlanView &P, const float *W, int B, const uint32_t *tape, const float *grad_cost,
+hipError_t launch_eval_bwd(const PlanView &P0, const float *W, int B, const uint32_t *tape, const float *grad_cost,
                            float *grad_W, hipStream_t st) {
+    // without a tape the minimising pair is found again (grid bounds in use)
+    PlanView P = P0;
+    if (!tape) {
+        const hipError_t eb = view_with_sdf_bound(P0, P, st);
+        if (eb != hipSuccess) return eb;
+    }
     if (tape)
         hipLaunchKernelGGL((k_eval_bwd<true, false>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
                            grad_W);

@@ -82,6 +82,12 @@ struct PlanView {
     const float *sdf;             // [nz][ny][nx] or null
     int32_t sdf_n[3];
     float sdf_o[3], sdf_inv_h, sdf_h;
+    // per block of 4 x 4 x 4 grid cells, a lower bound of every trilinear
+    // value computed in the block (null: not in use; the launchers that
+    // refresh it from the current grid set it)
+    const float *sdf_lb;
+    float *sdf_lb_buf;            // the plan's buffer for it (null without a grid)
+    int32_t sdf_lbn[3];           // blocks per axis
 };
 
 // ---------------------------------------------------------------------------
@@ -128,12 +134,11 @@ __device__ __forceinline__ float box_sd(float cx, float cy, float cz, float4 b0,
     return fsqrt(o2) + fminf(fmaxf(qx, fmaxf(qy, qz)), 0.0f);
 }
 
-// trilinear signed-distance lookup (voxel-centre samples, clamped coordinates)
-__device__ __forceinline__ float sdf_query(const PlanView &P, float cx, float cy, float cz, float *grad) {
+// grid cell of a point (clamped to the grid) and its fractional position
+__device__ __forceinline__ void sdf_cell(const PlanView &P, float cx, float cy, float cz, int (&i0)[3],
+                                         float (&f)[3], float (&dg)[3]) {
     float g[3] = {(cx - P.sdf_o[0]) * P.sdf_inv_h - 0.5f, (cy - P.sdf_o[1]) * P.sdf_inv_h - 0.5f,
                   (cz - P.sdf_o[2]) * P.sdf_inv_h - 0.5f};
-    int i0[3];
-    float f[3], dg[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float fl = floorf(g[a]);
@@ -145,6 +150,16 @@ __device__ __forceinline__ float sdf_query(const PlanView &P, float cx, float cy
         i0[a] = (int)il;
         f[a] = fr;
     }
+}
+
+// lower bound of the trilinear value anywhere in cell i0 (P.sdf_lb set)
+__device__ __forceinline__ float sdf_cell_bound(const PlanView &P, const int (&i0)[3]) {
+    return P.sdf_lb[((size_t)(i0[2] >> 2) * P.sdf_lbn[1] + (i0[1] >> 2)) * P.sdf_lbn[0] + (i0[0] >> 2)];
+}
+
+// trilinear interpolation in cell i0 at fractional position f
+__device__ __forceinline__ float sdf_interp(const PlanView &P, const int (&i0)[3], const float (&f)[3],
+                                           const float (&dg)[3], float *grad) {
     const int nx = P.sdf_n[0], ny = P.sdf_n[1];
     const float *base = P.sdf + ((size_t)i0[2] * ny + i0[1]) * nx + i0[0];
     const size_t sy = nx, sz = (size_t)nx * ny;
@@ -169,6 +184,14 @@ __device__ __forceinline__ float sdf_query(const PlanView &P, float cx, float cy
         grad[2] = gz * dg[2] * P.sdf_inv_h;
     }
     return phi;
+}
+
+// trilinear signed-distance lookup (voxel-centre samples, clamped coordinates)
+__device__ __forceinline__ float sdf_query(const PlanView &P, float cx, float cy, float cz, float *grad) {
+    int i0[3];
+    float f[3], dg[3];
+    sdf_cell(P, cx, cy, cz, i0, f, dg);
+    return sdf_interp(P, i0, f, dg, grad);
 }
 
 // ---------------------------------------------------------------------------

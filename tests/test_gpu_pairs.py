@@ -142,24 +142,40 @@ def test_pairs_random_configs(cp):
         np.testing.assert_array_equal(res[cp.PAIRS_ALL][1], res[mode][1])
 
 
-def test_pairs_sdf_scene(cp):
-    """A grid together with trees, boxes and the ground (the grid term is
-    never culled; the primitives are)."""
+@pytest.mark.parametrize("scene", ["grid_only", "mixed"])
+def test_pairs_sdf_scene(cp, scene):
+    """A grid alone, and a grid together with trees, boxes and the ground:
+    every mode but CP_PAIRS_ALL skips grid lookups by the block lower bounds
+    (and culls the primitives), with bitwise the same results, forward with
+    the tape and backward without it.  The grid is then changed in place and
+    the results must follow it (the bounds are refreshed by every call)."""
     prob = synth.c4_sdf(n_points=100_000)
     spec = prob.sdf
     sdf = cp.sdf_build(torch.from_numpy(prob.lidar).cuda(), spec)
     rng = np.random.default_rng(708)
-    mixed = synth.c0_plain().scene
-    prob = dataclasses.replace(prob, scene=mixed)
-    W = torch.from_numpy(synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, 64, prob.cost.K,
+    if scene == "mixed":
+        prob = dataclasses.replace(prob, scene=synth.c0_plain().scene)
+    W = torch.from_numpy(synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, 192, prob.cost.K,
                                                 sigma=0.3)).cuda()
-    out = {}
-    for mode in (cp.PAIRS_ALL, cp.PAIRS_WAVE):
-        plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=64, sdf=sdf, sdf_spec=spec, pair_filter=mode)
+    gc = torch.linspace(0.5, 2.0, W.shape[0], device="cuda")
+    plans = {}
+    for mode in (cp.PAIRS_ALL, cp.PAIRS_LANE, cp.PAIRS_WAVE, cp.PAIRS_AUTO):
+        plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=W.shape[0], sdf=sdf, sdf_spec=spec, pair_filter=mode)
         plan.set_endpoints(prob.q_start, prob.q_goal)
-        out[mode] = [_bits(x) for x in plan.eval(W, tape=True)]
-    for a, b in zip(out[cp.PAIRS_ALL], out[cp.PAIRS_WAVE]):
-        np.testing.assert_array_equal(a, b)
+        plans[mode] = plan
+    for step in ("built", "changed"):
+        print(f"[pairs] sdf {scene} {step}", flush=True)
+        out = {}
+        for mode, plan in plans.items():
+            out[mode] = [_bits(x) for x in plan.eval(W, tape=True)] + [_bits(plan.backward(W, gc, None))]
+        for mode in (cp.PAIRS_LANE, cp.PAIRS_WAVE, cp.PAIRS_AUTO):
+            for name, a, b in zip(("cost", "min_dist", "flags", "tape", "grad"), out[cp.PAIRS_ALL], out[mode]):
+                np.testing.assert_array_equal(a, b, err_msg=f"sdf {scene} {step}: {name} differs in mode {mode}")
+        if step == "built":
+            before = out[cp.PAIRS_ALL][1].copy()
+            sdf.sub_(0.25)  # every distance 25 cm smaller: bounds from the old grid would skip wrongly
+            torch.cuda.synchronize()
+    assert not np.array_equal(before, out[cp.PAIRS_ALL][1])
 
 
 def test_pairs_batch(cp):
