@@ -317,7 +317,7 @@ def bench_sdf(args, torch, cp, prob):
                                "peak": PEAK_HBM / 1e9,
                                "frac": queries * SDF_QUERY_BYTES / (fwd_ms * 1e-3) / PEAK_HBM, "traffic": None,
                                "note": "algorithmic bytes: 8 FP32 corners for every sphere's query; the kernel "
-                                       "skips the queries that the grid's 4x4x4-block lower bounds show cannot lower "
+                                       "skips the queries that the grid's 2x2x2-block lower bounds show cannot lower "
                                        "the minimum (bitwise-identical results) and the 32 MiB grid is cache "
                                        "resident, so this rate exceeds HBM bandwidth"})
 

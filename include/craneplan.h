@@ -141,7 +141,7 @@ typedef struct {
     int32_t max_B;    /* largest batch any call on this plan will pass */
     /* CP_PAIRS_ALL: every sphere-obstacle pair and every grid lookup is
      * evaluated in full.  In the other modes a sphere's grid lookup is
-     * skipped where a lower bound of the grid over its 4 x 4 x 4 block of
+     * skipped where a lower bound of the grid over its 2 x 2 x 2 block of
      * cells (refreshed from the grid by each evaluation call, so the borrowed
      * grid may change between calls) shows that it cannot bring the sphere
      * below the configuration's running minimum.

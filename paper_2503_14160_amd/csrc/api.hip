@@ -436,7 +436,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     v.sdf_lb_buf = nullptr;
     if (scene->d_sdf) {
         size_t nb = 1;
-        for (int a = 0; a < 3; ++a) nb *= (size_t)(v.sdf_lbn[a] = ((v.sdf_n[a] - 2) >> 2) + 1);
+        for (int a = 0; a < 3; ++a) nb *= (size_t)(v.sdf_lbn[a] = ((v.sdf_n[a] - 2) >> kSdfBlockLog2) + 1);
         e = hipMalloc((void **)&p->d_sdf_lb, nb * sizeof(float));
         if (e != hipSuccess) return bail(hip_fail(e, "plan workspace"));
         v.sdf_lb_buf = p->d_sdf_lb;

@@ -977,7 +977,7 @@ size_t eval_partial_count(int B, int ns) {
     return (size_t)((N + kWave - 1) / kWave) * eval_slots(ns);
 }
 
-// Per block of 4 x 4 x 4 cells, the smallest grid sample any of its cells
+// Per block of cells (2 x 2 x 2), the smallest grid sample any of its cells
 // interpolates, less a margin for the rounding of the three interpolation
 // steps (each loses at most 3 units in the last place of the largest sample
 // magnitude A; the margin is 1e-6 (A + 1)): a lower bound of every value
@@ -989,9 +989,10 @@ __global__ __launch_bounds__(256) void k_sdf_bound(PlanView P) {
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int nx = P.sdf_n[0], ny = P.sdf_n[1], nz = P.sdf_n[2];
     float mn = kInf, mx = 0.0f;
-    for (int z = 4 * bz; z <= min(4 * bz + 4, nz - 1); ++z)
-        for (int y = 4 * by; y <= min(4 * by + 4, ny - 1); ++y)
-            for (int x = 4 * bx; x <= min(4 * bx + 4, nx - 1); ++x) {
+    const int w = 1 << kSdfBlockLog2;
+    for (int z = w * bz; z <= min(w * bz + w, nz - 1); ++z)
+        for (int y = w * by; y <= min(w * by + w, ny - 1); ++y)
+            for (int x = w * bx; x <= min(w * bx + w, nx - 1); ++x) {
                 const float val = P.sdf[((size_t)z * ny + y) * nx + x];
                 mn = fminf(mn, val);
                 mx = fmaxf(mx, fabsf(val));

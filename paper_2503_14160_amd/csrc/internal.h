@@ -82,7 +82,7 @@ struct PlanView {
     const float *sdf;             // [nz][ny][nx] or null
     int32_t sdf_n[3];
     float sdf_o[3], sdf_inv_h, sdf_h;
-    // per block of 4 x 4 x 4 grid cells, a lower bound of every trilinear
+    // per block of 2 x 2 x 2 grid cells, a lower bound of every trilinear
     // value computed in the block (null: not in use; the launchers that
     // refresh it from the current grid set it)
     const float *sdf_lb;
@@ -152,9 +152,13 @@ __device__ __forceinline__ void sdf_cell(const PlanView &P, float cx, float cy, 
     }
 }
 
+// grid cells per bound block along each axis: 1 << kSdfBlockLog2
+constexpr int kSdfBlockLog2 = 1;
+
 // lower bound of the trilinear value anywhere in cell i0 (P.sdf_lb set)
 __device__ __forceinline__ float sdf_cell_bound(const PlanView &P, const int (&i0)[3]) {
-    return P.sdf_lb[((size_t)(i0[2] >> 2) * P.sdf_lbn[1] + (i0[1] >> 2)) * P.sdf_lbn[0] + (i0[0] >> 2)];
+    const int k = kSdfBlockLog2;
+    return P.sdf_lb[((size_t)(i0[2] >> k) * P.sdf_lbn[1] + (i0[1] >> k)) * P.sdf_lbn[0] + (i0[0] >> k)];
 }
 
 // trilinear interpolation in cell i0 at fractional position f
