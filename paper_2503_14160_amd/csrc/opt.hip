@@ -314,13 +314,14 @@ __global__ __launch_bounds__(kSelThreads) void k_rerank(OptView O) {
 // mean and covariance update (steps 4-6) and best-so-far
 // ---------------------------------------------------------------------------
 
-// One workgroup per 16 x 16 tile of the lower triangle of C.  Every workgroup
-// first forms the means of its tile's rows and columns (each a sum over the
-// elites in rank order, the same arithmetic in every workgroup, so all hold
-// identical values; diagonal tiles store theirs), then accumulates its
-// entries about those means.  Elites are staged through LDS 256 at a time.
-constexpr int kUpdTile = 16;
-constexpr int kUpdThreads = kUpdTile * kUpdTile;
+// One workgroup per 8 x 8 tile of the lower triangle of C, sixteen threads per
+// entry.  Every workgroup first forms the means of its tile's rows and columns
+// (the same arithmetic in every workgroup, so all hold identical values;
+// diagonal tiles store theirs), then accumulates its entries about those
+// means.  Elites are staged through LDS 256 at a time.
+constexpr int kUpdTile = 8;
+constexpr int kUpdParts = 16;  // interleaved partial sums per entry (elites j = part mod 16)
+constexpr int kUpdThreads = kUpdTile * kUpdTile * kUpdParts;
 constexpr int kUpdChunk = 256;
 constexpr int kUpdTilesPerDim = (CP_MAX_DIM + kUpdTile - 1) / kUpdTile;
 constexpr int kUpdTiles = kUpdTilesPerDim * (kUpdTilesPerDim + 1) / 2;
@@ -348,11 +349,13 @@ __device__ __forceinline__ void update_tile(const PlanView &P, const OptView &O,
     const int tj = t - ti * (ti + 1) / 2;
     if (ti >= nt) return;  // whole workgroup
     const int r0 = ti * kUpdTile, c0 = tj * kUpdTile;
-    const int r = tid / kUpdTile, c = tid % kUpdTile;
+    const int part = tid / (kUpdTile * kUpdTile), ent = tid % (kUpdTile * kUpdTile);
+    const int r = ent / kUpdTile, c = ent % kUpdTile;
     __shared__ double xr[kUpdChunk][kUpdTile], xc[kUpdChunk][kUpdTile];
     __shared__ double wch[kUpdChunk];
     __shared__ int ech[kUpdChunk];
     __shared__ double mr[kUpdTile], mc[kUpdTile];
+    __shared__ double pm[kUpdParts][2 * kUpdTile], pc[kUpdParts][kUpdTile * kUpdTile];
     __shared__ int s_improved;
     // stage elites j0 .. j0 + nj - 1 of the tile's rows and columns (minus the
     // means once they are known)
@@ -374,19 +377,28 @@ __device__ __forceinline__ void update_tile(const PlanView &P, const OptView &O,
         }
         __syncthreads();
     };
-    // means: sum_j w_j x_(j), in rank order
+    // Every sum over the elites is taken as 16 interleaved partial sums
+    // (ranks j = part mod 16, each in rank order) added in part order: the
+    // same arithmetic in every workgroup, whatever the launch.
+    // means: sum_j w_j x_(j)
     double m = 0.0;
     for (int j0 = 0; j0 < nu; j0 += kUpdChunk) {
         const int nj = min(kUpdChunk, nu - j0);
         stage(j0, nj, false);
-        if (tid < 2 * kUpdTile) {
-            for (int jj = 0; jj < nj; ++jj)
-                m = fma(wch[jj], tid < kUpdTile ? xr[jj][tid] : xc[jj][tid - kUpdTile], m);
+        if (ent < 2 * kUpdTile) {
+            for (int jj = part; jj < nj; jj += kUpdParts)
+                m = fma(wch[jj], ent < kUpdTile ? xr[jj][ent] : xc[jj][ent - kUpdTile], m);
         }
         __syncthreads();
     }
-    if (tid < kUpdTile) mr[tid] = m;
-    else if (tid < 2 * kUpdTile) mc[tid - kUpdTile] = m;
+    if (ent < 2 * kUpdTile) pm[part][ent] = m;
+    __syncthreads();
+    if (tid < 2 * kUpdTile) {
+        double s = pm[0][tid];
+        for (int q = 1; q < kUpdParts; ++q) s += pm[q][tid];
+        if (tid < kUpdTile) mr[tid] = s;
+        else mc[tid - kUpdTile] = s;
+    }
     __syncthreads();
     if (ti == tj && tid < kUpdTile && r0 + tid < D) O.mu[r0 + tid] = mr[tid];
     // covariance about the new mean: sum_j w_j (x_(j) - mu)(x_(j) - mu)^T + eps I
@@ -397,11 +409,15 @@ __device__ __forceinline__ void update_tile(const PlanView &P, const OptView &O,
         const int nj = min(kUpdChunk, nu - j0);
         stage(j0, nj, true);
         if (mine)
-            for (int jj = 0; jj < nj; ++jj) acc = fma(wch[jj] * xr[jj][r], xc[jj][c], acc);
+            for (int jj = part; jj < nj; jj += kUpdParts) acc = fma(wch[jj] * xr[jj][r], xc[jj][c], acc);
         __syncthreads();
     }
-    if (mine) {
-        const double v = acc + (e1 == e2 ? O.eps : 0.0);
+    pc[part][ent] = acc;
+    __syncthreads();
+    if (part == 0 && mine) {
+        double v = pc[0][ent];
+        for (int q = 1; q < kUpdParts; ++q) v += pc[q][ent];
+        v += e1 == e2 ? O.eps : 0.0;
         O.C[(size_t)e1 * D + e2] = v;
         O.C[(size_t)e2 * D + e1] = v;
     }
