@@ -72,7 +72,7 @@ __global__ void k_init_state(PlanView P, OptView O, float sigma0) {
 constexpr int kSampleTile = 16;  // paths per block
 
 __device__ __forceinline__ void sample_body(const PlanView &P, const OptView &O, int tile) {
-    __shared__ double z[kSampleTile][CP_MAX_DIM];
+    __shared__ double z[kSampleTile][CP_MAX_DIM + 1];  // padded rows: lanes of one column read across paths
     const int D = O.D;
     const int b0 = tile * kSampleTile;
     const uint32_t t = (uint32_t)*O.t;
@@ -91,8 +91,10 @@ __device__ __forceinline__ void sample_body(const PlanView &P, const OptView &O,
     }
     __syncthreads();
     const int n = P.n_joints;
+    // lanes run over the tile's paths for one coordinate e: the row of L is
+    // read once per coordinate (a broadcast) rather than once per lane
     for (int idx = threadIdx.x; idx < kSampleTile * D; idx += blockDim.x) {
-        const int bl = idx / D, e = idx % D, b = b0 + bl;
+        const int bl = idx % kSampleTile, e = idx / kSampleTile, b = b0 + bl;
         if (b >= O.B) continue;
         const double *Lr = O.L + (size_t)e * D;
         double s = O.mu[e];
