@@ -790,8 +790,6 @@ __device__ __forceinline__ void collision_grad(const PlanView &P, const float (&
     }
 }
 
-constexpr int kBwdThreads = 256;
-constexpr int kBwdWaves = kBwdThreads / kWave;
 constexpr int kMaxCtrl = CP_MAX_K + 6;
 // control points one wave can touch: 64 checkpoints span at most 64 windows
 // of four consecutive control points
@@ -800,12 +798,17 @@ constexpr int kWaveCtrl = kWave + 3;
 // One workgroup per path.  Each lane takes one checkpoint and forms its
 // contribution to the four control points of its span window; per wave and
 // control point the contributions are summed by DPP reductions (fixed order)
-// and the wave sums are added in wave order in double precision.
-template <bool TAPE, bool CULL>
-__global__ __launch_bounds__(kBwdThreads) void k_eval_bwd(PlanView P, const float *__restrict__ W, int B,
+// and the wave sums are added in wave order in double precision.  A
+// workgroup of NW waves takes 64 NW checkpoints per round; since every wave
+// covers the same 64 checkpoints whatever NW, and the wave sums are added in
+// the same order, the gradient does not depend on NW (16 for small launches,
+// whose few workgroups would otherwise run several rounds each).
+template <bool TAPE, bool CULL, int NW>
+__global__ __launch_bounds__(NW * 64) void k_eval_bwd(PlanView P, const float *__restrict__ W, int B,
                                                           const uint32_t *__restrict__ tape,
                                                           const float *__restrict__ grad_cost,
                                                           float *__restrict__ grad_W) {
+    constexpr int kBwdThreads = NW * kWave, kBwdWaves = NW;
     __shared__ float part[kBwdWaves][kWaveCtrl][CP_MAX_JOINTS];
     __shared__ int wlo[kBwdWaves], whi[kBwdWaves];
     __shared__ double acc[kMaxCtrl * CP_MAX_JOINTS];
@@ -1080,6 +1083,9 @@ hipError_t launch_batch_eval(const BatchProblem *probs, double2 *partial, int n,
     return hipGetLastError();
 }
 
+// paths up to which the adjoint runs 16 waves per path
+constexpr int kBwdWidePaths = 256;
+
 hipError_t launch_eval_bwd(const PlanView &P0, const float *W, int B, const uint32_t *tape, const float *grad_cost,
                            float *grad_W, hipStream_t st) {
     // without a tape the minimising pair is found again (grid bounds in use)
@@ -1088,15 +1094,22 @@ hipError_t launch_eval_bwd(const PlanView &P0, const float *W, int B, const uint
         const hipError_t eb = view_with_sdf_bound(P0, P, st);
         if (eb != hipSuccess) return eb;
     }
-    if (tape)
-        hipLaunchKernelGGL((k_eval_bwd<true, false>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
+    // one workgroup per path: 4 waves, or 16 when there are few paths
+    const bool wide = B <= kBwdWidePaths;
+    if (tape && wide)
+        hipLaunchKernelGGL((k_eval_bwd<true, false, 16>), dim3(B), dim3(1024), 0, st, P, W, B, tape, grad_cost, grad_W);
+    else if (tape)
+        hipLaunchKernelGGL((k_eval_bwd<true, false, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W);
+    else if (use_cull(P) && wide)
+        hipLaunchKernelGGL((k_eval_bwd<false, true, 16>), dim3(B), dim3(1024), 0, st, P, W, B, tape, grad_cost,
                            grad_W);
     else if (use_cull(P))
-        hipLaunchKernelGGL((k_eval_bwd<false, true>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
+        hipLaunchKernelGGL((k_eval_bwd<false, true, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W);
+    else if (wide)
+        hipLaunchKernelGGL((k_eval_bwd<false, false, 16>), dim3(B), dim3(1024), 0, st, P, W, B, tape, grad_cost,
                            grad_W);
     else
-        hipLaunchKernelGGL((k_eval_bwd<false, false>), dim3(B), dim3(kBwdThreads), 0, st, P, W, B, tape, grad_cost,
-                           grad_W);
+        hipLaunchKernelGGL((k_eval_bwd<false, false, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W);
     return hipGetLastError();
 }
 

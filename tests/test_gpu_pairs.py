@@ -260,10 +260,11 @@ def test_pairs_degenerate_scenes(cp, name):
 @pytest.mark.parametrize("wl,n_big,n_small", [("c1", 512, (64, 200, 7)), ("c0", 2048, (256, 1000, 1)),
                                               ("ragged", 6000, (100, 333, 2000))])
 def test_small_launch_split_matches_full_launch(cp, wl, n_big, n_small):
-    """Launches of few waves share each wave's sphere groups out over 2 or 4
-    waves; a path's cost, distance, flag and argmin record must not depend on
-    that: the first n paths evaluated alone (a split launch) equal the same
-    paths inside a population large enough for one wave per 64 configurations."""
+    """Launches of few waves share each wave's sphere groups out over 2, 4 or 8
+    waves, and the adjoint of few paths runs 16 waves per path instead of 4; a
+    path's cost, distance, flag, argmin record and gradient must not depend on
+    that: the first n paths evaluated alone (split launches) equal the same
+    paths inside a population large enough for the plain launches."""
     if wl == "c1":
         prob = synth.c1_full()
     elif wl == "c0":
@@ -274,14 +275,21 @@ def test_small_launch_split_matches_full_launch(cp, wl, n_big, n_small):
     rng = np.random.default_rng(720)
     W = synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, n_big, prob.cost.K, sigma=0.3)
     Wt = torch.from_numpy(np.ascontiguousarray(W, dtype=np.float32)).cuda()
+    gc = torch.linspace(0.5, 2.0, n_big, device="cuda")
     for mode in (cp.PAIRS_ALL, cp.PAIRS_LANE, cp.PAIRS_WAVE):
         plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=n_big, pair_filter=mode)
         plan.set_endpoints(prob.q_start, prob.q_goal)
-        big = [_bits(t) for t in plan.eval(Wt, tape=True)]
+        cost, md, fl, tape = plan.eval(Wt, tape=True)
+        big = [_bits(t) for t in (cost, md, fl, tape)]
+        big += [_bits(plan.backward(Wt, gc, tape)), _bits(plan.backward(Wt, gc, None))]
         for n in n_small:
             print(f"[split] {wl} mode={mode} {n} of {n_big} paths", flush=True)
-            small = [_bits(t) for t in plan.eval(Wt[:n].contiguous(), tape=True)]
-            for name, a, b in zip(("cost", "min_dist", "flags", "tape"), big, small):
+            Ws = Wt[:n].contiguous()
+            cost, md, fl, tape = plan.eval(Ws, tape=True)
+            small = [_bits(t) for t in (cost, md, fl, tape)]
+            small += [_bits(plan.backward(Ws, gc[:n].contiguous(), tape)),
+                      _bits(plan.backward(Ws, gc[:n].contiguous(), None))]
+            for name, a, b in zip(("cost", "min_dist", "flags", "tape", "grad", "grad without tape"), big, small):
                 np.testing.assert_array_equal(a[:n], b, err_msg=f"{wl} mode {mode} n={n}: {name}")
 
 
