@@ -616,7 +616,8 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
         if (opt->npol > 0) {
             CP_HIP(launch_polish_gather(P, v, st), "polish gather");
             for (int s = 0; s < opt->prm.polish_steps; ++s) {
-                CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, opt->d_tape_p, v.cost_p, v.min_dist, nullptr,
+                // (only the argmin tape of these evaluations is used)
+                CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, opt->d_tape_p, nullptr, nullptr, nullptr,
                                        st),
                        "polish eval");
                 CP_HIP(launch_eval_bwd(P, v.Wp, opt->npol, opt->d_tape_p, v.ones, v.grad_p, st), "polish adjoint");

@@ -1064,6 +1064,7 @@ hipError_t launch_eval_fwd(const PlanView &P0, const float *W, int B, double2 *p
         hipLaunchKernelGGL((k_eval_fwd<false, false>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (!cost && !min_dist && !flags) return hipSuccess;  // only the tape is wanted
     hipLaunchKernelGGL(k_eval_reduce, dim3((B + 255) / 256), dim3(256), 0, st, partial, slots, B, P.ns, P.margin,
                        cost, min_dist, flags);
     return hipGetLastError();

@@ -8,6 +8,7 @@ namespace cp {
 // evaluation (eval.hip)
 int eval_slots(int ns);
 size_t eval_partial_count(int B, int ns);
+// (cost, min_dist and flags all null: only the tape is written)
 hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *partial, uint32_t *tape, float *cost,
                            float *min_dist, uint8_t *flags, hipStream_t st);
 hipError_t launch_eval_bwd(const PlanView &P, const float *W, int B, const uint32_t *tape, const float *grad_cost,
