@@ -38,6 +38,13 @@ PEAK_HBM = 8.0e12     # MI355X HBM3E bytes/s
 # scaled by the same counter on a plain 1 GiB copy (profiles/k_eval_fwd_c1_full_hbm_bytes.md);
 # None once the kernel has changed since the counters were taken
 TRAFFIC_BYTES = 19.7e6
+# VALU instructions per wave of the culling k_eval_fwd on the bench's timed
+# launches (c1_full, converged population), from rocprofv3 SQ_INSTS_VALU /
+# SQ_WAVES (profiles/k_eval_fwd_c1_full_sq_counters.md); None once the kernel
+# has changed since.  The VALU issue ceiling: one wave64 FP32 instruction per
+# 4 cycles per SIMD (16 lanes; packed FP32 is not used), 1024 SIMDs, 2.4 GHz.
+VALU_PER_WAVE = 14190
+PEAK_VALU_ISSUE = 1024 * 2.4e9 / 4  # wave instructions per second
 # algorithmic bytes of one trilinear signed-distance query: 8 FP32 corners
 SDF_QUERY_BYTES = 32
 
@@ -128,6 +135,13 @@ def bench_iterations(args, torch, cp, prob, with_roofline):
     plain_ms = _timed(torch, lambda: plain.eval_into(W, c_plain, md), max(1, args.eval_reps // 3))
     out.update({
         "eval_ms": eval_ms,
+        "executed_valu": None if VALU_PER_WAVE is None else {
+            "valu_per_wave": VALU_PER_WAVE, "waves": (configs + 63) // 64,
+            "achieved": VALU_PER_WAVE * ((configs + 63) // 64) / (eval_ms * 1e-3) / 1e9,
+            "peak": PEAK_VALU_ISSUE / 1e9, "unit": "G wave-instructions/s",
+            "frac": VALU_PER_WAVE * ((configs + 63) // 64) / (eval_ms * 1e-3) / PEAK_VALU_ISSUE,
+            "note": "instructions the culling kernel executes (counters), over its live time: the kernel is "
+                    "VALU-issue bound, so time falls only with the instruction count"},
         "eval_configs_per_s": configs / (eval_ms * 1e-3),
         "roofline": {"bound": "alu", "kernel": "k_eval_fwd", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
