@@ -227,15 +227,14 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
                     r[s] = in ? fsqrt(__builtin_fmaf(dx, dx, dy * dy)) - c.z : -kInf;
                 }
             }
-            if (G == 1)
-                r[0] = wave_max_u(r[0]);
-            else
-                wave_max4(r[0], r[1], r[2], r[3]);
+            // one wave maximum over the lanes' largest U_s: each sphere's
+            // threshold U_s + slack(|U_s|) is at most U + slack(max(|U|, R_max))
+            // since -R_max <= U_s <= U
+            float rl = r[0];
 #pragma unroll
-            for (int s = 0; s < G; ++s) {
-                const float U = r[s];
-                umax = fmaxf(umax, U + (kCullAbs + kCullRel * (fabsf(U) + 2.0f * gr.rmax)));
-            }
+            for (int s = 1; s < G; ++s) rl = fmaxf(rl, r[s]);
+            const float U = wave_max_u(rl);
+            umax = U + (kCullAbs + kCullRel * (fmaxf(fabsf(U), gr.rmax) + 2.0f * gr.rmax));
         }
         const float e2 = fmaxf(umax + gr.rmax, 0.0f);
         // candidates: a cylinder can lower sphere s's minimum only if its
