@@ -241,7 +241,8 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
         // axis comes within U_s + R (+ slack) of s's centres, so within
         // max_s U_s + R of the group's box (within e2 of it for the grid
         // cells); a candidate is evaluated exactly for every sphere of the
-        // group, its data read out of its lane once.  (Per-sphere boxes would
+        // group, its entry fetched once through the scalar cache (by the
+        // index read out of its lane).  (Per-sphere boxes would
         // cull a few more pairs, about 7 % at c1, for four times the box
         // reductions and tests.)
         float a[G];
@@ -258,9 +259,8 @@ __device__ __forceinline__ void spheres_min_sd_culled(const PlanView &P, const f
             while (any) {
                 const int l = (int)__builtin_ctzll(any);
                 any &= any - 1;
-                const float ox = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cc.x), l));
-                const float oy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cc.y), l));
-                const float R = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cc.z), l));
+                const float4 o = ldg(P.cyl_cell, __builtin_amdgcn_readlane(idx, l));
+                const float ox = o.x, oy = o.y, R = o.z;
 #pragma unroll
                 for (int s = 0; s < G; ++s) {
                     const float dx = cx[s] - ox, dy = cy[s] - oy;
