@@ -365,6 +365,38 @@ def test_sampling_parity_dims(cp, kind, K):
     np.testing.assert_allclose(W, Wref, rtol=0, atol=2e-6 * np.maximum(1, np.abs(Wref)).max())
 
 
+@pytest.mark.parametrize("K,B,nu", [(16, 4096, 819), (24, 2048, 1000), (5, 512, 7)])
+def test_update_parity_many_elites(cp, K, B, nu):
+    """Steps (4)-(6) with many elites (each entry of C is a sum over nu elites,
+    taken on the device as 16 interleaved partial sums): from a given state,
+    one device iteration's new mean and covariance equal the oracle's update
+    of the same elites (the device's selection) drawn from the oracle's own
+    samples of that state."""
+    import dataclasses
+    base = synth.c1_full()
+    prob = dataclasses.replace(base, cost=dataclasses.replace(base.cost, K=K, M=8),
+                               opt=synth.OptParams(B=B, nu=nu, sigma0=0.2, eps=1e-6, seed=31, T=1))
+    D = K * prob.robot.n_active
+    rng = np.random.default_rng(34)
+    X = rng.normal(size=(D, 2 * D)) * 0.05
+    C = X @ X.T / (2 * D) + 1e-3 * np.eye(D)
+    mu = oracle.initial_mean(prob.robot, prob.q_start, prob.q_goal, K) + rng.normal(size=D) * 0.01
+    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B)
+    plan.set_endpoints(prob.q_start, prob.q_goal)
+    opt = cp.Optimizer(plan, prob.opt)
+    print(f"[update parity] D={D} B={B} nu={nu}", flush=True)
+    opt.set_state(mu, C, 2)
+    opt.step(1)
+    elite = opt.last()[2].cpu().numpy().astype(np.int64)
+    st = opt.get_state()
+    orc = oracle.Optimizer(prob)
+    orc.set_state(mu, C, 2)
+    xi = orc.sample()
+    mu_ref, C_ref = oracle.update(xi[elite], oracle.log_rank_weights(nu), prob.opt.eps)
+    np.testing.assert_allclose(st["mu"], mu_ref, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(st["C"], C_ref, rtol=0, atol=1e-13 * np.abs(C_ref).max() + 1e-15)
+
+
 def test_optimizer_runs_and_is_deterministic(cp):
     prob = synth.c0_plain()
     out = []
