@@ -91,12 +91,13 @@ struct cp_plan {
     float *d_qs = nullptr, *d_qg = nullptr;
     double2 *d_partial = nullptr;
     float *d_sdf_lb = nullptr;
+    float *d_clr = nullptr;
     PlanView view{};
 
     ~cp_plan() {
         DeviceGuard g(device);
         void *bufs[] = {d_joints, d_spheres, d_sphere_slot, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_hint, d_groups,
-                        d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial, d_sdf_lb};
+                        d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial, d_sdf_lb, d_clr};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
     }
@@ -440,6 +441,37 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         e = hipMalloc((void **)&p->d_sdf_lb, nb * sizeof(float));
         if (e != hipSuccess) return bail(hip_fail(e, "plan workspace"));
         v.sdf_lb_buf = p->d_sdf_lb;
+    }
+    // clearance grid (wave culling, primitive scenes; on the small scenes of
+    // the other modes the per-group test costs more than it saves): over the
+    // obstacles' footprints plus 2 m on every side, cells of at least 0.1 m,
+    // at most 512 per axis
+    v.clr = nullptr;
+    if (!scene->d_sdf && pair_filter == CP_PAIRS_WAVE && (p->n_cyl > 0 || p->n_box > 0)) {
+        double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+        for (int o = 0; o < p->n_cyl; ++o) {
+            const float *y = scene->cyl + 5 * o;
+            x0 = std::min(x0, (double)y[0] - y[2]); x1 = std::max(x1, (double)y[0] + y[2]);
+            y0 = std::min(y0, (double)y[1] - y[2]); y1 = std::max(y1, (double)y[1] + y[2]);
+        }
+        for (int o = 0; o < p->n_box; ++o) {
+            const float *y = scene->box + 6 * o;
+            x0 = std::min(x0, (double)y[0] - y[3]); x1 = std::max(x1, (double)y[0] + y[3]);
+            y0 = std::min(y0, (double)y[1] - y[4]); y1 = std::max(y1, (double)y[1] + y[4]);
+        }
+        const double pad = 2.0;
+        x0 -= pad; y0 -= pad; x1 += pad; y1 += pad;
+        const double h = std::max({0.1, (x1 - x0) / 512.0, (y1 - y0) / 512.0});
+        v.clr_nx = std::max(1, (int)std::ceil((x1 - x0) / h));
+        v.clr_ny = std::max(1, (int)std::ceil((y1 - y0) / h));
+        v.clr_x0 = (float)x0; v.clr_y0 = (float)y0;
+        v.clr_h = (float)h; v.clr_inv = (float)(1.0 / h);
+        // beyond the grid every footprint is at least `pad` away
+        v.clr_out = (float)(pad - 1e-4 - 1e-6 * (std::max({std::fabs(x0), std::fabs(x1), std::fabs(y0), std::fabs(y1)}) + pad + 1.0));
+        e = hipMalloc((void **)&p->d_clr, (size_t)v.clr_nx * v.clr_ny * sizeof(float));
+        if (e != hipSuccess) return bail(hip_fail(e, "plan workspace"));
+        if ((e = launch_clearance(v, p->d_clr, nullptr)) != hipSuccess) return bail(hip_fail(e, "clearance grid"));
+        v.clr = p->d_clr;
     }
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return bail(hip_fail(e, "plan create"));

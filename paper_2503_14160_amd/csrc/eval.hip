@@ -336,6 +336,21 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
         xf_point(T, sp.lx, sp.ly, sp.lz, cx[i], cy[i], cz[i]);
         finite = finite && fabsf(cx[i]) < kInf && fabsf(cy[i]) < kInf && fabsf(cz[i]) < kInf;
     }
+    if (CULL && P.clr) {
+        // the whole group is skipped when, on every lane, a lower bound of
+        // each of its spheres' distances (the clearance grid and the ground)
+        // is strictly above the lane's running minimum: no pair of the group
+        // could lower it or tie with it
+        bool above = finite;
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const SphereDev sp = ldg(P.spheres, s0 + i);
+            float lb = clearance_bound(P, cx[i], cy[i]);
+            if (P.has_ground) lb = fminf(lb, cz[i] - P.ground_z);
+            above = above && lb - sp.r > best.d;
+        }
+        if (__builtin_amdgcn_ballot_w64(ws.lane >= 0 && !above) == 0) return;
+    }
     if (CULL) {
         // the box bounds hold only for finite centres: a wave with a
         // non-finite one (from non-finite waypoints) evaluates every pair
@@ -964,6 +979,9 @@ int eval_slots(int ns) { return kWave / ns + 2; }
 // (a grid-only scene has neither cylinders nor boxes)
 static bool use_cull(const PlanView &P) { return P.pair_filter == CP_PAIRS_WAVE && (P.n_groups > 0 || P.n_box > 0); }
 
+// split launches from which the group-skip test is left out
+constexpr int kNoClearanceSplit = 4;
+
 // Waves per configuration wave: launches of fewer than about twelve waves
 // per SIMD (1024 SIMDs) share each wave's sphere groups out over 8, 4 or 2
 // waves (measured on the polish, c0 and c2 launches).
@@ -977,6 +995,39 @@ static int eval_split(int64_t waves) {
 size_t eval_partial_count(int B, int ns) {
     const int64_t N = (int64_t)B * ns;
     return (size_t)((N + kWave - 1) / kWave) * eval_slots(ns);
+}
+
+// Clearance grid: per cell, the least horizontal signed distance from its
+// centre to a cylinder (radial term) or a box footprint, less half the cell
+// diagonal (the distance is 1-Lipschitz) and a margin for the rounding of the
+// evaluation's FP32 distances: a lower bound of every such distance the
+// evaluation computes anywhere in the cell.
+__global__ __launch_bounds__(256) void k_clearance(PlanView P, float *__restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.clr_nx * P.clr_ny) return;
+    const double px = P.clr_x0 + (c % P.clr_nx + 0.5) * (double)P.clr_h;
+    const double py = P.clr_y0 + (c / P.clr_nx + 0.5) * (double)P.clr_h;
+    double d = 1e30;
+    for (int o = 0; o < P.n_cyl; ++o) {
+        const float4 q = P.cyl_orig[o];
+        d = fmin(d, sqrt((px - q.x) * (px - q.x) + (py - q.y) * (py - q.y)) - q.z);
+    }
+    for (int o = 0; o < P.n_box; ++o) {
+        // signed distance to the footprint rectangle: below the box's signed
+        // distance everywhere, inside the box included
+        const float4 b0 = P.box[2 * o], b1 = P.box[2 * o + 1];
+        const double qx = fabs(px - b0.x) - b0.w, qy = fabs(py - b0.y) - b1.x;
+        const double ex = fmax(qx, 0.0), ey = fmax(qy, 0.0);
+        d = fmin(d, sqrt(ex * ex + ey * ey) + fmin(fmax(qx, qy), 0.0));
+    }
+    const double m = 0.7072 * P.clr_h + 1e-4 + 1e-6 * (fabs(px) + fabs(py) + fabs(d) + 1.0);
+    out[c] = (float)(d - m);
+}
+
+hipError_t launch_clearance(const PlanView &P, float *out, hipStream_t st) {
+    const int n = P.clr_nx * P.clr_ny;
+    hipLaunchKernelGGL(k_clearance, dim3((n + 255) / 256), dim3(256), 0, st, P, out);
+    return hipGetLastError();
 }
 
 // Per block of cells (2 x 2 x 2), the smallest grid sample any of its cells
@@ -1025,6 +1076,9 @@ hipError_t launch_eval_fwd(const PlanView &P0, const float *W, int B, double2 *p
     const bool cull = use_cull(P);
     const int64_t waves = (N + kWave - 1) / kWave;
     const int split = eval_split(waves);
+    // with the sphere groups shared out, each wave's running minimum covers
+    // few groups and seldom lets one be skipped: no clearance test there
+    if (split >= kNoClearanceSplit) P.clr = nullptr;
     if (split == 8) {
         const dim3 sg((unsigned)waves);
         if (tape && cull)

@@ -88,6 +88,13 @@ struct PlanView {
     const float *sdf_lb;
     float *sdf_lb_buf;            // the plan's buffer for it (null without a grid)
     int32_t sdf_lbn[3];           // blocks per axis
+    // clearance grid over the obstacles' footprints (null: not in use): per
+    // cell a lower bound of the horizontal signed distance from any point of
+    // the cell to every cylinder (radial term) and every box footprint; points
+    // outside the grid are at least clr_out from all of them
+    const float *clr;
+    float clr_x0, clr_y0, clr_h, clr_inv, clr_out;
+    int32_t clr_nx, clr_ny;
 };
 
 // ---------------------------------------------------------------------------
@@ -150,6 +157,17 @@ __device__ __forceinline__ void sdf_cell(const PlanView &P, float cx, float cy, 
         i0[a] = (int)il;
         f[a] = fr;
     }
+}
+
+// lower bound of every primitive obstacle's signed distance at horizontal
+// position (x, y), the ground excepted (P.clr set, x and y finite): a
+// cylinder's distance is never below its radial term and a box's never below
+// the signed distance to its footprint rectangle
+__device__ __forceinline__ float clearance_bound(const PlanView &P, float x, float y) {
+    const float fx = (x - P.clr_x0) * P.clr_inv, fy = (y - P.clr_y0) * P.clr_inv;
+    if (fx >= 0.0f && fy >= 0.0f && fx < (float)P.clr_nx && fy < (float)P.clr_ny)
+        return P.clr[(size_t)(int)fy * P.clr_nx + (int)fx];
+    return P.clr_out;
 }
 
 // grid cells per bound block along each axis: 1 << kSdfBlockLog2

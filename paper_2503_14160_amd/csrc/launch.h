@@ -11,6 +11,8 @@ size_t eval_partial_count(int B, int ns);
 // (cost, min_dist and flags all null: only the tape is written)
 hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *partial, uint32_t *tape, float *cost,
                            float *min_dist, uint8_t *flags, hipStream_t st);
+// the clearance grid of a plan (P.clr_* set), into out [clr_ny][clr_nx]
+hipError_t launch_clearance(const PlanView &P, float *out, hipStream_t st);
 hipError_t launch_eval_bwd(const PlanView &P, const float *W, int B, const uint32_t *tape, const float *grad_cost,
                            float *grad_W, hipStream_t st);
 hipError_t launch_debug_fk(const PlanView &P, const float *Q, int N, float *centers, float *frames, hipStream_t st);
