@@ -447,6 +447,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     // obstacles' footprints plus 2 m on every side, cells of at least 0.1 m,
     // at most 512 per axis
     v.clr = nullptr;
+    v.lead_frame = -1;
     if (!scene->d_sdf && pair_filter == CP_PAIRS_WAVE && (p->n_cyl > 0 || p->n_box > 0)) {
         double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
         for (int o = 0; o < p->n_cyl; ++o) {
@@ -472,6 +473,12 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         if (e != hipSuccess) return bail(hip_fail(e, "plan workspace"));
         if ((e = launch_clearance(v, p->d_clr, nullptr)) != hipSuccess) return bail(hip_fail(e, "clearance grid"));
         v.clr = p->d_clr;
+        // the frame with the most spheres (the lowest on ties) is evaluated
+        // first; frame 0 needs no reordering
+        int lead = 0;
+        for (int f = 1; f <= p->n; ++f)
+            if (frame_start[f + 1] - frame_start[f] > frame_start[lead + 1] - frame_start[lead]) lead = f;
+        v.lead_frame = lead > 0 ? lead : -1;
     }
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return bail(hip_fail(e, "plan create"));

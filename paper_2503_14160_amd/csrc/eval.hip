@@ -403,8 +403,19 @@ __device__ __forceinline__ Best config_distance(const PlanView &P, const float (
     Xf T;
     xf_identity(T);
     int gi = 0;
-    for (int f = 0; f <= P.n_joints; ++f) {
-        if (f > 0) xf_joint(T, ldg(P.joints, f - 1), pick(q, f - 1));
+    // With the group skip, the frame holding the most spheres goes first (its
+    // early minimum lets more of the other groups be skipped), then the rest
+    // base first; the chain of transforms is rebuilt from the base when the
+    // order steps back.  The minimum does not depend on the order.
+    const int lead = CULL && P.clr ? P.lead_frame : -1;
+    int cur = 0;  // frame of T
+    for (int step = 0; step <= P.n_joints; ++step) {
+        const int f = lead < 0 ? step : step == 0 ? lead : step <= lead ? step - 1 : step;
+        if (f < cur) {
+            xf_identity(T);
+            cur = 0;
+        }
+        for (; cur < f; ++cur) xf_joint(T, ldg(P.joints, cur), pick(q, cur));
         const int s1 = ldg(P.frame_start, f + 1);
         int s = ldg(P.frame_start, f);
         for (; s + 4 <= s1; s += 4, ++gi)

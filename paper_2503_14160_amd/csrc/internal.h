@@ -95,6 +95,7 @@ struct PlanView {
     const float *clr;
     float clr_x0, clr_y0, clr_h, clr_inv, clr_out;
     int32_t clr_nx, clr_ny;
+    int32_t lead_frame;           // with clr: frame taken first (1..n), or -1
 };
 
 // ---------------------------------------------------------------------------
