@@ -467,8 +467,6 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         v.clr_ny = std::max(1, (int)std::ceil((y1 - y0) / h));
         v.clr_x0 = (float)x0; v.clr_y0 = (float)y0;
         v.clr_h = (float)h; v.clr_inv = (float)(1.0 / h);
-        // beyond the grid every footprint is at least `pad` away
-        v.clr_out = (float)(pad - 1e-4 - 1e-6 * (std::max({std::fabs(x0), std::fabs(x1), std::fabs(y0), std::fabs(y1)}) + pad + 1.0));
         e = hipMalloc((void **)&p->d_clr, (size_t)v.clr_nx * v.clr_ny * sizeof(float));
         if (e != hipSuccess) return bail(hip_fail(e, "plan workspace"));
         if ((e = launch_clearance(v, p->d_clr, nullptr)) != hipSuccess) return bail(hip_fail(e, "clearance grid"));

@@ -90,10 +90,9 @@ struct PlanView {
     int32_t sdf_lbn[3];           // blocks per axis
     // clearance grid over the obstacles' footprints (null: not in use): per
     // cell a lower bound of the horizontal signed distance from any point of
-    // the cell to every cylinder (radial term) and every box footprint; points
-    // outside the grid are at least clr_out from all of them
+    // the cell to every cylinder (radial term) and every box footprint
     const float *clr;
-    float clr_x0, clr_y0, clr_h, clr_inv, clr_out;
+    float clr_x0, clr_y0, clr_h, clr_inv;
     int32_t clr_nx, clr_ny;
     int32_t lead_frame;           // with clr: frame taken first (1..n), or -1
 };
@@ -164,11 +163,14 @@ __device__ __forceinline__ void sdf_cell(const PlanView &P, float cx, float cy, 
 // position (x, y), the ground excepted (P.clr set, x and y finite): a
 // cylinder's distance is never below its radial term and a box's never below
 // the signed distance to its footprint rectangle
+//
+// A point outside the grid takes the cell of its projection onto the grid's
+// rectangle: every obstacle lies inside that rectangle, and projecting onto
+// a convex set brings a point no closer to any point of the set.
 __device__ __forceinline__ float clearance_bound(const PlanView &P, float x, float y) {
-    const float fx = (x - P.clr_x0) * P.clr_inv, fy = (y - P.clr_y0) * P.clr_inv;
-    if (fx >= 0.0f && fy >= 0.0f && fx < (float)P.clr_nx && fy < (float)P.clr_ny)
-        return P.clr[(size_t)(int)fy * P.clr_nx + (int)fx];
-    return P.clr_out;
+    const int ix = (int)__builtin_amdgcn_fmed3f((x - P.clr_x0) * P.clr_inv, 0.0f, (float)(P.clr_nx - 1));
+    const int iy = (int)__builtin_amdgcn_fmed3f((y - P.clr_y0) * P.clr_inv, 0.0f, (float)(P.clr_ny - 1));
+    return P.clr[iy * P.clr_nx + ix];
 }
 
 // grid cells per bound block along each axis: 1 << kSdfBlockLog2
