@@ -42,7 +42,9 @@ TRAFFIC_BYTES = None
 # launches (c1_full, converged population), from rocprofv3 SQ_INSTS_VALU /
 # SQ_WAVES (profiles/k_eval_fwd_c1_full_sq_counters.md); None once the kernel
 # has changed since.  The VALU issue ceiling: one wave64 FP32 instruction per
-# 4 cycles per SIMD (16 lanes; packed FP32 is not used), 1024 SIMDs, 2.4 GHz.
+# 4 cycles per SIMD (16 lanes; packed FP32 is not used), 1024 SIMDs, 2.4 GHz:
+# the rate of VOP3 forms; some VOP2 forms issue faster, so a kernel rich in
+# them can reach or pass it.
 VALU_PER_WAVE = None
 PEAK_VALU_ISSUE = 1024 * 2.4e9 / 4  # wave instructions per second
 # algorithmic bytes of one trilinear signed-distance query: 8 FP32 corners
