@@ -37,7 +37,7 @@ PEAK_HBM = 8.0e12     # MI355X HBM3E bytes/s
 # HBM bytes per k_eval_fwd launch on c1_full from rocprofv3 FETCH_SIZE / WRITE_SIZE, each
 # scaled by the same counter on a plain 1 GiB copy (profiles/k_eval_fwd_c1_full_hbm_bytes.md);
 # None once the kernel has changed since the counters were taken
-TRAFFIC_BYTES = None
+TRAFFIC_BYTES = 19.2e6
 # VALU instructions per wave of the culling k_eval_fwd on the bench's timed
 # launches (c1_full, converged population), from rocprofv3 SQ_INSTS_VALU /
 # SQ_WAVES (profiles/k_eval_fwd_c1_full_sq_counters.md); None once the kernel
@@ -45,7 +45,7 @@ TRAFFIC_BYTES = None
 # 4 cycles per SIMD (16 lanes; packed FP32 is not used), 1024 SIMDs, 2.4 GHz:
 # the rate of VOP3 forms; some VOP2 forms issue faster, so a kernel rich in
 # them can reach or pass it.
-VALU_PER_WAVE = None
+VALU_PER_WAVE = 9216
 PEAK_VALU_ISSUE = 1024 * 2.4e9 / 4  # wave instructions per second
 # algorithmic bytes of one trilinear signed-distance query: 8 FP32 corners
 SDF_QUERY_BYTES = 32
