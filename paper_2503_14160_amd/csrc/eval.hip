@@ -377,7 +377,8 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
             int i0[3];
             float f[3], dg[3];
             sdf_cell(P, cx[i], cy[i], cz[i], i0, f, dg);
-            if (!P.sdf_lb || !(sdf_cell_bound(P, i0) - sp.r > best.d)) v[i] = fminf(v[i], sdf_interp(P, i0, f, dg, nullptr));
+            if (!P.sdf_lb || !(sdf_cell_bound(P, i0) - sp.r > best.d))
+                v[i] = fminf(v[i], sdf_interp(P, i0, f, dg, nullptr));
         }
         float d = v[i] - sp.r;
         if (ARG) {
