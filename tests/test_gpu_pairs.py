@@ -309,3 +309,29 @@ def test_pairs_sphere_group_sizes(cp, counts):
     rng = np.random.default_rng(740 + S)
     W = synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, 80, cost.K, sigma=0.4)
     _eval_modes(cp, prob, W, f"sphere counts {counts}", backward=True)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+def test_pairs_random_scenes(cp, seed):
+    """Random cranes and scenes (tree counts and radii, several tree heights,
+    box counts and sizes, scene extents, perturbation widths): the culling
+    with its group skip and lead frame equals the every-pair evaluation bit
+    for bit, forward with the tape and backward without it."""
+    rng = np.random.default_rng(760 + seed)
+    robot = synth.make_robot(7000 + seed, int(rng.integers(8, 72)))
+    qs, qg = synth.make_endpoints(rng, robot)
+    scene = synth.make_scene(rng, robot, qs, qg, n_cyl=int(rng.integers(48, 900)), n_box=int(rng.integers(0, 40)),
+                             half_extent=float(rng.uniform(6.0, 30.0)),
+                             r_range=(0.05, float(rng.uniform(0.2, 1.5))), height=float(rng.uniform(2.0, 20.0)),
+                             box_side=(0.3, float(rng.uniform(1.0, 8.0))))
+    if seed % 2:
+        # a second tree height: two cylinder groups
+        cyl = scene.cyl.copy()
+        cyl[::3, 4] = cyl[::3, 3] + 4.0
+        scene = dataclasses.replace(scene, cyl=cyl)
+    cost = synth.CostParams(K=int(rng.integers(3, 10)), M=int(rng.integers(5, 20)), hinge=synth.HINGE_SMOOTH,
+                            margin=0.1)
+    prob = synth.Problem("random", robot, scene, qs, qg, cost, synth.c1_full().opt)
+    W = synth.random_waypoints(rng, robot, qs, qg, int(rng.integers(40, 300)), cost.K,
+                               sigma=float(rng.uniform(0.05, 0.8)))
+    _eval_modes(cp, prob, W, f"random scene {seed}", backward=True)
