@@ -148,10 +148,13 @@ typedef struct {
      * CP_PAIRS_LANE: a sphere-cylinder pair whose squared axis distance shows
      * that it cannot lower the running minimum skips its square root.
      * CP_PAIRS_WAVE: the configurations of one hardware wave that belong to
-     * one path are bounded by a box per sphere; cylinders and boxes that no
-     * configuration in the box can come closer to than an upper bound of its
-     * minimum are skipped for the whole wave (waves that hold more than two
-     * paths are bounded as one box).  CP_PAIRS_AUTO: CP_PAIRS_WAVE for
+     * one path are bounded by a box per group of up to four spheres;
+     * cylinders and boxes that no configuration in the box can come closer to
+     * than an upper bound of its minimum are skipped for the whole wave
+     * (waves that hold more than two paths are bounded as one box), and a
+     * whole group of spheres is skipped when a lower bound of its distances
+     * (a clearance grid built at plan creation, and the ground) is above
+     * every configuration's running minimum.  CP_PAIRS_AUTO: CP_PAIRS_WAVE for
      * scenes of at least 48 cylinders and boxes, else CP_PAIRS_LANE (the
      * culling's fixed cost per wave outweighs its savings on small scenes;
      * in a batch, CP_PAIRS_WAVE if any problem qualifies; batched launches
