@@ -318,7 +318,7 @@ int cp_debug_fk(cp_plan *plan, const float *d_q, int32_t N, float *d_centers, fl
 int cp_debug_eval_configs(cp_plan *plan, const float *d_q, int32_t N, float *d_dist, uint32_t *d_argmin,
                           cp_stream_t stream);
 /* Selection step of Algorithm 1 (step 3) alone: indices of the nu smallest
- * (cost, index) pairs of d_cost [B] in rank order, NaN after every number,
+ * (cost, index) pairs of d_cost [B] in rank order, NaN ranked as +inf,
  * written to d_elite [nu]; 1 <= nu <= min(B, CP_MAX_ELITES).  Runs on the
  * current device. */
 int cp_debug_select(const float *d_cost, int32_t B, int32_t nu, int32_t *d_elite, cp_stream_t stream);

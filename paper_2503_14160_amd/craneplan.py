@@ -420,7 +420,7 @@ class Batch:
 
 
 def select(cost: torch.Tensor, nu: int) -> torch.Tensor:
-    """Indices of the nu smallest (cost, index) pairs in rank order, NaN last
+    """Indices of the nu smallest (cost, index) pairs in rank order, NaN as +inf
     (the selection step of the optimizer, exported for tests)."""
     cost = cost.to(torch.float32).contiguous()
     out = torch.empty(nu, dtype=torch.int32, device=cost.device)

@@ -18,6 +18,9 @@ using namespace cp;
 namespace {
 
 thread_local std::string g_err;
+// an error a HIP call made before the current entry point had left behind
+// (the launch checks read the thread's last error, so it is taken first)
+thread_local hipError_t g_stale = hipSuccess;
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
@@ -25,9 +28,16 @@ int fail(int code, const std::string &msg) {
 }
 
 int hip_fail(hipError_t e, const char *what) {
-    return fail(e == hipErrorOutOfMemory ? CP_ERR_NOMEM : CP_ERR_HIP,
-                std::string(what) + ": " + hipGetErrorString(e));
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    if (g_stale != hipSuccess)
+        msg += std::string(" (an earlier HIP call on this thread, before this entry point, had failed with: ") +
+               hipGetErrorString(g_stale) + ")";
+    return fail(e == hipErrorOutOfMemory ? CP_ERR_NOMEM : CP_ERR_HIP, msg);
 }
+
+// takes any error left by earlier HIP calls, so the checks of this entry
+// point's launches see their own
+void take_stale_error() { g_stale = hipGetLastError(); }
 
 #define CP_HIP(call, what)                               \
     do {                                                 \
@@ -39,6 +49,7 @@ int hip_fail(hipError_t e, const char *what) {
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev) {
+        take_stale_error();
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
         if (prev != dev) (void)hipSetDevice(dev);
     }
@@ -552,6 +563,7 @@ int cp_debug_eval_configs(cp_plan *plan, const float *d_q, int32_t N, float *d_d
 int cp_debug_select(const float *d_cost, int32_t B, int32_t nu, int32_t *d_elite, cp_stream_t stream) {
     if (!d_cost || !d_elite) return fail(CP_ERR_INVALID_ARG, "null argument");
     if (B < 1 || nu < 1 || nu > B || nu > CP_MAX_ELITES) return fail(CP_ERR_SIZE, "B or nu out of range");
+    take_stale_error();
     OptView v{};
     v.cost = const_cast<float *>(d_cost);
     v.B = B;
@@ -1045,6 +1057,7 @@ int cp_sdf_build(const float *d_points, int64_t N, const int32_t dims[3], const 
     if (!(voxel > 0.0f) || !finite(voxel)) return fail(CP_ERR_INVALID_ARG, "voxel must be > 0");
     const size_t n = (size_t)dims[0] * dims[1] * dims[2];
     if (n > ((size_t)1 << 31)) return fail(CP_ERR_SIZE, "grid too large");
+    take_stale_error();
     int dev;
     CP_HIP(hipGetDevice(&dev), "device");
     hipStream_t st = (hipStream_t)stream;

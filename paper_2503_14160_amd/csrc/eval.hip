@@ -499,6 +499,22 @@ __device__ __forceinline__ uint32_t argmin_obstacle_near(const PlanView &P, floa
     return bo;
 }
 
+// The obstacle of the winning pair of a configuration.  In a scene of the
+// ground and a grid alone it follows from the minimum itself: the winning
+// sphere's minimum over the two is one of them exactly (where its grid term
+// was skipped, the grid's lower bound already lay above the ground term), and
+// a tie keeps the ground, the lower number, as the full rescan does.  A
+// non-finite centre or minimum takes the rescan.
+template <bool CULL>
+__device__ __forceinline__ uint32_t argmin_of(const PlanView &P, const Best &best) {
+    if (P.sdf && P.n_cyl == 0 && P.n_box == 0 && fabsf(best.cz) < kInf && fabsf(best.v) < kInf) {
+        if (P.has_ground && best.cz - P.ground_z == best.v) return 0;
+        return best.v < kInf ? CP_OBS_SDF : 0u;
+    }
+    return CULL ? argmin_obstacle_near(P, best.cx, best.cy, best.cz, best.v)
+                : argmin_obstacle(P, best.cx, best.cy, best.cz);
+}
+
 // Configuration of checkpoint k of path b: q (all joints) and the step
 // q_k - q_{k-1}; also the span window start j and the weights.
 __device__ __forceinline__ void interpolate(const PlanView &P, const float *Wb, int k, float (&q)[CP_MAX_JOINTS],
@@ -604,9 +620,7 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     float phi = hinge_value(P, best.d, dphi);
     float c = __builtin_fmaf(P.w_c, phi, __builtin_fmaf(P.w_l, jl, jp));
     if (TAPE && active) {
-        uint32_t o = CULL ? argmin_obstacle_near(P, best.cx, best.cy, best.cz, best.v)
-                          : argmin_obstacle(P, best.cx, best.cy, best.cz);
-        tape[g] = ((uint32_t)best.s << 16) | o;
+        tape[g] = ((uint32_t)best.s << 16) | argmin_of<CULL>(P, best);
     }
     float dk = best.d;
     if (!active) { c = 0.0f; dk = kInf; }
@@ -881,8 +895,7 @@ __global__ __launch_bounds__(NW * 64) void k_eval_bwd(PlanView P, const float *_
             ws.lane = 0;
             Best best = config_distance<true, CULL>(P, q, ws);
             s_orig = best.s;
-            o = CULL ? argmin_obstacle_near(P, best.cx, best.cy, best.cz, best.v)
-                     : argmin_obstacle(P, best.cx, best.cy, best.cz);
+            o = argmin_of<CULL>(P, best);
         }
         collision_grad(P, q, s_orig, o, gq);
         float c[4][CP_MAX_JOINTS];

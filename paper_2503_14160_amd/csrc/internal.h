@@ -358,9 +358,10 @@ __device__ __forceinline__ float hinge_value(const PlanView &P, float d, float &
     return 0.0f;
 }
 
-// total order key of a cost: increasing in the cost, NaN after everything
+// order key of a cost: increasing in the cost, -0 equal to +0, and NaN equal
+// to +inf (the two then go by index); 0xFFFFFFFF is above every cost's key
 __device__ __forceinline__ uint32_t cost_key(float c) {
-    if (c != c) return 0xFFFFFFFFu;
+    if (c != c) return 0xFF800000u;
     if (c == 0.0f) c = 0.0f;
     uint32_t u = __float_as_uint(c);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);

@@ -144,19 +144,168 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *b
     return incl - v;
 }
 
-// bitonic sort of n (power of two) 64-bit keys in shared memory, ascending
-__device__ __forceinline__ void bitonic_sort(uint64_t *a, int n) {
-    for (int size = 2; size <= n; size <<= 1) {
+// LDS writes of this wave become visible to its other lanes
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ascending bitonic sort of np (a power of two, <= 4 * kSelThreads) 64-bit
+// keys in LDS.  Wave w owns elements [256 w, 256 w + 256), four per lane, so
+// the stages of stride below 256 touch one wave's elements only and need no
+// workgroup barrier.  Ends with one.
+__device__ __forceinline__ void bitonic_sort(uint64_t *a, int np) {
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const bool owner = w * 256 < np;
+    bool wide_before = true;
+    for (int size = 2; size <= np; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const int jx = i ^ stride;
-                if (jx > i) {
-                    const bool up = (i & size) == 0;
-                    const uint64_t x = a[i], y = a[jx];
-                    if ((x > y) == up) { a[i] = y; a[jx] = x; }
+            const bool wide = stride >= 256;
+            if (wide || wide_before) __syncthreads();
+            else wave_lds_sync();
+            wide_before = wide;
+            if (owner) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int i = w * 256 + k * 64 + lane, jx = i ^ stride;
+                    if (i < np && jx > i) {
+                        const bool up = (i & size) == 0;
+                        const uint64_t x = a[i], y = a[jx];
+                        if ((x > y) == up) { a[i] = y; a[jx] = x; }
+                    }
                 }
             }
-            __syncthreads();
+        }
+    }
+    __syncthreads();
+}
+
+// the digit of a radix-select pass: the first bin where the running count
+// reaches `remaining`, and how many of that bin are still to be taken (four
+// bins per lane of wave 0, an inclusive scan of the lane sums)
+__device__ __forceinline__ void select_digit(const uint32_t *hist, uint32_t remaining, uint32_t &s_digit,
+                                             uint32_t &s_rem) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        uint32_t h[4], sum = 0;
+        for (int d = 0; d < 4; ++d) sum += h[d] = hist[4 * tid + d];
+        uint32_t incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t up = __shfl_up(incl, o, 64);
+            if (tid >= o) incl += up;
+        }
+        uint32_t cum = incl - sum;
+        for (int d = 0; d < 4; ++d) {
+            if (cum < remaining && cum + h[d] >= remaining) {
+                s_digit = (uint32_t)(4 * tid + d);
+                s_rem = remaining - cum;
+            }
+            cum += h[d];
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Radix select with PER keys per thread held in registers: slot j of thread
+// t is path j kSelThreads + t.  Slots past B hold the largest key; their
+// indices lie above every path's, so they are never among the nu smallest
+// (key, index) pairs and every slot can be processed alike.  Leaves the nu
+// selected keys, unordered, in sorted[0, nu).
+template <int PER>
+__device__ __forceinline__ void select_regs(const float *__restrict__ cost, int B, int nu, uint32_t *hist,
+                                            uint32_t *eqoff, uint64_t *sorted, uint32_t &s_digit, uint32_t &s_rem,
+                                            uint32_t &s_count) {
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    // slot j reads cost[t + min(j kSelThreads, B - 1 - t)], always in bounds,
+    // and keeps it when j kSelThreads <= B - 1 - t
+    const float *ct = cost + tid;
+    const int lim = B - 1 - tid;
+    uint32_t key[PER];
+#pragma unroll
+    for (int j0 = 0; j0 < PER; j0 += 8) {
+        float c[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) c[j] = ct[min((j0 + j) * kSelThreads, lim)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            key[j0 + j] = cost_key(c[j]) | ((j0 + j) * kSelThreads <= lim ? 0u : 0xFFFFFFFFu);
+    }
+    uint32_t prefix = 0, mask = 0, remaining = (uint32_t)nu;
+    // most significant byte first; a wave whose counted keys share one digit
+    // adds them with one atomic (the leading bytes of similar costs agree)
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        if (tid < 256) hist[tid] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const bool m = (key[j] & mask) == prefix;
+            const uint64_t bm = __builtin_amdgcn_ballot_w64(m);
+            if (bm) {
+                const uint32_t d = (key[j] >> shift) & 255u;
+                const int lead = __builtin_ctzll(bm);
+                const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)d, lead);
+                if (__builtin_amdgcn_ballot_w64(m && d == dl) == bm) {
+                    if (lane == lead) atomicAdd(&hist[dl], (uint32_t)__builtin_popcountll(bm));
+                } else if (m) {
+                    atomicAdd(&hist[d], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        select_digit(hist, remaining, s_digit, s_rem);
+        __syncthreads();
+        prefix |= s_digit << shift;
+        mask |= 255u << shift;
+        remaining = s_rem;
+    }
+    // keys below the threshold, and the `remaining` lowest-index keys equal
+    // to it: the equal keys are counted per (slot, wave), in index order, and
+    // one wave turns the counts into offsets
+    if (tid == 0) s_count = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const uint64_t be = __builtin_amdgcn_ballot_w64(key[j] == prefix);
+        if (lane == 0) eqoff[j * 16 + w] = (uint32_t)__builtin_popcountll(be);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        uint32_t c[16], sum = 0;
+        for (int x = 0; x < 16; ++x) sum += c[x] = tid < PER ? eqoff[tid * 16 + x] : 0u;
+        uint32_t incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t up = __shfl_up(incl, o, 64);
+            if (tid >= o) incl += up;
+        }
+        uint32_t run = incl - sum;
+        if (tid < PER)
+            for (int x = 0; x < 16; ++x) { eqoff[tid * 16 + x] = run; run += c[x]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const bool eq = key[j] == prefix;
+        const uint64_t be = __builtin_amdgcn_ballot_w64(eq);
+        const bool take_eq = be && eq && eqoff[j * 16 + w] + lanes_below(be) < remaining;
+        const bool sel = key[j] < prefix || take_eq;
+        const uint64_t bm = __builtin_amdgcn_ballot_w64(sel);
+        if (bm) {
+            const int lead = __builtin_ctzll(bm);
+            uint32_t base = 0;
+            if (lane == lead) base = atomicAdd(&s_count, (uint32_t)__builtin_popcountll(bm));
+            base = (uint32_t)__builtin_amdgcn_readlane((int)base, lead);
+            if (sel) {
+                // the key is copied to a fresh register first: a 64-bit store
+                // straight from key[j] would make the register allocator keep
+                // every key in the upper half of a register pair
+                uint32_t kc;
+                asm volatile("v_mov_b32 %0, %1" : "=v"(kc) : "v"(key[j]));
+                sorted[base + lanes_below(bm)] = ((uint64_t)kc << 32) | (uint32_t)(j * kSelThreads + tid);
+            }
         }
     }
 }
@@ -166,7 +315,7 @@ __device__ __forceinline__ void select_body(const float *__restrict__ cost, int 
     __shared__ uint32_t hist[256];
     __shared__ uint32_t scanbuf[kSelThreads];
     __shared__ uint64_t sorted[CP_MAX_ELITES];
-    __shared__ uint32_t s_digit, s_rem;
+    __shared__ uint32_t s_digit, s_rem, s_count;
     const int tid = threadIdx.x;
     if (B <= kSelThreads) {
         // small populations: every path's rank in the (cost, index) order is
@@ -182,67 +331,57 @@ __device__ __forceinline__ void select_body(const float *__restrict__ cost, int 
         }
         return;
     }
-    uint32_t prefix = 0, mask = 0, remaining = (uint32_t)nu;
-    // radix select on the 32-bit order key, most significant byte first
-    for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 24 - 8 * pass;
-        if (tid < 256) hist[tid] = 0;
-        __syncthreads();
-        for (int i = tid; i < B; i += kSelThreads) {
+    if (B <= 16 * kSelThreads) {
+        select_regs<16>(cost, B, nu, hist, scanbuf, sorted, s_digit, s_rem, s_count);
+    } else if (B <= 32 * kSelThreads) {
+        select_regs<32>(cost, B, nu, hist, scanbuf, sorted, s_digit, s_rem, s_count);
+    } else if (B <= 64 * kSelThreads) {
+        select_regs<64>(cost, B, nu, hist, scanbuf, sorted, s_digit, s_rem, s_count);
+    } else {
+        // larger populations: the same radix select reading the costs from
+        // global memory on every pass
+        uint32_t prefix = 0, mask = 0, remaining = (uint32_t)nu;
+        for (int pass = 0; pass < 4; ++pass) {
+            const int shift = 24 - 8 * pass;
+            if (tid < 256) hist[tid] = 0;
+            __syncthreads();
+            for (int i = tid; i < B; i += kSelThreads) {
+                const uint32_t key = cost_key(cost[i]);
+                if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            select_digit(hist, remaining, s_digit, s_rem);
+            __syncthreads();
+            prefix |= s_digit << shift;
+            mask |= 255u << shift;
+            remaining = s_rem;
+            __syncthreads();
+        }
+        // keys below the threshold, plus the `remaining` lowest-index keys
+        // equal to it, from contiguous chunks in thread order
+        const int chunk = (B + kSelThreads - 1) / kSelThreads;
+        const int i0 = min(B, tid * chunk), i1 = min(B, i0 + chunk);
+        uint32_t n_less = 0, n_eq = 0;
+        for (int i = i0; i < i1; ++i) {
             const uint32_t key = cost_key(cost[i]);
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+            n_less += key < prefix;
+            n_eq += key == prefix;
         }
-        __syncthreads();
-        if (tid < 64) {
-            // the digit where the running count first reaches `remaining`:
-            // four bins per lane, an inclusive scan of the lane sums across
-            // the wave, then the one lane whose bins cross it
-            uint32_t h[4], sum = 0;
-            for (int d = 0; d < 4; ++d) sum += h[d] = hist[4 * tid + d];
-            uint32_t incl = sum;
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t up = __shfl_up(incl, o, 64);
-                if (tid >= o) incl += up;
-            }
-            uint32_t cum = incl - sum;
-            for (int d = 0; d < 4; ++d) {
-                if (cum < remaining && cum + h[d] >= remaining) {
-                    s_digit = (uint32_t)(4 * tid + d);
-                    s_rem = remaining - cum;
-                }
-                cum += h[d];
-            }
+        uint32_t tot;
+        const uint32_t eq_before = block_exclusive_scan(n_eq, scanbuf, tot);
+        const uint32_t take_eq = eq_before >= remaining ? 0u : min(n_eq, remaining - eq_before);
+        const uint32_t off = block_exclusive_scan(n_less + take_eq, scanbuf, tot);
+        uint32_t pos = off, eq_seen = 0;
+        for (int i = i0; i < i1; ++i) {
+            const uint32_t key = cost_key(cost[i]);
+            bool sel = key < prefix;
+            if (key == prefix) { sel = eq_seen < take_eq; ++eq_seen; }
+            if (sel) sorted[pos++] = ((uint64_t)key << 32) | (uint32_t)i;
         }
-        __syncthreads();
-        prefix |= s_digit << shift;
-        mask |= 255u << shift;
-        remaining = s_rem;
-        __syncthreads();
-    }
-    // keys below the threshold, plus the `remaining` lowest-index keys equal to it
-    const int chunk = (B + kSelThreads - 1) / kSelThreads;
-    const int i0 = min(B, tid * chunk), i1 = min(B, i0 + chunk);
-    uint32_t n_less = 0, n_eq = 0;
-    for (int i = i0; i < i1; ++i) {
-        const uint32_t key = cost_key(cost[i]);
-        n_less += key < prefix;
-        n_eq += key == prefix;
-    }
-    uint32_t tot;
-    const uint32_t eq_before = block_exclusive_scan(n_eq, scanbuf, tot);
-    const uint32_t take_eq = eq_before >= remaining ? 0u : min(n_eq, remaining - eq_before);
-    const uint32_t off = block_exclusive_scan(n_less + take_eq, scanbuf, tot);
-    uint32_t pos = off, eq_seen = 0;
-    for (int i = i0; i < i1; ++i) {
-        const uint32_t key = cost_key(cost[i]);
-        bool sel = key < prefix;
-        if (key == prefix) { sel = eq_seen < take_eq; ++eq_seen; }
-        if (sel) sorted[pos++] = ((uint64_t)key << 32) | (uint32_t)i;
     }
     int np = 1;
     while (np < nu) np <<= 1;
     for (int i = nu + tid; i < np; i += kSelThreads) sorted[i] = ~0ull;
-    __syncthreads();
     bitonic_sort(sorted, np);
     for (int r = tid; r < nu; r += kSelThreads) elite[r] = (int32_t)(uint32_t)(sorted[r] & 0xFFFFFFFFu);
 }

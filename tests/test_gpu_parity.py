@@ -269,7 +269,8 @@ def test_autograd_function(cp):
 # ----------------------------------------------------------------------------
 
 @pytest.mark.parametrize("B,nu", [(1, 1), (256, 25), (1000, 999), (1024, 1024), (1024, 100), (1025, 100),
-                                  (16384, 819), (65536, 3276), (5000, 4096)])
+                                  (16384, 819), (16385, 4096), (32768, 1), (32769, 1638), (65536, 3276),
+                                  (65535, 4096), (65537, 3276), (100000, 2000), (5000, 4096)])
 def test_select_parity(cp, B, nu):
     rng = np.random.default_rng(110 + B)
     cost = np.round(rng.normal(size=B) * 3, 2).astype(np.float32)  # many ties
@@ -278,6 +279,29 @@ def test_select_parity(cp, B, nu):
         cost[:3] = [np.inf, -np.inf, 0.0]
     got = cp.select(torch.from_numpy(cost).cuda(), nu).cpu().numpy()
     np.testing.assert_array_equal(got, oracle.select(cost.astype(np.float64), nu))
+
+
+@pytest.mark.parametrize("B", [300, 3000, 20000, 65536, 70000])
+def test_select_nonfinite_and_ties(cp, B):
+    """Ranks that reach the non-finite costs: NaN ranks as +inf, so NaNs and
+    +infs interleave by index; -0 equals +0; all-equal and one-value-heavy
+    populations exercise the equal-key rule at the threshold."""
+    rng = np.random.default_rng(7 + B)
+    nu = min(B, 4096)
+    cost = rng.uniform(1.0, 2.0, size=B).astype(np.float32)
+    nonfin = rng.choice(B, size=B - nu // 2, replace=False)
+    cost[nonfin] = np.nan
+    cost[nonfin[rng.random(nonfin.size) < 0.3]] = np.inf
+    cost[rng.choice(B, size=min(B, 40), replace=False)] = -0.0
+    cost[rng.choice(B, size=min(B, 40), replace=False)] = 0.0
+    cases = [cost,
+             np.full(B, 3.5, np.float32),
+             np.where(rng.random(B) < 0.9, np.float32(20.0), rng.uniform(19.0, 21.0, B)).astype(np.float32),
+             # the same leading bytes everywhere: 20 + multiples of 2^-19
+             (20.0 + rng.integers(0, 64, B) * 2.0 ** -19).astype(np.float32)]
+    for c in cases:
+        got = cp.select(torch.from_numpy(c).cuda(), nu).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.select(c.astype(np.float64), nu))
 
 
 def _elite_compare(e_gpu, cost_ref, nu, tol):
