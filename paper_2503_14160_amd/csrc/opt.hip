@@ -506,15 +506,46 @@ __device__ __forceinline__ void update_tile(const PlanView &P, const OptView &O,
             wch[i] = O.w[j0 + i];
         }
         __syncthreads();
-        for (int idx = tid; idx < nj * 2 * kUpdTile; idx += kUpdThreads) {
-            const int jj = idx / (2 * kUpdTile), q = idx % (2 * kUpdTile);
-            const bool row = q < kUpdTile;
-            const int qq = row ? q : q - kUpdTile;
-            const int e = (row ? r0 : c0) + qq;
-            double v = e < D ? elite_value(P, O, ech[jj], e) : 0.0;
-            if (centred) v -= row ? mr[qq] : mc[qq];
-            if (row) xr[jj][qq] = v;
-            else xc[jj][qq] = v;
+        if (O.npol == 0) {
+            // every elite is a sample: each thread's loads are issued
+            // together, at clamped (always valid) addresses
+            constexpr int kPer = kUpdChunk * 2 * kUpdTile / kUpdThreads;
+            static_assert(kPer * kUpdThreads == kUpdChunk * 2 * kUpdTile, "stage split");
+            const int nslot = nj * 2 * kUpdTile;
+            double v[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                if (u * kUpdThreads >= nslot) break;
+                const int idx = tid + u * kUpdThreads;
+                const int jj = idx / (2 * kUpdTile), q = idx % (2 * kUpdTile);
+                const int e = q < kUpdTile ? r0 + q : c0 + q - kUpdTile;
+                v[u] = O.xi[(size_t)ech[min(jj, nj - 1)] * D + min(e, D - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                if (u * kUpdThreads >= nslot) break;
+                const int idx = tid + u * kUpdThreads;
+                const int jj = idx / (2 * kUpdTile), q = idx % (2 * kUpdTile);
+                if (jj >= nj) continue;
+                const bool row = q < kUpdTile;
+                const int qq = row ? q : q - kUpdTile;
+                const int e = (row ? r0 : c0) + qq;
+                double x = e < D ? v[u] : 0.0;
+                if (centred) x -= row ? mr[qq] : mc[qq];
+                if (row) xr[jj][qq] = x;
+                else xc[jj][qq] = x;
+            }
+        } else {
+            for (int idx = tid; idx < nj * 2 * kUpdTile; idx += kUpdThreads) {
+                const int jj = idx / (2 * kUpdTile), q = idx % (2 * kUpdTile);
+                const bool row = q < kUpdTile;
+                const int qq = row ? q : q - kUpdTile;
+                const int e = (row ? r0 : c0) + qq;
+                double x = e < D ? elite_value(P, O, ech[jj], e) : 0.0;
+                if (centred) x -= row ? mr[qq] : mc[qq];
+                if (row) xr[jj][qq] = x;
+                else xc[jj][qq] = x;
+            }
         }
         __syncthreads();
     };
@@ -708,12 +739,16 @@ __device__ __forceinline__ void chol_reg(const OptView &O) {
     bool ok = false;
     for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
         const double jitter = attempt == 0 ? 0.0 : O.eps * (attempt == 1 ? 10.0 : attempt == 2 ? 100.0 : 1000.0);
+        // lower triangle of row `lane` (C is symmetric: column reads
+        // coalesce); every lane loads an in-bounds entry unconditionally, so
+        // all DM loads are in flight together
+        const int lr = lane < D ? lane : D - 1;
+        double cv[DM];
 #pragma unroll
-        for (int j = 0; j < DM; ++j) {
-            // lower triangle of row `lane` (C is symmetric: column reads coalesce)
-            a[j] = lane < D && j < D ? (j <= lane ? O.C[(size_t)j * D + lane] + (j == lane ? jitter : 0.0) : 0.0)
-                                     : (j == lane ? 1.0 : 0.0);
-        }
+        for (int j = 0; j < DM; ++j) cv[j] = O.C[(size_t)(j < D ? j : D - 1) * D + lr];
+#pragma unroll
+        for (int j = 0; j < DM; ++j)
+            a[j] = lane < D && j < D ? (j <= lane ? cv[j] + (j == lane ? jitter : 0.0) : 0.0) : (j == lane ? 1.0 : 0.0);
         bool fail = false;
 #pragma unroll
         for (int k = 0; k < DM; ++k) {
