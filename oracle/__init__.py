@@ -18,7 +18,8 @@ Readings of the paper taken here (each is also listed in the design notes):
 * the sampling distribution is N(mu, C) with sigma folded into C
   (C_0 = sigma0^2 I), sampled through the lower Cholesky factor;
 * the covariance update uses the freshly updated mean;
-* elites are the first nu of the stable order on (cost, index), NaN last.
+* elites are the first nu of the stable order on (cost, index), NaN ranked
+  as +inf (a NaN and a +inf then go by index).
 
 Parity status: every function here is pinned by a CPU test (closed forms,
 invariants, brute force, finite differences, published Philox vectors) except
@@ -402,7 +403,7 @@ def expand(robot, xi: np.ndarray, K: int) -> np.ndarray:
 
 def select(cost: np.ndarray, nu: int) -> np.ndarray:
     """Step (3): indices of the nu lowest costs, stable on (cost, index), NaN
-    ranked after every number."""
+    ranked as +inf (so a NaN and a +inf go by index) and -0 equal to +0."""
     key = np.where(np.isnan(cost), np.inf, cost)
     order = np.lexsort((np.arange(cost.shape[0]), key))
     return order[:nu]

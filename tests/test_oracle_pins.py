@@ -591,7 +591,10 @@ def test_selection_brute_force(orc):
     rng = np.random.default_rng(21)
     cost = np.round(rng.normal(size=300), 1)  # many ties
     cost[[3, 50, 77]] = np.nan
-    for nu in (1, 10, 150, 300):
+    cost[[1, 60, 299]] = np.inf  # interleaved with the NaNs by index
+    cost[[5, 6]] = [-0.0, 0.0]
+    cost[[7]] = -0.0
+    for nu in (1, 10, 150, 295, 300):
         got = orc.select(cost, nu)
         keyed = sorted(range(cost.size), key=lambda i: (math.inf if math.isnan(cost[i]) else cost[i], i))
         assert got.tolist() == keyed[:nu]
