@@ -242,6 +242,10 @@ int cp_optimizer_set_state(cp_opt *opt, const double *mu, const double *C, int64
  * waypoints [B][K][n], costs [B] and elite indices [nu] in rank order (after
  * polish: indices >= B denote polished elite slots).  Any may be NULL. */
 int cp_optimizer_last(cp_opt *opt, float *d_waypoints, float *d_cost, int32_t *d_elite, cp_stream_t stream);
+/* The selection of the last iteration (Algorithm 1, step 3): elite indices
+ * d_idx [nu] in rank order and costs d_cost [B], enqueued on stream; the same
+ * as cp_optimizer_last without the waypoints.  Either may be NULL. */
+int cp_optimizer_last_elites(cp_opt *opt, int32_t *d_idx, float *d_cost, cp_stream_t stream);
 
 /*
  * Batches of independent planning problems (the paper's batch generation of
@@ -295,6 +299,12 @@ int cp_batch_get_tuning(const cp_batch *batch, cp_batch_tuning *tuning);
  * cache (cache_path may be NULL: no cache).  The chosen shape is applied
  * and returned in *chosen (may be NULL). */
 int cp_batch_tune(cp_batch *batch, const char *cache_path, cp_batch_tuning *chosen);
+/* Autotune (SYNC) whatever of plan and batch is given (either may be NULL,
+ * not both).  A batch is tuned as by cp_batch_tune.  A plan has nothing to
+ * time: its evaluation's launch shape follows at every call from the number
+ * of paths (how many waves share a configuration's sphere groups) and its
+ * pair filter from the scene, so a plan alone returns CP_OK. */
+int cp_tune(cp_plan *plan, cp_batch *batch, const char *cache_path);
 
 /* Signed-distance grid from a point cloud (for scenes given as lidar):
  * voxels holding at least one point are occupied (index floor((p - o) / h) in

@@ -34,7 +34,7 @@ EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_en
            "cp_optimizer_step", "cp_optimizer_get_state", "cp_optimizer_set_state", "cp_optimizer_last",
            "cp_sdf_build", "cp_debug_fk", "cp_debug_eval_configs", "cp_debug_select", "cp_batch_create",
            "cp_batch_destroy", "cp_batch_run", "cp_batch_eval", "cp_batch_get_state", "cp_batch_set_tuning",
-           "cp_batch_get_tuning", "cp_batch_tune"]
+           "cp_batch_get_tuning", "cp_batch_tune", "cp_optimizer_last_elites", "cp_tune"]
 
 
 class CranePlanError(RuntimeError):
@@ -103,6 +103,8 @@ def lib():
         L.cp_batch_set_tuning.argtypes = [_vp, _vp]
         L.cp_batch_get_tuning.argtypes = [_vp, _vp]
         L.cp_batch_tune.argtypes = [_vp, ctypes.c_char_p, _vp]
+        L.cp_optimizer_last_elites.argtypes = [_vp, _vp, _vp, _vp]
+        L.cp_tune.argtypes = [_vp, _vp, ctypes.c_char_p]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -343,6 +345,14 @@ class Optimizer:
         _check(lib().cp_optimizer_last(self._h, _ptr(W), _ptr(cost), _ptr(elite), _stream()))
         return W, cost, elite
 
+    def last_elites(self):
+        """The last iteration's elite indices [nu] (rank order) and costs [B]."""
+        dev = self.plan.device
+        elite = torch.empty(self.nu, dtype=torch.int32, device=dev)
+        cost = torch.empty(self.B, dtype=torch.float32, device=dev)
+        _check(lib().cp_optimizer_last_elites(self._h, _ptr(elite), _ptr(cost), _stream()))
+        return elite, cost
+
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("rounds", _c_i32), ("wg_per_cu", _c_i32)]
@@ -417,6 +427,12 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         _check(lib().cp_batch_tune(self._h, path, ctypes.byref(t)))
         return t.rounds, t.wg_per_cu
+
+
+def tune(plan: Optional["Plan"] = None, batch: Optional["Batch"] = None, cache_path: Optional[str] = None):
+    """cp_tune: autotune a batch (a plan alone has no launch parameters to time)."""
+    path = cache_path.encode() if cache_path else None
+    _check(lib().cp_tune(plan._h if plan is not None else None, batch._h if batch is not None else None, path))
 
 
 def select(cost: torch.Tensor, nu: int) -> torch.Tensor:

@@ -682,6 +682,10 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
     return CP_OK;
 }
 
+int cp_optimizer_last_elites(cp_opt *opt, int32_t *d_idx, float *d_cost, cp_stream_t stream) {
+    return cp_optimizer_last(opt, nullptr, d_cost, d_idx, stream);
+}
+
 int cp_optimizer_get_state(cp_opt *opt, double *mu, double *C, int64_t *iter, float *best_cost,
                            float *best_waypoints) {
     if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
@@ -1083,6 +1087,12 @@ int cp_sdf_build(const float *d_points, int64_t N, const int32_t dims[3], const 
     if (e == hipSuccess && !owned.empty()) e = hipStreamSynchronize(st);
     cleanup();
     if (e != hipSuccess) return hip_fail(e, "sdf build");
+    return CP_OK;
+}
+
+int cp_tune(cp_plan *plan, cp_batch *batch, const char *cache_path) {
+    if (!plan && !batch) return fail(CP_ERR_INVALID_ARG, "null plan and batch");
+    if (batch) return cp_batch_tune(batch, cache_path, nullptr);
     return CP_OK;
 }
 

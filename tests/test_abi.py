@@ -84,3 +84,12 @@ def test_plan_argument_errors_without_device():
         with pytest.raises(craneplan.CranePlanError) as ei:
             craneplan.Plan(p.robot, p.scene, p.cost, max_B=4, pair_filter=mode)
         assert "pair_filter" in str(ei.value)
+
+
+def test_tune_rejects_no_target_before_touching_the_device():
+    from paper_2503_14160_amd import craneplan
+    if not os.path.exists(craneplan.LIB_PATH):
+        from paper_2503_14160_amd import build
+        build.build()
+    with pytest.raises(craneplan.CranePlanError):
+        craneplan.tune()

@@ -440,6 +440,12 @@ def test_optimizer_runs_and_is_deterministic(cp):
     assert all(y <= x for x, y in zip(b1, b1[1:]))
     assert b1[-1] < b1[0]
     assert s1["t"] == prob.opt.T
+    # the last selection, alone and with the population; a plan has nothing to tune
+    elite, cost = opt.last_elites()
+    _, cost_all, elite_all = opt.last()
+    assert torch.equal(elite, elite_all) and torch.equal(cost, cost_all)
+    np.testing.assert_array_equal(elite.cpu().numpy(), oracle.select(cost.cpu().numpy().astype(np.float64), prob.opt.nu))
+    cp.tune(plan=plan)
 
 
 def test_optimizer_resume_reproduces(cp):
