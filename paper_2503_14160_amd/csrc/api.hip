@@ -660,8 +660,13 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
     const PlanView &P = p->view;
     for (int it = 0; it < n_iters; ++it) {
         CP_HIP(launch_sample(P, v, st), "sample");
-        CP_HIP(launch_eval_fwd(P, v.W, v.B, p->d_partial, nullptr, v.cost, v.min_dist, nullptr, st), "eval");
-        CP_HIP(launch_select(v, st), "select");
+        if (reduce_select_fits(v.B)) {
+            CP_HIP(launch_eval_fwd(P, v.W, v.B, p->d_partial, nullptr, nullptr, nullptr, nullptr, st), "eval");
+            CP_HIP(launch_reduce_select(p->d_partial, eval_slots(P.ns), P.ns, P.margin, v, st), "select");
+        } else {
+            CP_HIP(launch_eval_fwd(P, v.W, v.B, p->d_partial, nullptr, v.cost, v.min_dist, nullptr, st), "eval");
+            CP_HIP(launch_select(v, st), "select");
+        }
         if (opt->npol > 0) {
             CP_HIP(launch_polish_gather(P, v, st), "polish gather");
             for (int s = 0; s < opt->prm.polish_steps; ++s) {

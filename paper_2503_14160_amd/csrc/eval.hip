@@ -690,23 +690,6 @@ __global__ __launch_bounds__(256, CULL ? 5 : 6) void k_eval_persistent(const Bat
     }
 }
 
-__device__ __forceinline__ void reduce_one(const double2 *__restrict__ partial, int slots, int ns, float margin,
-                                           float *__restrict__ cost, float *__restrict__ min_dist,
-                                           uint8_t *__restrict__ flags, int b) {
-    const int64_t g0 = (int64_t)b * ns, g1 = g0 + ns - 1;
-    double s = 0.0;
-    float m = kInf;
-    for (int64_t w = g0 / kWave; w <= g1 / kWave; ++w) {
-        const int p0 = (int)((w * kWave) / ns);
-        const double2 v = partial[w * slots + (b - p0)];
-        s += v.x;
-        m = fminf(m, (float)v.y);
-    }
-    cost[b] = (float)s;
-    if (min_dist) min_dist[b] = m;
-    if (flags) flags[b] = (uint8_t)(m < margin);
-}
-
 __global__ __launch_bounds__(256) void k_eval_reduce(const double2 *__restrict__ partial, int slots, int B, int ns,
                                                      float margin, float *__restrict__ cost,
                                                      float *__restrict__ min_dist, uint8_t *__restrict__ flags) {
@@ -1142,7 +1125,8 @@ hipError_t launch_eval_fwd(const PlanView &P0, const float *W, int B, double2 *p
         hipLaunchKernelGGL((k_eval_fwd<false, false>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (!cost && !min_dist && !flags) return hipSuccess;  // only the tape is wanted
+    // no outputs: the caller takes the per-path sums itself, or wants only the tape
+    if (!cost && !min_dist && !flags) return hipSuccess;
     hipLaunchKernelGGL(k_eval_reduce, dim3((B + 255) / 256), dim3(256), 0, st, partial, slots, B, P.ns, P.margin,
                        cost, min_dist, flags);
     return hipGetLastError();

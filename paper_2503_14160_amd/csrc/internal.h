@@ -358,6 +358,25 @@ __device__ __forceinline__ float hinge_value(const PlanView &P, float d, float &
     return 0.0f;
 }
 
+// path b's cost (FP64 sum of its checkpoints' partial sums, in wave order),
+// minimum distance and collision flag from the evaluation's partial sums
+__device__ __forceinline__ void reduce_one(const double2 *__restrict__ partial, int slots, int ns, float margin,
+                                           float *__restrict__ cost, float *__restrict__ min_dist,
+                                           uint8_t *__restrict__ flags, int b) {
+    const int64_t g0 = (int64_t)b * ns, g1 = g0 + ns - 1;
+    double s = 0.0;
+    float m = kInf;
+    for (int64_t w = g0 / kWave; w <= g1 / kWave; ++w) {
+        const int p0 = (int)((w * kWave) / ns);
+        const double2 v = partial[w * slots + (b - p0)];
+        s += v.x;
+        m = fminf(m, (float)v.y);
+    }
+    cost[b] = (float)s;
+    if (min_dist) min_dist[b] = m;
+    if (flags) flags[b] = (uint8_t)(m < margin);
+}
+
 // order key of a cost: increasing in the cost, -0 equal to +0, and NaN equal
 // to +inf (the two then go by index); 0xFFFFFFFF is above every cost's key
 __device__ __forceinline__ uint32_t cost_key(float c) {

@@ -73,6 +73,11 @@ hipError_t launch_batch_iteration(const BatchProblem *probs, double2 *partial, i
                                   int n_items, int rounds, int grid, bool cull, hipStream_t st);
 
 hipError_t launch_sample(const PlanView &P, const OptView &O, hipStream_t st);
+// the per-path sums of an evaluation (launched without outputs) and the
+// selection in one launch, for populations with reduce_select_fits(B)
+bool reduce_select_fits(int B);
+hipError_t launch_reduce_select(const double2 *partial, int slots, int ns, float margin, const OptView &O,
+                                hipStream_t st);
 hipError_t launch_select(const OptView &O, hipStream_t st);
 hipError_t launch_polish_gather(const PlanView &P, const OptView &O, hipStream_t st);
 hipError_t launch_polish_gd(const PlanView &P, const OptView &O, hipStream_t st);

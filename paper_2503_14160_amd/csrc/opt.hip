@@ -391,6 +391,16 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const float *__restrict_
     select_body(cost, B, nu, elite);
 }
 
+// populations up to kSelThreads: the evaluation's per-path sums and the
+// selection in one workgroup (each thread sums its own path, then ranks it)
+__global__ __launch_bounds__(kSelThreads) void k_reduce_select(const double2 *__restrict__ partial, int slots, int ns,
+                                                               float margin, float *__restrict__ cost,
+                                                               float *__restrict__ min_dist, int B, int nu,
+                                                               int32_t *__restrict__ elite) {
+    if ((int)threadIdx.x < B) reduce_one(partial, slots, ns, margin, cost, min_dist, nullptr, threadIdx.x);
+    select_body(cost, B, nu, elite);
+}
+
 // batch: one workgroup per problem
 __global__ __launch_bounds__(kSelThreads) void k_select_batched(const BatchProblem *__restrict__ probs) {
     const OptView &O = probs[blockIdx.x].O;
@@ -805,6 +815,15 @@ hipError_t launch_init_state(const PlanView &P, const OptView &O, float sigma0, 
 
 hipError_t launch_sample(const PlanView &P, const OptView &O, hipStream_t st) {
     hipLaunchKernelGGL(k_sample, dim3((O.B + kSampleTile - 1) / kSampleTile), dim3(256), 0, st, P, O);
+    return hipGetLastError();
+}
+
+bool reduce_select_fits(int B) { return B <= kSelThreads; }
+
+hipError_t launch_reduce_select(const double2 *partial, int slots, int ns, float margin, const OptView &O,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_select, dim3(1), dim3(kSelThreads), 0, st, partial, slots, ns, margin, O.cost,
+                       O.min_dist, O.B, O.nu, O.elite0);
     return hipGetLastError();
 }
 
