@@ -230,8 +230,7 @@ def bench_batch(args, torch, cp, probs):
     work = np.array([p.opt.B * p.cost.n_s for p in probs], np.float64)
     print(f"[bench] c3_batch: {n} problems, building", file=sys.stderr, flush=True)
     batch = cp.Batch(probs)
-    cache = os.path.join(ROOT, "gpurun_out", "c3_tune_cache.txt") if os.path.isdir(
-        os.path.join(ROOT, "gpurun_out")) else None
+    cache = args.tune_cache
     t0 = time.perf_counter()
     tuning = batch.tune(cache)
     tune_s = time.perf_counter() - t0
@@ -348,12 +347,14 @@ def main():
     ap.add_argument("--eval-reps", type=int, default=10)
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=30)
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="c3_batch: text cache of tuned launch shapes (default: none, the tuner times every shape)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU in this build",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library evaluates and optimizes "
+              f"on a single device", file=sys.stderr)
         sys.exit(2)
 
     import torch
