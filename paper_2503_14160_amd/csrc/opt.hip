@@ -219,6 +219,7 @@ template <int PER>
 __device__ __forceinline__ void select_regs(const float *__restrict__ cost, int B, int nu, uint32_t *hist,
                                             uint32_t *eqoff, uint64_t *sorted, uint32_t &s_digit, uint32_t &s_rem,
                                             uint32_t &s_count) {
+    static_assert(PER % 8 == 0 && PER <= 64, "keys are loaded eight at a time; eqoff holds 64 slots");
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     // slot j reads cost[t + min(j kSelThreads, B - 1 - t)], always in bounds,
     // and keeps it when j kSelThreads <= B - 1 - t
