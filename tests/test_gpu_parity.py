@@ -182,6 +182,34 @@ def test_eval_full_size_sampled(cp):
     np.testing.assert_array_equal(md2.cpu().numpy(), md.cpu().numpy()[idx])
 
 
+def test_eval_c4_full_size_sampled(cp):
+    """c4_sdf at its benchmark size: the grid built on the device from 1 M
+    points (256 x 256 x 128), 65536 paths x 608 checkpoints evaluated in the
+    benchmark's launch; sampled paths against the oracle, which builds its
+    own grid from the same points."""
+    prob = synth.c4_sdf()
+    B, spec = prob.opt.B, prob.sdf
+    print(f"[eval full] c4_sdf B={B} grid={spec.dims}", flush=True)
+    sdf = cp.sdf_build(torch.from_numpy(prob.lidar).cuda(), spec)
+    rng = np.random.default_rng(107)
+    W = synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, B, prob.cost.K, sigma=0.2)
+    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, sdf=sdf, sdf_spec=spec)
+    plan.set_endpoints(prob.q_start, prob.q_goal)
+    cost, md, fl = plan.eval(torch.from_numpy(W).cuda())
+    torch.cuda.synchronize()
+    phi_ref, _, _, _ = oracle.sdf_build(prob.lidar, spec)
+    idx = np.sort(rng.choice(B, size=24, replace=False))
+    idx[0], idx[-1] = 0, B - 1
+    m = oracle.Model(prob.robot, prob.scene, prob.cost, sdf=phi_ref, sdf_spec=spec)
+    ref = oracle.eval_paths(m, prob.q_start, prob.q_goal, W[idx].astype(np.float64), per_checkpoint=True)
+    tol, _ = _cost_tol(ref, prob.cost, prob.robot.n_joints)
+    c = cost.cpu().numpy()[idx].astype(np.float64)
+    assert np.all(np.abs(c - ref["cost"]) <= tol)
+    assert np.all(np.abs(md.cpu().numpy()[idx] - ref["min_dist"]) <= EPS_D)
+    clear = np.abs(ref["min_dist"] - float(np.float32(prob.cost.margin))) > 1e-4
+    np.testing.assert_array_equal(fl.cpu().numpy()[idx][clear], ref["flags"][clear])
+
+
 def test_eval_deterministic(cp):
     prob = synth.c0_plain()
     rng = np.random.default_rng(106)
@@ -518,7 +546,7 @@ def test_sdf_build_and_query_parity(cp):
     plan = cp.Plan(prob.robot, scene, prob.cost, max_B=1, sdf=sdf, sdf_spec=spec)
     Q = synth.random_configs(rng, prob.robot, 512)
     d, a = plan.debug_configs(torch.from_numpy(Q).cuda())
-    m = oracle.Model(prob.robot, scene, prob.cost, sdf=sdf.cpu().numpy(), sdf_spec=spec)
+    m = oracle.Model(prob.robot, scene, prob.cost, sdf=phi_ref, sdf_spec=spec)
     dr, sr, orr, sec = oracle.eval_configs(m, Q.astype(np.float64))
     assert np.all(np.abs(d.cpu().numpy() - dr) <= 1e-4)
     assert np.all((a.cpu().numpy().view(np.uint32) & 0xFFFF) == 0xFFFF)
