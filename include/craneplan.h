@@ -332,6 +332,14 @@ int cp_debug_eval_configs(cp_plan *plan, const float *d_q, int32_t N, float *d_d
  * written to d_elite [nu]; 1 <= nu <= min(B, CP_MAX_ELITES).  Runs on the
  * current device. */
 int cp_debug_select(const float *d_cost, int32_t B, int32_t nu, int32_t *d_elite, cp_stream_t stream);
+/* Steps (4)-(6) of Algorithm 1 alone, for tests: the log-rank weighted mean
+ * and the covariance about it, from the last iteration's samples with the
+ * caller's elite indices d_elite [nu] (rank order, each in 0..B-1; device
+ * memory, read back and range-checked first, so the call synchronises) in
+ * place of the selection.  Replaces mu and C (the factor is not refreshed)
+ * and advances the iteration counter and best-so-far as a step would.
+ * CP_ERR_INVALID_ARG for an index out of range or an optimizer with polish. */
+int cp_debug_update(cp_opt *opt, const int32_t *d_elite, cp_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,8 @@ EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_en
            "cp_optimizer_step", "cp_optimizer_get_state", "cp_optimizer_set_state", "cp_optimizer_last",
            "cp_sdf_build", "cp_debug_fk", "cp_debug_eval_configs", "cp_debug_select", "cp_batch_create",
            "cp_batch_destroy", "cp_batch_run", "cp_batch_eval", "cp_batch_get_state", "cp_batch_set_tuning",
-           "cp_batch_get_tuning", "cp_batch_tune", "cp_optimizer_last_elites", "cp_tune"]
+           "cp_batch_get_tuning", "cp_batch_tune", "cp_optimizer_last_elites", "cp_tune",
+           "cp_debug_update"]
 
 
 class CranePlanError(RuntimeError):
@@ -105,6 +106,7 @@ def lib():
         L.cp_batch_tune.argtypes = [_vp, ctypes.c_char_p, _vp]
         L.cp_optimizer_last_elites.argtypes = [_vp, _vp, _vp, _vp]
         L.cp_tune.argtypes = [_vp, _vp, ctypes.c_char_p]
+        L.cp_debug_update.argtypes = [_vp, _vp, _vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -344,6 +346,12 @@ class Optimizer:
         elite = torch.empty(self.nu, dtype=torch.int32, device=dev)
         _check(lib().cp_optimizer_last(self._h, _ptr(W), _ptr(cost), _ptr(elite), _stream()))
         return W, cost, elite
+
+    def debug_update(self, elite: torch.Tensor):
+        """Steps (4)-(6) alone on the last samples with the given elite indices
+        (rank order), in place of the selection (tests)."""
+        elite = elite.to(device=self.plan.device, dtype=torch.int32).contiguous()
+        _check(lib().cp_debug_update(self._h, _ptr(elite), _stream()))
 
     def last_elites(self):
         """The last iteration's elite indices [nu] (rank order) and costs [B]."""

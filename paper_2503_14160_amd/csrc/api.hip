@@ -687,6 +687,23 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
     return CP_OK;
 }
 
+int cp_debug_update(cp_opt *opt, const int32_t *d_elite, cp_stream_t stream) {
+    if (!opt || !d_elite) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (opt->npol > 0) return fail(CP_ERR_INVALID_ARG, "not with polish");
+    cp_plan *p = opt->plan;
+    DeviceGuard g(p->device);
+    const OptView &v = opt->view;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> idx(v.nu);
+    CP_HIP(hipStreamSynchronize(st), "sync");
+    CP_HIP(hipMemcpy(idx.data(), d_elite, v.nu * sizeof(int32_t), hipMemcpyDeviceToHost), "elites");
+    for (int32_t i : idx)
+        if (i < 0 || i >= v.B) return fail(CP_ERR_INVALID_ARG, "elite index out of range");
+    CP_HIP(hipMemcpyAsync(v.elite0, d_elite, v.nu * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "elites");
+    CP_HIP(launch_update(p->view, v, st), "update");
+    return CP_OK;
+}
+
 int cp_optimizer_last_elites(cp_opt *opt, int32_t *d_idx, float *d_cost, cp_stream_t stream) {
     return cp_optimizer_last(opt, nullptr, d_cost, d_idx, stream);
 }
