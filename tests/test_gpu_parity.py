@@ -366,8 +366,10 @@ def test_optimizer_one_step_parity(cp):
     W = W.cpu().numpy()
     Wref = oracle.expand(prob.robot, step["xi"], prob.cost.K)
     np.testing.assert_allclose(W, Wref, rtol=0, atol=2e-6 * np.maximum(1, np.abs(Wref)).max())
+    # the oracle evaluates its own samples, stored in FP32 as the device stores its own
     m = oracle.Model(prob.robot, prob.scene, prob.cost)
-    ref = oracle.eval_paths(m, prob.q_start, prob.q_goal, W.astype(np.float64), per_checkpoint=True)
+    Wq = Wref.astype(np.float32).astype(np.float64)
+    ref = oracle.eval_paths(m, prob.q_start, prob.q_goal, Wq, per_checkpoint=True)
     tol, _ = _cost_tol(ref, prob.cost, prob.robot.n_joints)
     c = cost.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(c - ref["cost"]) <= tol)
