@@ -73,13 +73,15 @@ constexpr int kSampleTile = 16;  // paths per block
 
 __device__ __forceinline__ void sample_body(const PlanView &P, const OptView &O, int tile) {
     __shared__ double z[kSampleTile][CP_MAX_DIM + 1];  // padded rows: lanes of one column read across paths
-    const int D = O.D;
+    __shared__ int wofs[CP_MAX_DIM];                   // coordinate e -> its offset in a path's waypoints
+    const int D = O.D, n = P.n_joints, per = P.K * n;
     const int b0 = tile * kSampleTile;
     const uint32_t t = (uint32_t)*O.t;
     const uint32_t k0 = (uint32_t)O.seed, k1 = (uint32_t)(O.seed >> 32);
     const int G = (D + 3) / 4;
+    // items run path-minor (bl = idx mod 16): no division by a runtime count
     for (int idx = threadIdx.x; idx < kSampleTile * G; idx += blockDim.x) {
-        const int bl = idx / G, g = idx % G, b = b0 + bl;
+        const int bl = idx % kSampleTile, g = idx / kSampleTile, b = b0 + bl;
         if (b >= O.B) continue;
         const uint4 x = philox4x32_10(make_uint4((uint32_t)g, (uint32_t)b, t, O.problem_id), k0, k1);
         double zz[4];
@@ -89,8 +91,8 @@ __device__ __forceinline__ void sample_body(const PlanView &P, const OptView &O,
         for (int h = 0; h < 4; ++h)
             if (4 * g + h < D) z[bl][4 * g + h] = zz[h];
     }
+    for (int e = threadIdx.x; e < D; e += blockDim.x) wofs[e] = (e / O.n_act) * n + O.act[e % O.n_act];
     __syncthreads();
-    const int n = P.n_joints;
     // lanes run over the tile's paths for one coordinate e: the row of L is
     // read once per coordinate (a broadcast) rather than once per lane
     for (int idx = threadIdx.x; idx < kSampleTile * D; idx += blockDim.x) {
@@ -100,16 +102,15 @@ __device__ __forceinline__ void sample_body(const PlanView &P, const OptView &O,
         double s = O.mu[e];
         for (int e2 = 0; e2 <= e; ++e2) s = fma(Lr[e2], z[bl][e2], s);
         O.xi[(size_t)b * D + e] = s;
-        const int k = e / O.n_act, a = e % O.n_act;
-        O.W[((size_t)b * P.K + k) * n + O.act[a]] = (float)s;
+        O.W[(size_t)b * per + wofs[e]] = (float)s;
     }
-    // joints that are not sampled take their hold value
-    for (int idx = threadIdx.x; idx < kSampleTile * P.K * n; idx += blockDim.x) {
-        const int bl = idx / (P.K * n), r = idx % (P.K * n), b = b0 + bl;
-        if (b >= O.B) continue;
-        const int jj = r % n;
-        const JointDev J = P.joints[jj];
-        if (!J.active) O.W[(size_t)b * P.K * n + r] = J.qhold;
+    // joints that are not sampled take their hold value (one division per
+    // waypoint entry, shared by the tile's paths)
+    const int nb = min(kSampleTile, O.B - b0);
+    for (int r = threadIdx.x; r < per; r += blockDim.x) {
+        const JointDev J = P.joints[r % n];
+        if (J.active) continue;
+        for (int bl = 0; bl < nb; ++bl) O.W[(size_t)(b0 + bl) * per + r] = J.qhold;
     }
 }
 
