@@ -212,10 +212,10 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 }
 
 // Radix select with PER keys per thread held in registers: slot j of thread
-// t is path j kSelThreads + t.  Slots past B hold the largest key; their
-// indices lie above every path's, so they are never among the nu smallest
-// (key, index) pairs and every slot can be processed alike.  Leaves the nu
-// selected keys, unordered, in sorted[0, nu).
+// t is path j kSelThreads + t.  Slots past B hold a key above every path's,
+// and their indices lie above every path's, so they are never among the nu
+// smallest (key, index) pairs and every slot can be processed alike.  Leaves
+// the nu selected (relative key, index) pairs, unordered, in sorted[0, nu).
 template <int PER>
 __device__ __forceinline__ void select_regs(const float *__restrict__ cost, int B, int nu, uint32_t *hist,
                                             uint32_t *eqoff, uint64_t *sorted, uint32_t &s_digit, uint32_t &s_rem,
@@ -233,14 +233,44 @@ __device__ __forceinline__ void select_regs(const float *__restrict__ cost, int 
 #pragma unroll
         for (int j = 0; j < 8; ++j) c[j] = ct[min((j0 + j) * kSelThreads, lim)];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            key[j0 + j] = cost_key(c[j]) | ((j0 + j) * kSelThreads <= lim ? 0u : 0xFFFFFFFFu);
+        for (int j = 0; j < 8; ++j) key[j0 + j] = cost_key(c[j]);
     }
+    // The keys are taken relative to the smallest one, and the digits run
+    // over the bits of the span only: similar costs, whose keys share their
+    // leading bytes, then spread over the first pass's bins instead of piling
+    // onto a few (same-bin atomics serialise).  Slots past B get span + 1,
+    // above every path's key; the order of the paths' keys is unchanged.
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        if (j * kSelThreads <= lim) {
+            kmin = min(kmin, key[j]);
+            kmax = max(kmax, key[j]);
+        }
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o, 64));
+        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o, 64));
+    }
+    if (lane == 0) { hist[w] = kmin; hist[16 + w] = kmax; }
+    __syncthreads();
+    kmin = hist[0];
+    kmax = hist[16];
+    for (int x = 1; x < kSelThreads / 64; ++x) {
+        kmin = min(kmin, hist[x]);
+        kmax = max(kmax, hist[16 + x]);
+    }
+    __syncthreads();
+    const uint32_t span1 = kmax - kmin + 1u;  // keys lie in [0x007FFFFF, 0xFF800000]: no wrap
+    const int nb = 32 - __builtin_clz(span1);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) key[j] = j * kSelThreads <= lim ? key[j] - kmin : span1;
     uint32_t prefix = 0, mask = 0, remaining = (uint32_t)nu;
-    // most significant byte first; a wave whose counted keys share one digit
-    // adds them with one atomic (the leading bytes of similar costs agree)
-    for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 24 - 8 * pass;
+    // most significant digit first (8 bits, the last one possibly fewer); a
+    // wave whose counted keys share one digit adds them with one atomic
+    for (int hi = nb; hi > 0;) {
+        const int lo = hi > 8 ? hi - 8 : 0;
+        const uint32_t dmask = (1u << (hi - lo)) - 1u;
         if (tid < 256) hist[tid] = 0;
         __syncthreads();
 #pragma unroll
@@ -248,7 +278,7 @@ __device__ __forceinline__ void select_regs(const float *__restrict__ cost, int 
             const bool m = (key[j] & mask) == prefix;
             const uint64_t bm = __builtin_amdgcn_ballot_w64(m);
             if (bm) {
-                const uint32_t d = (key[j] >> shift) & 255u;
+                const uint32_t d = (key[j] >> lo) & dmask;
                 const int lead = __builtin_ctzll(bm);
                 const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)d, lead);
                 if (__builtin_amdgcn_ballot_w64(m && d == dl) == bm) {
@@ -261,9 +291,10 @@ __device__ __forceinline__ void select_regs(const float *__restrict__ cost, int 
         __syncthreads();
         select_digit(hist, remaining, s_digit, s_rem);
         __syncthreads();
-        prefix |= s_digit << shift;
-        mask |= 255u << shift;
+        prefix |= s_digit << lo;
+        mask |= dmask << lo;
         remaining = s_rem;
+        hi = lo;
     }
     // keys below the threshold, and the `remaining` lowest-index keys equal
     // to it: the equal keys are counted per (slot, wave), in index order, and
