@@ -674,8 +674,16 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
                 CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, opt->d_tape_p, nullptr, nullptr, nullptr,
                                        st),
                        "polish eval");
-                CP_HIP(launch_eval_bwd(P, v.Wp, opt->npol, opt->d_tape_p, v.ones, v.grad_p, st), "polish adjoint");
-                CP_HIP(launch_polish_gd(P, v, st), "polish step");
+                // the adjoint applies each path's gradient step itself
+                PolishStep ps{};
+                ps.W = v.Wp;
+                for (int a = 0; a < CP_MAX_JOINTS; ++a) ps.act[a] = v.act[a];
+                ps.eta = v.eta;
+                ps.clip = v.clip;
+                ps.D = v.D;
+                ps.n_act = v.n_act;
+                CP_HIP(launch_eval_bwd(P, v.Wp, opt->npol, opt->d_tape_p, v.ones, v.grad_p, st, &ps),
+                       "polish adjoint and step");
             }
             CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, nullptr, v.cost_p, v.min_dist, nullptr, st),
                    "polish eval");

@@ -830,7 +830,7 @@ template <bool TAPE, bool CULL, int NW>
 __global__ __launch_bounds__(NW * 64) void k_eval_bwd(PlanView P, const float *__restrict__ W, int B,
                                                           const uint32_t *__restrict__ tape,
                                                           const float *__restrict__ grad_cost,
-                                                          float *__restrict__ grad_W) {
+                                                          float *__restrict__ grad_W, PolishStep pol) {
     constexpr int kBwdThreads = NW * kWave, kBwdWaves = NW;
     __shared__ float part[kBwdWaves][kWaveCtrl][CP_MAX_JOINTS];
     __shared__ int wlo[kBwdWaves], whi[kBwdWaves];
@@ -922,6 +922,25 @@ __global__ __launch_bounds__(NW * 64) void k_eval_bwd(PlanView P, const float *_
     for (int idx = tid; idx < P.K * n; idx += kBwdThreads) {
         const int i = idx / n, jj = idx % n;
         grad_W[(size_t)b * P.K * n + idx] = gc * (float)acc[(i + lead) * n + jj];
+    }
+    if (pol.W && wv == 0) {
+        // the polish step on this path (its waypoints are not read again):
+        // the gradient entries as written above, squared and summed per lane
+        // then across the wave, then the clipped step
+        float s = 0.0f;
+        for (int e = lane; e < pol.D; e += kWave) {
+            const int k = e / pol.n_act, jj = pol.act[e % pol.n_act];
+            const float g = gc * (float)acc[(k + lead) * n + jj];
+            s = __builtin_fmaf(g, g, s);
+        }
+        s = wave_sum(s);
+        const float scale = pol.eta / fmaxf(1.0f, fsqrt(s) / pol.clip);
+        float *Wb = pol.W + (size_t)b * P.K * n;
+        for (int e = lane; e < pol.D; e += kWave) {
+            const int k = e / pol.n_act, jj = pol.act[e % pol.n_act];
+            const float g = gc * (float)acc[(k + lead) * n + jj];
+            Wb[k * n + jj] = Wb[k * n + jj] - scale * g;
+        }
     }
 }
 
@@ -1150,7 +1169,9 @@ hipError_t launch_batch_eval(const BatchProblem *probs, double2 *partial, int n,
 constexpr int kBwdWidePaths = 256;
 
 hipError_t launch_eval_bwd(const PlanView &P0, const float *W, int B, const uint32_t *tape, const float *grad_cost,
-                           float *grad_W, hipStream_t st) {
+                           float *grad_W, hipStream_t st, const PolishStep *pol) {
+    PolishStep ps{};
+    if (pol) ps = *pol;
     // without a tape the minimising pair is found again (grid bounds in use)
     PlanView P = P0;
     if (!tape) {
@@ -1160,19 +1181,19 @@ hipError_t launch_eval_bwd(const PlanView &P0, const float *W, int B, const uint
     // one workgroup per path: 4 waves, or 16 when there are few paths
     const bool wide = B <= kBwdWidePaths;
     if (tape && wide)
-        hipLaunchKernelGGL((k_eval_bwd<true, false, 16>), dim3(B), dim3(1024), 0, st, P, W, B, tape, grad_cost, grad_W);
+        hipLaunchKernelGGL((k_eval_bwd<true, false, 16>), dim3(B), dim3(1024), 0, st, P, W, B, tape, grad_cost, grad_W, ps);
     else if (tape)
-        hipLaunchKernelGGL((k_eval_bwd<true, false, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W);
+        hipLaunchKernelGGL((k_eval_bwd<true, false, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W, ps);
     else if (use_cull(P) && wide)
         hipLaunchKernelGGL((k_eval_bwd<false, true, 16>), dim3(B), dim3(1024), 0, st, P, W, B, tape, grad_cost,
-                           grad_W);
+                           grad_W, ps);
     else if (use_cull(P))
-        hipLaunchKernelGGL((k_eval_bwd<false, true, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W);
+        hipLaunchKernelGGL((k_eval_bwd<false, true, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W, ps);
     else if (wide)
         hipLaunchKernelGGL((k_eval_bwd<false, false, 16>), dim3(B), dim3(1024), 0, st, P, W, B, tape, grad_cost,
-                           grad_W);
+                           grad_W, ps);
     else
-        hipLaunchKernelGGL((k_eval_bwd<false, false, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W);
+        hipLaunchKernelGGL((k_eval_bwd<false, false, 4>), dim3(B), dim3(256), 0, st, P, W, B, tape, grad_cost, grad_W, ps);
     return hipGetLastError();
 }
 

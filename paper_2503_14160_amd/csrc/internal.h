@@ -358,6 +358,17 @@ __device__ __forceinline__ float hinge_value(const PlanView &P, float d, float &
     return 0.0f;
 }
 
+// The gradient polish's step on an elite path (a clipped gradient step, which
+// the paper does not specify): W <- W - eta g / max(1, |g| / g_max) on the
+// sampled joints, applied by the adjoint to each path right after its
+// gradient is complete; W null: no step.
+struct PolishStep {
+    float *W;                      // the adjoint's own input waypoints [B][K][n]
+    int32_t act[CP_MAX_JOINTS];    // sampled joint ids
+    float eta, clip;
+    int32_t D, n_act;
+};
+
 // path b's cost (FP64 sum of its checkpoints' partial sums, in wave order),
 // minimum distance and collision flag from the evaluation's partial sums
 __device__ __forceinline__ void reduce_one(const double2 *__restrict__ partial, int slots, int ns, float margin,

@@ -13,8 +13,9 @@ hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *pa
                            float *min_dist, uint8_t *flags, hipStream_t st);
 // the clearance grid of a plan (P.clr_* set), into out [clr_ny][clr_nx]
 hipError_t launch_clearance(const PlanView &P, float *out, hipStream_t st);
+// with pol (W set): the polish's step on every path after its gradient
 hipError_t launch_eval_bwd(const PlanView &P, const float *W, int B, const uint32_t *tape, const float *grad_cost,
-                           float *grad_W, hipStream_t st);
+                           float *grad_W, hipStream_t st, const PolishStep *pol = nullptr);
 hipError_t launch_debug_fk(const PlanView &P, const float *Q, int N, float *centers, float *frames, hipStream_t st);
 hipError_t launch_debug_configs(const PlanView &P, const float *Q, int N, float *dist, uint32_t *arg,
                                 hipStream_t st);
@@ -80,7 +81,6 @@ hipError_t launch_reduce_select(const double2 *partial, int slots, int ns, float
                                 hipStream_t st);
 hipError_t launch_select(const OptView &O, hipStream_t st);
 hipError_t launch_polish_gather(const PlanView &P, const OptView &O, hipStream_t st);
-hipError_t launch_polish_gd(const PlanView &P, const OptView &O, hipStream_t st);
 hipError_t launch_rerank(const OptView &O, hipStream_t st);
 hipError_t launch_update(const PlanView &P, const OptView &O, hipStream_t st);
 hipError_t launch_chol(const OptView &O, hipStream_t st);

@@ -452,25 +452,6 @@ __global__ void k_polish_gather(PlanView P, OptView O) {
     }
 }
 
-// W <- W - eta g / max(1, |g| / g_max) on the sampled joints; one wave per path
-__global__ __launch_bounds__(64) void k_polish_step(PlanView P, OptView O) {
-    const int i = blockIdx.x;
-    const int n = P.n_joints;
-    float *Wi = O.Wp + (size_t)i * P.K * n;
-    const float *gi = O.grad_p + (size_t)i * P.K * n;
-    float s = 0.0f;
-    for (int e = threadIdx.x; e < O.D; e += 64) {
-        const float g = gi[(e / O.n_act) * n + O.act[e % O.n_act]];
-        s = __builtin_fmaf(g, g, s);
-    }
-    s = wave_sum(s);
-    const float scale = O.eta / fmaxf(1.0f, fsqrt(s) / O.clip);
-    for (int e = threadIdx.x; e < O.D; e += 64) {
-        const int off = (e / O.n_act) * n + O.act[e % O.n_act];
-        Wi[off] = Wi[off] - scale * gi[off];
-    }
-}
-
 // elites re-ranked after polish: polished slots (index B + i) carry their new
 // cost, the rest keep theirs; ties keep the earlier rank
 __global__ __launch_bounds__(kSelThreads) void k_rerank(OptView O) {
@@ -868,11 +849,6 @@ hipError_t launch_select(const OptView &O, hipStream_t st) {
 hipError_t launch_polish_gather(const PlanView &P, const OptView &O, hipStream_t st) {
     const int n = O.npol * P.K * P.n_joints;
     hipLaunchKernelGGL(k_polish_gather, dim3((n + 255) / 256), dim3(256), 0, st, P, O);
-    return hipGetLastError();
-}
-
-hipError_t launch_polish_gd(const PlanView &P, const OptView &O, hipStream_t st) {
-    hipLaunchKernelGGL(k_polish_step, dim3(O.npol), dim3(64), 0, st, P, O);
     return hipGetLastError();
 }
 
