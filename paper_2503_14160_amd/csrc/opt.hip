@@ -128,6 +128,12 @@ __global__ __launch_bounds__(256) void k_sample_batched(const BatchProblem *__re
 // ---------------------------------------------------------------------------
 
 constexpr int kSelThreads = 1024;
+// populations up to this size, and those of up to kSelThreads that keep more
+// than half of their paths, are ranked by counting (each thread compares its
+// key with every other); the others take the radix select (measured: rank
+// counting 21 us at B = 600, 32 us at B = 1024; radix 21 and 22 us, but 39 us
+// at B = nu = 1024, where the elites' sort is the whole population's)
+constexpr int kSelRankMax = 768;
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *buf, uint32_t &total) {
     const int tid = threadIdx.x;
@@ -350,7 +356,7 @@ __device__ __forceinline__ void select_body(const float *__restrict__ cost, int 
     __shared__ uint64_t sorted[CP_MAX_ELITES];
     __shared__ uint32_t s_digit, s_rem, s_count;
     const int tid = threadIdx.x;
-    if (B <= kSelThreads) {
+    if (B <= kSelRankMax || (B <= kSelThreads && 2 * nu > B)) {
         // small populations: every path's rank in the (cost, index) order is
         // the number of smaller 64-bit keys, counted directly (broadcast LDS
         // reads); the first nu ranks are the elites
@@ -364,7 +370,9 @@ __device__ __forceinline__ void select_body(const float *__restrict__ cost, int 
         }
         return;
     }
-    if (B <= 16 * kSelThreads) {
+    if (B <= 8 * kSelThreads) {
+        select_regs<8>(cost, B, nu, hist, scanbuf, sorted, s_digit, s_rem, s_count);
+    } else if (B <= 16 * kSelThreads) {
         select_regs<16>(cost, B, nu, hist, scanbuf, sorted, s_digit, s_rem, s_count);
     } else if (B <= 32 * kSelThreads) {
         select_regs<32>(cost, B, nu, hist, scanbuf, sorted, s_digit, s_rem, s_count);
@@ -431,6 +439,7 @@ __global__ __launch_bounds__(kSelThreads) void k_reduce_select(const double2 *__
                                                                float *__restrict__ min_dist, int B, int nu,
                                                                int32_t *__restrict__ elite) {
     if ((int)threadIdx.x < B) reduce_one(partial, slots, ns, margin, cost, min_dist, nullptr, threadIdx.x);
+    __syncthreads();  // the radix select reads other threads' sums
     select_body(cost, B, nu, elite);
 }
 
