@@ -246,6 +246,14 @@ int cp_optimizer_last(cp_opt *opt, float *d_waypoints, float *d_cost, int32_t *d
  * d_idx [nu] in rank order and costs d_cost [B], enqueued on stream; the same
  * as cp_optimizer_last without the waypoints.  Either may be NULL. */
 int cp_optimizer_last_elites(cp_opt *opt, int32_t *d_idx, float *d_cost, cp_stream_t stream);
+/* The gradient polish of the last iteration (a setting of the differentiable
+ * workload; the paper's Algorithm 1 has no such step): the polished elites'
+ * waypoints d_waypoints [polish_elites][K][n] in the order of the selection
+ * before polish, and their costs d_cost [polish_elites] (enqueued on stream;
+ * either may be NULL).  The elite index polish_slot + B of
+ * cp_optimizer_last names row polish_slot here.  CP_ERR_STATE for an
+ * optimizer without polish. */
+int cp_optimizer_last_polished(cp_opt *opt, float *d_waypoints, float *d_cost, cp_stream_t stream);
 
 /*
  * Batches of independent planning problems (the paper's batch generation of
@@ -288,6 +296,12 @@ int cp_batch_eval(cp_batch *batch, cp_stream_t stream);
 /* State of problem p, as cp_optimizer_get_state (SYNC). */
 int cp_batch_get_state(cp_batch *batch, int32_t p, double *mu, double *C, int64_t *iter, float *best_cost,
                        float *best_waypoints);
+
+/* The last iteration's population of problem p, as cp_optimizer_last:
+ * waypoints [B_p][K_p][n_p], costs [B_p], elite indices [nu_p] in rank
+ * order (enqueued on stream; any may be NULL). */
+int cp_batch_last(cp_batch *batch, int32_t p, float *d_waypoints, float *d_cost, int32_t *d_elite,
+                  cp_stream_t stream);
 
 /* Set / read the launch shape (setting drops captured graphs). */
 int cp_batch_set_tuning(cp_batch *batch, const cp_batch_tuning *tuning);
@@ -336,9 +350,12 @@ int cp_debug_select(const float *d_cost, int32_t B, int32_t nu, int32_t *d_elite
  * and the covariance about it, from the last iteration's samples with the
  * caller's elite indices d_elite [nu] (rank order, each in 0..B-1; device
  * memory, read back and range-checked first, so the call synchronises) in
- * place of the selection.  Replaces mu and C (the factor is not refreshed)
- * and advances the iteration counter and best-so-far as a step would.
- * CP_ERR_INVALID_ARG for an index out of range or an optimizer with polish. */
+ * place of the selection.  With polish settings, the first polish_elites of
+ * them are polished, re-evaluated and re-ranked first, as in a step.
+ * Replaces mu and C (the factor is not refreshed) and advances the iteration
+ * counter and best-so-far as a step would (the caller's first elite standing
+ * for the iteration's best sample).  CP_ERR_INVALID_ARG for an index out of
+ * range. */
 int cp_debug_update(cp_opt *opt, const int32_t *d_elite, cp_stream_t stream);
 
 #ifdef __cplusplus

@@ -449,13 +449,20 @@ class Optimizer:
         z = normals(self.p.opt.seed, self.t, self.p.opt.B, self.D, self.problem_id)
         return self.mu[None, :] + z @ L.T
 
-    def polish(self, xi_elite):
-        """Gradient polish of the elites: each takes ``polish_steps`` steps
-        W <- W - eta g / max(1, |g| / g_max) on the active joints."""
+    def polish(self, xi_elite, trace: Optional[list] = None):
+        """Gradient polish of the elites (a workload setting, not in the
+        paper): each takes ``polish_steps`` steps
+        W <- W - eta g / max(1, |g| / g_max), where g is the analytic gradient
+        of the path cost restricted to the sampled joints and |g| its norm
+        over those joints only; joints that are not sampled keep their hold
+        value.  With ``trace`` (a list), the iterate before every step is
+        appended to it."""
         o = self.p.opt
         act = self.p.robot.active.astype(bool)
         xi = xi_elite.copy()
         for _ in range(o.polish_steps):
+            if trace is not None:
+                trace.append(xi.copy())
             W = expand(self.p.robot, xi, self.K)
             _, g = grad_paths(self.model, self.p.q_start, self.p.q_goal, W)
             g = g[:, :, act].reshape(xi.shape[0], -1)

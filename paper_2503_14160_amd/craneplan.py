@@ -35,7 +35,7 @@ EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_en
            "cp_sdf_build", "cp_debug_fk", "cp_debug_eval_configs", "cp_debug_select", "cp_batch_create",
            "cp_batch_destroy", "cp_batch_run", "cp_batch_eval", "cp_batch_get_state", "cp_batch_set_tuning",
            "cp_batch_get_tuning", "cp_batch_tune", "cp_optimizer_last_elites", "cp_tune",
-           "cp_debug_update"]
+           "cp_debug_update", "cp_optimizer_last_polished", "cp_batch_last"]
 
 
 class CranePlanError(RuntimeError):
@@ -107,6 +107,8 @@ def lib():
         L.cp_optimizer_last_elites.argtypes = [_vp, _vp, _vp, _vp]
         L.cp_tune.argtypes = [_vp, _vp, ctypes.c_char_p]
         L.cp_debug_update.argtypes = [_vp, _vp, _vp]
+        L.cp_optimizer_last_polished.argtypes = [_vp, _vp, _vp, _vp]
+        L.cp_batch_last.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -306,6 +308,7 @@ class Optimizer:
         self._h = h
         self.plan = plan
         self.B, self.nu = o.B, o.nu
+        self.npol = o.polish_elites if o.polish_steps > 0 else 0
         self.D = plan.K * plan.n_active
 
     def close(self):
@@ -347,9 +350,20 @@ class Optimizer:
         _check(lib().cp_optimizer_last(self._h, _ptr(W), _ptr(cost), _ptr(elite), _stream()))
         return W, cost, elite
 
+    def last_polished(self):
+        """The last iteration's polished elites [polish_elites,K,n] (in the
+        order of the selection before polish) and their costs."""
+        dev = self.plan.device
+        npol = self.npol
+        W = torch.empty((npol, self.plan.K, self.plan.n_joints), dtype=torch.float32, device=dev)
+        cost = torch.empty(npol, dtype=torch.float32, device=dev)
+        _check(lib().cp_optimizer_last_polished(self._h, _ptr(W), _ptr(cost), _stream()))
+        return W, cost
+
     def debug_update(self, elite: torch.Tensor):
         """Steps (4)-(6) alone on the last samples with the given elite indices
-        (rank order), in place of the selection (tests)."""
+        (rank order), in place of the selection, after the polish of the
+        first polish_elites of them if the optimizer polishes (tests)."""
         elite = elite.to(device=self.plan.device, dtype=torch.int32).contiguous()
         _check(lib().cp_debug_update(self._h, _ptr(elite), _stream()))
 
@@ -392,6 +406,7 @@ class Batch:
         self.n = n
         self.shapes = [(p.cost.K, p.robot.n_joints, int(p.cost.K * int(np.count_nonzero(p.robot.active))))
                        for p in problems]
+        self.pops = [(int(p.opt.B), int(p.opt.nu)) for p in problems]
 
     def close(self):
         if getattr(self, "_h", None):
@@ -420,6 +435,18 @@ class Batch:
         _check(lib().cp_batch_get_state(self._h, int(p), mu.ctypes.data, C.ctypes.data, ctypes.byref(t),
                                         ctypes.byref(bc), bw.ctypes.data))
         return dict(mu=mu, C=C, t=t.value, best_cost=bc.value, best_W=bw)
+
+    def last(self, p: int, device: int = 0):
+        """Problem p's last population: waypoints [B,K,n], costs [B], elite
+        indices [nu] in rank order (cp_batch_last)."""
+        K, n, _ = self.shapes[p]
+        B, nu = self.pops[p]
+        dev = torch.device("cuda", device)
+        W = torch.empty((B, K, n), dtype=torch.float32, device=dev)
+        cost = torch.empty(B, dtype=torch.float32, device=dev)
+        elite = torch.empty(nu, dtype=torch.int32, device=dev)
+        _check(lib().cp_batch_last(self._h, int(p), _ptr(W), _ptr(cost), _ptr(elite), _stream()))
+        return W, cost, elite
 
     def set_tuning(self, rounds: int, wg_per_cu: int):
         t = _Tuning(int(rounds), int(wg_per_cu))

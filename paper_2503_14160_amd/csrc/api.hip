@@ -618,6 +618,7 @@ int cp_optimizer_create(cp_plan *plan, const cp_opt_params *prm, cp_opt **out) {
         (e = o->alloc(&v.W, prm->B * per)) != hipSuccess || (e = o->alloc(&v.cost, prm->B)) != hipSuccess ||
         (e = o->alloc(&v.min_dist, prm->B)) != hipSuccess || (e = o->alloc(&v.elite, prm->nu)) != hipSuccess ||
         (e = o->alloc(&v.elite0, prm->nu)) != hipSuccess || (e = o->alloc(&v.Wp, np * per)) != hipSuccess ||
+        (e = o->alloc(&v.Wp2, np * per)) != hipSuccess || (e = o->alloc(&v.md_p, np)) != hipSuccess ||
         (e = o->alloc(&v.cost_p, np)) != hipSuccess || (e = o->alloc(&v.grad_p, np * per)) != hipSuccess ||
         (e = o->alloc(&v.ones, np)) != hipSuccess || (e = o->alloc(&v.w, prm->nu)) != hipSuccess ||
         (e = o->alloc(&v.t, 1)) != hipSuccess || (e = o->alloc(&v.status, 1)) != hipSuccess ||
@@ -650,6 +651,39 @@ int cp_optimizer_destroy(cp_opt *opt) {
     return CP_OK;
 }
 
+// The gradient polish of the selected elites (elite0[0..npol)), their
+// re-evaluation and the re-ranking of the elites.  Each step reads the
+// waypoints from one of two buffers and writes the stepped ones to the other;
+// the gather picks the first buffer so that the last step writes v.Wp.
+static int enqueue_polish(cp_opt *opt, hipStream_t st) {
+    cp_plan *p = opt->plan;
+    const OptView &v = opt->view;
+    const PlanView &P = p->view;
+    float *buf[2] = {v.Wp, v.Wp2};
+    int cur = opt->prm.polish_steps & 1;
+    CP_HIP(launch_polish_gather(P, v, buf[cur], st), "polish gather");
+    PolishStep ps{};
+    for (int a = 0; a < CP_MAX_JOINTS; ++a) ps.act[a] = v.act[a];
+    for (int a = 0; a < v.n_act; ++a) ps.act_mask |= 1u << v.act[a];
+    ps.eta = v.eta;
+    ps.clip = v.clip;
+    ps.D = v.D;
+    ps.n_act = v.n_act;
+    for (int s = 0; s < opt->prm.polish_steps; ++s) {
+        // (only the argmin tape of this evaluation is used)
+        CP_HIP(launch_eval_fwd(P, buf[cur], opt->npol, p->d_partial, opt->d_tape_p, nullptr, nullptr, nullptr, st),
+               "polish eval");
+        // the adjoint applies each path's gradient step itself
+        ps.W_out = buf[cur ^ 1];
+        CP_HIP(launch_eval_bwd(P, buf[cur], opt->npol, opt->d_tape_p, v.ones, v.grad_p, st, &ps),
+               "polish adjoint and step");
+        cur ^= 1;
+    }
+    CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, nullptr, v.cost_p, v.md_p, nullptr, st), "polish eval");
+    CP_HIP(launch_rerank(v, st), "rerank");
+    return CP_OK;
+}
+
 int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
     if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
     if (n_iters < 0) return fail(CP_ERR_SIZE, "n_iters must be >= 0");
@@ -668,26 +702,8 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
             CP_HIP(launch_select(v, st), "select");
         }
         if (opt->npol > 0) {
-            CP_HIP(launch_polish_gather(P, v, st), "polish gather");
-            for (int s = 0; s < opt->prm.polish_steps; ++s) {
-                // (only the argmin tape of these evaluations is used)
-                CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, opt->d_tape_p, nullptr, nullptr, nullptr,
-                                       st),
-                       "polish eval");
-                // the adjoint applies each path's gradient step itself
-                PolishStep ps{};
-                ps.W = v.Wp;
-                for (int a = 0; a < CP_MAX_JOINTS; ++a) ps.act[a] = v.act[a];
-                ps.eta = v.eta;
-                ps.clip = v.clip;
-                ps.D = v.D;
-                ps.n_act = v.n_act;
-                CP_HIP(launch_eval_bwd(P, v.Wp, opt->npol, opt->d_tape_p, v.ones, v.grad_p, st, &ps),
-                       "polish adjoint and step");
-            }
-            CP_HIP(launch_eval_fwd(P, v.Wp, opt->npol, p->d_partial, nullptr, v.cost_p, v.min_dist, nullptr, st),
-                   "polish eval");
-            CP_HIP(launch_rerank(v, st), "rerank");
+            const int rc = enqueue_polish(opt, st);
+            if (rc) return rc;
         }
         CP_HIP(launch_update(P, v, st), "update");
         CP_HIP(launch_chol(v, st), "cholesky");
@@ -697,7 +713,6 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
 
 int cp_debug_update(cp_opt *opt, const int32_t *d_elite, cp_stream_t stream) {
     if (!opt || !d_elite) return fail(CP_ERR_INVALID_ARG, "null argument");
-    if (opt->npol > 0) return fail(CP_ERR_INVALID_ARG, "not with polish");
     cp_plan *p = opt->plan;
     DeviceGuard g(p->device);
     const OptView &v = opt->view;
@@ -708,7 +723,24 @@ int cp_debug_update(cp_opt *opt, const int32_t *d_elite, cp_stream_t stream) {
     for (int32_t i : idx)
         if (i < 0 || i >= v.B) return fail(CP_ERR_INVALID_ARG, "elite index out of range");
     CP_HIP(hipMemcpyAsync(v.elite0, d_elite, v.nu * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "elites");
+    if (opt->npol > 0) {
+        const int rc = enqueue_polish(opt, st);
+        if (rc) return rc;
+    }
     CP_HIP(launch_update(p->view, v, st), "update");
+    return CP_OK;
+}
+
+int cp_optimizer_last_polished(cp_opt *opt, float *d_waypoints, float *d_cost, cp_stream_t stream) {
+    if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
+    if (opt->npol == 0) return fail(CP_ERR_STATE, "the optimizer has no polish");
+    DeviceGuard g(opt->plan->device);
+    const OptView &v = opt->view;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t per = (size_t)opt->plan->K * opt->plan->n;
+    if (d_waypoints)
+        CP_HIP(hipMemcpyAsync(d_waypoints, v.Wp, opt->npol * per * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+    if (d_cost) CP_HIP(hipMemcpyAsync(d_cost, v.cost_p, opt->npol * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
     return CP_OK;
 }
 
@@ -967,6 +999,12 @@ int cp_batch_get_state(cp_batch *b, int32_t p, double *mu, double *C, int64_t *i
     if (!b) return fail(CP_ERR_INVALID_ARG, "null batch");
     if (p < 0 || p >= b->n) return fail(CP_ERR_SIZE, "problem index out of range");
     return cp_optimizer_get_state(b->opts[p], mu, C, iter, best_cost, best_waypoints);
+}
+
+int cp_batch_last(cp_batch *b, int32_t p, float *d_waypoints, float *d_cost, int32_t *d_elite, cp_stream_t stream) {
+    if (!b) return fail(CP_ERR_INVALID_ARG, "null batch");
+    if (p < 0 || p >= b->n) return fail(CP_ERR_SIZE, "problem index out of range");
+    return cp_optimizer_last(b->opts[p], d_waypoints, d_cost, d_elite, stream);
 }
 
 int cp_batch_set_tuning(cp_batch *b, const cp_batch_tuning *t) {

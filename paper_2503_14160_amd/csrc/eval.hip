@@ -923,10 +923,11 @@ __global__ __launch_bounds__(NW * 64) void k_eval_bwd(PlanView P, const float *_
         const int i = idx / n, jj = idx % n;
         grad_W[(size_t)b * P.K * n + idx] = gc * (float)acc[(i + lead) * n + jj];
     }
-    if (pol.W && wv == 0) {
-        // the polish step on this path (its waypoints are not read again):
-        // the gradient entries as written above, squared and summed per lane
-        // then across the wave, then the clipped step
+    if (pol.W_out && wv == 0) {
+        // the polish step on this path, written to the step's output buffer
+        // (the input W is only read): the gradient entries as written above,
+        // squared and summed per lane then across the wave, then the clipped
+        // step on the sampled joints; the other entries are copied
         float s = 0.0f;
         for (int e = lane; e < pol.D; e += kWave) {
             const int k = e / pol.n_act, jj = pol.act[e % pol.n_act];
@@ -935,11 +936,16 @@ __global__ __launch_bounds__(NW * 64) void k_eval_bwd(PlanView P, const float *_
         }
         s = wave_sum(s);
         const float scale = pol.eta / fmaxf(1.0f, fsqrt(s) / pol.clip);
-        float *Wb = pol.W + (size_t)b * P.K * n;
-        for (int e = lane; e < pol.D; e += kWave) {
-            const int k = e / pol.n_act, jj = pol.act[e % pol.n_act];
-            const float g = gc * (float)acc[(k + lead) * n + jj];
-            Wb[k * n + jj] = Wb[k * n + jj] - scale * g;
+        float *Wo = pol.W_out + (size_t)b * P.K * n;
+        for (int idx = lane; idx < P.K * n; idx += kWave) {
+            const int k = idx / n, jj = idx - k * n;
+            const float w = Wb[idx];
+            if ((pol.act_mask >> jj) & 1u) {
+                const float g = gc * (float)acc[(k + lead) * n + jj];
+                Wo[idx] = w - scale * g;
+            } else {
+                Wo[idx] = w;
+            }
         }
     }
 }

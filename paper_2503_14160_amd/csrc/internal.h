@@ -359,12 +359,15 @@ __device__ __forceinline__ float hinge_value(const PlanView &P, float d, float &
 }
 
 // The gradient polish's step on an elite path (a clipped gradient step, which
-// the paper does not specify): W <- W - eta g / max(1, |g| / g_max) on the
-// sampled joints, applied by the adjoint to each path right after its
-// gradient is complete; W null: no step.
+// the paper does not specify): W' = W - eta g / max(1, |g| / g_max) on the
+// sampled joints (|g| over those joints only), the other joints copied,
+// applied by the adjoint to each path right after its gradient is complete
+// and written to W_out, a buffer distinct from the adjoint's input; W_out
+// null: no step.
 struct PolishStep {
-    float *W;                      // the adjoint's own input waypoints [B][K][n]
+    float *W_out;                  // [B][K][n] stepped waypoints
     int32_t act[CP_MAX_JOINTS];    // sampled joint ids
+    uint32_t act_mask;             // bit j set: joint j is sampled
     float eta, clip;
     int32_t D, n_act;
 };

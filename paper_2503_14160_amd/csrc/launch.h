@@ -38,7 +38,9 @@ struct OptView {
     int32_t *elite;    // [nu] elite indices in rank order (>= B: polished slot)
     int32_t *elite0;   // [nu] elite indices before polish
     float *Wp;         // [npol][K][n] polished elites
+    float *Wp2;        // [npol][K][n] the other buffer of the polish steps (each step reads one, writes the other)
     float *cost_p;     // [npol]
+    float *md_p;       // [npol] minimum distances of the polished elites
     float *grad_p;     // [npol][K][n]
     float *ones;       // [npol] 1.0
     double *w;         // [nu] log-rank weights
@@ -80,7 +82,8 @@ bool reduce_select_fits(int B);
 hipError_t launch_reduce_select(const double2 *partial, int slots, int ns, float margin, const OptView &O,
                                 hipStream_t st);
 hipError_t launch_select(const OptView &O, hipStream_t st);
-hipError_t launch_polish_gather(const PlanView &P, const OptView &O, hipStream_t st);
+// the elites to polish (elite0[0..npol)) copied from the population into dst
+hipError_t launch_polish_gather(const PlanView &P, const OptView &O, float *dst, hipStream_t st);
 hipError_t launch_rerank(const OptView &O, hipStream_t st);
 hipError_t launch_update(const PlanView &P, const OptView &O, hipStream_t st);
 hipError_t launch_chol(const OptView &O, hipStream_t st);

@@ -453,11 +453,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select_batched(const BatchProbl
 // gradient polish of the elites
 // ---------------------------------------------------------------------------
 
-__global__ void k_polish_gather(PlanView P, OptView O) {
+__global__ void k_polish_gather(PlanView P, OptView O, float *__restrict__ dst) {
     const int per = P.K * P.n_joints;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < O.npol * per; idx += gridDim.x * blockDim.x) {
         const int i = idx / per, r = idx % per;
-        O.Wp[idx] = O.W[(size_t)O.elite0[i] * per + r];
+        dst[idx] = O.W[(size_t)O.elite0[i] * per + r];
     }
 }
 
@@ -855,9 +855,9 @@ hipError_t launch_select(const OptView &O, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_polish_gather(const PlanView &P, const OptView &O, hipStream_t st) {
+hipError_t launch_polish_gather(const PlanView &P, const OptView &O, float *dst, hipStream_t st) {
     const int n = O.npol * P.K * P.n_joints;
-    hipLaunchKernelGGL(k_polish_gather, dim3((n + 255) / 256), dim3(256), 0, st, P, O);
+    hipLaunchKernelGGL(k_polish_gather, dim3((n + 255) / 256), dim3(256), 0, st, P, O, dst);
     return hipGetLastError();
 }
 

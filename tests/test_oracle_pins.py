@@ -5,6 +5,7 @@ brute-force computation, a published value or a textbook formula written
 independently here, chosen so that a plausible slip in the oracle (a dropped
 term, a wrong sign or index, a transposed operand) fails at least one test.
 """
+import dataclasses
 import math
 import os
 from fractions import Fraction
@@ -652,6 +653,138 @@ def test_optimizer_free_space_moves_to_straight_line(orc):
     optimum = float(np.sum((qg.astype(np.float64) - qs) ** 2)) / prob.cost.n_s
     assert optimum <= best[-1] < 1.05 * optimum
     assert np.abs(opt.mu - target).max() < 0.5 * err0
+
+
+# ----------------------------------------------------------------------------
+# gradient polish of the elites (a workload setting; the paper's Algorithm 1
+# is derivative free)
+# ----------------------------------------------------------------------------
+
+def _polish_problem(scene, K=5, M=4, steps=1, eta=1e-3, clip=10.0, hinge=synth.HINGE_HARD, margin=0.0,
+                    interp=synth.INTERP_LINEAR, nu=4):
+    rb = _robot()
+    qs = np.array([0.2, 0.5, -0.3, 1.0, 0.0, 0.0], np.float32)
+    qg = np.array([1.4, 0.9, -0.6, 2.0, 0.0, 0.0], np.float32)
+    opt = synth.OptParams(B=8, nu=nu, sigma0=0.2, eps=1e-6, seed=5, T=1, polish_elites=nu, polish_steps=steps,
+                          polish_eta=eta, polish_clip=clip)
+    return synth.Problem("polish", rb, scene, qs, qg, _cost(K, M, interp=interp, hinge=hinge, margin=margin), opt)
+
+
+def _linear_jp_grad(qs, qg, xi, K, M, act):
+    """Free space, linear interpolation, squared J_p: the polygon is
+    (q_s, W_0..W_{K-1}, q_g) and every checkpoint step of segment j is
+    (P_{j+1} - P_j) / M, so J_p = sum_j |P_{j+1} - P_j|^2 / M and
+    dJ_p / dW_i = (2 / M) (2 P_{i+1} - P_i - P_{i+2}) (written out here, not
+    taken from the oracle)."""
+    na = int(act.sum())
+    P = np.concatenate([np.asarray(qs, np.float64)[act][None], xi.reshape(K, na),
+                        np.asarray(qg, np.float64)[act][None]], 0)
+    return ((2.0 / M) * (2 * P[1:-1] - P[:-2] - P[2:])).reshape(-1)
+
+
+def test_polish_free_space_steps_follow_the_closed_form_gradient(orc):
+    """In free space within the joint limits the cost is J_p alone; each
+    unclipped polish step is x - eta g with g the closed-form gradient above,
+    and every step lowers J.  Several steps are the closed-form iteration."""
+    prob = _polish_problem(_empty_scene(), steps=5, eta=1e-2)
+    opt = orc.Optimizer(prob)
+    act = prob.robot.active.astype(bool)
+    rng = np.random.default_rng(41)
+    x0 = np.tile(opt.mu, (4, 1)) + rng.normal(size=(4, opt.D)) * 0.05
+    ref = x0.copy()
+    for _ in range(5):
+        g = np.stack([_linear_jp_grad(prob.q_start, prob.q_goal, r, prob.cost.K, prob.cost.M, act) for r in ref])
+        assert np.all(np.linalg.norm(g, axis=1) < prob.opt.polish_clip)  # unclipped regime
+        ref = ref - prob.opt.polish_eta * g
+    trace = []
+    got = opt.polish(x0, trace=trace)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+    assert len(trace) == 5
+    m = opt.model
+    costs = [orc.eval_paths(m, prob.q_start, prob.q_goal, orc.expand(prob.robot, x, prob.cost.K))["cost"]
+             for x in trace + [got]]
+    for a, b in zip(costs, costs[1:]):
+        assert np.all(b < a)
+
+
+def test_polish_clipped_step_has_length_eta_gmax(orc):
+    """Far from the straight line the gradient norm exceeds g_max: the step is
+    eta g_max g / |g| exactly (its length eta g_max, its direction -g)."""
+    prob = _polish_problem(_empty_scene(), M=1, steps=1, eta=1e-3, clip=0.5)
+    opt = orc.Optimizer(prob)
+    rb = prob.robot
+    act = rb.active.astype(bool)
+    rng = np.random.default_rng(42)
+    x0 = np.tile(opt.mu, (3, 1)) + rng.normal(size=(3, opt.D)) * 0.1
+    lo = np.tile(rb.q_min[act], prob.cost.K)
+    hi = np.tile(rb.q_max[act], prob.cost.K)
+    assert np.all((x0 > lo) & (x0 < hi))  # no limit cost: J = J_p
+    g = np.stack([_linear_jp_grad(prob.q_start, prob.q_goal, r, prob.cost.K, prob.cost.M, act) for r in x0])
+    nrm = np.linalg.norm(g, axis=1)
+    assert np.all(nrm > 0.5)
+    got = opt.polish(x0)
+    step = x0 - got
+    np.testing.assert_allclose(np.linalg.norm(step, axis=1), 1e-3 * 0.5, rtol=1e-12)
+    np.testing.assert_allclose(step, 1e-3 * 0.5 * g / nrm[:, None], rtol=0, atol=1e-15)
+
+
+def test_polish_uses_the_sampled_joints_only(orc):
+    """With an obstacle touching the hanger spheres the cost also depends on
+    the passive swing joints, but the polish steps and clips on the sampled
+    joints alone: step = eta g_a / max(1, |g_a| / g_max) with g_a the sampled
+    joints' part of the (FD-pinned) gradient; the passive joints stay at their
+    hold value."""
+    rb = _robot()
+    prob0 = _polish_problem(_empty_scene(), interp=synth.INTERP_BSPLINE, hinge=synth.HINGE_SMOOTH, margin=0.1)
+    opt0 = orc.Optimizer(prob0)
+    m0 = opt0.model
+    # an obstacle at the hanger of the middle of the path
+    W = orc.expand(rb, opt0.mu[None], prob0.cost.K)
+    mid = orc.path_points(m0, prob0.q_start, prob0.q_goal, W[0])[prob0.cost.n_s // 2]
+    _, cen, _ = orc.fk(m0, mid)
+    s_hang = int(np.where(rb.sphere_frame == 6)[0][-1])
+    c = cen[s_hang]
+    box = np.array([[c[0] + 0.3, c[1], c[2], 0.3, 0.3, 0.3]], np.float32)
+    scene = synth.Scene(cyl=np.zeros((0, 5), np.float32), box=box, has_ground=0)
+    for clip in (1e6, 1.0):
+        prob = _polish_problem(scene, interp=synth.INTERP_BSPLINE, hinge=synth.HINGE_SMOOTH, margin=0.1, clip=clip)
+        opt = orc.Optimizer(prob)
+        x0 = opt.mu[None].copy()
+        _, gfull = orc.grad_paths(opt.model, prob.q_start, prob.q_goal, orc.expand(rb, x0, prob.cost.K))
+        assert np.abs(gfull[0][:, 4:]).max() > 1e-3  # the passive joints do matter
+        ga = gfull[:, :, rb.active.astype(bool)].reshape(1, -1)
+        scale = prob.opt.polish_eta / max(1.0, np.linalg.norm(ga) / clip)
+        got = opt.polish(x0)
+        np.testing.assert_allclose(got, x0 - scale * ga, rtol=0, atol=1e-15)
+        assert got.shape == x0.shape
+        Wp = orc.expand(rb, got, prob.cost.K)
+        np.testing.assert_array_equal(Wp[:, :, ~rb.active.astype(bool)], 0.0)
+
+
+def test_optimizer_step_with_idle_polish_equals_plain_step(orc):
+    """A polish of zero step length re-evaluates the elites unchanged, and the
+    stable re-ranking keeps their order: the step equals the plain one.  With
+    a real polish, best-so-far takes the best polished elite."""
+    rng = np.random.default_rng(43)
+    rb = _robot()
+    qs, qg = synth.make_endpoints(rng, rb)
+    sc = synth.make_scene(rng, rb, qs, qg, n_cyl=12, n_box=1, half_extent=6.0)
+    base = synth.Problem("p", rb, sc, qs, qg, _cost(4, 4, hinge=synth.HINGE_SMOOTH, margin=0.1),
+                         synth.OptParams(B=32, nu=6, sigma0=0.3, eps=1e-6, seed=11, T=1))
+    idle = dataclasses.replace(base, opt=dataclasses.replace(base.opt, polish_elites=6, polish_steps=2,
+                                                             polish_eta=0.0))
+    a = orc.Optimizer(base).step()
+    b = orc.Optimizer(idle).step()
+    np.testing.assert_array_equal(a["mu"], b["mu"])
+    np.testing.assert_array_equal(a["C"], b["C"])
+    real = dataclasses.replace(base, opt=dataclasses.replace(base.opt, polish_elites=6, polish_steps=3,
+                                                             polish_eta=1e-3))
+    o = orc.Optimizer(real)
+    r = o.step()
+    xe = r["xi"][r["elite"]][:6]
+    xp = o.polish(xe)
+    cp_ = orc.eval_paths(o.model, qs, qg, orc.expand(rb, xp, 4))["cost"]
+    assert o.best_cost <= min(cp_.min(), r["cost"].min())
 
 
 # ----------------------------------------------------------------------------
