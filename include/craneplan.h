@@ -209,6 +209,21 @@ int cp_eval_paths(cp_plan *plan, const float *d_waypoints, int32_t B, float *d_c
                   uint8_t *d_flags, uint32_t *d_tape, cp_stream_t stream);
 
 /*
+ * cp_eval_paths for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same evaluation, bitwise the same outputs, with the per-wave partial
+ * sums in a static 24 MiB device array instead of the plan's workspace.  The
+ * call allocates nothing.  The array is one per GPU, shared by every plan on
+ * it and holding the last call's contents: calls that overlap on one GPU
+ * (several streams or threads) race and must be ordered by the caller.
+ * Limit: ceil(B n_s / 64) (64 / n_s + 2) * 16 bytes <= 24 MiB (for n_s >= 64
+ * about B n_s <= 25 M configurations; the 65536 x 608 population fits);
+ * beyond it CP_ERR_SIZE, with nothing enqueued.
+ */
+int cp_eval_paths_noalloc(cp_plan *plan, const float *d_waypoints, int32_t B, float *d_cost, float *d_min_dist,
+                          uint8_t *d_flags, uint32_t *d_tape, cp_stream_t stream);
+
+/*
  * Adjoint of cp_eval_paths: d_grad_waypoints[b] = d_grad_cost[b] * dJ_b/dW_b
  * [B][K][n] (every joint, sampled or not).  d_tape is the tape written by
  * cp_eval_paths for the same waypoints, or NULL to recompute the argmin

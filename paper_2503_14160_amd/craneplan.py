@@ -35,7 +35,7 @@ EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_en
            "cp_sdf_build", "cp_debug_fk", "cp_debug_eval_configs", "cp_debug_select", "cp_batch_create",
            "cp_batch_destroy", "cp_batch_run", "cp_batch_eval", "cp_batch_get_state", "cp_batch_set_tuning",
            "cp_batch_get_tuning", "cp_batch_tune", "cp_optimizer_last_elites", "cp_tune",
-           "cp_debug_update", "cp_optimizer_last_polished", "cp_batch_last"]
+           "cp_debug_update", "cp_optimizer_last_polished", "cp_batch_last", "cp_eval_paths_noalloc"]
 
 
 class CranePlanError(RuntimeError):
@@ -109,6 +109,7 @@ def lib():
         L.cp_debug_update.argtypes = [_vp, _vp, _vp]
         L.cp_optimizer_last_polished.argtypes = [_vp, _vp, _vp, _vp]
         L.cp_batch_last.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
+        L.cp_eval_paths_noalloc.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, _vp, _vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -249,6 +250,12 @@ class Plan:
         """Enqueue an evaluation into caller-provided buffers (no allocation)."""
         _check(lib().cp_eval_paths(self._h, _ptr(W), W.shape[0], _ptr(cost), _ptr(md), _ptr(fl), _ptr(tape),
                                    _stream()))
+
+    def eval_noalloc_into(self, W, cost, md, fl=None, tape=None):
+        """cp_eval_paths_noalloc: the evaluation into caller-provided buffers,
+        with the library allocating nothing (static per-GPU scratch)."""
+        _check(lib().cp_eval_paths_noalloc(self._h, _ptr(W), W.shape[0], _ptr(cost), _ptr(md), _ptr(fl), _ptr(tape),
+                                           _stream()))
 
     def backward(self, W: torch.Tensor, grad_cost: torch.Tensor, tape: Optional[torch.Tensor] = None):
         """d(sum_b grad_cost[b] J_b) / dW, [B,K,n]."""

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -77,6 +78,34 @@ constexpr int kAutoCullObstacles = 48;
 int resolve_pairs(int mode, int n_obstacles) {
     if (mode != CP_PAIRS_AUTO) return mode;
     return n_obstacles >= kAutoCullObstacles ? CP_PAIRS_WAVE : CP_PAIRS_LANE;
+}
+
+// Scratch of the allocation-free evaluation (cp_eval_paths_noalloc): the
+// per-wave partial sums of one evaluation, in a static array that every GPU
+// the library runs on holds until the process ends.  In host code `scratch`
+// is only a stand-in for the symbol: its device address, per device, comes
+// from hipGetSymbolAddress at plan creation and is the only way host code
+// refers to this memory.
+constexpr size_t kNoAllocScratchBytes = (size_t)24 << 20;
+static __device__ __align__(256) double2 scratch[kNoAllocScratchBytes / sizeof(double2)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2 *g_scratch_ptr[kMaxDevices] = {};
+
+// the address of `scratch` on `dev`, which must be the current device
+hipError_t scratch_on(int dev, double2 **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double2 *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -210,6 +239,11 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     CP_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
     if (device < 0 || device >= ndev) return fail(CP_ERR_INVALID_ARG, "bad device");
     DeviceGuard guard(device);
+    {
+        // the allocation-free evaluation's scratch address on this device
+        double2 *sp = nullptr;
+        CP_HIP(scratch_on(device, &sp), "scratch address");
+    }
     cp_plan *p = new (std::nothrow) cp_plan();
     if (!p) return fail(CP_ERR_NOMEM, "host allocation");
     p->device = device;
@@ -529,6 +563,21 @@ int cp_eval_paths(cp_plan *plan, const float *d_waypoints, int32_t B, float *d_c
     DeviceGuard g(plan->device);
     CP_HIP(launch_eval_fwd(plan->view, d_waypoints, B, plan->d_partial, d_tape, d_cost, d_min_dist, d_flags,
                            (hipStream_t)stream),
+           "eval launch");
+    return CP_OK;
+}
+
+int cp_eval_paths_noalloc(cp_plan *plan, const float *d_waypoints, int32_t B, float *d_cost, float *d_min_dist,
+                          uint8_t *d_flags, uint32_t *d_tape, cp_stream_t stream) {
+    if (!plan || !d_waypoints || !d_cost || !d_min_dist) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (B < 1 || B > plan->max_B) return fail(CP_ERR_SIZE, "B out of range (1..max_B)");
+    if (eval_partial_count(B, plan->ns) * sizeof(double2) > kNoAllocScratchBytes)
+        return fail(CP_ERR_SIZE, "B * n_s exceeds the static scratch of cp_eval_paths_noalloc (24 MiB of per-wave "
+                                 "partial sums); use cp_eval_paths");
+    DeviceGuard g(plan->device);
+    double2 *sp = nullptr;
+    CP_HIP(scratch_on(plan->device, &sp), "scratch address");
+    CP_HIP(launch_eval_fwd(plan->view, d_waypoints, B, sp, d_tape, d_cost, d_min_dist, d_flags, (hipStream_t)stream),
            "eval launch");
     return CP_OK;
 }
