@@ -34,21 +34,43 @@ sys.path.insert(0, ROOT)
 F_CYL, F_BOX, F_SPHERE, F_CONFIG = 15, 20, 7, 1500
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_HBM = 8.0e12     # MI355X HBM3E bytes/s
-# HBM bytes per k_eval_fwd launch on c1_full from rocprofv3 FETCH_SIZE / WRITE_SIZE, each
-# scaled by the same counter on a plain 1 GiB copy (profiles/k_eval_fwd_c1_full_hbm_bytes.md);
-# None once the kernel has changed since the counters were taken
-TRAFFIC_BYTES = 19.2e6
-# VALU instructions per wave of the culling k_eval_fwd on the bench's timed
-# launches (c1_full, converged population), from rocprofv3 SQ_INSTS_VALU /
-# SQ_WAVES (profiles/k_eval_fwd_c1_full_sq_counters.md); None once the kernel
-# has changed since.  The VALU issue ceiling: one wave64 FP32 instruction per
-# 4 cycles per SIMD (16 lanes; packed FP32 is not used), 1024 SIMDs, 2.4 GHz:
-# the rate of VOP3 forms; some VOP2 forms issue faster, so a kernel rich in
-# them can reach or pass it.
-VALU_PER_WAVE = 9216
-PEAK_VALU_ISSUE = 1024 * 2.4e9 / 4  # wave instructions per second
 # algorithmic bytes of one trilinear signed-distance query: 8 FP32 corners
 SDF_QUERY_BYTES = 32
+# counter figures of the timed evaluation launches (rocprofv3 summaries); each
+# file names the command it was taken with and a hash of the kernel sources,
+# and its figures are used only while both still match
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_2503_14160_amd/csrc/eval.hip", "paper_2503_14160_amd/csrc/internal.h",
+                  "paper_2503_14160_amd/build.py"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profile_figures(name, workload, steps, warmup):
+    """The 'figure: key = value' lines of profiles/<name> if the file was taken
+    on the current kernel sources with the same workload, steps and warmup;
+    else None (with the reason)."""
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
+        return None, f"{name} missing"
+    fig = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("figure:") and "=" in line:
+            k, v = line[len("figure:"):].split("=", 1)
+            fig[k.strip()] = v.strip()
+    want = {"source_sha16": kernel_source_hash(), "workload": workload, "steps": str(steps), "warmup": str(warmup)}
+    for k, v in want.items():
+        if fig.get(k) != v:
+            return None, f"{name}: {k} is {fig.get(k)}, this run has {v}"
+    return fig, name
 
 
 def flops_per_config(n_spheres, n_cyl, n_box):
@@ -94,67 +116,79 @@ def base_line(args, metric, value, unit, ms_step, config, **extra):
 # ----------------------------------------------------------------------------
 
 def bench_iterations(args, torch, cp, prob, with_roofline):
+    """Optimizer iterations from creation: the timed region runs the
+    workload's whole loop (K iterations from t = 0, after W warm-up
+    iterations and a reset to the initial state), and every evaluation
+    kernel inside it is bracketed by HIP events on the step's stream."""
     B, ns = prob.opt.B, prob.cost.n_s
     plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B)
     plan.set_endpoints(prob.q_start, prob.q_goal)
     opt = cp.Optimizer(plan, prob.opt)
+    st0 = opt.get_state()
     torch.cuda.synchronize()
     print(f"[bench] {prob.name} warmup {args.warmup}", file=sys.stderr, flush=True)
     opt.step(args.warmup)
+    opt.set_state(st0["mu"], st0["C"], 0)
+    opt.time_eval(args.steps)
     torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} iterations", file=sys.stderr, flush=True)
+    print(f"[bench] timing {args.steps} iterations from t = 0", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ms = _timed(torch, lambda: opt.step(args.steps), 1)
     wall = time.perf_counter() - t0
+    eval_total_ms, launches = opt.eval_time()
+    opt.time_eval(0)
+    eval_ms = eval_total_ms / max(launches, 1)
     ms_step = ms / args.steps
     st = opt.get_state()
     configs = B * ns
     config = {"workload": prob.name, "paths": B, "waypoints": prob.cost.K, "points_per_span": prob.cost.M,
               "checkpoints": ns, "spheres": prob.robot.n_spheres, "cylinders": prob.scene.n_cyl,
-              "boxes": prob.scene.n_box, "elites": prob.opt.nu, "iterations_timed": args.steps}
+              "boxes": prob.scene.n_box, "elites": prob.opt.nu, "iterations_timed": args.steps,
+              "from_iteration": 0}
     out = base_line(args, "configs checked/s (FK+collision)", configs * args.steps / (ms * 1e-3), "configs/s",
-                    ms_step, config, planner_iters_per_s=1e3 / ms_step, best_cost=st["best_cost"], wall_s=wall)
+                    ms_step, config, planner_iters_per_s=1e3 / ms_step, best_cost=st["best_cost"], wall_s=wall,
+                    eval_ms=eval_ms, eval_launches_timed=launches, eval_configs_per_s=configs / (eval_ms * 1e-3))
     if not with_roofline:
         return out, plan, opt
 
-    # evaluation kernel alone, on the same stream, on the last population
+    # executed FP32 work of the timed launches, from the counters
+    fig, why = profile_figures("k_eval_fwd_c1_full_counters.md", prob.name, args.steps, args.warmup)
+    fpc = flops_per_config(prob.robot.n_spheres, prob.scene.n_cyl, prob.scene.n_box)
+    alg_flops = fpc * configs
+    # the same evaluation with every pair in full (identical results) on the
+    # last population: the all-pairs definition's own roofline
     W, cost, _ = opt.last()
     md = torch.empty_like(cost)
-    plan.eval_into(W, cost, md)
-    torch.cuda.synchronize()
-    print(f"[bench] eval kernel x{args.eval_reps}", file=sys.stderr, flush=True)
-    eval_ms = _timed(torch, lambda: plan.eval_into(W, cost, md), args.eval_reps)
-    fpc = flops_per_config(prob.robot.n_spheres, prob.scene.n_cyl, prob.scene.n_box)
-    flops = fpc * B * ns
-    achieved = flops / (eval_ms * 1e-3)
-    # the same evaluation with every pair in full (no square-root skipping):
-    # identical results, the brute-force reference for the roofline
     plain = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, pair_filter=cp.PAIRS_ALL)
     plain.set_endpoints(prob.q_start, prob.q_goal)
     c_plain = torch.empty_like(cost)
+    c_cull = torch.empty_like(cost)
     plain.eval_into(W, c_plain, md)
+    plan.eval_into(W, c_cull, md)
     torch.cuda.synchronize()
+    print("[bench] all-pairs evaluation", file=sys.stderr, flush=True)
     plain_ms = _timed(torch, lambda: plain.eval_into(W, c_plain, md), max(1, args.eval_reps // 3))
-    out.update({
-        "eval_ms": eval_ms,
-        "executed_valu": None if VALU_PER_WAVE is None else {
-            "valu_per_wave": VALU_PER_WAVE, "waves": (configs + 63) // 64,
-            "achieved": VALU_PER_WAVE * ((configs + 63) // 64) / (eval_ms * 1e-3) / 1e9,
-            "peak": PEAK_VALU_ISSUE / 1e9, "unit": "G wave-instructions/s",
-            "frac": VALU_PER_WAVE * ((configs + 63) // 64) / (eval_ms * 1e-3) / PEAK_VALU_ISSUE,
-            "note": "instructions the culling kernel executes (counters), over its live time: the kernel is "
-                    "VALU-issue bound, so time falls only with the instruction count"},
-        "eval_configs_per_s": configs / (eval_ms * 1e-3),
-        "roofline": {"bound": "alu", "kernel": "k_eval_fwd", "achieved": achieved / 1e12,
-                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                     "traffic": TRAFFIC_BYTES, "flops_per_config": fpc,
-                     "note": "algorithmic flops of the all-pairs definition; the kernel culls sphere-obstacle "
-                             "pairs that cannot lower any minimum (bitwise-identical results), so this rate exceeds "
-                             "the hardware peak; all_pairs_kernel is the same evaluation with every pair in full",
-                     "all_pairs_kernel": {"ms": plain_ms, "achieved": flops / (plain_ms * 1e-3) / 1e12,
-                                          "frac": flops / (plain_ms * 1e-3) / PEAK_FP32,
-                                          "identical_costs": bool(torch.equal(c_plain, cost))}},
-    })
+    roof = {"bound": "alu", "kernel": "k_eval_fwd<false, true> (wave culling)", "unit": "TFLOP/s",
+            "peak": PEAK_FP32 / 1e12, "launch_ms": eval_ms, "launches": launches,
+            "achieved": None, "frac": None, "traffic": None, "counters": why,
+            "effective": {"achieved": alg_flops / (eval_ms * 1e-3) / 1e12, "unit": "TFLOP/s",
+                          "flops_per_config": fpc,
+                          "note": "algorithmic flops of the all-pairs definition over the culling kernel's time: the "
+                                  "kernel skips pairs that cannot lower any minimum (bitwise-identical results), so "
+                                  "this rate is not a fraction of the hardware peak"},
+            "all_pairs_kernel": {"ms": plain_ms, "achieved": alg_flops / (plain_ms * 1e-3) / 1e12,
+                                 "frac": alg_flops / (plain_ms * 1e-3) / PEAK_FP32,
+                                 "identical_costs": bool(torch.equal(c_plain, c_cull))}}
+    if fig is not None:
+        flops = float(fig["fp32_flops_per_launch"])
+        roof.update({"achieved": flops / (eval_ms * 1e-3) / 1e12, "frac": flops / (eval_ms * 1e-3) / PEAK_FP32,
+                     "flops_per_launch": flops, "profile_kernel_trace_ms": float(fig["kernel_trace_ms"]),
+                     "flops_definition": "executed FP32 VALU flops per launch: 64 lanes x rocprofv3 "
+                                         "SQ_INSTS_VALU_FLOPS_FP32 (ADD + MUL + 2 FMA + TRANS per wave "
+                                         "instruction), averaged over the timed launches (profiles/" + why + ")"})
+        if fig.get("hbm_bytes_per_launch") not in (None, "null"):
+            roof["traffic"] = float(fig["hbm_bytes_per_launch"])
+    out["roofline"] = roof
     return out, plan, opt
 
 
@@ -278,6 +312,9 @@ def bench_batch(args, torch, cp, probs):
 # ----------------------------------------------------------------------------
 
 def bench_sdf(args, torch, cp, prob):
+    """c4_sdf: the grid built on the device from the lidar cloud, then
+    optimizer iterations from t = 0 in which every iteration also takes the
+    population's gradient (forward with the argmin tape, then the adjoint)."""
     spec = prob.sdf
     pts = torch.from_numpy(prob.lidar).cuda()
     cp.sdf_build(pts, spec)
@@ -298,14 +335,32 @@ def bench_sdf(args, torch, cp, prob):
     plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=B, sdf=sdf, sdf_spec=spec)
     plan.set_endpoints(prob.q_start, prob.q_goal)
     opt = cp.Optimizer(plan, prob.opt)
-    opt.step(args.warmup)
+    opt.record_tape(True)
+    st0 = opt.get_state()
+    g = torch.empty((B, prob.cost.K, prob.robot.n_joints), dtype=torch.float32, device="cuda")
+
+    def step():
+        opt.step(1)
+        opt.population_grad(g)
+    for _ in range(args.warmup):
+        step()
+    opt.set_state(st0["mu"], st0["C"], 0)
+    opt.time_eval(args.steps)
     torch.cuda.synchronize()
-    ms = _timed(torch, lambda: opt.step(args.steps), 1)
+    print(f"[bench] c4_sdf {args.steps} iterations with the population gradient", file=sys.stderr, flush=True)
+
+    def loop():
+        for _ in range(args.steps):
+            step()
+    ms = _timed(torch, loop, 1)
+    eval_total_ms, launches = opt.eval_time()
+    opt.time_eval(0)
+    eval_ms = eval_total_ms / max(launches, 1)
     ms_step = ms / args.steps
+    # forward alone and forward + backward on the last population
     W, cost, _ = opt.last()
     md = torch.empty_like(cost)
     tape = torch.empty((B, plan.n_s), dtype=torch.int32, device="cuda")
-    g = torch.empty_like(W)
     ones = torch.ones(B, device="cuda")
     plan.eval_into(W, cost, md, tape=tape)
     plan.backward_into(W, ones, g, tape)
@@ -320,27 +375,47 @@ def bench_sdf(args, torch, cp, prob):
     queries = B * ns * prob.robot.n_spheres
     config = {"workload": "c4_sdf", "points": int(prob.lidar.shape[0]), "grid": list(spec.dims),
               "voxel": spec.voxel, "paths": B, "waypoints": prob.cost.K, "checkpoints": ns,
-              "spheres": prob.robot.n_spheres}
+              "spheres": prob.robot.n_spheres, "iterations_timed": args.steps, "from_iteration": 0,
+              "step": "sample, evaluate (with argmin tape), select, update, factor, population gradient"}
+    roof = {"kernel": "k_eval_fwd<true, false> (grid lookups, argmin tape)", "launch_ms": eval_ms,
+            "launches": launches, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None,
+            "effective": {"achieved": queries * SDF_QUERY_BYTES / (eval_ms * 1e-3) / 1e9, "unit": "GB/s",
+                          "note": "algorithmic bytes, 8 FP32 corners for every sphere's query, over the launch: "
+                                  "the kernel skips the lookups that the grid's 2x2x2-block lower bounds show "
+                                  "cannot lower the minimum (bitwise-identical results) and the 32 MiB grid is "
+                                  "cache resident, so this is not a fraction of HBM bandwidth"}}
+    fig, why = profile_figures("k_eval_fwd_c4_sdf_counters.md", "c4_sdf", args.steps, args.warmup)
+    roof["counters"] = why
+    if fig is not None:
+        flops = float(fig["fp32_flops_per_launch"])
+        hbm = float(fig["hbm_bytes_per_launch"])
+        f_alu = flops / (eval_ms * 1e-3) / PEAK_FP32
+        f_hbm = hbm / (eval_ms * 1e-3) / PEAK_HBM
+        roof["traffic"] = hbm
+        roof["fp32"] = {"achieved": flops / (eval_ms * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                        "frac": f_alu}
+        roof["hbm"] = {"achieved": hbm / (eval_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                       "frac": f_hbm}
+        if f_alu >= f_hbm:
+            roof.update(bound="alu", achieved=roof["fp32"]["achieved"], peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                        frac=f_alu)
+        else:
+            roof.update(bound="hbm", achieved=roof["hbm"]["achieved"], peak=PEAK_HBM / 1e9, unit="GB/s",
+                        frac=f_hbm)
     return base_line(args, "configs checked/s (FK+collision)", B * ns * args.steps / (ms * 1e-3), "configs/s",
                      ms_step, config, planner_iters_per_s=1e3 / ms_step, sdf_build_ms=build_ms,
                      sdf_build_roofline={"bound": "hbm", "unit": "GB/s", "bytes": build_bytes,
                                          "achieved": build_bytes / (build_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
                                          "frac": build_bytes / (build_ms * 1e-3) / PEAK_HBM}, fwd_ms=fwd_ms,
-                     fwd_bwd_ms=fb_ms, fwd_bwd_over_fwd=fb_ms / fwd_ms,
-                     roofline={"bound": "hbm", "kernel": "k_eval_fwd", "unit": "GB/s",
-                               "achieved": queries * SDF_QUERY_BYTES / (fwd_ms * 1e-3) / 1e9,
-                               "peak": PEAK_HBM / 1e9,
-                               "frac": queries * SDF_QUERY_BYTES / (fwd_ms * 1e-3) / PEAK_HBM, "traffic": None,
-                               "note": "algorithmic bytes: 8 FP32 corners for every sphere's query; the kernel "
-                                       "skips the queries that the grid's 2x2x2-block lower bounds show cannot lower "
-                                       "the minimum (bitwise-identical results) and the 32 MiB grid is cache "
-                                       "resident, so this rate exceeds HBM bandwidth"})
+                     fwd_bwd_ms=fb_ms, fwd_bwd_over_fwd=fb_ms / fwd_ms, eval_ms=eval_ms, roofline=roof)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed iterations (default: the workload's iteration count, 50 for c1_full; 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c1_full", choices=["c1_full", "c0_plain", "c2_diff", "c3_batch", "c4_sdf"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -357,6 +432,8 @@ def main():
               f"on a single device", file=sys.stderr)
         sys.exit(2)
 
+    if args.steps is None:
+        args.steps = 50 if args.workload in ("c1_full", "c4_sdf") else 20
     import torch
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4

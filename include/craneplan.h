@@ -244,6 +244,30 @@ int cp_optimizer_destroy(cp_opt *opt); /* SYNC; NULL is a no-op */
  * covariance update) without host synchronisation. */
 int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream);
 
+/* Record the argmin tape of every population evaluation of the following
+ * steps (SYNC; enable != 0 allocates B n_s 4-byte entries, 0 frees them), so
+ * that the population's gradient can follow each step cheaply. */
+int cp_optimizer_record_tape(cp_opt *opt, int32_t enable);
+/* Gradient of the last population's summed cost, d(sum_b J_b)/dW_b, into
+ * d_grad_waypoints [B][K][n] (the adjoint of the last evaluation through its
+ * tape; the samples after the step are unchanged, so this is the gradient at
+ * the evaluated waypoints).  Enqueued on stream; CP_ERR_STATE without a
+ * recorded tape.  (The paper's Algorithm 1 is derivative free; this serves
+ * gradient-based refinement of the population.) */
+int cp_optimizer_population_grad(cp_opt *opt, float *d_grad_waypoints, cp_stream_t stream);
+
+/* Timing of the evaluation launches inside cp_optimizer_step (SYNC): with
+ * max_launches > 0, each of the next max_launches evaluations (Algorithm 1
+ * step 2, the population's evaluation kernel alone: not the grid's bound
+ * refresh before it nor the per-path sums after it) is bracketed by a pair of
+ * HIP events on the step's stream; 0 switches timing off.  The call creates
+ * the events (and destroys earlier ones). */
+int cp_optimizer_time_eval(cp_opt *opt, int32_t max_launches);
+/* Sum of the timed evaluations' durations in milliseconds and their number
+ * since the last call (SYNC: waits for the last timed launch); the event
+ * pairs are then reused. */
+int cp_optimizer_eval_time(cp_opt *opt, double *total_ms, int32_t *launches);
+
 /* State (SYNC): mu [D] and C [D][D] (double, D = K * sampled joints), the
  * iteration counter, the best cost seen and its waypoints [K][n].  Any
  * pointer may be NULL.  Returns CP_ERR_NOT_PD if a covariance could not be

@@ -35,7 +35,9 @@ EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_en
            "cp_sdf_build", "cp_debug_fk", "cp_debug_eval_configs", "cp_debug_select", "cp_batch_create",
            "cp_batch_destroy", "cp_batch_run", "cp_batch_eval", "cp_batch_get_state", "cp_batch_set_tuning",
            "cp_batch_get_tuning", "cp_batch_tune", "cp_optimizer_last_elites", "cp_tune",
-           "cp_debug_update", "cp_optimizer_last_polished", "cp_batch_last", "cp_eval_paths_noalloc"]
+           "cp_debug_update", "cp_optimizer_last_polished", "cp_batch_last", "cp_eval_paths_noalloc",
+           "cp_optimizer_time_eval", "cp_optimizer_eval_time", "cp_optimizer_record_tape",
+           "cp_optimizer_population_grad"]
 
 
 class CranePlanError(RuntimeError):
@@ -110,6 +112,10 @@ def lib():
         L.cp_optimizer_last_polished.argtypes = [_vp, _vp, _vp, _vp]
         L.cp_batch_last.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
         L.cp_eval_paths_noalloc.argtypes = [_vp, _vp, i32, _vp, _vp, _vp, _vp, _vp]
+        L.cp_optimizer_time_eval.argtypes = [_vp, i32]
+        L.cp_optimizer_eval_time.argtypes = [_vp, _vp, _vp]
+        L.cp_optimizer_record_tape.argtypes = [_vp, i32]
+        L.cp_optimizer_population_grad.argtypes = [_vp, _vp, _vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -356,6 +362,32 @@ class Optimizer:
         elite = torch.empty(self.nu, dtype=torch.int32, device=dev)
         _check(lib().cp_optimizer_last(self._h, _ptr(W), _ptr(cost), _ptr(elite), _stream()))
         return W, cost, elite
+
+    def record_tape(self, enable: bool = True):
+        """Record the argmin tape of every population evaluation (enables
+        population_grad)."""
+        _check(lib().cp_optimizer_record_tape(self._h, int(bool(enable))))
+
+    def population_grad(self, out: Optional[torch.Tensor] = None):
+        """d(sum_b J_b)/dW of the last population [B,K,n] (needs record_tape)."""
+        if out is None:
+            out = torch.empty((self.B, self.plan.K, self.plan.n_joints), dtype=torch.float32,
+                              device=self.plan.device)
+        _check(lib().cp_optimizer_population_grad(self._h, _ptr(out), _stream()))
+        return out
+
+    def time_eval(self, max_launches: int):
+        """Bracket the next max_launches evaluation kernels of step() with HIP
+        events (0: off)."""
+        _check(lib().cp_optimizer_time_eval(self._h, int(max_launches)))
+
+    def eval_time(self):
+        """(total milliseconds, launches) of the evaluations timed since the
+        last call."""
+        ms = ctypes.c_double()
+        n = _c_i32()
+        _check(lib().cp_optimizer_eval_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def last_polished(self):
         """The last iteration's polished elites [polish_elites,K,n] (in the

@@ -150,12 +150,38 @@ struct cp_opt {
     OptView view{};
     uint32_t *d_tape_p = nullptr;
     std::vector<void *> bufs;
+    // the population's argmin tape and unit path weights (cp_optimizer_record_tape)
+    uint32_t *d_tape = nullptr;
+    float *d_ones_B = nullptr;
+    // evaluation timing (cp_optimizer_time_eval): one event pair per timed
+    // evaluation launch, used in order until cp_optimizer_eval_time reads them
+    std::vector<EvalEvents> ev;
+    size_t ev_used = 0;
 
+    void drop_events() {
+        for (EvalEvents &e : ev) {
+            (void)hipEventDestroy(e.begin);
+            (void)hipEventDestroy(e.end);
+        }
+        ev.clear();
+        ev_used = 0;
+    }
+    void drop_tape() {
+        if (d_tape) (void)hipFree(d_tape);
+        if (d_ones_B) (void)hipFree(d_ones_B);
+        d_tape = nullptr;
+        d_ones_B = nullptr;
+    }
     ~cp_opt() {
         DeviceGuard g(plan->device);
+        (void)hipDeviceSynchronize();
+        drop_events();
+        drop_tape();
         for (void *p : bufs)
             if (p) (void)hipFree(p);
     }
+    // the next event pair, or null when timing is off or every pair is in use
+    const EvalEvents *next_events() { return ev_used < ev.size() ? &ev[ev_used++] : nullptr; }
     template <class T>
     hipError_t alloc(T **p, size_t count) {
         *p = nullptr;
@@ -743,11 +769,13 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
     const PlanView &P = p->view;
     for (int it = 0; it < n_iters; ++it) {
         CP_HIP(launch_sample(P, v, st), "sample");
+        const EvalEvents *ev = opt->next_events();
         if (reduce_select_fits(v.B)) {
-            CP_HIP(launch_eval_fwd(P, v.W, v.B, p->d_partial, nullptr, nullptr, nullptr, nullptr, st), "eval");
+            CP_HIP(launch_eval_fwd(P, v.W, v.B, p->d_partial, opt->d_tape, nullptr, nullptr, nullptr, st, ev), "eval");
             CP_HIP(launch_reduce_select(p->d_partial, eval_slots(P.ns), P.ns, P.margin, v, st), "select");
         } else {
-            CP_HIP(launch_eval_fwd(P, v.W, v.B, p->d_partial, nullptr, v.cost, v.min_dist, nullptr, st), "eval");
+            CP_HIP(launch_eval_fwd(P, v.W, v.B, p->d_partial, opt->d_tape, v.cost, v.min_dist, nullptr, st, ev),
+                   "eval");
             CP_HIP(launch_select(v, st), "select");
         }
         if (opt->npol > 0) {
@@ -757,6 +785,75 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
         CP_HIP(launch_update(P, v, st), "update");
         CP_HIP(launch_chol(v, st), "cholesky");
     }
+    return CP_OK;
+}
+
+int cp_optimizer_record_tape(cp_opt *opt, int32_t enable) {
+    if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
+    DeviceGuard g(opt->plan->device);
+    CP_HIP(hipDeviceSynchronize(), "sync");
+    if (!enable) {
+        opt->drop_tape();
+        return CP_OK;
+    }
+    if (opt->d_tape) return CP_OK;
+    const OptView &v = opt->view;
+    hipError_t e = hipMalloc((void **)&opt->d_tape, (size_t)v.B * opt->plan->ns * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&opt->d_ones_B, (size_t)v.B * sizeof(float));
+    if (e == hipSuccess) {
+        std::vector<float> ones(v.B, 1.0f);
+        e = hipMemcpy(opt->d_ones_B, ones.data(), v.B * sizeof(float), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        opt->drop_tape();
+        return hip_fail(e, "tape buffers");
+    }
+    return CP_OK;
+}
+
+int cp_optimizer_population_grad(cp_opt *opt, float *d_grad_waypoints, cp_stream_t stream) {
+    if (!opt || !d_grad_waypoints) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (!opt->d_tape) return fail(CP_ERR_STATE, "no tape: call cp_optimizer_record_tape first");
+    cp_plan *p = opt->plan;
+    DeviceGuard g(p->device);
+    const OptView &v = opt->view;
+    CP_HIP(launch_eval_bwd(p->view, v.W, v.B, opt->d_tape, opt->d_ones_B, d_grad_waypoints, (hipStream_t)stream),
+           "population adjoint");
+    return CP_OK;
+}
+
+int cp_optimizer_time_eval(cp_opt *opt, int32_t max_launches) {
+    if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
+    if (max_launches < 0 || max_launches > 65536) return fail(CP_ERR_SIZE, "max_launches out of range (0..65536)");
+    DeviceGuard g(opt->plan->device);
+    CP_HIP(hipDeviceSynchronize(), "sync");
+    opt->drop_events();
+    for (int i = 0; i < max_launches; ++i) {
+        EvalEvents e{};
+        CP_HIP(hipEventCreate(&e.begin), "event");
+        hipError_t er = hipEventCreate(&e.end);
+        if (er != hipSuccess) {
+            (void)hipEventDestroy(e.begin);
+            return hip_fail(er, "event");
+        }
+        opt->ev.push_back(e);
+    }
+    return CP_OK;
+}
+
+int cp_optimizer_eval_time(cp_opt *opt, double *total_ms, int32_t *launches) {
+    if (!opt || !total_ms || !launches) return fail(CP_ERR_INVALID_ARG, "null argument");
+    DeviceGuard g(opt->plan->device);
+    double sum = 0.0;
+    for (size_t i = 0; i < opt->ev_used; ++i) {
+        CP_HIP(hipEventSynchronize(opt->ev[i].end), "event sync");
+        float ms = 0.0f;
+        CP_HIP(hipEventElapsedTime(&ms, opt->ev[i].begin, opt->ev[i].end), "event time");
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (int32_t)opt->ev_used;
+    opt->ev_used = 0;
     return CP_OK;
 }
 

@@ -1099,10 +1099,14 @@ static hipError_t view_with_sdf_bound(const PlanView &P, PlanView &Q, hipStream_
 }
 
 hipError_t launch_eval_fwd(const PlanView &P0, const float *W, int B, double2 *partial, uint32_t *tape,
-                           float *cost, float *min_dist, uint8_t *flags, hipStream_t st) {
+                           float *cost, float *min_dist, uint8_t *flags, hipStream_t st, const EvalEvents *ev) {
     PlanView P;
     const hipError_t eb = view_with_sdf_bound(P0, P, st);
     if (eb != hipSuccess) return eb;
+    if (ev) {
+        const hipError_t er = hipEventRecord(ev->begin, st);
+        if (er != hipSuccess) return er;
+    }
     const int64_t N = (int64_t)B * P.ns;
     const int slots = eval_slots(P.ns);
     const dim3 grid((unsigned)((N + 255) / 256));
@@ -1150,6 +1154,7 @@ hipError_t launch_eval_fwd(const PlanView &P0, const float *W, int B, double2 *p
         hipLaunchKernelGGL((k_eval_fwd<false, false>), grid, dim3(256), 0, st, P, W, B, partial, slots, tape);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev->end, st)) != hipSuccess) return e;
     // no outputs: the caller takes the per-path sums itself, or wants only the tape
     if (!cost && !min_dist && !flags) return hipSuccess;
     hipLaunchKernelGGL(k_eval_reduce, dim3((B + 255) / 256), dim3(256), 0, st, partial, slots, B, P.ns, P.margin,

@@ -8,9 +8,15 @@ namespace cp {
 // evaluation (eval.hip)
 int eval_slots(int ns);
 size_t eval_partial_count(int B, int ns);
+// events recorded on the stream right before and right after the evaluation
+// kernel (the grid bound refresh before it and the per-path sums after it
+// fall outside)
+struct EvalEvents {
+    hipEvent_t begin, end;
+};
 // (cost, min_dist and flags all null: only the tape is written)
 hipError_t launch_eval_fwd(const PlanView &P, const float *W, int B, double2 *partial, uint32_t *tape, float *cost,
-                           float *min_dist, uint8_t *flags, hipStream_t st);
+                           float *min_dist, uint8_t *flags, hipStream_t st, const EvalEvents *ev = nullptr);
 // the clearance grid of a plan (P.clr_* set), into out [clr_ny][clr_nx]
 hipError_t launch_clearance(const PlanView &P, float *out, hipStream_t st);
 // with pol (W set): the polish's step on every path after its gradient

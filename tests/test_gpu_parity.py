@@ -382,6 +382,44 @@ def test_backward_grid_scene_parity(cp):
         assert rel_an <= 1e-4 and rel_fd <= 1e-4, (b, rel_an, rel_fd)
 
 
+def test_population_gradient_after_a_step(cp):
+    """An optimizer that records the argmin tape steps exactly as one that
+    does not, and its population gradient is the adjoint of the evaluated
+    population (bitwise the plan's backward with the evaluation's tape, and
+    the oracle's analytic gradient on paths without a kink)."""
+    import dataclasses
+    prob = dataclasses.replace(_diff_problem(K=8, M=8),
+                               opt=synth.OptParams(B=512, nu=25, sigma0=0.3, eps=1e-6, seed=19, T=1))
+    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=prob.opt.B)
+    plan.set_endpoints(prob.q_start, prob.q_goal)
+    a = cp.Optimizer(plan, prob.opt)
+    b = cp.Optimizer(plan, prob.opt)
+    b.record_tape(True)
+    a.step(2)
+    b.step(2)
+    sa, sb = a.get_state(), b.get_state()
+    np.testing.assert_array_equal(sa["mu"], sb["mu"])
+    np.testing.assert_array_equal(sa["C"], sb["C"])
+    g = b.population_grad()
+    W, cost, _ = b.last()
+    _, _, _, tape = plan.eval(W, tape=True)
+    ones = torch.ones(prob.opt.B, device="cuda")
+    assert torch.equal(g, plan.backward(W, ones, tape))
+    m = oracle.Model(prob.robot, prob.scene, prob.cost)
+    Wd = W[:48].cpu().numpy().astype(np.float64)
+    ref = oracle.eval_paths(m, prob.q_start, prob.q_goal, Wd, per_checkpoint=True)
+    ok = ((ref["second"] - ref["d"]) > 1e-5).all(1) & (np.abs(ref["d"] - 0.1) > 1e-5).all(1)
+    assert ok.sum() >= 8
+    _, gref = oracle.grad_paths(m, prob.q_start, prob.q_goal, Wd[ok])
+    gg = g[:48].cpu().numpy().astype(np.float64)[ok]
+    for r in range(gg.shape[0]):
+        assert np.linalg.norm(gg[r] - gref[r]) <= 1e-4 * max(np.linalg.norm(gref[r]), 1e-12)
+    c = cp.Optimizer(plan, prob.opt)
+    with pytest.raises(cp.CranePlanError) as ei:
+        c.population_grad()
+    assert ei.value.code == -5
+
+
 def test_autograd_function(cp):
     prob = _diff_problem(K=8, M=8)
     rng = np.random.default_rng(109)
