@@ -1,8 +1,10 @@
 // Signed-distance grid from a lidar point cloud: voxel occupancy, exact
-// squared Euclidean distance transforms (separable: one 1-D lower-envelope
-// pass per axis over integer squared distances), and the signed field at
-// voxel centres.  Every pass is exact integer arithmetic, so the squared
-// distances are bit-identical to any other exact method.
+// squared Euclidean distance transforms (separable: a two-sweep nearest-target
+// pass along x, O(L) per line, then one pass per other axis over integer
+// squared distances: the lower envelope of parabolas, O(L) per line, for
+// long lines and the plain minimum, O(L^2) per line but parallel over every
+// output, for short ones), and the signed field at voxel centres.  Every pass is exact integer arithmetic, so the squared distances
+// are bit-identical to any other exact method.
 #include <algorithm>
 
 #include "launch.h"
@@ -28,51 +30,185 @@ __global__ void k_occupancy(const float *__restrict__ pts, int64_t N, int nx, in
     }
 }
 
-// pass along x: g(x) = min over target voxels x' of the row of (x - x')^2
-__global__ __launch_bounds__(256) void k_edt_x(const uint8_t *__restrict__ occ, uint8_t target, int nx,
-                                               int32_t *__restrict__ out) {
-    extern __shared__ int32_t row[];
-    const size_t base = (size_t)blockIdx.x * nx;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = occ[base + x] == target ? 0 : kEdtInf;
+// LDS budget of one block of the line passes (lines are staged as a tile
+// [L][lines per block], L <= 4096 per axis)
+constexpr size_t kEdtLds = 48u << 10;
+
+// lines per block of a pass whose tile takes `bytes` per entry (a power of two,
+// 1..64)
+static int edt_lines(int L, size_t bytes) {
+    int nl = 64;
+    while (nl > 1 && (size_t)L * nl * bytes > kEdtLds) nl >>= 1;
+    return nl;
+}
+
+// pass along x: squared distance along the row to the nearest target voxel.
+// A block stages nl rows (coalesced reads along x) transposed into LDS; each
+// thread then takes one row in two sweeps (nearest target at or before x,
+// then at or after it: O(nx) per row) and the block stores the results
+// coalesced.
+__global__ __launch_bounds__(64) void k_edt_row(const uint8_t *__restrict__ occ, uint8_t target, int nx, int rows,
+                                                int32_t *__restrict__ out) {
+    extern __shared__ int32_t lds[];
+    const int nl = blockDim.x, t = threadIdx.x;
+    const int r0 = blockIdx.x * nl;
+    const int nr = min(nl, rows - r0);
+    int32_t *res = lds;                                         // [nx][nl]
+    uint8_t *hit = reinterpret_cast<uint8_t *>(lds + (size_t)nx * nl);  // [nx][nl]
+    for (int idx = t; idx < nr * nx; idx += nl) {
+        const int c = idx / nx, x = idx - c * nx;
+        hit[x * nl + c] = occ[(size_t)(r0 + c) * nx + x] == target;
+    }
     __syncthreads();
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        int32_t best = kEdtInf;
-        for (int x2 = 0; x2 < nx; ++x2) {
-            const int32_t d = x - x2;
-            const int32_t v = row[x2] + d * d;
-            best = v < best ? v : best;
+    if (t < nr) {
+        int last = -1;
+        for (int x = 0; x < nx; ++x) {
+            if (hit[x * nl + t]) last = x;
+            res[x * nl + t] = last < 0 ? kEdtInf : (x - last) * (x - last);
         }
-        out[base + x] = best;
+        last = -1;
+        for (int x = nx - 1; x >= 0; --x) {
+            if (hit[x * nl + t]) last = x;
+            if (last >= 0) {
+                const int32_t d = (last - x) * (last - x);
+                if (d < res[x * nl + t]) res[x * nl + t] = d;
+            }
+        }
+    }
+    __syncthreads();
+    for (int idx = t; idx < nr * nx; idx += nl) {
+        const int c = idx / nx, x = idx - c * nx;
+        out[(size_t)(r0 + c) * nx + x] = res[x * nl + c];
     }
 }
 
 // pass along a strided axis of length L (y: stride nx; z: stride nx*ny):
-// out(l) = min over l' of in(l') + (l - l')^2, for 32 consecutive x at once
+// out(q) = min over l of f(l) + (q - l)^2, the lower envelope of the
+// parabolas rooted at the finite samples (Felzenszwalb and Huttenlocher,
+// "Distance Transforms of Sampled Functions", 2012), one thread per line,
+// O(L) per line.  The envelope's breakpoints are rationals
+// s(a, b) = (h_a - h_b) / (2 (a - b)), h_l = f(l) + l^2; they are never
+// formed: every comparison of two of them, or of one with an integer q, is
+// made by cross-multiplication in 64-bit integers, so the result is exact
+// (the same minimum as the brute-force definition).  A block takes nl lines
+// of consecutive x (coalesced reads and writes of each sample) and stages
+// their samples in LDS ([L][nl] int32) beside the stack of envelope roots
+// ([L][nl] int16).
+__global__ __launch_bounds__(64) void k_edt_envelope(const int32_t *__restrict__ in, int32_t *__restrict__ out, int L,
+                                                     size_t stride, size_t outer_stride, int nx, int lines) {
+    extern __shared__ int32_t lds[];
+    const int nl = blockDim.x, t = threadIdx.x;
+    const int l0 = blockIdx.x * nl;
+    const int nln = min(nl, lines - l0);
+    int32_t *f = lds;                                                   // [L][nl]
+    int16_t *stk = reinterpret_cast<int16_t *>(lds + (size_t)L * nl);  // [L][nl]
+    auto base_of = [&](int line) { return (size_t)(line / nx) * outer_stride + (line % nx); };
+    for (int idx = t; idx < L * nln; idx += nl) {
+        const int q = idx / nln, c = idx - q * nln;
+        f[q * nl + c] = in[base_of(l0 + c) + (size_t)q * stride];
+    }
+    __syncthreads();
+    if (t >= nln) return;  // (no barrier below)
+    int32_t *o = out + base_of(l0 + t);
+    auto h = [&](int l) { return (int64_t)f[l * nl + t] + (int64_t)l * l; };
+    // envelope: stk[0..k], roots in increasing order
+    int k = -1;
+    int v = 0;        // root at the top
+    int64_t hv = 0;   // its h
+    for (int q = 0; q < L; ++q) {
+        const int32_t fq = f[q * nl + t];
+        if (fq >= kEdtInf) continue;
+        const int64_t hq = (int64_t)fq + (int64_t)q * q;
+        // pop while the new parabola's breakpoint with the top is at or before
+        // the top's own breakpoint with the one below it
+        while (k >= 1) {
+            const int u = stk[(k - 1) * nl + t];
+            const int64_t hu = h(u);
+            if ((hq - hv) * (int64_t)(v - u) <= (hv - hu) * (int64_t)(q - v)) {
+                --k;
+                v = u;
+                hv = hu;
+            } else {
+                break;
+            }
+        }
+        stk[++k * nl + t] = (int16_t)q;
+        v = q;
+        hv = hq;
+    }
+    if (k < 0) {
+        for (int q = 0; q < L; ++q) o[(size_t)q * stride] = kEdtInf;
+        return;
+    }
+    const int top = k;
+    k = 0;
+    v = stk[t];
+    hv = h(v);
+    int w = top > 0 ? stk[nl + t] : 0;
+    int64_t hw = top > 0 ? h(w) : 0;
+    for (int q = 0; q < L; ++q) {
+        // advance while the breakpoint of roots k and k + 1 lies before q
+        while (k < top && hw - hv < 2 * (int64_t)q * (w - v)) {
+            ++k;
+            v = w;
+            hv = hw;
+            if (k < top) {
+                w = stk[(k + 1) * nl + t];
+                hw = h(w);
+            }
+        }
+        o[(size_t)q * stride] = (int32_t)(hv - (int64_t)v * v + (int64_t)(q - v) * (q - v));
+    }
+}
+
+// The same pass for short lines (L <= kEdtShort): every output takes the plain
+// minimum over the line's samples, O(L) per output and O(L^2) per line, but
+// every output is independent, so the whole grid works in parallel; at the
+// lengths of the workloads (128 and 256) this measures faster than the
+// envelope's sequential walk per line (one thread per line leaves the chip
+// mostly idle).  32 lines of consecutive x per block, staged in LDS
+// ([L][32] int32, at most 64 KiB).
+constexpr int kEdtShort = 512;
 constexpr int kEdtCols = 32;
 
-__global__ __launch_bounds__(256) void k_edt_strided(const int32_t *__restrict__ in, int32_t *__restrict__ out, int L,
-                                                     size_t stride, size_t outer_stride, int nx) {
+__global__ __launch_bounds__(256) void k_edt_short(const int32_t *__restrict__ in, int32_t *__restrict__ out, int L,
+                                                   size_t stride, size_t outer_stride, int nx) {
     extern __shared__ int32_t tile[];  // [L][kEdtCols]
     const int x0 = blockIdx.x * kEdtCols;
     const size_t base = (size_t)blockIdx.y * outer_stride + x0;
     const int ncol = min(kEdtCols, nx - x0);
+    // staged as g(l) = f(l) + l^2, so that f(l') + (l - l')^2 = g(l') - 2 l l' + l^2:
+    // one 24-bit multiply-add and a minimum per sample (l, l' < 512).  A sample
+    // without a target (f = kEdtInf) keeps g >= kEdtInf + l'^2, so its terms stay
+    // at or above kEdtInf, above every finite squared distance (< 2^26).
     for (int idx = threadIdx.x; idx < L * kEdtCols; idx += blockDim.x) {
         const int l = idx / kEdtCols, c = idx % kEdtCols;
-        tile[idx] = c < ncol ? in[base + (size_t)l * stride + c] : kEdtInf;
+        const int32_t f = c < ncol ? in[base + (size_t)l * stride + c] : kEdtInf;
+        tile[idx] = min(f, kEdtInf) + l * l;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < L * kEdtCols; idx += blockDim.x) {
         const int l = idx / kEdtCols, c = idx % kEdtCols;
         if (c >= ncol) continue;
-        int32_t best = kEdtInf;
-        for (int l2 = 0; l2 < L; ++l2) {
-            const int32_t d = l - l2;
-            const int32_t f = tile[l2 * kEdtCols + c];
-            const int32_t v = f >= kEdtInf ? kEdtInf : f + d * d;
-            best = v < best ? v : best;
-        }
-        out[base + (size_t)l * stride + c] = best;
+        const int m2l = -2 * l;
+        int32_t best = 2 * kEdtInf;
+        for (int l2 = 0; l2 < L; ++l2) best = min(best, tile[l2 * kEdtCols + c] + __mul24(m2l, l2));
+        out[base + (size_t)l * stride + c] = min(best + l * l, kEdtInf);
     }
+}
+
+// one strided pass: the plain minimum for short lines, the envelope for long ones
+static hipError_t edt_pass(const int32_t *in, int32_t *out, int L, size_t stride, size_t outer_stride, int nx,
+                           int n_outer, hipStream_t st) {
+    if (L <= kEdtShort) {
+        hipLaunchKernelGGL(k_edt_short, dim3((nx + kEdtCols - 1) / kEdtCols, n_outer), dim3(256),
+                           (size_t)L * kEdtCols * sizeof(int32_t), st, in, out, L, stride, outer_stride, nx);
+    } else {
+        const int lines = nx * n_outer, nl = edt_lines(L, 6);
+        hipLaunchKernelGGL(k_edt_envelope, dim3((lines + nl - 1) / nl), dim3(nl), (size_t)L * nl * 6, st, in, out, L,
+                           stride, outer_stride, nx, lines);
+    }
+    return hipGetLastError();
 }
 
 __global__ void k_edt_finish(int32_t *__restrict__ e, size_t n, int32_t none) {
@@ -94,16 +230,15 @@ __global__ void k_sdf_sign(const uint8_t *__restrict__ occ, const int32_t *__res
 static hipError_t edt3(const uint8_t *occ, uint8_t target, int nx, int ny, int nz, int32_t *out, int32_t *tmp,
                        hipStream_t st) {
     // x pass into out, y pass out -> tmp, z pass tmp -> out
-    hipLaunchKernelGGL(k_edt_x, dim3(ny * nz), dim3(256), nx * sizeof(int32_t), st, occ, target, nx, out);
+    const int rows = ny * nz;
+    const int xl = edt_lines(nx, 5);
+    hipLaunchKernelGGL(k_edt_row, dim3((rows + xl - 1) / xl), dim3(xl), (size_t)nx * xl * 5, st, occ, target, nx, rows,
+                       out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int cx = (nx + kEdtCols - 1) / kEdtCols;
-    hipLaunchKernelGGL(k_edt_strided, dim3(cx, nz), dim3(256), ny * kEdtCols * sizeof(int32_t), st, out, tmp, ny,
-                       (size_t)nx, (size_t)nx * ny, nx);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edt_strided, dim3(cx, ny), dim3(256), nz * kEdtCols * sizeof(int32_t), st, tmp, out, nz,
-                       (size_t)nx * ny, (size_t)nx, nx);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // y lines: (x, z), stride nx; z lines: (x, y), stride nx * ny
+    if ((e = edt_pass(out, tmp, ny, (size_t)nx, (size_t)nx * ny, nx, nz, st)) != hipSuccess) return e;
+    if ((e = edt_pass(tmp, out, nz, (size_t)nx * ny, (size_t)nx, nx, ny, st)) != hipSuccess) return e;
     const size_t n = (size_t)nx * ny * nz;
     const int32_t none = nx * nx + ny * ny + nz * nz;
     hipLaunchKernelGGL(k_edt_finish, dim3(1024), dim3(256), 0, st, out, n, none);

@@ -93,3 +93,28 @@ def test_tune_rejects_no_target_before_touching_the_device():
         build.build()
     with pytest.raises(craneplan.CranePlanError):
         craneplan.tune()
+
+
+def test_sdf_build_argument_checks_without_device():
+    """cp_sdf_build refuses grid sizes outside 2..4096 per axis (the distance
+    transforms' per-line stacks are sized for that) and other bad arguments
+    before any device work."""
+    import ctypes
+
+    import numpy as np
+
+    from paper_2503_14160_amd import craneplan
+    if not os.path.exists(craneplan.LIB_PATH):
+        from paper_2503_14160_amd import build
+        build.build()
+    L = craneplan.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    org = np.zeros(3, np.float32)
+    for dims, voxel, code in (((4097, 4, 4), 0.1, -2), ((4, 1, 4), 0.1, -2), ((8, 8, 8), 0.0, -1),
+                              ((8, 8, 8), float("nan"), -1)):
+        d = np.array(dims, np.int32)
+        rc = L.cp_sdf_build(fake, 10, d.ctypes.data, org.ctypes.data, voxel, fake, None, None, None, None)
+        assert rc == code, (dims, voxel, rc)
+    d = np.array((8, 8, 8), np.int32)
+    assert L.cp_sdf_build(fake, -1, d.ctypes.data, org.ctypes.data, 0.1, fake, None, None, None, None) == -2
+    assert L.cp_sdf_build(None, 10, d.ctypes.data, org.ctypes.data, 0.1, fake, None, None, None, None) == -1

@@ -854,3 +854,34 @@ def test_sdf_build_and_query_parity(cp):
     dr, sr, orr, sec = oracle.eval_configs(m, Q.astype(np.float64))
     assert np.all(np.abs(d.cpu().numpy() - dr) <= 1e-4)
     assert np.all((a.cpu().numpy().view(np.uint32) & 0xFFFF) == 0xFFFF)
+
+
+@pytest.mark.parametrize("dims,n_pts", [((4096, 2, 3), 40), ((3, 1500, 4), 30), ((5, 6, 1100), 25),
+                                        ((9, 8, 7), 0), ((4, 4, 4), 4000), ((33, 17, 65), 300)])
+def test_sdf_build_shapes(cp, dims, n_pts):
+    """Distance transforms on grids of uneven shape: one axis up to the
+    4096 limit (the envelope passes' shared-memory stack then holds fewer
+    lines per block), no occupied voxel (every squared distance is the
+    'none' value nx^2 + ny^2 + nz^2), every voxel occupied; occupancy and both
+    squared EDTs bit-exact against the oracle's plain line minima."""
+    spec = synth.SdfSpec(dims=dims, origin=(-1.0, 2.0, 0.5), voxel=0.25)
+    rng = np.random.default_rng(sum(dims) + n_pts)
+    ext = np.array(dims) * spec.voxel
+    pts = (np.array(spec.origin) + rng.uniform(0, 1, size=(n_pts, 3)) * ext).astype(np.float32)
+    if n_pts == 4000:  # every voxel of the 4 x 4 x 4 grid
+        g = np.stack(np.meshgrid(*[np.arange(4) + 0.5] * 3, indexing="ij"), -1).reshape(-1, 3)
+        pts = np.concatenate([pts, (np.array(spec.origin) + g * spec.voxel).astype(np.float32)])
+    pts = np.ascontiguousarray(pts.reshape(-1, 3), np.float32)
+    print(f"[sdf shapes] dims={dims} points={pts.shape[0]}", flush=True)
+    dev = torch.from_numpy(pts).cuda() if pts.shape[0] else torch.zeros((0, 3), device="cuda")
+    sdf, occ, eo, ef = cp.sdf_build(dev, spec, with_edt=True)
+    torch.cuda.synchronize()
+    phi_ref, occ_ref, eo_ref, ef_ref = oracle.sdf_build(pts, spec)
+    np.testing.assert_array_equal(occ.cpu().numpy(), occ_ref)
+    np.testing.assert_array_equal(eo.cpu().numpy(), eo_ref)
+    np.testing.assert_array_equal(ef.cpu().numpy(), ef_ref)
+    np.testing.assert_allclose(sdf.cpu().numpy(), phi_ref, rtol=2e-7, atol=1e-7)
+    if n_pts == 0:
+        assert (eo_ref == sum(d * d for d in dims)).all()
+    if n_pts == 4000:
+        assert occ_ref.all() and (ef_ref == sum(d * d for d in dims)).all()
