@@ -59,7 +59,8 @@ class _Robot(ctypes.Structure):
                 ("origin", ctypes.c_void_p), ("q_min", ctypes.c_void_p), ("q_max", ctypes.c_void_p),
                 ("q_hold", ctypes.c_void_p), ("active", ctypes.c_void_p), ("n_spheres", ctypes.c_int32),
                 ("sphere_frame", ctypes.c_void_p), ("sphere_center", ctypes.c_void_p),
-                ("sphere_radius", ctypes.c_void_p), ("tip", ctypes.c_void_p)]
+                ("sphere_radius", ctypes.c_void_p), ("tip", ctypes.c_void_p), ("n_self", ctypes.c_int32),
+                ("self_pairs", ctypes.c_void_p)]
 
 
 class _Scene(ctypes.Structure):
@@ -138,6 +139,9 @@ class Model:
         r.sphere_center = keep(robot.sphere_center, np.float32)
         r.sphere_radius = keep(robot.sphere_radius, np.float32)
         r.tip = keep(robot.tip, np.float32)
+        pairs = np.asarray(getattr(robot, "self_pairs", np.zeros((0, 2))), np.int32).reshape(-1, 2)
+        r.n_self = int(pairs.shape[0])
+        r.self_pairs = keep(pairs if pairs.size else np.zeros((1, 2)), np.int32)
         s = _Scene()
         s.has_ground = int(scene.has_ground)
         s.ground_z = float(scene.ground_z)

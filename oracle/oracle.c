@@ -46,6 +46,8 @@ typedef struct {
     const float *sphere_center;    /* [S,3] */
     const float *sphere_radius;    /* [S] */
     const float *tip;              /* [3] */
+    int32_t n_self;                /* frame pairs checked for self-collision */
+    const int32_t *self_pairs;     /* [n_self][2] frame indices */
 } orc_robot;
 
 typedef struct {
@@ -260,8 +262,19 @@ double orc_sdf_query(const orc_scene *sc, const double c[3], double *grad) {
 }
 
 /* obstacle numbering of the tape: 0 = ground, 1..n_cyl = cylinders,
- * n_cyl+1.. = boxes, 0xFFFF = the signed-distance grid */
+ * n_cyl+1.. = boxes, 0xFFFF = the signed-distance grid; a self-collision pair
+ * of spheres (a, b), a < b, is recorded as sphere a and obstacle 0xFF00 + b */
 #define ORC_OBS_SDF 0xFFFF
+#define ORC_OBS_SELF 0xFF00
+
+/* whether the frame pair {fa, fb} is listed for self-collision checks */
+static int self_listed(const orc_robot *rb, int fa, int fb) {
+    for (int i = 0; i < rb->n_self; ++i) {
+        int a = rb->self_pairs[2 * i], b = rb->self_pairs[2 * i + 1];
+        if ((a == fa && b == fb) || (a == fb && b == fa)) return 1;
+    }
+    return 0;
+}
 
 static double sd_obstacle(const orc_scene *sc, int o, const double c[3], double *grad) {
     if (o == ORC_OBS_SDF) return orc_sdf_query(sc, c, grad);
@@ -273,8 +286,11 @@ static double sd_obstacle(const orc_scene *sc, int o, const double c[3], double 
     return orc_sd_box(c, sc->box + 6 * (o - 1 - sc->n_cyl), grad);
 }
 
-/* d(q): minimum over every (sphere, obstacle) pair of sd(centre) - radius.
- * Ties keep the lowest sphere, then the lowest obstacle number. */
+/* d(q): minimum over every (sphere, obstacle) pair of sd(centre) - radius,
+ * and over every self-collision pair (spheres a < b on a listed frame pair)
+ * of |c_a - c_b| - r_a - r_b (Sec. 3.2 names self-collision beside collision
+ * with the environment).  Ties keep the lowest sphere, then its obstacles in
+ * number order, then its self pairs by the other sphere. */
 double orc_config_distance(const orc_robot *rb, const orc_scene *sc, const double *q,
                            int32_t *arg_s, int32_t *arg_o, double *second) {
     xform F[ORC_MAXJ + 1];
@@ -299,6 +315,20 @@ double orc_config_distance(const orc_robot *rb, const orc_scene *sc, const doubl
             if (d < best) {
                 best2 = best;
                 best = d; bs = s; bo = code;
+            } else if (d < best2) {
+                best2 = d;
+            }
+        }
+        for (int b = s + 1; b < rb->n_spheres; ++b) {
+            if (rb->n_self == 0 || !self_listed(rb, rb->sphere_frame[s], rb->sphere_frame[b])) continue;
+            double lb[3], cb[3];
+            sphere_local(rb, b, lb);
+            xf_apply(&F[rb->sphere_frame[b]], lb, cb);
+            double dx = c[0] - cb[0], dy = c[1] - cb[1], dz = c[2] - cb[2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz) - r - (double)rb->sphere_radius[b];
+            if (d < best) {
+                best2 = best;
+                best = d; bs = s; bo = ORC_OBS_SELF + b;
             } else if (d < best2) {
                 best2 = d;
             }
@@ -413,6 +443,24 @@ static double limit_cost(const orc_robot *rb, const double *q, double *grad) {
     return J;
 }
 
+/* d c / d q_j for a point c rigidly attached to frame f, into dc */
+static void point_jacobian_col(const orc_robot *rb, const xform *F, int j, const double c[3], double dc[3]) {
+    /* joint j moves frame j+1; its axis in world coordinates is R_j a_j
+     * and passes through the origin of frame j+1 */
+    double a[3], aw[3];
+    for (int i = 0; i < 3; ++i) a[i] = rb->axis[3 * j + i];
+    for (int i = 0; i < 3; ++i)
+        aw[i] = F[j].R[3 * i] * a[0] + F[j].R[3 * i + 1] * a[1] + F[j].R[3 * i + 2] * a[2];
+    if (rb->type[j] == ORC_REVOLUTE) {
+        double r[3] = {c[0] - F[j + 1].p[0], c[1] - F[j + 1].p[1], c[2] - F[j + 1].p[2]};
+        dc[0] = aw[1] * r[2] - aw[2] * r[1];
+        dc[1] = aw[2] * r[0] - aw[0] * r[2];
+        dc[2] = aw[0] * r[1] - aw[1] * r[0];
+    } else {
+        dc[0] = aw[0]; dc[1] = aw[1]; dc[2] = aw[2];
+    }
+}
+
 /* gradient of d(q) with respect to q through the minimising pair */
 static void distance_grad_q(const orc_robot *rb, const orc_scene *sc, const double *q, int s, int o,
                             double *gq) {
@@ -421,25 +469,30 @@ static void distance_grad_q(const orc_robot *rb, const orc_scene *sc, const doub
     double l[3], c[3], gc[3];
     sphere_local(rb, s, l);
     xf_apply(&F[rb->sphere_frame[s]], l, c);
-    sd_obstacle(sc, o, c, gc);
     for (int j = 0; j < rb->n_joints; ++j) gq[j] = 0.0;
+    if (o >= ORC_OBS_SELF && o < ORC_OBS_SDF) {
+        /* self pair: d = |c_s - c_b| - r_s - r_b, dd/dq = n . (dc_s/dq - dc_b/dq) */
+        int b = o - ORC_OBS_SELF;
+        double lb[3], cb[3];
+        sphere_local(rb, b, lb);
+        xf_apply(&F[rb->sphere_frame[b]], lb, cb);
+        double n[3] = {c[0] - cb[0], c[1] - cb[1], c[2] - cb[2]};
+        double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (!(len > 0.0)) return;
+        for (int i = 0; i < 3; ++i) n[i] /= len;
+        for (int j = 0; j < rb->n_joints; ++j) {
+            double da[3] = {0.0, 0.0, 0.0}, db[3] = {0.0, 0.0, 0.0};
+            if (j < rb->sphere_frame[s]) point_jacobian_col(rb, F, j, c, da);
+            if (j < rb->sphere_frame[b]) point_jacobian_col(rb, F, j, cb, db);
+            gq[j] = n[0] * (da[0] - db[0]) + n[1] * (da[1] - db[1]) + n[2] * (da[2] - db[2]);
+        }
+        return;
+    }
+    sd_obstacle(sc, o, c, gc);
     int f = rb->sphere_frame[s];
     for (int j = 0; j < f; ++j) {
-        /* joint j moves frame j+1; its axis in world coordinates is R_j a_j
-         * and passes through the origin of frame j+1 */
-        double a[3], aw[3];
-        for (int i = 0; i < 3; ++i) a[i] = rb->axis[3 * j + i];
-        for (int i = 0; i < 3; ++i)
-            aw[i] = F[j].R[3 * i] * a[0] + F[j].R[3 * i + 1] * a[1] + F[j].R[3 * i + 2] * a[2];
         double dc[3];
-        if (rb->type[j] == ORC_REVOLUTE) {
-            double r[3] = {c[0] - F[j + 1].p[0], c[1] - F[j + 1].p[1], c[2] - F[j + 1].p[2]};
-            dc[0] = aw[1] * r[2] - aw[2] * r[1];
-            dc[1] = aw[2] * r[0] - aw[0] * r[2];
-            dc[2] = aw[0] * r[1] - aw[1] * r[0];
-        } else {
-            dc[0] = aw[0]; dc[1] = aw[1]; dc[2] = aw[2];
-        }
+        point_jacobian_col(rb, F, j, c, dc);
         gq[j] = gc[0] * dc[0] + gc[1] * dc[1] + gc[2] * dc[2];
     }
 }

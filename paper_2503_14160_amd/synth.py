@@ -60,6 +60,9 @@ class Robot:
     sphere_radius: np.ndarray  # f32 [S]
     tip: np.ndarray          # f32 [3]
     link_lengths: np.ndarray  # f32 [5]  L1..L5 (column, boom, arm, telescope, hanger)
+    # frame pairs whose spheres are checked against each other (self-collision);
+    # empty: the environment only
+    self_pairs: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 2), np.int32))
 
     @property
     def n_joints(self) -> int:
@@ -217,6 +220,23 @@ def make_robot(seed: int, n_spheres: int) -> Robot:
                  q_hold=q_hold, active=active,
                  sphere_frame=np.array(frames, np.int32), sphere_center=_f32(centers),
                  sphere_radius=radius, tip=_f32([0.0, 0.0, -L5]), link_lengths=L)
+
+
+def crane_self_pairs(robot: Robot) -> np.ndarray:
+    """Frame pairs of the crane's links that are not adjacent: the sphere-
+    carrying frames in chain order are the column (1), boom (2), arm (3),
+    telescope (4) and hanger (6, joined to the telescope through the
+    sphere-less frame 5); links next to each other in that order share a
+    joint and are not checked."""
+    frames = sorted(set(int(f) for f in robot.sphere_frame if f > 0))
+    pairs = [(a, b) for i, a in enumerate(frames) for b in frames[i + 2:]]
+    return np.array(pairs, np.int32).reshape(-1, 2)
+
+
+def with_self_collision(robot: Robot) -> Robot:
+    """The same crane with its non-adjacent link pairs checked for
+    self-collision."""
+    return dataclasses.replace(robot, self_pairs=crane_self_pairs(robot))
 
 
 def make_endpoints(rng: np.random.Generator, robot: Robot):

@@ -289,6 +289,102 @@ def test_config_distance_is_min_over_pairs(orc):
         assert sec[i] == sorted(v[0] for v in vals)[1]
 
 
+def _self_vals(orc, m, rb, q):
+    """Every listed self pair of spheres (a < b) at q, written out from the
+    oracle's FK centres: (|c_a - c_b| - r_a - r_b, a, 0xFF00 + b)."""
+    _, cen, _ = orc.fk(m, q)
+    listed = {tuple(sorted(p)) for p in rb.self_pairs.tolist()}
+    vals = []
+    for a in range(rb.n_spheres):
+        for b in range(a + 1, rb.n_spheres):
+            if tuple(sorted((int(rb.sphere_frame[a]), int(rb.sphere_frame[b])))) in listed:
+                d = float(np.linalg.norm(cen[a] - cen[b])) - float(rb.sphere_radius[a]) - float(rb.sphere_radius[b])
+                vals.append((d, a, 0xFF00 + b))
+    return vals
+
+
+def test_self_collision_is_min_over_listed_sphere_pairs(orc):
+    """With self-collision frame pairs listed (the crane's non-adjacent links)
+    d(q) is the minimum over the scene pairs and over every sphere pair of a
+    listed frame pair of |c_a - c_b| - r_a - r_b, ties by (sphere, scene
+    obstacles first, then the other sphere); random folded configurations
+    reach negative self distances."""
+    rb = synth.with_self_collision(_robot(S=24))
+    assert len(rb.self_pairs) == 6
+    rng = np.random.default_rng(31)
+    qs, qg = synth.make_endpoints(rng, rb)
+    sc = synth.make_scene(rng, rb, qs, qg, n_cyl=6, n_box=1, half_extent=8.0)
+    m = orc.Model(rb, sc, None)
+    m0 = orc.Model(rb, _empty_scene(), None)
+    Q = synth.random_configs(rng, rb, 60, margin=0.0)
+    # telescope retracted and the hanger swung up toward the arm on half of them
+    Q[:30, 3] = rng.uniform(0.0, 0.6, size=30)
+    Q[:30, 5] = rng.choice([-1.0, 1.0], size=30) * rng.uniform(1.2, 1.57, size=30)
+    d, s_arg, o_arg, sec = orc.eval_configs(m, Q)
+    d0, s0, o0, _ = orc.eval_configs(m0, Q)
+    neg = 0
+    for i in range(Q.shape[0]):
+        _, cen, _ = orc.fk(m, Q[i])
+        selfv = _self_vals(orc, m, rb, Q[i])
+        vals = []
+        for s in range(rb.n_spheres):
+            r = float(rb.sphere_radius[s])
+            vals.append((cen[s, 2] - r, s, 0))
+            for o in range(sc.n_cyl):
+                vals.append((orc.sd_cylinder(cen[s], sc.cyl[o]) - r, s, 1 + o))
+            for o in range(sc.n_box):
+                vals.append((orc.sd_box(cen[s], sc.box[o]) - r, s, 1 + sc.n_cyl + o))
+        vals += selfv
+        best = min(vals, key=lambda v: (v[0], v[1], v[2]))
+        assert d[i] == pytest.approx(best[0], abs=1e-12)
+        assert (s_arg[i], o_arg[i]) == (best[1], best[2])
+        assert sec[i] == pytest.approx(sorted(v[0] for v in vals)[1], abs=1e-12)
+        sbest = min(selfv, key=lambda v: (v[0], v[1], v[2]))
+        assert d0[i] == pytest.approx(sbest[0], abs=1e-12) and (s0[i], o0[i]) == (sbest[1], sbest[2])
+        neg += sbest[0] < 0
+    assert neg >= 5
+
+
+def test_self_collision_invariant_under_slew(orc):
+    """Self distances depend on the joint angles below the slew only: turning
+    the whole crane about the vertical axis leaves them unchanged."""
+    rb = synth.with_self_collision(_robot(S=24))
+    m0 = orc.Model(rb, _empty_scene(), None)
+    rng = np.random.default_rng(32)
+    Q = synth.random_configs(rng, rb, 30)
+    Q2 = Q.copy()
+    Q2[:, 0] += rng.uniform(-3, 3, size=30)
+    d1, s1, o1, _ = orc.eval_configs(m0, Q)
+    d2, s2, o2, _ = orc.eval_configs(m0, Q2)
+    np.testing.assert_allclose(d1, d2, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(o1 >= 0xFF00, True)
+
+
+def test_self_collision_gradient_matches_central_differences(orc):
+    """Paths with the hanger swung up toward the arm and no scene: the
+    collision term comes from self pairs alone; the analytic gradient (through
+    both spheres' chains, passive joints included) matches FP64 central
+    differences on paths without a kink."""
+    rb = synth.with_self_collision(_robot(S=16))
+    rng = np.random.default_rng(33)
+    qs = np.array([0.3, 0.9, -1.0, 0.2, 0.0, 1.35], np.float32)
+    qg = np.array([1.5, 0.7, -1.2, 0.4, 0.0, 1.45], np.float32)
+    K, M = 4, 4
+    m = orc.Model(rb, _empty_scene(), _cost(K, M, hinge=synth.HINGE_SMOOTH, margin=0.1))
+    W = synth.random_waypoints(rng, rb, qs, qg, 12, K, sigma=0.2).astype(np.float64)
+    W[:, :, 5] = 1.4 + rng.normal(size=(12, K)) * 0.05
+    ok = _fd_ok_mask(orc, m, qs, qg, W, 0.1)
+    ref = orc.eval_paths(m, qs, qg, W, per_checkpoint=True)
+    assert ((ref["d"] < 0.1) & (ok[:, None])).any()  # self pairs inside the hinge on kept paths
+    assert ok.sum() >= 4
+    W = W[ok]
+    _, g = orc.grad_paths(m, qs, qg, W)
+    fd = orc.fd_grad(m, qs, qg, W, h=1e-6)
+    for b in range(W.shape[0]):
+        err = np.linalg.norm(g[b] - fd[b]) / max(np.linalg.norm(fd[b]), 1e-12)
+        assert err <= 1e-6, (b, err)
+
+
 # ----------------------------------------------------------------------------
 # interpolation
 # ----------------------------------------------------------------------------

@@ -44,3 +44,16 @@ def test_batch_problems_clear(orc):
         m = orc.Model(p.robot, p.scene, p.cost)
         d, _, _, _ = orc.eval_configs(m, np.stack([p.q_start, p.q_goal]).astype(np.float64))
         assert np.all(d > 0.0), (p.name, d)
+
+
+@pytest.mark.parametrize("name", ["c0_plain", "c1_full", "c2_diff"])
+def test_workload_endpoints_clear_of_self_collision(orc, name):
+    """The crane's non-adjacent link pairs (self-collision) are clear at every
+    workload's start and goal."""
+    p = synth.WORKLOADS[name]()
+    rb = synth.with_self_collision(p.robot)
+    empty = synth.Scene(cyl=np.zeros((0, 5), np.float32), box=np.zeros((0, 6), np.float32), has_ground=0)
+    m = orc.Model(rb, empty, p.cost)
+    d, _, o, _ = orc.eval_configs(m, np.stack([p.q_start, p.q_goal]).astype(np.float64))
+    assert np.all(d > 0.0), d
+    assert np.all(o >= 0xFF00)
