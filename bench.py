@@ -417,7 +417,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed iterations (default: the workload's iteration count, 50 for c1_full; 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1_full", choices=["c1_full", "c0_plain", "c2_diff", "c3_batch", "c4_sdf"])
+    ap.add_argument("--workload", default="c1_full",
+                    choices=["c1_full", "c1_self", "c0_plain", "c2_diff", "c3_batch", "c4_sdf", "ik"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eval-reps", type=int, default=10)
     ap.add_argument("--batch-problems", type=int, default=256)
@@ -433,7 +434,7 @@ def main():
         sys.exit(2)
 
     if args.steps is None:
-        args.steps = 50 if args.workload in ("c1_full", "c4_sdf") else 20
+        args.steps = 50 if args.workload in ("c1_full", "c1_self", "c4_sdf") else 20
     import torch
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
@@ -453,6 +454,13 @@ def main():
         if not args.no_cpu_baseline:
             print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
             out["cpu_baseline"] = cpu_baseline(prob)
+    elif args.workload == "c1_self":
+        # c1_full with the crane's non-adjacent link pairs also checked against each other
+        import dataclasses
+        prob = synth.c1_full()
+        prob = dataclasses.replace(prob, name="c1_self", robot=synth.with_self_collision(prob.robot))
+        out, _, _ = bench_iterations(args, torch, cp, prob, with_roofline=False)
+        out["config"]["self_pairs"] = prob.robot.self_pairs.tolist()
     elif args.workload == "c0_plain":
         out, _, _ = bench_iterations(args, torch, cp, synth.c0_plain(), with_roofline=False)
     elif args.workload == "c2_diff":

@@ -76,8 +76,12 @@ enum { CP_PAIRS_ALL = 0, CP_PAIRS_LANE = 1, CP_PAIRS_WAVE = 2, CP_PAIRS_AUTO = 3
 
 /* tape entry of a checkpoint: (sphere << 16) | obstacle, where obstacle 0 is
  * the ground, 1..n_cyl the cylinders, n_cyl+1..n_cyl+n_box the boxes, and
- * CP_OBS_SDF the signed-distance grid (scene and sphere table order). */
+ * CP_OBS_SDF the signed-distance grid (scene and sphere table order); a
+ * self-collision pair of spheres a < b is recorded as sphere a and obstacle
+ * CP_OBS_SELF + b.  On equal distances the lower sphere wins, then its scene
+ * obstacles in number order, then its self pairs by the other sphere. */
 #define CP_OBS_SDF 0xFFFFu
+#define CP_OBS_SELF 0xFF00u
 
 /*
  * Crane: a serial chain (Sec. 2).  Joint j (0-based) moves frame j+1 relative
@@ -100,6 +104,14 @@ typedef struct {
     const int32_t *sphere_frame; /* [S] */
     const float *sphere_center;  /* [S][3] */
     const float *sphere_radius;  /* [S] > 0 */
+    /* Self-collision (Sec. 3.2 counts it with collision against the scene):
+     * frame pairs (in 0..n_joints, distinct) whose spheres are checked
+     * against each other; d(q) then also takes the minimum over every such
+     * sphere pair of |c_a - c_b| - r_a - r_b.  0 / NULL: the scene only.
+     * Repeated pairs and pairs with a frame that carries no sphere are
+     * ignored. */
+    int32_t n_self_pairs;        /* 0..64 */
+    const int32_t *self_pairs;   /* [n_self_pairs][2] */
 } cp_robot_desc;
 
 /*
@@ -114,7 +126,7 @@ typedef struct {
 typedef struct {
     int32_t has_ground;
     float ground_z;
-    int32_t n_cyl;               /* 0..65533 together with n_box */
+    int32_t n_cyl;               /* 0..65279 together with n_box */
     const float *cyl;            /* [n_cyl][5] */
     int32_t n_box;
     const float *box;            /* [n_box][6] */

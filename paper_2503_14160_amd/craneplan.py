@@ -49,7 +49,7 @@ class CranePlanError(RuntimeError):
 class _Robot(ctypes.Structure):
     _fields_ = [("n_joints", _c_i32), ("type", _vp), ("axis", _vp), ("origin", _vp), ("q_min", _vp),
                 ("q_max", _vp), ("q_hold", _vp), ("active", _vp), ("n_spheres", _c_i32), ("sphere_frame", _vp),
-                ("sphere_center", _vp), ("sphere_radius", _vp)]
+                ("sphere_center", _vp), ("sphere_radius", _vp), ("n_self_pairs", _c_i32), ("self_pairs", _vp)]
 
 
 class _Scene(ctypes.Structure):
@@ -162,6 +162,9 @@ def _fill_robot(r, robot, keep):
     r.sphere_frame = _keep_ptr(keep, robot.sphere_frame, np.int32)
     r.sphere_center = _keep_ptr(keep, robot.sphere_center, np.float32)
     r.sphere_radius = _keep_ptr(keep, robot.sphere_radius, np.float32)
+    pairs = _host(getattr(robot, "self_pairs", np.zeros((0, 2))), np.int32).reshape(-1, 2)
+    r.n_self_pairs = int(pairs.shape[0])
+    r.self_pairs = _keep_ptr(keep, pairs, np.int32) if pairs.size else None
 
 
 def _fill_scene(s, scene, keep, sdf=None, sdf_spec=None):

@@ -125,6 +125,8 @@ struct cp_plan {
     int32_t *d_cell_start = nullptr;
     int32_t *d_hint = nullptr;
     GroupDev *d_groups = nullptr;
+    int2 *d_self_pairs = nullptr;
+    float4 *d_frame_bound = nullptr;
     int32_t *d_angle_start = nullptr;
     float4 *d_cyl_orig = nullptr;
     float4 *d_box = nullptr;
@@ -137,7 +139,8 @@ struct cp_plan {
     ~cp_plan() {
         DeviceGuard g(device);
         void *bufs[] = {d_joints, d_spheres, d_sphere_slot, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_hint, d_groups,
-                        d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial, d_sdf_lb, d_clr};
+                        d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial, d_sdf_lb, d_clr,
+                        d_self_pairs, d_frame_bound};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
     }
@@ -220,7 +223,16 @@ static int validate_plan_args(const cp_robot_desc *r, const cp_scene_desc *s, co
         if (r->sphere_frame[i] < 0 || r->sphere_frame[i] > r->n_joints) return fail(CP_ERR_INVALID_ARG, "bad sphere frame");
         if (!(r->sphere_radius[i] > 0.0f) || !finite(r->sphere_radius[i])) return fail(CP_ERR_INVALID_ARG, "bad sphere radius");
     }
-    if (s->n_cyl < 0 || s->n_box < 0 || s->n_cyl + s->n_box > 65533) return fail(CP_ERR_SIZE, "obstacle count out of range");
+    if (r->n_self_pairs < 0 || r->n_self_pairs > 64) return fail(CP_ERR_SIZE, "n_self_pairs out of range (0..64)");
+    if (r->n_self_pairs > 0 && !r->self_pairs) return fail(CP_ERR_INVALID_ARG, "null self_pairs");
+    for (int i = 0; i < r->n_self_pairs; ++i) {
+        const int a = r->self_pairs[2 * i], b = r->self_pairs[2 * i + 1];
+        if (a < 0 || a > r->n_joints || b < 0 || b > r->n_joints || a == b)
+            return fail(CP_ERR_INVALID_ARG, "bad self-collision frame pair");
+    }
+    // obstacle numbers stay below CP_OBS_SELF
+    if (s->n_cyl < 0 || s->n_box < 0 || s->n_cyl + s->n_box > (int)CP_OBS_SELF - 1)
+        return fail(CP_ERR_SIZE, "obstacle count out of range");
     if ((s->n_cyl > 0 && !s->cyl) || (s->n_box > 0 && !s->box)) return fail(CP_ERR_INVALID_ARG, "null obstacle table");
     for (int o = 0; o < s->n_cyl; ++o) {
         const float *y = s->cyl + 5 * o;
@@ -460,6 +472,37 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         box.push_back(make_float4(y[0], y[1], y[2], y[3]));
         box.push_back(make_float4(y[4], y[5], 0.0f, 0.0f));
     }
+    // self-collision: frame pairs (fa < fb) with spheres on both, sorted and
+    // unique; per frame the bounding sphere of its spheres (centre of their
+    // box, radius rounded up)
+    std::vector<int2> self_pairs;
+    for (int i = 0; i < robot->n_self_pairs; ++i) {
+        const int a = std::min(robot->self_pairs[2 * i], robot->self_pairs[2 * i + 1]);
+        const int b = std::max(robot->self_pairs[2 * i], robot->self_pairs[2 * i + 1]);
+        if (frame_start[a + 1] == frame_start[a] || frame_start[b + 1] == frame_start[b]) continue;
+        self_pairs.push_back(make_int2(a, b));
+    }
+    std::sort(self_pairs.begin(), self_pairs.end(),
+              [](const int2 &u, const int2 &w) { return u.x != w.x ? u.x < w.x : u.y < w.y; });
+    self_pairs.erase(std::unique(self_pairs.begin(), self_pairs.end(),
+                                 [](const int2 &u, const int2 &w) { return u.x == w.x && u.y == w.y; }),
+                     self_pairs.end());
+    std::vector<float4> frame_bound(p->n + 1, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+    for (int f = 0; f <= p->n; ++f) {
+        if (frame_start[f + 1] == frame_start[f]) continue;
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int k = frame_start[f]; k < frame_start[f + 1]; ++k) {
+            const double l[3] = {spheres[k].lx, spheres[k].ly, spheres[k].lz};
+            for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], l[a]); hi[a] = std::max(hi[a], l[a]); }
+        }
+        const double c[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+        double rad = 0.0;
+        for (int k = frame_start[f]; k < frame_start[f + 1]; ++k) {
+            const double dx = spheres[k].lx - c[0], dy = spheres[k].ly - c[1], dz = spheres[k].lz - c[2];
+            rad = std::max(rad, std::sqrt(dx * dx + dy * dy + dz * dz) + (double)spheres[k].r);
+        }
+        frame_bound[f] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)(rad * (1.0 + 1e-6) + 1e-6));
+    }
     std::vector<float> hold(robot->q_hold, robot->q_hold + p->n);
     hipError_t e;
     if ((e = upload(&p->d_joints, p->joints)) != hipSuccess || (e = upload(&p->d_spheres, spheres)) != hipSuccess ||
@@ -470,6 +513,8 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         (e = upload(&p->d_groups, groups)) != hipSuccess || (e = upload(&p->d_angle_start, angle_start)) != hipSuccess ||
         (e = upload(&p->d_cyl_orig, cyl_orig)) != hipSuccess ||
         (e = upload(&p->d_box, box)) != hipSuccess || (e = upload(&p->d_qs, hold)) != hipSuccess ||
+        (e = upload(&p->d_self_pairs, self_pairs)) != hipSuccess ||
+        (e = upload(&p->d_frame_bound, frame_bound)) != hipSuccess ||
         (e = upload(&p->d_qg, hold)) != hipSuccess)
         return bail(hip_fail(e, "plan tables"));
     e = hipMalloc((void **)&p->d_partial, eval_partial_count(p->max_B, p->ns) * sizeof(double2));
@@ -495,6 +540,9 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     v.hint = p->d_hint;
     v.pair_filter = pair_filter;
     v.qs = p->d_qs; v.qg = p->d_qg;
+    v.n_self = (int)self_pairs.size();
+    v.self_pairs = p->d_self_pairs;
+    v.frame_bound = p->d_frame_bound;
     v.sdf = scene->d_sdf;
     for (int a = 0; a < 3; ++a) {
         v.sdf_n[a] = scene->d_sdf ? scene->sdf_dims[a] : 2;

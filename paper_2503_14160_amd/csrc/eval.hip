@@ -317,7 +317,18 @@ struct Best {
     float r;         // its radius
     float v;         // its minimum signed distance over the obstacles (d = v - r)
     float cx, cy, cz;
+    int sb;          // a self-collision pair (s, sb), s < sb; -1: a scene obstacle
 };
+
+// Pair order on equal distances: the lower sphere, then (for the same
+// sphere) its scene obstacles before its self pairs, self pairs by the other
+// sphere.  Candidate (d, s, sb) (sb = -1: a scene obstacle) beats `best`?
+__device__ __forceinline__ bool pair_before(float d, int s, int sb, const Best &best) {
+    if (d != best.d) return d < best.d;
+    if (s != best.s) return s < best.s;
+    if (sb < 0) return best.sb >= 0;
+    return best.sb >= 0 && sb < best.sb;
+}
 
 // How the lanes of a wave split into paths for the wave-level culling: n
 // segments (1 or 2) and this lane's segment (-1: result unused).
@@ -382,12 +393,69 @@ __device__ __forceinline__ void sphere_group(const PlanView &P, const Xf &T, int
         }
         float d = v[i] - sp.r;
         if (ARG) {
-            if (d < best.d || (d == best.d && sp.orig < best.s)) {
+            if (pair_before(d, sp.orig, -1, best)) {
                 best.d = d; best.s = sp.orig; best.r = sp.r; best.v = v[i];
-                best.cx = cx[i]; best.cy = cy[i]; best.cz = cz[i];
+                best.cx = cx[i]; best.cy = cy[i]; best.cz = cz[i]; best.sb = -1;
             }
         } else {
             best.d = fminf(best.d, d);
+        }
+    }
+}
+
+// Self-collision (Sec. 3.2 names it beside collision with the scene): the
+// minimum over every sphere pair of the listed frame pairs of
+// |c_a - c_b| - r_a - r_b, taken after the scene.  Frame pairs come sorted by
+// (fa, fb), fa < fb: the chain runs once from the base to each fa and on
+// from there to its fb's.  Outside CP_PAIRS_ALL a frame pair is skipped when
+// on every lane a lower bound of all its sphere pairs (the distance between
+// the frames' bounding spheres, less a rounding slack far above FP32 error)
+// lies strictly above the lane's running minimum: such pairs cannot lower or
+// tie it, so results are bitwise those of taking every pair.
+template <bool ARG>
+__device__ __forceinline__ void self_min(const PlanView &P, const float (&q)[CP_MAX_JOINTS], Best &best, WaveSeg ws) {
+    int i = 0;
+    while (i < P.n_self) {
+        const int fa = ldg(P.self_pairs, i).x;
+        Xf Ta;
+        xf_identity(Ta);
+        for (int j = 0; j < fa; ++j) xf_joint(Ta, ldg(P.joints, j), pick(q, j));
+        Xf T = Ta;
+        int cur = fa;
+        for (; i < P.n_self && ldg(P.self_pairs, i).x == fa; ++i) {
+            const int fb = ldg(P.self_pairs, i).y;
+            for (; cur < fb; ++cur) xf_joint(T, ldg(P.joints, cur), pick(q, cur));
+            if (P.pair_filter != CP_PAIRS_ALL) {
+                const float4 ba = ldg(P.frame_bound, fa), bb = ldg(P.frame_bound, fb);
+                float ax, ay, az, bx, by, bz;
+                xf_point(Ta, ba.x, ba.y, ba.z, ax, ay, az);
+                xf_point(T, bb.x, bb.y, bb.z, bx, by, bz);
+                const float dx = ax - bx, dy = ay - by, dz = az - bz;
+                const float lb = fsqrt(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) - ba.w - bb.w -
+                                 (1e-3f + 1e-5f * (fabsf(ax) + fabsf(ay) + fabsf(az) + fabsf(bx) + fabsf(by) + fabsf(bz)));
+                if (__builtin_amdgcn_ballot_w64(ws.lane >= 0 && !(lb > best.d)) == 0) continue;
+            }
+            const int a1 = ldg(P.frame_start, fa + 1), b0 = ldg(P.frame_start, fb), b1 = ldg(P.frame_start, fb + 1);
+            for (int sa = ldg(P.frame_start, fa); sa < a1; ++sa) {
+                const SphereDev pa = ldg(P.spheres, sa);
+                float cx, cy, cz;
+                xf_point(Ta, pa.lx, pa.ly, pa.lz, cx, cy, cz);
+                for (int sb = b0; sb < b1; ++sb) {
+                    const SphereDev pb = ldg(P.spheres, sb);
+                    float ex, ey, ez;
+                    xf_point(T, pb.lx, pb.ly, pb.lz, ex, ey, ez);
+                    const float dx = cx - ex, dy = cy - ey, dz = cz - ez;
+                    const float d = fsqrt(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) - pa.r - pb.r;
+                    if (ARG) {
+                        const int lo = min(pa.orig, pb.orig), hi = max(pa.orig, pb.orig);
+                        if (pair_before(d, lo, hi, best)) {
+                            best.d = d; best.s = lo; best.sb = hi;
+                        }
+                    } else {
+                        best.d = fminf(best.d, d);
+                    }
+                }
+            }
         }
     }
 }
@@ -401,6 +469,7 @@ __device__ __forceinline__ Best config_distance(const PlanView &P, const float (
     Best best;
     best.d = kInf; best.s = 0x7fffffff; best.r = 0.0f; best.v = kInf;
     best.cx = best.cy = best.cz = 0.0f;
+    best.sb = -1;
     Xf T;
     xf_identity(T);
     int gi = 0;
@@ -430,6 +499,7 @@ __device__ __forceinline__ Best config_distance(const PlanView &P, const float (
             }
         }
     }
+    if (P.n_self > 0 && part == 0) self_min<ARG>(P, q, best, ws);
     return best;
 }
 
@@ -507,6 +577,7 @@ __device__ __forceinline__ uint32_t argmin_obstacle_near(const PlanView &P, floa
 // non-finite centre or minimum takes the rescan.
 template <bool CULL>
 __device__ __forceinline__ uint32_t argmin_of(const PlanView &P, const Best &best) {
+    if (best.sb >= 0) return CP_OBS_SELF + (uint32_t)best.sb;
     if (P.sdf && P.n_cyl == 0 && P.n_box == 0 && fabsf(best.cz) < kInf && fabsf(best.v) < kInf) {
         if (P.has_ground && best.cz - P.ground_z == best.v) return 0;
         return best.v < kInf ? CP_OBS_SDF : 0u;
@@ -556,7 +627,7 @@ __device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[C
 // Per-lane minima of the waves of a workgroup (up to 8), for merging split parts.
 struct MergeBuf {
     float d[8][kWave], r[8][kWave], v[8][kWave], cx[8][kWave], cy[8][kWave], cz[8][kWave];
-    int s[8][kWave];
+    int s[8][kWave], sb[8][kWave];
 };
 
 // One configuration per lane: g is the flattened (path, checkpoint) index;
@@ -597,7 +668,7 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
         if (part != 0) {
             mb->d[wv][ln] = best.d;
             if (TAPE) {
-                mb->s[wv][ln] = best.s; mb->r[wv][ln] = best.r; mb->v[wv][ln] = best.v;
+                mb->s[wv][ln] = best.s; mb->r[wv][ln] = best.r; mb->v[wv][ln] = best.v; mb->sb[wv][ln] = best.sb;
                 mb->cx[wv][ln] = best.cx; mb->cy[wv][ln] = best.cy; mb->cz[wv][ln] = best.cz;
             }
         }
@@ -606,9 +677,9 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
         for (int u = 1; u < split; ++u) {
             const float d = mb->d[wv + u][ln];
             if (TAPE) {
-                const int so = mb->s[wv + u][ln];
-                if (d < best.d || (d == best.d && so < best.s)) {
-                    best.d = d; best.s = so; best.r = mb->r[wv + u][ln]; best.v = mb->v[wv + u][ln];
+                const int so = mb->s[wv + u][ln], sbo = mb->sb[wv + u][ln];
+                if (pair_before(d, so, sbo, best)) {
+                    best.d = d; best.s = so; best.sb = sbo; best.r = mb->r[wv + u][ln]; best.v = mb->v[wv + u][ln];
                     best.cx = mb->cx[wv + u][ln]; best.cy = mb->cy[wv + u][ln]; best.cz = mb->cz[wv + u][ln];
                 }
             } else {
@@ -763,17 +834,24 @@ __device__ __forceinline__ float obstacle_sd_grad(const PlanView &P, uint32_t o,
 }
 
 // d cost_k / d q for the collision term through the tape's pair (s, o):
-// recomputes the chain, the sphere centre and the pair's signed distance.
+// recomputes the chain, the sphere centre and the pair's signed distance.  A
+// self-collision pair (o = CP_OBS_SELF + b) differentiates
+// |c_s - c_b| - r_s - r_b through both spheres' chains.
 __device__ __forceinline__ void collision_grad(const PlanView &P, const float (&q)[CP_MAX_JOINTS], int s_orig,
                                                uint32_t o, float (&gq)[CP_MAX_JOINTS]) {
-    // locate the sphere (table sorted by frame; `orig` is the caller's index)
+    const bool self = o >= CP_OBS_SELF && o < CP_OBS_SDF;
+    const int b_orig = self ? (int)(o - CP_OBS_SELF) : 0;
+    // locate the spheres (table sorted by frame; `orig` is the caller's index)
     const int si = (s_orig >= 0 && s_orig < P.n_spheres) ? ldg(P.sphere_slot, s_orig) : 0;
+    const int bi = (self && b_orig < P.n_spheres) ? ldg(P.sphere_slot, b_orig) : 0;
     const SphereDev sp = ldg(P.spheres, si);
+    const SphereDev sq = ldg(P.spheres, bi);
     float aw[CP_MAX_JOINTS][3], pj[CP_MAX_JOINTS][3];
-    float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+    float cx = 0.0f, cy = 0.0f, cz = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
     Xf T;
     xf_identity(T);
     if (sp.frame == 0) xf_point(T, sp.lx, sp.ly, sp.lz, cx, cy, cz);
+    if (sq.frame == 0) xf_point(T, sq.lx, sq.ly, sq.lz, ex, ey, ez);
 #pragma unroll
     for (int f = 1; f <= CP_MAX_JOINTS; ++f) {
         if (f <= P.n_joints) {
@@ -785,28 +863,53 @@ __device__ __forceinline__ void collision_grad(const PlanView &P, const float (&
             xf_joint(T, J, q[f - 1]);
             pj[f - 1][0] = T.p[0]; pj[f - 1][1] = T.p[1]; pj[f - 1][2] = T.p[2];
             if (sp.frame == f) xf_point(T, sp.lx, sp.ly, sp.lz, cx, cy, cz);
+            if (sq.frame == f) xf_point(T, sq.lx, sq.ly, sq.lz, ex, ey, ez);
         }
     }
-    // a tape entry that names no obstacle of this plan contributes nothing
-    const bool valid = (o == CP_OBS_SDF) ? (P.sdf != nullptr)
-                                          : (o == 0 ? P.has_ground != 0 : (int)o <= P.n_cyl + P.n_box);
+    // a tape entry that names no pair of this plan contributes nothing
+    const bool valid = self ? (P.n_self > 0 && b_orig < P.n_spheres)
+                            : (o == CP_OBS_SDF) ? (P.sdf != nullptr)
+                                                : (o == 0 ? P.has_ground != 0 : (int)o <= P.n_cyl + P.n_box);
     if (!valid || s_orig >= P.n_spheres) return;
     float gr[3];
-    float sd = obstacle_sd_grad(P, o, cx, cy, cz, gr);
+    float sd;
+    if (self) {
+        // gradient of |c_s - c_b| with respect to c_s (minus it for c_b)
+        const float dx = cx - ex, dy = cy - ey, dz = cz - ez;
+        const float len = fsqrt(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+        const float inv = len > 0.0f ? 1.0f / len : 0.0f;
+        gr[0] = dx * inv; gr[1] = dy * inv; gr[2] = dz * inv;
+        sd = len - sq.r;
+    } else {
+        sd = obstacle_sd_grad(P, o, cx, cy, cz, gr);
+    }
     float dphi;
     hinge_value(P, sd - sp.r, dphi);
     float scale = P.w_c * dphi;
 #pragma unroll
     for (int jj = 0; jj < CP_MAX_JOINTS; ++jj) {
-        if (jj < P.n_joints && jj < sp.frame && scale != 0.0f) {
-            float jx, jy, jz;
-            if (P.joints[jj].type == CP_REVOLUTE) {
-                float rx = cx - pj[jj][0], ry = cy - pj[jj][1], rz = cz - pj[jj][2];
-                jx = aw[jj][1] * rz - aw[jj][2] * ry;
-                jy = aw[jj][2] * rx - aw[jj][0] * rz;
-                jz = aw[jj][0] * ry - aw[jj][1] * rx;
-            } else {
-                jx = aw[jj][0]; jy = aw[jj][1]; jz = aw[jj][2];
+        if (jj < P.n_joints && scale != 0.0f && (jj < sp.frame || (self && jj < sq.frame))) {
+            const bool rev = P.joints[jj].type == CP_REVOLUTE;
+            float jx = 0.0f, jy = 0.0f, jz = 0.0f;
+            if (jj < sp.frame) {
+                if (rev) {
+                    float rx = cx - pj[jj][0], ry = cy - pj[jj][1], rz = cz - pj[jj][2];
+                    jx = aw[jj][1] * rz - aw[jj][2] * ry;
+                    jy = aw[jj][2] * rx - aw[jj][0] * rz;
+                    jz = aw[jj][0] * ry - aw[jj][1] * rx;
+                } else {
+                    jx = aw[jj][0]; jy = aw[jj][1]; jz = aw[jj][2];
+                }
+            }
+            if (self && jj < sq.frame) {
+                if (rev) {
+                    float rx = ex - pj[jj][0], ry = ey - pj[jj][1], rz = ez - pj[jj][2];
+                    jx -= aw[jj][1] * rz - aw[jj][2] * ry;
+                    jy -= aw[jj][2] * rx - aw[jj][0] * rz;
+                    jz -= aw[jj][0] * ry - aw[jj][1] * rx;
+                } else {
+                    jx -= aw[jj][0]; jy -= aw[jj][1]; jz -= aw[jj][2];
+                }
             }
             gq[jj] += scale * __builtin_fmaf(gr[0], jx, __builtin_fmaf(gr[1], jy, gr[2] * jz));
         }
@@ -995,7 +1098,7 @@ __global__ __launch_bounds__(256) void k_debug_configs(PlanView P, const float *
     ws.n = 1;
     ws.lane = 0;
     Best best = config_distance<true, CULL>(P, q, ws);
-    uint32_t o = argmin_obstacle(P, best.cx, best.cy, best.cz);
+    uint32_t o = best.sb >= 0 ? CP_OBS_SELF + (uint32_t)best.sb : argmin_obstacle(P, best.cx, best.cy, best.cz);
     if (i < N) {
         dist[i] = best.d;
         if (arg) arg[i] = ((uint32_t)best.s << 16) | o;

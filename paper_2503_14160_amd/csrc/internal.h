@@ -95,6 +95,11 @@ struct PlanView {
     float clr_x0, clr_y0, clr_h, clr_inv;
     int32_t clr_nx, clr_ny;
     int32_t lead_frame;           // with clr: frame taken first (1..n), or -1
+    // self-collision: frame pairs (fa, fb), fa < fb, sorted, both with
+    // spheres; per frame a bounding sphere of its spheres (local centre, radius)
+    int32_t n_self;
+    const int2 *self_pairs;
+    const float4 *frame_bound;    // [n_joints + 1]
 };
 
 // ---------------------------------------------------------------------------
