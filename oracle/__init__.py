@@ -5,10 +5,11 @@ CPU-baseline leg are the only users.  The product path (the HIP library and its
 binding) never imports this package, and this package imports nothing of the
 product except the seeded input generator.
 
-The heavy loops (kinematics, distances, spline, cost, gradient, Philox, EDT)
-are in ``oracle.c``; the optimizer of Algorithm 1 (sampling, selection,
-log-rank weights, mean and covariance update) is written out here with numpy,
-step by step in the paper's order.
+The heavy loops (kinematics, distances, spline, cost, gradient, Philox, EDT,
+the IK residual and its Jacobian) are in ``oracle.c``; the optimizer of
+Algorithm 1 (sampling, selection, log-rank weights, mean and covariance
+update) and the Levenberg-Marquardt loop of the collision-free IK (Sec. 3.2)
+are written out here with numpy, step by step.
 
 Readings of the paper taken here (each is also listed in the design notes):
 * the spline keeps the paper's four copies of the start and goal control
@@ -104,6 +105,9 @@ def lib():
         L.orc_edt_brute.argtypes = [vp, ctypes.c_uint8, vp, vp]
         L.orc_edt_separable.argtypes = [vp, ctypes.c_uint8, vp, vp]
         L.orc_sdf_from_edt.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.c_float, vp]
+        L.orc_so3_log.argtypes = [vp, vp]
+        L.orc_so3_jr_inv.argtypes = [vp, vp]
+        L.orc_ik_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -295,6 +299,105 @@ def fd_grad(model: Model, q_start, q_goal, W, h: float = 1e-6):
             g[:, i, j] = (cp - cm) / (2.0 * h)
     return g
 
+
+
+# ----------------------------------------------------------------------------
+# collision-free inverse kinematics (Sec. 3.2, eq. IK opt)
+# ----------------------------------------------------------------------------
+
+def so3_log(R):
+    """Rotation vector w (|w| in [0, pi]) of the rotation matrix R [3,3]."""
+    R = np.ascontiguousarray(R, np.float64)
+    w = np.zeros(3)
+    lib().orc_so3_log(_p(R), _p(w))
+    return w
+
+
+def so3_jr_inv(w):
+    """Inverse right Jacobian of SO(3) at the rotation vector w [3] -> [3,3]."""
+    w = np.ascontiguousarray(w, np.float64)
+    J = np.zeros((3, 3))
+    lib().orc_so3_jr_inv(_p(w), _p(J))
+    return J
+
+
+def ik_weights(par) -> np.ndarray:
+    return np.array([par.lambda_q, par.lambda_c, par.lambda_e, par.lambda_r], np.float64)
+
+
+def ik_residual(model: Model, par, target, q, q_ref, jacobian: bool = True):
+    """Residual r [8+n] of the IK problem at q, its Jacobian [8+n, n] (or
+    None) and info = (|p_g - p_d|, |Log(R_d^T R_g)|, d(q), |g_p|, argmin
+    sphere, argmin obstacle).  ``target`` is R_d row-major then p_d [12]."""
+    n = model.robot.n_joints
+    lam = ik_weights(par)
+    t = np.ascontiguousarray(target, np.float64)
+    q = np.ascontiguousarray(q, np.float64)
+    qr = np.ascontiguousarray(q_ref, np.float64)
+    r = np.zeros(8 + n)
+    J = np.zeros((8 + n, n)) if jacobian else None
+    info = np.zeros(6)
+    lib().orc_ik_residual(model.pr, model.ps, _p(lam), _p(t), _p(q), _p(qr), _p(r), _p(J), _p(info))
+    return r, J, info
+
+
+def ik_solve(model: Model, par, target, q_init, q_ref, trace: Optional[list] = None):
+    """Levenberg-Marquardt on F(q) = |r(q)|^2 / 2 (eq. IK opt), with the
+    damping schedule of Madsen, Nielsen and Tingleff ("Methods for non-linear
+    least squares problems", 2004, Sec. 3.2): mu_0 = tau max diag(J^T J);
+    each iteration solves (J^T J + mu I) h = -J^T r, takes q' = q + h (clamped
+    to the joint limits if ``par.clamp``), and accepts it when the gain ratio
+    rho = (F(q) - F(q')) / (L(0) - L(q' - q)) is positive, with
+    L(0) - L(s) = -s.g - s.A s / 2 the decrease predicted by the linear model;
+    then mu *= max(1/3, 1 - (2 rho - 1)^3), nu = 2, else mu *= nu, nu *= 2.
+    Stops when max |J^T r| <= eps_grad (status 1), when
+    |h| <= eps_step (|q| + eps_step) (status 2), or after max_iters trial
+    steps (status 0).  Returns (q, F, info, iterations, status); with
+    ``trace`` the accepted iterates (q, F) are appended to it."""
+    lo = np.asarray(model.robot.q_min, np.float64)
+    hi = np.asarray(model.robot.q_max, np.float64)
+    q = np.array(q_init, np.float64)
+    if par.clamp:
+        q = np.clip(q, lo, hi)
+    r, J, info = ik_residual(model, par, target, q, q_ref)
+    F = 0.5 * float(r @ r)
+    A = J.T @ J
+    g = J.T @ r
+    mu = par.tau * float(np.max(np.diag(A)))
+    nu = 2.0
+    it = 0
+    status = 0
+    if trace is not None:
+        trace.append((q.copy(), F))
+    while it < par.max_iters:
+        if float(np.max(np.abs(g))) <= par.eps_grad:
+            status = 1
+            break
+        h = np.linalg.solve(A + mu * np.eye(A.shape[0]), -g)
+        if float(np.linalg.norm(h)) <= par.eps_step * (float(np.linalg.norm(q)) + par.eps_step):
+            status = 2
+            break
+        qn = q + h
+        if par.clamp:
+            qn = np.clip(qn, lo, hi)
+        s = qn - q
+        rn, Jn, infon = ik_residual(model, par, target, qn, q_ref)
+        Fn = 0.5 * float(rn @ rn)
+        pred = -float(s @ g) - 0.5 * float(s @ A @ s)
+        it += 1
+        if pred > 0.0 and F - Fn > 0.0:
+            rho = (F - Fn) / pred
+            q, r, J, info, F = qn, rn, Jn, infon, Fn
+            A = J.T @ J
+            g = J.T @ r
+            mu *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+            nu = 2.0
+            if trace is not None:
+                trace.append((q.copy(), F))
+        else:
+            mu *= nu
+            nu *= 2.0
+    return q, F, info, it, status
 
 # ----------------------------------------------------------------------------
 # RNG

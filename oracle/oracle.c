@@ -613,6 +613,176 @@ void orc_eval_configs(const orc_robot *rb, const orc_scene *sc, const double *q,
 }
 
 /* ------------------------------------------------------------------------ */
+/* collision-free inverse kinematics (Sec. 3.2, eq. IK opt)                  */
+/* ------------------------------------------------------------------------ */
+
+static void cross3(const double a[3], const double b[3], double out[3]) {
+    double x = a[1] * b[2] - a[2] * b[1];
+    double y = a[2] * b[0] - a[0] * b[2];
+    double z = a[0] * b[1] - a[1] * b[0];
+    out[0] = x; out[1] = y; out[2] = z;
+}
+
+/* Logarithm of SO(3): the rotation vector w = theta n (theta in [0, pi]) of
+ * the rotation R (row-major).  With v = vee(R - R^T) = 2 sin(theta) n and
+ * cos(theta) = (tr R - 1) / 2, theta = atan2(|v| / 2, cos theta); the axis is
+ * v / |v|, except close to theta = pi, where v vanishes and the axis comes
+ * from the symmetric part (R + R^T) / 2 - cos(theta) I = (1 - cos theta) n n^T
+ * (its largest diagonal entry, sign taken so that n . v >= 0). */
+void orc_so3_log(const double *R, double *w) {
+    double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
+    double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    double th = atan2(0.5 * vn, c);
+    if (c > -0.9) {
+        for (int i = 0; i < 3; ++i) w[i] = vn > 0.0 ? th * v[i] / vn : 0.0;
+        return;
+    }
+    double S[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S[3 * i + j] = 0.5 * (R[3 * i + j] + R[3 * j + i]) - (i == j ? c : 0.0);
+    int k = 0;
+    for (int i = 1; i < 3; ++i)
+        if (S[4 * i] > S[4 * k]) k = i;
+    double n[3];
+    double nk = sqrt(S[4 * k] / (1.0 - c));
+    for (int i = 0; i < 3; ++i) n[i] = i == k ? nk : S[3 * k + i] / ((1.0 - c) * nk);
+    double dot = n[0] * v[0] + n[1] * v[1] + n[2] * v[2];
+    double sg = dot < 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < 3; ++i) w[i] = sg * th * n[i];
+}
+
+/* Inverse of the right Jacobian of SO(3) at w: the derivative of
+ * Log(Exp(w) Exp(e)) with respect to e at e = 0,
+ *   J_r^-1(w) = I + [w]/2 + (1/theta^2 - (1 + cos theta) / (2 theta sin theta)) [w]^2,
+ * the last coefficient by its series 1/12 + theta^2/720 + theta^4/30240 for
+ * small theta (cancellation). */
+void orc_so3_jr_inv(const double w[3], double *Ji) {
+    double t2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double th = sqrt(t2);
+    double k;
+    if (th < 1e-2)
+        k = 1.0 / 12.0 + t2 / 720.0 + t2 * t2 / 30240.0;
+    else
+        k = 1.0 / t2 - (1.0 + cos(th)) / (2.0 * th * sin(th));
+    double W[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int l = 0; l < 3; ++l) s += W[3 * i + l] * W[3 * l + j];
+            Ji[3 * i + j] = (i == j ? 1.0 : 0.0) + 0.5 * W[3 * i + j] + k * s;
+        }
+}
+
+/* d^2 p / dq_i dq_j of a point p rigidly attached to the last frame: with
+ * u = min(i, j), v = max(i, j), world axes a and pivots o (origin of the
+ * frame each joint moves),
+ *   v revolute:  a_u x (a_v x (p - o_v)) if u is revolute, 0 if prismatic;
+ *   v prismatic: a_u x a_v if u < v is revolute, 0 otherwise. */
+static void point_hessian(const orc_robot *rb, const double aw[][3], const double piv[][3], const double p[3],
+                          int i, int j, double out[3]) {
+    int u = i < j ? i : j, v = i < j ? j : i;
+    out[0] = out[1] = out[2] = 0.0;
+    if (rb->type[v] == ORC_REVOLUTE) {
+        if (rb->type[u] != ORC_REVOLUTE) return;
+        double r[3] = {p[0] - piv[v][0], p[1] - piv[v][1], p[2] - piv[v][2]}, t[3];
+        cross3(aw[v], r, t);
+        cross3(aw[u], t, out);
+    } else {
+        if (u == v || rb->type[u] != ORC_REVOLUTE) return;
+        cross3(aw[u], aw[v], out);
+    }
+}
+
+/*
+ * Residual of the IK problem at q and its Jacobian (Sec. 3.2):
+ *   r[0..2] = p_g - p_d                       (position of the tip point)
+ *   r[3..5] = lambda_q Log(R_d^T R_g)         (orientation of the last frame)
+ *   r[6]    = lambda_c ReLU(-d(q))            (collision, scene and self)
+ *   r[7]    = lambda_e |g_p|^2                (equilibrium of the passive joints)
+ *   r[8..]  = lambda_r (q - q_ref)            (regularisation, n entries)
+ * g_p is the gravitational generalised force on the joints that are not
+ * actuated (active[j] = 0) of a unit weight at the tip: g_p,j = dz_tip/dq_j
+ * (the crane's mass model is not given; the load hangs at the tip).
+ * lam = (lambda_q, lambda_c, lambda_e, lambda_r); target = R_d (row-major)
+ * then p_d.  J [8+n][n] row-major (may be NULL).  info (may be NULL):
+ * |p_g - p_d|, |Log(R_d^T R_g)|, d(q), |g_p|, argmin sphere, argmin obstacle.
+ */
+void orc_ik_residual(const orc_robot *rb, const orc_scene *sc, const double *lam, const double *target,
+                     const double *q, const double *q_ref, double *r, double *J, double *info) {
+    const int n = rb->n_joints, m = 8 + n;
+    xform F[ORC_MAXJ + 1];
+    fk_frames(rb, q, F);
+    double tl[3] = {rb->tip[0], rb->tip[1], rb->tip[2]}, p[3];
+    xf_apply(&F[n], tl, p);
+    double aw[ORC_MAXJ][3], piv[ORC_MAXJ][3], dp[ORC_MAXJ][3];
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < 3; ++i)
+            aw[j][i] = F[j].R[3 * i] * rb->axis[3 * j] + F[j].R[3 * i + 1] * rb->axis[3 * j + 1] +
+                       F[j].R[3 * i + 2] * rb->axis[3 * j + 2];
+        for (int i = 0; i < 3; ++i) piv[j][i] = F[j + 1].p[i];
+        point_jacobian_col(rb, F, j, p, dp[j]);
+    }
+    /* position */
+    for (int i = 0; i < 3; ++i) r[i] = p[i] - target[9 + i];
+    /* orientation: E = R_d^T R_g */
+    double E[9], w[3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int l = 0; l < 3; ++l) s += target[3 * l + i] * F[n].R[3 * l + j];
+            E[3 * i + j] = s;
+        }
+    orc_so3_log(E, w);
+    for (int i = 0; i < 3; ++i) r[3 + i] = lam[0] * w[i];
+    /* collision */
+    int32_t as, ao;
+    double d = orc_config_distance(rb, sc, q, &as, &ao, NULL);
+    r[6] = d < 0.0 ? lam[1] * (-d) : 0.0;
+    /* equilibrium of the passive joints */
+    double gp2 = 0.0;
+    for (int j = 0; j < n; ++j)
+        if (!rb->active[j]) gp2 += dp[j][2] * dp[j][2];
+    r[7] = lam[2] * gp2;
+    for (int j = 0; j < n; ++j) r[8 + j] = lam[3] * (q[j] - q_ref[j]);
+    if (info) {
+        info[0] = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        info[1] = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        info[2] = d;
+        info[3] = sqrt(gp2);
+        info[4] = as;
+        info[5] = ao;
+    }
+    if (!J) return;
+    for (int k = 0; k < m * n; ++k) J[k] = 0.0;
+    double Ji[9];
+    orc_so3_jr_inv(w, Ji);
+    double gd[ORC_MAXJ];
+    if (d < 0.0) distance_grad_q(rb, sc, q, as, ao, gd);
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < 3; ++i) J[i * n + j] = dp[j][i];
+        if (rb->type[j] == ORC_REVOLUTE) {
+            /* rotating about the world axis a_j is R_g -> R_g Exp(dq R_g^T a_j) */
+            double b[3];
+            for (int i = 0; i < 3; ++i)
+                b[i] = F[n].R[i] * aw[j][0] + F[n].R[3 + i] * aw[j][1] + F[n].R[6 + i] * aw[j][2];
+            for (int i = 0; i < 3; ++i)
+                J[(3 + i) * n + j] = lam[0] * (Ji[3 * i] * b[0] + Ji[3 * i + 1] * b[1] + Ji[3 * i + 2] * b[2]);
+        }
+        if (d < 0.0) J[6 * n + j] = -lam[1] * gd[j];
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) {
+            if (rb->active[k]) continue;
+            double h[3];
+            point_hessian(rb, aw, piv, p, k, j, h);
+            s += dp[k][2] * h[2];
+        }
+        J[7 * n + j] = 2.0 * lam[2] * s;
+        J[(8 + j) * n + j] = lam[3];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as   */
 /* easy as 1, 2, 3", SC'11) and Box-Muller normals                           */
 /* ------------------------------------------------------------------------ */

@@ -146,6 +146,43 @@ class OptParams:
 
 
 @dataclasses.dataclass
+class IkParams:
+    """Weights and solver settings of the collision-free IK (Sec. 3.2): the
+    residual is [p_g - p_d, lambda_q Log(R_d^T R_g), lambda_c ReLU(-d(q)),
+    lambda_e |g_p|^2, lambda_r (q - q_ref)], minimised by Levenberg-Marquardt
+    (``max_iters`` trial steps, initial damping ``tau`` max diag(J^T J),
+    stops on max |J^T r| <= eps_grad or |h| <= eps_step (|q| + eps_step);
+    ``clamp`` keeps q within the joint limits)."""
+
+    lambda_q: float = 1.0
+    lambda_c: float = 10.0
+    lambda_e: float = 1.0
+    lambda_r: float = 1e-2
+    max_iters: int = 50
+    tau: float = 1e-3
+    eps_grad: float = 1e-6
+    eps_step: float = 1e-7
+    clamp: int = 1
+
+
+@dataclasses.dataclass
+class IkProblem:
+    """Batched IK: the tip poses of the configurations ``q_star`` [N,n] are the
+    targets; ``q_init`` [N*R,n] holds R starting configurations per target
+    (rows r*... grouped by target: rows i*R .. i*R+R-1 belong to target i);
+    ``q_ref`` [n] is the crane's current configuration (regularisation)."""
+
+    name: str
+    robot: Robot
+    scene: Scene
+    q_star: np.ndarray
+    q_init: np.ndarray
+    q_ref: np.ndarray
+    restarts: int
+    params: IkParams
+
+
+@dataclasses.dataclass
 class Problem:
     name: str
     robot: Robot
@@ -420,6 +457,43 @@ def c4_sdf(n_points: int = 1_000_000) -> Problem:
     opt = OptParams(B=65536, nu=3276, sigma0=0.2, eps=1e-6, seed=RNG_SEED + 4, T=50)
     scene = Scene(cyl=_f32(np.zeros((0, 5))), box=_f32(np.zeros((0, 6))), has_ground=0)
     return Problem("c4_sdf", robot, scene, qs, qg, cost, opt, sdf=C4_SPEC, lidar=lidar)
+
+
+def hanging_configs(rng: np.random.Generator, robot: Robot, N: int) -> np.ndarray:
+    """N crane configurations [N,n] with the grapple hanging at rest: slew
+    U(-pi, pi), boom U(0.2, 1.1) rad, arm pitch relative to the horizon
+    alpha = boom + arm U(-0.4, 0.5) rad, telescope U(0.2, 2.8) m, first swing
+    joint 0 and second swing joint alpha (the hanger then points straight
+    down, where a weight at its end exerts no torque on either swing joint)."""
+    q = np.zeros((N, robot.n_joints), np.float64)
+    q[:, 0] = rng.uniform(-math.pi, math.pi, size=N)
+    q[:, 1] = rng.uniform(0.2, 1.1, size=N)
+    alpha = rng.uniform(-0.4, 0.5, size=N)
+    q[:, 2] = alpha - q[:, 1]
+    q[:, 3] = rng.uniform(0.2, 2.8, size=N)
+    q[:, 4] = 0.0
+    q[:, 5] = alpha
+    return _f32(q)
+
+
+def ik_c1(n_targets: int = 1024, restarts: int = 8) -> IkProblem:
+    """Batched collision-free IK on the c1_full crane (with its non-adjacent
+    link pairs checked for self-collision) and scene: the grasp poses of
+    ``n_targets`` hanging configurations, ``restarts`` starting points each
+    (the crane's start configuration, then configurations uniform within
+    the joint limits with the swing joints at 0)."""
+    base = c1_full()
+    robot = with_self_collision(base.robot)
+    rng = np.random.default_rng(SCENE_SEED + 5)
+    q_star = hanging_configs(rng, robot, n_targets)
+    q_init = np.empty((n_targets, restarts, robot.n_joints), np.float64)
+    q_init[:, 0, :] = base.q_start
+    lo = robot.q_min.astype(np.float64)
+    hi = robot.q_max.astype(np.float64)
+    q_init[:, 1:, :] = rng.uniform(lo, hi, size=(n_targets, restarts - 1, robot.n_joints))
+    q_init[:, 1:, 4:] = 0.0
+    return IkProblem("ik_c1", robot, base.scene, q_star, _f32(q_init.reshape(-1, robot.n_joints)),
+                     _f32(base.q_start), restarts, IkParams())
 
 
 WORKLOADS = {"c0_plain": c0_plain, "c1_full": c1_full, "c2_diff": c2_diff, "c4_sdf": c4_sdf}

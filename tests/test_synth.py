@@ -57,3 +57,16 @@ def test_workload_endpoints_clear_of_self_collision(orc, name):
     d, _, o, _ = orc.eval_configs(m, np.stack([p.q_start, p.q_goal]).astype(np.float64))
     assert np.all(d > 0.0), d
     assert np.all(o >= 0xFF00)
+
+
+def test_ik_workload_layout():
+    p = synth.ik_c1(n_targets=32, restarts=4)
+    n = p.robot.n_joints
+    assert p.q_star.shape == (32, n) and p.q_init.shape == (32 * 4, n)
+    assert p.q_star.dtype == np.float32 and p.q_init.dtype == np.float32
+    lo, hi = p.robot.q_min, p.robot.q_max
+    assert np.all(p.q_init >= lo) and np.all(p.q_init <= hi)
+    assert np.all(p.q_star >= lo) and np.all(p.q_star <= hi)
+    # the first start of every target is the crane's start configuration
+    np.testing.assert_array_equal(p.q_init.reshape(32, 4, n)[:, 0], np.broadcast_to(p.q_ref, (32, n)))
+    assert len(p.robot.self_pairs) > 0
