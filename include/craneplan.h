@@ -112,6 +112,9 @@ typedef struct {
      * ignored. */
     int32_t n_self_pairs;        /* 0..64 */
     const int32_t *self_pairs;   /* [n_self_pairs][2] */
+    /* Tip (grapple centre point) in the last frame: the end-effector point
+     * of the inverse kinematics, H_g = (R of frame n, R tip + p of frame n). */
+    float tip[3];
 } cp_robot_desc;
 
 /*
@@ -384,6 +387,65 @@ int cp_tune(cp_plan *plan, cp_batch *batch, const char *cache_path);
  * allocates nothing and returns without waiting. */
 int cp_sdf_build(const float *d_points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
                  float *d_sdf, uint8_t *d_occ, int32_t *d_edt_occ, int32_t *d_edt_free, cp_stream_t stream);
+
+/*
+ * Collision-free inverse kinematics (Sec. 3.2, eq. IK opt): for each row i,
+ *   q_i = argmin_q |r(q)|^2,  r = [ p_g - p_d,                  (3)
+ *                                   lambda_q Log(R_d^T R_g),    (3, SO(3) log)
+ *                                   lambda_c ReLU(-d(q)),       (1, scene and self)
+ *                                   lambda_e |g_p|^2,           (1)
+ *                                   lambda_r (q - q_ref) ]      (n_joints)
+ * where (R_g, p_g) is the pose of the last frame with p_g its tip point,
+ * d(q) the signed distance of the evaluation, and g_p the gravitational
+ * generalised force that a unit weight at the tip exerts on the joints that
+ * are not actuated (active[j] = 0): g_p,j = d z_tip / d q_j, zero when the
+ * load hangs at rest.  Solved by Levenberg-Marquardt with the gain-ratio
+ * damping update (Madsen, Nielsen, Tingleff 2004): mu_0 = tau max diag(J^T J);
+ * per iteration (J^T J + mu I) h = -J^T r, q' = q + h (clamped to
+ * [q_min, q_max] with clamp != 0), accepted when the cost decrease over the
+ * decrease the linear model predicts is positive (then
+ * mu *= max(1/3, 1 - (2 rho - 1)^3), else mu *= nu, nu *= 2).  A row stops
+ * when max |J^T r| <= eps_grad, when |h| <= eps_step (|q| + eps_step), or
+ * after max_iters trial steps.
+ */
+typedef struct {
+    float lambda_q, lambda_c, lambda_e, lambda_r;  /* residual weights, >= 0 */
+    int32_t max_iters;                             /* 0..1000 trial steps */
+    float tau;                                     /* > 0 */
+    float eps_grad, eps_step;                      /* >= 0 */
+    int32_t clamp;                                 /* 1: keep q within the limits */
+} cp_ik_params;
+
+/*
+ * Solve N independent IK rows (enqueued on stream; one hardware wave per row,
+ * the wave's lanes sharing out the sphere-obstacle pairs of d(q)).
+ *  d_target [N][12]: R_d row-major then p_d (metres);
+ *  d_q_init [N][n]: starting configurations; d_q_ref [N][n] (NULL: q_init);
+ *  d_q [N][n] out: solutions; d_info [N][6] out (may be NULL): cost
+ *  F = |r|^2 / 2, |p_g - p_d|, |Log(R_d^T R_g)|, d(q), |g_p|, trial steps
+ *  taken; d_status [N] out (may be NULL): 1 gradient test met, 2 step test
+ *  met, 0 iteration limit.
+ * With restarts > 1, rows come in groups of `restarts` (rows i*restarts ..
+ * i*restarts + restarts - 1 solve target i from different starting points;
+ * N must be a multiple of restarts) and d_best [N / restarts] (may be NULL)
+ * receives, per group, the row with the lowest F (NaN as +inf; ties: the
+ * lowest row); d_best requires d_info.  1 <= N <= 1048576.  The plan's scene
+ * and robot (spheres, self pairs, tip) are used; its cost parameters are not.
+ * Device buffers are the caller's, contiguous, on the plan's device.
+ * Errors: CP_ERR_INVALID_ARG (null pointers, weights negative or not finite,
+ * max_iters outside 0..1000, tau <= 0, d_best without d_info), CP_ERR_SIZE
+ * (N out of range or not a multiple of restarts), CP_ERR_HIP (launch).
+ */
+int cp_ik_solve(cp_plan *plan, const cp_ik_params *params, const float *d_target, const float *d_q_init,
+                const float *d_q_ref, int32_t N, int32_t restarts, float *d_q, float *d_info, int32_t *d_status,
+                int32_t *d_best, cp_stream_t stream);
+
+/* Test export: the IK residual r [N][8+n] and its Jacobian [N][8+n][n]
+ * (either may be NULL) at configurations d_q [N][n] for targets d_target
+ * [N][12] and references d_q_ref [N][n] (NULL: d_q), with the weights of
+ * params (the solver settings are ignored). */
+int cp_debug_ik_residual(cp_plan *plan, const cp_ik_params *params, const float *d_target, const float *d_q,
+                         const float *d_q_ref, int32_t N, float *d_r, float *d_J, cp_stream_t stream);
 
 /* Test exports.  Forward kinematics of N joint vectors d_q [N][n]:
  * sphere centres [N][S][3] (sphere table order) and frames [N][n+1][12]

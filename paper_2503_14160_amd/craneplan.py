@@ -37,7 +37,7 @@ EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_en
            "cp_batch_get_tuning", "cp_batch_tune", "cp_optimizer_last_elites", "cp_tune",
            "cp_debug_update", "cp_optimizer_last_polished", "cp_batch_last", "cp_eval_paths_noalloc",
            "cp_optimizer_time_eval", "cp_optimizer_eval_time", "cp_optimizer_record_tape",
-           "cp_optimizer_population_grad"]
+           "cp_optimizer_population_grad", "cp_ik_solve", "cp_debug_ik_residual"]
 
 
 class CranePlanError(RuntimeError):
@@ -49,7 +49,8 @@ class CranePlanError(RuntimeError):
 class _Robot(ctypes.Structure):
     _fields_ = [("n_joints", _c_i32), ("type", _vp), ("axis", _vp), ("origin", _vp), ("q_min", _vp),
                 ("q_max", _vp), ("q_hold", _vp), ("active", _vp), ("n_spheres", _c_i32), ("sphere_frame", _vp),
-                ("sphere_center", _vp), ("sphere_radius", _vp), ("n_self_pairs", _c_i32), ("self_pairs", _vp)]
+                ("sphere_center", _vp), ("sphere_radius", _vp), ("n_self_pairs", _c_i32), ("self_pairs", _vp),
+                ("tip", _c_f32 * 3)]
 
 
 class _Scene(ctypes.Structure):
@@ -62,6 +63,12 @@ class _Cost(ctypes.Structure):
     _fields_ = [("K", _c_i32), ("M", _c_i32), ("interp", _c_i32), ("jp_mode", _c_i32), ("hinge", _c_i32),
                 ("margin", _c_f32), ("lambda_c", _c_f32), ("w_c", _c_f32), ("w_l", _c_f32), ("max_B", _c_i32),
                 ("pair_filter", _c_i32)]
+
+
+class _Ik(ctypes.Structure):
+    _fields_ = [("lambda_q", _c_f32), ("lambda_c", _c_f32), ("lambda_e", _c_f32), ("lambda_r", _c_f32),
+                ("max_iters", _c_i32), ("tau", _c_f32), ("eps_grad", _c_f32), ("eps_step", _c_f32),
+                ("clamp", _c_i32)]
 
 
 class _Opt(ctypes.Structure):
@@ -116,6 +123,8 @@ def lib():
         L.cp_optimizer_eval_time.argtypes = [_vp, _vp, _vp]
         L.cp_optimizer_record_tape.argtypes = [_vp, i32]
         L.cp_optimizer_population_grad.argtypes = [_vp, _vp, _vp]
+        L.cp_ik_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, i32, i32, _vp, _vp, _vp, _vp, _vp]
+        L.cp_debug_ik_residual.argtypes = [_vp, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -165,6 +174,9 @@ def _fill_robot(r, robot, keep):
     pairs = _host(getattr(robot, "self_pairs", np.zeros((0, 2))), np.int32).reshape(-1, 2)
     r.n_self_pairs = int(pairs.shape[0])
     r.self_pairs = _keep_ptr(keep, pairs, np.int32) if pairs.size else None
+    tip = _host(getattr(robot, "tip", np.zeros(3)), np.float32).reshape(3)
+    for a in range(3):
+        r.tip[a] = float(tip[a])
 
 
 def _fill_scene(s, scene, keep, sdf=None, sdf_spec=None):
@@ -187,6 +199,14 @@ def _fill_cost(c, cost, max_B, pair_filter=PAIRS_AUTO):
     c.margin, c.lambda_c, c.w_c, c.w_l = cost.margin, cost.lambda_c, cost.w_c, cost.w_l
     c.max_B = int(max_B)
     c.pair_filter = int(pair_filter)
+
+
+def _fill_ik(k, par):
+    k.lambda_q, k.lambda_c = float(par.lambda_q), float(par.lambda_c)
+    k.lambda_e, k.lambda_r = float(par.lambda_e), float(par.lambda_r)
+    k.max_iters, k.tau = int(par.max_iters), float(par.tau)
+    k.eps_grad, k.eps_step = float(par.eps_grad), float(par.eps_step)
+    k.clamp = int(par.clamp)
 
 
 def _fill_opt(o, opt, problem_id=0):
@@ -293,6 +313,49 @@ class Plan:
         a = torch.empty(N, dtype=torch.int32, device=Q.device)
         _check(lib().cp_debug_eval_configs(self._h, _ptr(Q), N, _ptr(d), _ptr(a), _stream()))
         return d, a
+
+
+    def _rows(self, a: torch.Tensor, N: int, width: int, name: str) -> torch.Tensor:
+        if a.dtype != torch.float32 or a.shape != (N, width) or a.device != self.device:
+            raise ValueError(f"{name} must be float32 [{N},{width}] on {self.device}")
+        return a.contiguous()
+
+    def ik_solve(self, params, target: torch.Tensor, q_init: torch.Tensor, q_ref: Optional[torch.Tensor] = None,
+                 restarts: int = 1):
+        """cp_ik_solve: (q [N,n], info [N,6], status [N], best [N/restarts])
+        for targets [N,12] (R_d row-major, p_d), starts q_init [N,n] and
+        regularisation references q_ref [N,n] (None: q_init)."""
+        N = q_init.shape[0]
+        n = self.n_joints
+        target = self._rows(target, N, 12, "target")
+        q_init = self._rows(q_init, N, n, "q_init")
+        if q_ref is not None:
+            q_ref = self._rows(q_ref, N, n, "q_ref")
+        k = _Ik()
+        _fill_ik(k, params)
+        q = torch.empty((N, n), dtype=torch.float32, device=self.device)
+        info = torch.empty((N, 6), dtype=torch.float32, device=self.device)
+        status = torch.empty(N, dtype=torch.int32, device=self.device)
+        best = torch.empty(max(1, N // int(restarts)), dtype=torch.int32, device=self.device)
+        _check(lib().cp_ik_solve(self._h, ctypes.byref(k), _ptr(target), _ptr(q_init), _ptr(q_ref), N, int(restarts),
+                                 _ptr(q), _ptr(info), _ptr(status), _ptr(best), _stream()))
+        return q, info, status, best
+
+    def ik_residual(self, params, target: torch.Tensor, q: torch.Tensor, q_ref: Optional[torch.Tensor] = None):
+        """cp_debug_ik_residual: residual [N,8+n] and Jacobian [N,8+n,n]."""
+        N = q.shape[0]
+        n = self.n_joints
+        target = self._rows(target, N, 12, "target")
+        q = self._rows(q, N, n, "q")
+        if q_ref is not None:
+            q_ref = self._rows(q_ref, N, n, "q_ref")
+        k = _Ik()
+        _fill_ik(k, params)
+        r = torch.empty((N, 8 + n), dtype=torch.float32, device=self.device)
+        J = torch.empty((N, 8 + n, n), dtype=torch.float32, device=self.device)
+        _check(lib().cp_debug_ik_residual(self._h, ctypes.byref(k), _ptr(target), _ptr(q), _ptr(q_ref), N, _ptr(r),
+                                          _ptr(J), _stream()))
+        return r, J
 
 
 class EvalPaths(torch.autograd.Function):

@@ -230,6 +230,8 @@ static int validate_plan_args(const cp_robot_desc *r, const cp_scene_desc *s, co
         if (a < 0 || a > r->n_joints || b < 0 || b > r->n_joints || a == b)
             return fail(CP_ERR_INVALID_ARG, "bad self-collision frame pair");
     }
+    for (int i = 0; i < 3; ++i)
+        if (!finite(r->tip[i])) return fail(CP_ERR_INVALID_ARG, "non-finite tip");
     // obstacle numbers stay below CP_OBS_SELF
     if (s->n_cyl < 0 || s->n_box < 0 || s->n_cyl + s->n_box > (int)CP_OBS_SELF - 1)
         return fail(CP_ERR_SIZE, "obstacle count out of range");
@@ -543,6 +545,7 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     v.n_self = (int)self_pairs.size();
     v.self_pairs = p->d_self_pairs;
     v.frame_bound = p->d_frame_bound;
+    for (int a = 0; a < 3; ++a) v.tip[a] = robot->tip[a];
     v.sdf = scene->d_sdf;
     for (int a = 0; a < 3; ++a) {
         v.sdf_n[a] = scene->d_sdf ? scene->sdf_dims[a] : 2;
@@ -693,6 +696,50 @@ int cp_debug_select(const float *d_cost, int32_t B, int32_t nu, int32_t *d_elite
     v.nu = nu;
     v.elite0 = d_elite;
     CP_HIP(launch_select(v, (hipStream_t)stream), "select launch");
+    return CP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// collision-free inverse kinematics
+// ---------------------------------------------------------------------------
+
+static int validate_ik_params(const cp_ik_params *p) {
+    if (!p) return fail(CP_ERR_INVALID_ARG, "null IK parameters");
+    const float lam[4] = {p->lambda_q, p->lambda_c, p->lambda_e, p->lambda_r};
+    for (float v : lam)
+        if (!finite(v) || v < 0.0f) return fail(CP_ERR_INVALID_ARG, "IK weights must be finite and >= 0");
+    if (p->max_iters < 0 || p->max_iters > 1000) return fail(CP_ERR_INVALID_ARG, "max_iters out of range (0..1000)");
+    if (!finite(p->tau) || p->tau <= 0.0f) return fail(CP_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (!finite(p->eps_grad) || p->eps_grad < 0.0f || !finite(p->eps_step) || p->eps_step < 0.0f)
+        return fail(CP_ERR_INVALID_ARG, "IK tolerances must be finite and >= 0");
+    return CP_OK;
+}
+
+constexpr int32_t kMaxIkRows = 1 << 20;
+
+int cp_ik_solve(cp_plan *plan, const cp_ik_params *params, const float *d_target, const float *d_q_init,
+                const float *d_q_ref, int32_t N, int32_t restarts, float *d_q, float *d_info, int32_t *d_status,
+                int32_t *d_best, cp_stream_t stream) {
+    if (!plan || !d_target || !d_q_init || !d_q) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (int rc = validate_ik_params(params)) return rc;
+    if (N < 1 || N > kMaxIkRows) return fail(CP_ERR_SIZE, "N out of range (1..1048576)");
+    if (restarts < 1 || N % restarts != 0) return fail(CP_ERR_SIZE, "N must be a positive multiple of restarts");
+    if (d_best && !d_info) return fail(CP_ERR_INVALID_ARG, "d_best needs d_info (the rows' costs)");
+    DeviceGuard g(plan->device);
+    CP_HIP(launch_ik_solve(plan->view, *params, d_target, d_q_init, d_q_ref, N, restarts, d_q, d_info, d_status,
+                           d_best, (hipStream_t)stream),
+           "IK launch");
+    return CP_OK;
+}
+
+int cp_debug_ik_residual(cp_plan *plan, const cp_ik_params *params, const float *d_target, const float *d_q,
+                         const float *d_q_ref, int32_t N, float *d_r, float *d_J, cp_stream_t stream) {
+    if (!plan || !d_target || !d_q) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (int rc = validate_ik_params(params)) return rc;
+    if (N < 1 || N > kMaxIkRows) return fail(CP_ERR_SIZE, "N out of range (1..1048576)");
+    DeviceGuard g(plan->device);
+    CP_HIP(launch_ik_residual(plan->view, *params, d_target, d_q, d_q_ref, N, d_r, d_J, (hipStream_t)stream),
+           "IK residual launch");
     return CP_OK;
 }
 

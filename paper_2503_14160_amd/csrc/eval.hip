@@ -781,58 +781,6 @@ __global__ __launch_bounds__(256) void k_reduce_batched(const BatchProblem *__re
 // adjoint
 // ---------------------------------------------------------------------------
 
-// gradient of the signed distance of obstacle o at c (same case split as the
-// exact SDFs); returns the signed distance
-__device__ __forceinline__ float obstacle_sd_grad(const PlanView &P, uint32_t o, float cx, float cy, float cz,
-                                                  float (&gr)[3]) {
-    if (o == CP_OBS_SDF) return sdf_query(P, cx, cy, cz, gr);
-    if (o == 0) {
-        gr[0] = 0.0f; gr[1] = 0.0f; gr[2] = 1.0f;
-        return cz - P.ground_z;
-    }
-    if ((int)o <= P.n_cyl) {
-        const float4 c = P.cyl_orig[o - 1];
-        const GroupDev g = P.groups[__float_as_int(c.w)];
-        float dx = cx - c.x, dy = cy - c.y, dz = cz - g.zc;
-        float rho = fsqrt(__builtin_fmaf(dx, dx, dy * dy));
-        float a = rho - c.z, b = fabsf(dz) - g.hz;
-        float sd = cyl_combine(a, b);
-        float inv = rho > 0.0f ? 1.0f / rho : 0.0f;
-        float gax = dx * inv, gay = dy * inv, gbz = dz >= 0.0f ? 1.0f : -1.0f;
-        if (a > 0.0f && b > 0.0f) {
-            float out = sd;  // sqrt(a^2 + b^2) here
-            gr[0] = a * gax / out; gr[1] = a * gay / out; gr[2] = b * gbz / out;
-        } else if (a > 0.0f || (b <= 0.0f && a >= b)) {
-            gr[0] = gax; gr[1] = gay; gr[2] = 0.0f;
-        } else {
-            gr[0] = 0.0f; gr[1] = 0.0f; gr[2] = gbz;
-        }
-        return sd;
-    }
-    const int bi = (int)o - 1 - P.n_cyl;
-    const float4 b0 = P.box[2 * bi], b1 = P.box[2 * bi + 1];
-    float d[3] = {cx - b0.x, cy - b0.y, cz - b0.z};
-    float h[3] = {b0.w, b1.x, b1.y};
-    float qv[3], sg[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { sg[i] = d[i] >= 0.0f ? 1.0f : -1.0f; qv[i] = fabsf(d[i]) - h[i]; }
-    float sd = box_sd(cx, cy, cz, b0, b1);
-    float px = fmaxf(qv[0], 0.0f), py = fmaxf(qv[1], 0.0f), pz = fmaxf(qv[2], 0.0f);
-    float o2 = __builtin_fmaf(px, px, __builtin_fmaf(py, py, pz * pz));
-    if (o2 > 0.0f) {
-        float inv = 1.0f / fsqrt(o2);
-        gr[0] = sg[0] * px * inv; gr[1] = sg[1] * py * inv; gr[2] = sg[2] * pz * inv;
-    } else {
-        int am = 0;
-        if (qv[1] > qv[am]) am = 1;
-        if (qv[2] > qv[am]) am = 2;
-        gr[0] = am == 0 ? sg[0] : 0.0f;
-        gr[1] = am == 1 ? sg[1] : 0.0f;
-        gr[2] = am == 2 ? sg[2] : 0.0f;
-    }
-    return sd;
-}
-
 // d cost_k / d q for the collision term through the tape's pair (s, o):
 // recomputes the chain, the sphere centre and the pair's signed distance.  A
 // self-collision pair (o = CP_OBS_SELF + b) differentiates

@@ -95,6 +95,13 @@ hipError_t launch_update(const PlanView &P, const OptView &O, hipStream_t st);
 hipError_t launch_chol(const OptView &O, hipStream_t st);
 hipError_t launch_init_state(const PlanView &P, const OptView &O, float sigma0, hipStream_t st);
 
+// collision-free inverse kinematics (ik.hip); best needs info
+hipError_t launch_ik_solve(const PlanView &P, const cp_ik_params &prm, const float *target, const float *q_init,
+                           const float *q_ref, int N, int restarts, float *q_out, float *info, int32_t *status,
+                           int32_t *best, hipStream_t st);
+hipError_t launch_ik_residual(const PlanView &P, const cp_ik_params &prm, const float *target, const float *q,
+                              const float *q_ref, int N, float *r, float *J, hipStream_t st);
+
 // signed-distance grid (sdf.hip)
 hipError_t launch_sdf_build(const float *points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
                             float *sdf, uint8_t *occ, int32_t *edt_occ, int32_t *edt_free, int32_t *work,

@@ -118,3 +118,37 @@ def test_sdf_build_argument_checks_without_device():
     d = np.array((8, 8, 8), np.int32)
     assert L.cp_sdf_build(fake, -1, d.ctypes.data, org.ctypes.data, 0.1, fake, None, None, None, None) == -2
     assert L.cp_sdf_build(None, 10, d.ctypes.data, org.ctypes.data, 0.1, fake, None, None, None, None) == -1
+
+
+def test_ik_argument_checks_without_device():
+    """cp_ik_solve / cp_debug_ik_residual refuse bad weights, iteration
+    limits, sizes and a best-row output without the per-row costs before
+    touching the plan or the device."""
+    import ctypes
+
+    from paper_2503_14160_amd import craneplan, synth
+    if not os.path.exists(craneplan.LIB_PATH):
+        from paper_2503_14160_amd import build
+        build.build()
+    L = craneplan.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the checks fail first
+
+    def solve(par, N=8, restarts=1, info=fake, best=None, plan=fake):
+        k = craneplan._Ik()
+        craneplan._fill_ik(k, par)
+        return L.cp_ik_solve(plan, ctypes.byref(k), fake, fake, None, N, restarts, fake, info, None, best, None)
+
+    good = synth.IkParams()
+    assert solve(good, plan=None) == -1
+    for bad in (dict(lambda_q=-1.0), dict(lambda_c=float("nan")), dict(max_iters=-1), dict(max_iters=1001),
+                dict(tau=0.0), dict(eps_grad=-1e-3), dict(eps_step=float("inf"))):
+        par = synth.IkParams(**bad)
+        assert solve(par) == -1, bad
+    assert solve(good, N=0) == -2
+    assert solve(good, N=(1 << 20) + 1) == -2
+    assert solve(good, N=10, restarts=4) == -2
+    assert solve(good, N=8, restarts=0) == -2
+    assert solve(good, N=8, restarts=4, info=None, best=fake) == -1
+    k = craneplan._Ik()
+    craneplan._fill_ik(k, synth.IkParams(lambda_r=-1.0))
+    assert L.cp_debug_ik_residual(fake, ctypes.byref(k), fake, fake, None, 4, fake, fake, None) == -1
