@@ -14,7 +14,8 @@ sample of the same workload.
 Other workloads print their own line: c0_plain (small single problem),
 c2_diff (adjoint: fwd+bwd vs fwd, gradient error, polished iterations),
 c3_batch (many problems: batched graph launch vs one problem at a time),
-c4_sdf (lidar -> signed-distance grid, trilinear queries, fwd+bwd).
+c4_sdf (lidar -> signed-distance grid, trilinear queries, fwd+bwd),
+ik (batched collision-free inverse kinematics with restarts).
 """
 import argparse
 import json
@@ -32,6 +33,10 @@ sys.path.insert(0, ROOT)
 # sphere-box pair 20, per sphere 7 (height term of the shared tree extent and
 # the ground), interpolation + forward kinematics 1500
 F_CYL, F_BOX, F_SPHERE, F_CONFIG = 15, 20, 7, 1500
+# a sphere-cylinder pair with its own height term (no shared extent): radial term 7, height term 2,
+# combination 9, minus the radius 1, running minimum 1; a sphere-sphere self pair: difference 3,
+# squared length 5, square root 1, radii 2, minimum 1; a sphere against the ground 3
+F_CYL_FULL, F_SELF, F_GROUND = 20, 12, 3
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_HBM = 8.0e12     # MI355X HBM3E bytes/s
 # algorithmic bytes of one trilinear signed-distance query: 8 FP32 corners
@@ -411,6 +416,96 @@ def bench_sdf(args, torch, cp, prob):
                      fwd_bwd_ms=fb_ms, fwd_bwd_over_fwd=fb_ms / fwd_ms, eval_ms=eval_ms, roofline=roof)
 
 
+# ----------------------------------------------------------------------------
+# ik: batched collision-free inverse kinematics
+# ----------------------------------------------------------------------------
+
+def bench_ik(args, torch, cp, cand):
+    """ik: the grasp poses of hanging configurations on the c1 crane (with its
+    self pairs) in the c1 forest, picked where the configuration keeps 0.1 m
+    from the scene and itself (by the library's own distance), several
+    starting points per target, one launch solving every row by
+    Levenberg-Marquardt; reports rows and targets per second and the launch
+    against the FP32 vector roofline, counting each d(q) evaluation's
+    all-pairs flops (the kernel takes every pair)."""
+    from paper_2503_14160_amd import synth
+    plan = cp.Plan(cand.robot, cand.scene, synth_cost_any(), max_B=1)
+    dist, _ = plan.debug_configs(torch.from_numpy(cand.q_star).cuda())
+    prob = cand.pick(dist.cpu().numpy() > synth.IK_TARGET_CLEARANCE)
+    n = prob.robot.n_joints
+    N = prob.q_init.shape[0]
+    R = prob.restarts
+    # targets: the last frame's rotation and its tip point at q_star (the library's own kinematics)
+    qs = torch.from_numpy(prob.q_star).cuda()
+    _, frames = plan.debug_fk(qs)
+    Rm = frames[:, n, :9].reshape(-1, 3, 3)
+    tip = torch.from_numpy(np.asarray(prob.robot.tip, np.float32)).cuda()
+    p = torch.matmul(Rm, tip) + frames[:, n, 9:12]
+    T = torch.cat([frames[:, n, :9], p], dim=1).repeat_interleave(R, dim=0).contiguous()
+    q0 = torch.from_numpy(prob.q_init).cuda()
+    qr = torch.from_numpy(np.broadcast_to(prob.q_ref, (N, n)).copy()).cuda()
+    par = prob.params
+    for _ in range(max(1, args.warmup)):
+        q, info, status, best = plan.ik_solve(par, T, q0, qr, restarts=R)
+    torch.cuda.synchronize()
+    print(f"[bench] ik: {N} rows ({N // R} targets x {R} starts), {args.steps} timed launches", file=sys.stderr,
+          flush=True)
+    ms = _timed(torch, lambda: plan.ik_solve(par, T, q0, qr, restarts=R), args.steps)
+    q, info, status, best = plan.ik_solve(par, T, q0, qr, restarts=R)
+    inf = info.cpu().numpy()
+    evals = float(np.sum(1.0 + inf[:, 5]))
+    S = prob.robot.n_spheres
+    n_self = self_sphere_pairs(prob.robot)
+    # per d(q) evaluation: every sphere against the ground, the cylinders (each with its own height
+    # term) and the boxes, and the self pairs; the chain, the residual and Jacobian rows and the normal
+    # equations of each row and evaluation are not counted
+    f_eval = S * (prob.scene.n_cyl * F_CYL_FULL + prob.scene.n_box * F_BOX + F_GROUND) + n_self * F_SELF
+    flops = evals * f_eval
+    bi = best.cpu().numpy()
+    Fb = inf[bi, 0]
+    config = {"workload": "ik_c1", "targets": N // R, "restarts": R, "rows": N, "max_iters": par.max_iters,
+              "target_clearance_m": synth.IK_TARGET_CLEARANCE, "candidates": int(cand.q_star.shape[0]),
+              "spheres": S, "cylinders": prob.scene.n_cyl, "boxes": prob.scene.n_box, "self_sphere_pairs": n_self,
+              "weights": [par.lambda_q, par.lambda_c, par.lambda_e, par.lambda_r]}
+    roof = {"bound": "alu", "kernel": "k_ik_solve", "unit": "TFLOP/s", "peak": PEAK_FP32 / 1e12,
+            "launch_ms": ms, "achieved": flops / (ms * 1e-3) / 1e12, "frac": flops / (ms * 1e-3) / PEAK_FP32,
+            "traffic": None, "flops_per_launch": flops, "flops_per_distance": f_eval,
+            "distance_evaluations": evals,
+            "note": "algorithmic flops of the distance evaluations (every sphere-obstacle and self pair per trial "
+                    "step) over the launch; the wave-uniform solver arithmetic is not counted"}
+    out = base_line(args, "IK rows solved/s", N / (ms * 1e-3), "rows/s", ms, config,
+                    targets_per_s=(N // R) / (ms * 1e-3), mean_trial_steps=float(inf[:, 5].mean()),
+                    status_counts={str(k): int(v) for k, v in zip(*np.unique(status.cpu().numpy(),
+                                                                               return_counts=True))},
+                    best_pos_err_median=float(np.median(inf[bi, 1])), best_cost_median=float(np.median(Fb)),
+                    best_in_collision=float(np.mean(inf[bi, 3] < 0)), roofline=roof)
+    return out, T, prob
+
+
+def synth_cost_any():
+    from paper_2503_14160_amd import synth
+    return synth.CostParams(K=4, M=4)
+
+
+def self_sphere_pairs(robot):
+    counts = np.bincount(np.asarray(robot.sphere_frame), minlength=robot.n_joints + 1)
+    return int(sum(counts[a] * counts[b] for a, b in np.asarray(robot.self_pairs).reshape(-1, 2)))
+
+
+def cpu_baseline_ik(prob, T, rows=48):
+    import oracle
+    oracle.build()
+    m = oracle.Model(prob.robot, prob.scene, None)
+    Tn = T[:rows].cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    for i in range(rows):
+        oracle.ik_solve(m, prob.params, Tn[i], prob.q_init[i].astype(np.float64), prob.q_ref.astype(np.float64))
+    dt = time.perf_counter() - t0
+    return {"value": rows / dt, "unit": "rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {rows} of {prob.q_init.shape[0]} rows of the ik workload, solved one after "
+                      f"another (C residual + numpy Levenberg-Marquardt, FP64), {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,6 +562,11 @@ def main():
         out = bench_diff(args, torch, cp, synth.c2_diff())
     elif args.workload == "c3_batch":
         out = bench_batch(args, torch, cp, synth.c3_batch(args.batch_problems))
+    elif args.workload == "ik":
+        out, T, prob = bench_ik(args, torch, cp, synth.ik_c1())
+        if not args.no_cpu_baseline:
+            print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline_ik(prob, T)
     else:
         out = bench_sdf(args, torch, cp, synth.c4_sdf())
     print(json.dumps(out))

@@ -1,11 +1,17 @@
 // Collision-free inverse kinematics (Sec. 3.2, eq. IK opt): one hardware wave
 // per row.  Every lane carries the row's whole solver state (the kinematic
 // chain, the residual, the normal equations), so the Levenberg-Marquardt
-// arithmetic is wave-uniform; the lanes share out only the signed distance
-// d(q), the minimum over every (sphere, obstacle) and self-collision pair,
-// which is where the work is: each lane takes every 64th obstacle against all
-// spheres (sphere centres broadcast from LDS) and the wave reduces the
-// minimum with its pair.
+// arithmetic and control flow are wave-uniform; the lanes share out the
+// signed distance d(q), the minimum over every (sphere, obstacle) and
+// self-collision pair, which is where the work is.  Each lane holds one or
+// two spheres (sorted slots lane, lane + 64) and runs them against every
+// obstacle, the obstacle records being wave-uniform scalar loads (the path
+// evaluation's pair loop, with its shared height term per group of trees);
+// the self pairs are dealt out over the lanes from the centres in LDS.  The
+// minimising pair, in the oracle's tie order, comes from a second pass over
+// the obstacles, dealt out over the lanes, for the lowest-numbered sphere
+// that attains the minimum.  Kernels are instantiated for at most 6 or 8
+// joints (NJ) and for 1 or 2 spheres per lane (G).
 #include "launch.h"
 
 namespace cp {
@@ -49,26 +55,42 @@ struct IkShared {
 };
 
 // The chain at q, wave-uniform: world axis and pivot (origin of the frame the
-// joint moves) of every joint, the last frame's rotation, the tip point; and
-// each lane's two spheres (sorted slots lane, lane + 64) placed in LDS.
+// joint moves) of every joint, the last frame's rotation, the tip point.
+template <int NJ>
 struct Chain {
-    float aw[CP_MAX_JOINTS][3], piv[CP_MAX_JOINTS][3];
+    float aw[NJ][3], piv[NJ][3];
     float R[9];
     float p[3];
 };
 
-__device__ __forceinline__ void chain_and_spheres(const PlanView &P, const float (&q)[CP_MAX_JOINTS], Chain &C,
-                                                  IkShared &sh) {
+// This lane's spheres (sorted slots lane + 64 s, s < G): centre, radius and
+// caller index; slots past the last sphere hold a far-away centre (every
+// distance +inf) and radius 0.
+template <int G>
+struct LaneSpheres {
+    float x[G], y[G], z[G], r[G];
+    uint32_t orig[G];
+    bool valid[G];
+};
+
+template <int NJ, int G>
+__device__ __forceinline__ void chain_and_spheres(const PlanView &P, const float (&q)[NJ], Chain<NJ> &C,
+                                                  LaneSpheres<G> &ls, IkShared &sh) {
     const int lane = threadIdx.x;
-    const int i0 = lane, i1 = lane + kWave;
-    SphereDev s0{}, s1{};
-    if (i0 < P.n_spheres) s0 = ldg(P.spheres, i0);
-    if (i1 < P.n_spheres) s1 = ldg(P.spheres, i1);
-    float c0[3] = {0.0f, 0.0f, 0.0f}, c1[3] = {0.0f, 0.0f, 0.0f};
+    SphereDev sd[G];
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+        const int i = lane + s * kWave;
+        ls.valid[s] = i < P.n_spheres;
+        sd[s] = ls.valid[s] ? ldg(P.spheres, i) : SphereDev{};
+        ls.x[s] = kInf; ls.y[s] = kInf; ls.z[s] = kInf;
+        ls.r[s] = ls.valid[s] ? sd[s].r : 0.0f;
+        ls.orig[s] = ls.valid[s] ? (uint32_t)sd[s].orig : 0xFFFFu;
+    }
     Xf T;
     xf_identity(T);
 #pragma unroll
-    for (int f = 0; f <= CP_MAX_JOINTS; ++f) {
+    for (int f = 0; f <= NJ; ++f) {
         if (f > P.n_joints) break;
         if (f > 0) {
             const JointDev J = ldg(P.joints, f - 1);
@@ -79,58 +101,57 @@ __device__ __forceinline__ void chain_and_spheres(const PlanView &P, const float
             xf_joint(T, J, q[f - 1]);
             C.piv[f - 1][0] = T.p[0]; C.piv[f - 1][1] = T.p[1]; C.piv[f - 1][2] = T.p[2];
         }
-        if (i0 < P.n_spheres && s0.frame == f) xf_point(T, s0.lx, s0.ly, s0.lz, c0[0], c0[1], c0[2]);
-        if (i1 < P.n_spheres && s1.frame == f) xf_point(T, s1.lx, s1.ly, s1.lz, c1[0], c1[1], c1[2]);
+#pragma unroll
+        for (int s = 0; s < G; ++s)
+            if (ls.valid[s] && sd[s].frame == f) xf_point(T, sd[s].lx, sd[s].ly, sd[s].lz, ls.x[s], ls.y[s], ls.z[s]);
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) C.R[i] = T.r[i];
     xf_point(T, P.tip[0], P.tip[1], P.tip[2], C.p[0], C.p[1], C.p[2]);
     __syncthreads();  // the previous evaluation's readers are done
-    if (i0 < P.n_spheres) {
-        sh.c[i0] = make_float4(c0[0], c0[1], c0[2], s0.r);
-        sh.orig[i0] = s0.orig;
-    }
-    if (i1 < P.n_spheres) {
-        sh.c[i1] = make_float4(c1[0], c1[1], c1[2], s1.r);
-        sh.orig[i1] = s1.orig;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+        const int i = lane + s * kWave;
+        if (ls.valid[s]) {
+            sh.c[i] = make_float4(ls.x[s], ls.y[s], ls.z[s], ls.r[s]);
+            sh.orig[i] = (int32_t)ls.orig[s];
+        }
     }
     __syncthreads();
 }
 
-// d(q) and its pair, wave-uniform (centres in LDS)
-__device__ __forceinline__ PairMin wave_distance(const PlanView &P, const IkShared &sh) {
+// signed distance of obstacle `code` (0 ground, 1.. cylinders, then boxes, in
+// the caller's order) at c, the same arithmetic as the pair loop
+__device__ __forceinline__ float obstacle_sd(const PlanView &P, int code, float cx, float cy, float cz) {
+    if (code == 0) return cz - P.ground_z;
+    if (code <= P.n_cyl) {
+        const float4 cy4 = ldg(P.cyl_orig, code - 1);
+        const GroupDev gr = ldg(P.groups, __float_as_int(cy4.w));
+        return cyl_combine(cyl_radial(cx, cy, cy4), fabsf(cz - gr.zc) - gr.hz);
+    }
+    const int o = code - 1 - P.n_cyl;
+    return box_sd(cx, cy, cz, ldg(P.box, 2 * o), ldg(P.box, 2 * o + 1));
+}
+
+// d(q) and its pair, wave-uniform
+template <int G>
+__device__ __forceinline__ PairMin wave_distance(const PlanView &P, const LaneSpheres<G> &ls, const IkShared &sh) {
     const int lane = threadIdx.x;
-    const int S = P.n_spheres;
-    PairMin b;
-    b.d = kInf;
-    b.key = 0xFFFFFFFFu;
-    // ground and grid: one sphere per lane
-    for (int i = lane; i < S; i += kWave) {
-        const float4 c = sh.c[i];
-        const uint32_t ks = (uint32_t)sh.orig[i] << 17;
-        if (P.has_ground) pm_take(b, (c.z - P.ground_z) - c.w, ks);
-        if (P.sdf) pm_take(b, sdf_query(P, c.x, c.y, c.z, nullptr) - c.w, ks | kKeySdf);
-    }
-    // cylinders and boxes: every 64th obstacle against every sphere
-    for (int o = lane; o < P.n_cyl; o += kWave) {
-        const float4 cy = ldg(P.cyl_orig, o);
-        const GroupDev gr = ldg(P.groups, __float_as_int(cy.w));
-        const uint32_t ko = 1u + (uint32_t)o;
-        for (int i = 0; i < S; ++i) {
-            const float4 c = sh.c[i];
-            const float sd = cyl_combine(cyl_radial(c.x, c.y, cy), fabsf(c.z - gr.zc) - gr.hz);
-            pm_take(b, sd - c.w, ((uint32_t)sh.orig[i] << 17) | ko);
-        }
-    }
-    for (int o = lane; o < P.n_box; o += kWave) {
-        const float4 b0 = ldg(P.box, 2 * o), b1 = ldg(P.box, 2 * o + 1);
-        const uint32_t ko = 1u + (uint32_t)(P.n_cyl + o);
-        for (int i = 0; i < S; ++i) {
-            const float4 c = sh.c[i];
-            pm_take(b, box_sd(c.x, c.y, c.z, b0, b1) - c.w, ((uint32_t)sh.orig[i] << 17) | ko);
-        }
+    // scene: every obstacle against this lane's spheres
+    float v[G], ds[G];
+    spheres_min_sd<G>(P, ls.x, ls.y, ls.z, v);
+    float lane_min = kInf;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+        ds[s] = v[s] - ls.r[s];
+        if (P.sdf && ls.valid[s]) ds[s] = fminf(ds[s], sdf_query(P, ls.x[s], ls.y[s], ls.z[s], nullptr) - ls.r[s]);
+        if (!ls.valid[s]) ds[s] = kInf;
+        lane_min = fminf(lane_min, ds[s]);
     }
     // self-collision: the sphere pairs of each listed frame pair shared out
+    PairMin bs;
+    bs.d = kInf;
+    bs.key = 0xFFFFFFFFu;
     for (int k = 0; k < P.n_self; ++k) {
         const int2 fp = ldg(P.self_pairs, k);
         const int a0 = ldg(P.frame_start, fp.x), na = ldg(P.frame_start, fp.x + 1) - a0;
@@ -142,20 +163,42 @@ __device__ __forceinline__ PairMin wave_distance(const PlanView &P, const IkShar
             const float d = fsqrt(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) - ca.w - cb.w;
             const uint32_t oa = (uint32_t)sh.orig[ia], ob = (uint32_t)sh.orig[ib];
             const uint32_t lo = min(oa, ob), hi = max(oa, ob);
-            pm_take(b, d, (lo << 17) | (kKeySelf + hi));
+            pm_take(bs, d, (lo << 17) | (kKeySelf + hi));
         }
     }
+    lane_min = fminf(lane_min, bs.d);
     PairMin w;
-    w.d = wave_min_u(b.d);
-    w.key = wave_min_u32(b.d == w.d ? b.key : 0xFFFFFFFFu);
+    w.d = wave_min_u(lane_min);
+    // the lowest-numbered sphere whose scene distance attains the minimum,
+    // and its lowest obstacle among those that do
+    uint32_t so = 0xFFFFFFFFu;
+#pragma unroll
+    for (int s = 0; s < G; ++s)
+        if (ds[s] == w.d) so = min(so, ls.orig[s]);
+    so = wave_min_u32(so);
+    uint32_t key = 0xFFFFFFFFu;
+    if (so != 0xFFFFFFFFu) {
+        const float4 c = sh.c[ldg(P.sphere_slot, (int)so)];
+        uint32_t kc = 0xFFFFFFFFu;
+        const int n_codes = 1 + P.n_cyl + P.n_box;
+        for (int code = lane; code < n_codes; code += kWave) {
+            if (code == 0 && !P.has_ground) continue;
+            if (obstacle_sd(P, code, c.x, c.y, c.z) - c.w == w.d) kc = min(kc, (uint32_t)code);
+        }
+        if (lane == 0 && P.sdf && sdf_query(P, c.x, c.y, c.z, nullptr) - c.w == w.d) kc = min(kc, kKeySdf);
+        kc = wave_min_u32(kc);
+        key = (so << 17) | kc;
+    }
+    w.key = min(key, wave_min_u32(bs.d == w.d ? bs.key : 0xFFFFFFFFu));
     return w;
 }
 
 // d d(q) / d q through the minimising pair (wave-uniform)
-__device__ __forceinline__ void distance_grad(const PlanView &P, const Chain &C, const IkShared &sh, const PairMin &pm,
-                                              float (&gd)[CP_MAX_JOINTS]) {
+template <int NJ>
+__device__ __forceinline__ void distance_grad(const PlanView &P, const Chain<NJ> &C, const IkShared &sh,
+                                              const PairMin &pm, float (&gd)[NJ]) {
 #pragma unroll
-    for (int j = 0; j < CP_MAX_JOINTS; ++j) gd[j] = 0.0f;
+    for (int j = 0; j < NJ; ++j) gd[j] = 0.0f;
     const int s = (int)(pm.key >> 17);
     const uint32_t ok = pm.key & 0x1FFFFu;
     if (s >= P.n_spheres) return;
@@ -180,7 +223,7 @@ __device__ __forceinline__ void distance_grad(const PlanView &P, const Chain &C,
         obstacle_sd_grad(P, ok == kKeySdf ? CP_OBS_SDF : ok, c.x, c.y, c.z, g);
     }
 #pragma unroll
-    for (int j = 0; j < CP_MAX_JOINTS; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         if (j >= P.n_joints) break;
         const bool rev = ldg(P.joints, j).type == CP_REVOLUTE;
         float v[3] = {0.0f, 0.0f, 0.0f};
@@ -272,22 +315,25 @@ __device__ __forceinline__ void so3_jr_inv(const float (&w)[3], float (&Ji)[9]) 
 
 // Residual rows 0..7 (the regularisation rows are implicit) and their
 // Jacobian [8][n], wave-uniform.
+template <int NJ>
 struct IkEval {
     float r[8];
-    float J[8][CP_MAX_JOINTS];
+    float J[8][NJ];
     float pos_err, rot_err, d, gp;
 };
 
+template <int NJ, int G>
 __device__ __forceinline__ void ik_eval(const PlanView &P, const IkPrm &prm, const float (&tg)[12],
-                                        const float (&q)[CP_MAX_JOINTS], IkShared &sh, IkEval &E) {
+                                        const float (&q)[NJ], IkShared &sh, IkEval<NJ> &E) {
     const int n = P.n_joints;
-    Chain C;
-    chain_and_spheres(P, q, C, sh);
-    const PairMin pm = wave_distance(P, sh);
+    Chain<NJ> C;
+    LaneSpheres<G> ls;
+    chain_and_spheres<NJ, G>(P, q, C, ls, sh);
+    const PairMin pm = wave_distance<G>(P, ls, sh);
     // d p / d q_j
-    float dp[CP_MAX_JOINTS][3];
+    float dp[NJ][3];
 #pragma unroll
-    for (int j = 0; j < CP_MAX_JOINTS; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         dp[j][0] = dp[j][1] = dp[j][2] = 0.0f;
         if (j < n) {
             if (ldg(P.joints, j).type == CP_REVOLUTE) {
@@ -317,9 +363,9 @@ __device__ __forceinline__ void ik_eval(const PlanView &P, const IkPrm &prm, con
     E.d = pm.d;
     E.r[6] = pm.d < 0.0f ? prm.lc * (-pm.d) : 0.0f;
     // equilibrium of the joints that are not actuated
-    float gp[CP_MAX_JOINTS], gp2 = 0.0f;
+    float gp[NJ], gp2 = 0.0f;
 #pragma unroll
-    for (int j = 0; j < CP_MAX_JOINTS; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         gp[j] = (j < n && !ldg(P.joints, j).active) ? dp[j][2] : 0.0f;
         gp2 = __builtin_fmaf(gp[j], gp[j], gp2);
     }
@@ -328,10 +374,10 @@ __device__ __forceinline__ void ik_eval(const PlanView &P, const IkPrm &prm, con
     // Jacobian
     float Ji[9];
     so3_jr_inv(w, Ji);
-    float gd[CP_MAX_JOINTS];
+    float gd[NJ];
     if (pm.d < 0.0f) distance_grad(P, C, sh, pm, gd);
 #pragma unroll
-    for (int j = 0; j < CP_MAX_JOINTS; ++j) {
+    for (int j = 0; j < NJ; ++j) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) E.J[i][j] = 0.0f;
         if (j >= n) continue;
@@ -353,7 +399,7 @@ __device__ __forceinline__ void ik_eval(const PlanView &P, const IkPrm &prm, con
         // for revolute u; v prismatic -> a_u x a_v for revolute u < v
         float s = 0.0f;
 #pragma unroll
-        for (int k = 0; k < CP_MAX_JOINTS; ++k) {
+        for (int k = 0; k < NJ; ++k) {
             if (k >= n || gp[k] == 0.0f) continue;
             const int u = k < j ? k : j, v = k < j ? j : k;
             const bool ur = ldg(P.joints, u).type == CP_REVOLUTE;
@@ -377,14 +423,15 @@ __device__ __forceinline__ double sq_d(float x) { return (double)x * (double)x; 
 
 // F = |r|^2 / 2 over the eight explicit rows and the regularisation rows
 // lambda_r (q - q_ref)
-__device__ __forceinline__ double half_sq_norm(const IkEval &E, const IkPrm &prm, int n,
-                                               const float (&q)[CP_MAX_JOINTS], const float (&qr)[CP_MAX_JOINTS]) {
+template <int NJ>
+__device__ __forceinline__ double half_sq_norm(const IkEval<NJ> &E, const IkPrm &prm, int n, const float (&q)[NJ],
+                                               const float (&qr)[NJ]) {
     const double lr2 = (double)prm.lr * (double)prm.lr;
     double f = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) f += sq_d(E.r[k]);
 #pragma unroll
-    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+    for (int i = 0; i < NJ; ++i) {
         const double dq = i < n ? (double)q[i] - (double)qr[i] : 0.0;
         f += lr2 * dq * dq;
     }
@@ -392,14 +439,14 @@ __device__ __forceinline__ double half_sq_norm(const IkEval &E, const IkPrm &prm
 }
 
 // A = J^T J + lambda_r^2 I and g = J^T r + lambda_r^2 (q - q_ref) over the n
-// joints, padded to CP_MAX_JOINTS with identity rows (so the padded entries
-// of the step are 0)
-__device__ __forceinline__ void normal_eq(const IkEval &E, const IkPrm &prm, int n, const float (&q)[CP_MAX_JOINTS],
-                                          const float (&qr)[CP_MAX_JOINTS], double (&A)[CP_MAX_JOINTS][CP_MAX_JOINTS],
-                                          double (&g)[CP_MAX_JOINTS]) {
+// joints, padded to NJ with identity rows (so the padded entries of the step
+// are 0)
+template <int NJ>
+__device__ __forceinline__ void normal_eq(const IkEval<NJ> &E, const IkPrm &prm, int n, const float (&q)[NJ],
+                                          const float (&qr)[NJ], double (&A)[NJ][NJ], double (&g)[NJ]) {
     const double lr2 = (double)prm.lr * (double)prm.lr;
 #pragma unroll
-    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+    for (int i = 0; i < NJ; ++i) {
         const double dq = i < n ? (double)q[i] - (double)qr[i] : 0.0;
         double gi = lr2 * dq;
 #pragma unroll
@@ -419,12 +466,13 @@ __device__ __forceinline__ void normal_eq(const IkEval &E, const IkPrm &prm, int
 
 // (A + mu I) h = -g by a Cholesky factorisation in double precision; false if
 // a pivot is not positive
-__device__ __forceinline__ bool damped_solve(const double (&A)[CP_MAX_JOINTS][CP_MAX_JOINTS], const double (&g)[CP_MAX_JOINTS],
-                                             double mu, int n, double (&h)[CP_MAX_JOINTS]) {
-    double L[CP_MAX_JOINTS][CP_MAX_JOINTS];
+template <int NJ>
+__device__ __forceinline__ bool damped_solve(const double (&A)[NJ][NJ], const double (&g)[NJ], double mu, int n,
+                                             double (&h)[NJ]) {
+    double L[NJ][NJ];
     bool ok = true;
 #pragma unroll
-    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+    for (int i = 0; i < NJ; ++i) {
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
             double s = A[i][j] + ((i == j && i < n) ? mu : 0.0);
@@ -438,29 +486,31 @@ __device__ __forceinline__ bool damped_solve(const double (&A)[CP_MAX_JOINTS][CP
             }
         }
     }
-    double y[CP_MAX_JOINTS];
+    double y[NJ];
 #pragma unroll
-    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+    for (int i = 0; i < NJ; ++i) {
         double s = -g[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
         y[i] = s / L[i][i];
     }
 #pragma unroll
-    for (int i = CP_MAX_JOINTS - 1; i >= 0; --i) {
+    for (int i = NJ - 1; i >= 0; --i) {
         double s = y[i];
 #pragma unroll
-        for (int k = i + 1; k < CP_MAX_JOINTS; ++k) s -= L[k][i] * h[k];
+        for (int k = i + 1; k < NJ; ++k) s -= L[k][i] * h[k];
         h[i] = s / L[i][i];
     }
     return ok;
 }
 
-__device__ __forceinline__ void load_row(const float *src, int row, int n, float (&q)[CP_MAX_JOINTS]) {
+template <int NJ>
+__device__ __forceinline__ void load_row(const float *src, int row, int n, float (&q)[NJ]) {
 #pragma unroll
-    for (int j = 0; j < CP_MAX_JOINTS; ++j) q[j] = j < n ? ldg(src, (int64_t)row * n + j) : 0.0f;
+    for (int j = 0; j < NJ; ++j) q[j] = j < n ? ldg(src, (int64_t)row * n + j) : 0.0f;
 }
 
+template <int NJ, int G>
 __global__ __launch_bounds__(kWave) void k_ik_solve(PlanView P, IkPrm prm, const float *__restrict__ target,
                                                     const float *__restrict__ q_init, const float *__restrict__ q_ref,
                                                     int N, float *__restrict__ q_out, float *__restrict__ info,
@@ -472,41 +522,41 @@ __global__ __launch_bounds__(kWave) void k_ik_solve(PlanView P, IkPrm prm, const
     float tg[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) tg[i] = ldg(target, (int64_t)row * 12 + i);
-    float q[CP_MAX_JOINTS], qr[CP_MAX_JOINTS], lo[CP_MAX_JOINTS], hi[CP_MAX_JOINTS];
+    float q[NJ], qr[NJ], lo[NJ], hi[NJ];
     load_row(q_init, row, n, q);
     load_row(q_ref ? q_ref : q_init, row, n, qr);
 #pragma unroll
-    for (int j = 0; j < CP_MAX_JOINTS; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         lo[j] = j < n ? ldg(P.joints, j).qmin : 0.0f;
         hi[j] = j < n ? ldg(P.joints, j).qmax : 0.0f;
         if (prm.clamp) q[j] = fminf(fmaxf(q[j], lo[j]), hi[j]);
     }
     // state of the iteration: q, F(q), A = J^T J (+ lambda_r^2 I), g = J^T r
-    IkEval E;
-    ik_eval(P, prm, tg, q, sh, E);
-    double A[CP_MAX_JOINTS][CP_MAX_JOINTS], g[CP_MAX_JOINTS];
+    IkEval<NJ> E;
+    ik_eval<NJ, G>(P, prm, tg, q, sh, E);
+    double A[NJ][NJ], g[NJ];
     double F = half_sq_norm(E, prm, n, q, qr);
     normal_eq(E, prm, n, q, qr, A, g);
     float info_pos = E.pos_err, info_rot = E.rot_err, info_d = E.d, info_gp = E.gp;
     double amax = 0.0;
 #pragma unroll
-    for (int i = 0; i < CP_MAX_JOINTS; ++i)
+    for (int i = 0; i < NJ; ++i)
         if (i < n) amax = fmax(amax, A[i][i]);
     double mu = (double)prm.tau * amax, nu = 2.0;
     int it = 0, status = 0;
     while (it < prm.max_iters) {
         double gmax = 0.0;
 #pragma unroll
-        for (int i = 0; i < CP_MAX_JOINTS; ++i) gmax = fmax(gmax, fabs(g[i]));
+        for (int i = 0; i < NJ; ++i) gmax = fmax(gmax, fabs(g[i]));
         if (gmax <= (double)prm.eps_grad) {
             status = 1;
             break;
         }
-        double h[CP_MAX_JOINTS];
+        double h[NJ];
         damped_solve(A, g, mu, n, h);
         double hn = 0.0, qn2 = 0.0;
 #pragma unroll
-        for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+        for (int i = 0; i < NJ; ++i) {
             hn += h[i] * h[i];
             qn2 += (double)q[i] * (double)q[i];
         }
@@ -518,26 +568,26 @@ __global__ __launch_bounds__(kWave) void k_ik_solve(PlanView P, IkPrm prm, const
         // trial point (FP32 joint values, clamped) and the decrease the
         // linear model predicts for the step actually taken:
         // L(0) - L(s) = -s.g - s.A s / 2
-        float qt[CP_MAX_JOINTS];
+        float qt[NJ];
         double pred = 0.0;
         {
-            double st[CP_MAX_JOINTS];
+            double st[NJ];
 #pragma unroll
-            for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+            for (int i = 0; i < NJ; ++i) {
                 float v = (float)((double)q[i] + h[i]);
                 if (prm.clamp) v = fminf(fmaxf(v, lo[i]), hi[i]);
                 qt[i] = i < n ? v : 0.0f;
                 st[i] = (double)qt[i] - (double)q[i];
             }
 #pragma unroll
-            for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+            for (int i = 0; i < NJ; ++i) {
                 double as = 0.0;
 #pragma unroll
-                for (int j = 0; j < CP_MAX_JOINTS; ++j) as += A[i][j] * st[j];
+                for (int j = 0; j < NJ; ++j) as += A[i][j] * st[j];
                 pred -= st[i] * g[i] + 0.5 * st[i] * as;
             }
         }
-        ik_eval(P, prm, tg, qt, sh, E);
+        ik_eval<NJ, G>(P, prm, tg, qt, sh, E);
         const double Ft = half_sq_norm(E, prm, n, qt, qr);
         ++it;
         if (pred > 0.0 && F - Ft > 0.0) {
@@ -546,7 +596,7 @@ __global__ __launch_bounds__(kWave) void k_ik_solve(PlanView P, IkPrm prm, const
             mu *= fmax(1.0 / 3.0, 1.0 - t * t * t);
             nu = 2.0;
 #pragma unroll
-            for (int i = 0; i < CP_MAX_JOINTS; ++i) q[i] = qt[i];
+            for (int i = 0; i < NJ; ++i) q[i] = qt[i];
             F = Ft;
             normal_eq(E, prm, n, q, qr, A, g);
             info_pos = E.pos_err; info_rot = E.rot_err; info_d = E.d; info_gp = E.gp;
@@ -584,6 +634,7 @@ __global__ __launch_bounds__(256) void k_ik_best(const float *__restrict__ info,
     best[t] = arg;
 }
 
+template <int NJ, int G>
 __global__ __launch_bounds__(kWave) void k_ik_residual(PlanView P, IkPrm prm, const float *__restrict__ target,
                                                        const float *__restrict__ qv, const float *__restrict__ q_ref,
                                                        int N, float *__restrict__ r_out, float *__restrict__ J_out) {
@@ -594,11 +645,11 @@ __global__ __launch_bounds__(kWave) void k_ik_residual(PlanView P, IkPrm prm, co
     float tg[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) tg[i] = ldg(target, (int64_t)row * 12 + i);
-    float q[CP_MAX_JOINTS], qr[CP_MAX_JOINTS];
+    float q[NJ], qr[NJ];
     load_row(qv, row, n, q);
     load_row(q_ref ? q_ref : qv, row, n, qr);
-    IkEval E;
-    ik_eval(P, prm, tg, q, sh, E);
+    IkEval<NJ> E;
+    ik_eval<NJ, G>(P, prm, tg, q, sh, E);
     if (threadIdx.x != 0) return;
     if (r_out) {
         float *r = r_out + (int64_t)row * m;
@@ -628,8 +679,20 @@ IkPrm to_prm(const cp_ik_params &p) {
 hipError_t launch_ik_solve(const PlanView &P, const cp_ik_params &prm, const float *target, const float *q_init,
                            const float *q_ref, int N, int restarts, float *q_out, float *info, int32_t *status,
                            int32_t *best, hipStream_t st) {
-    hipLaunchKernelGGL(k_ik_solve, dim3(N), dim3(kWave), 0, st, P, to_prm(prm), target, q_init, q_ref, N, q_out, info,
-                       status);
+    const IkPrm d = to_prm(prm);
+    const bool small = P.n_joints <= 6, one = P.n_spheres <= kWave;
+    if (small && one)
+        hipLaunchKernelGGL((k_ik_solve<6, 1>), dim3(N), dim3(kWave), 0, st, P, d, target, q_init, q_ref, N, q_out, info,
+                           status);
+    else if (small)
+        hipLaunchKernelGGL((k_ik_solve<6, 2>), dim3(N), dim3(kWave), 0, st, P, d, target, q_init, q_ref, N, q_out, info,
+                           status);
+    else if (one)
+        hipLaunchKernelGGL((k_ik_solve<CP_MAX_JOINTS, 1>), dim3(N), dim3(kWave), 0, st, P, d, target, q_init, q_ref, N,
+                           q_out, info, status);
+    else
+        hipLaunchKernelGGL((k_ik_solve<CP_MAX_JOINTS, 2>), dim3(N), dim3(kWave), 0, st, P, d, target, q_init, q_ref, N,
+                           q_out, info, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !best) return e;
     const int groups = N / restarts;
@@ -639,7 +702,18 @@ hipError_t launch_ik_solve(const PlanView &P, const cp_ik_params &prm, const flo
 
 hipError_t launch_ik_residual(const PlanView &P, const cp_ik_params &prm, const float *target, const float *q,
                               const float *q_ref, int N, float *r, float *J, hipStream_t st) {
-    hipLaunchKernelGGL(k_ik_residual, dim3(N), dim3(kWave), 0, st, P, to_prm(prm), target, q, q_ref, N, r, J);
+    const IkPrm d = to_prm(prm);
+    const bool small = P.n_joints <= 6, one = P.n_spheres <= kWave;
+    if (small && one)
+        hipLaunchKernelGGL((k_ik_residual<6, 1>), dim3(N), dim3(kWave), 0, st, P, d, target, q, q_ref, N, r, J);
+    else if (small)
+        hipLaunchKernelGGL((k_ik_residual<6, 2>), dim3(N), dim3(kWave), 0, st, P, d, target, q, q_ref, N, r, J);
+    else if (one)
+        hipLaunchKernelGGL((k_ik_residual<CP_MAX_JOINTS, 1>), dim3(N), dim3(kWave), 0, st, P, d, target, q, q_ref, N, r,
+                           J);
+    else
+        hipLaunchKernelGGL((k_ik_residual<CP_MAX_JOINTS, 2>), dim3(N), dim3(kWave), 0, st, P, d, target, q, q_ref, N, r,
+                           J);
     return hipGetLastError();
 }
 

@@ -590,4 +590,108 @@ __device__ __forceinline__ float fmin_q(float a, float b) {
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// every sphere-obstacle pair of G sphere centres per lane, obstacle records
+// wave-uniform (the path evaluation's plain and lane-filtered modes, and the
+// inverse kinematics' distance)
+// ---------------------------------------------------------------------------
+
+// Four cylinders against G spheres: running minimum of (radial distance - R).
+template <int G>
+__device__ __forceinline__ void cyl_chunk(const float (&cx)[G], const float (&cy)[G], const float4 *c, float (&a)[G]) {
+    const float4 c0 = ldg(c, 0), c1 = ldg(c, 1), c2 = ldg(c, 2), c3 = ldg(c, 3);
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+        float r0 = cyl_radial(cx[s], cy[s], c0);
+        float r1 = cyl_radial(cx[s], cy[s], c1);
+        float r2 = cyl_radial(cx[s], cy[s], c2);
+        float r3 = cyl_radial(cx[s], cy[s], c3);
+        a[s] = fminf(a[s], fminf(fminf(r0, r1), fminf(r2, r3)));
+    }
+}
+
+// Same result with the square root taken only where it can matter: a pair
+// lowers the running minimum a only if rho - R < a, which needs
+// rho^2 < (a + R_max)^2.  The threshold carries 1e-4 m plus a relative 1e-6
+// of slack, far above the rounding of the threshold and of the square root
+// (both a few 1e-7 relative), so rounding never hides a pair that would lower
+// a; pairs that are skipped cannot change the minimum, so the result is
+// bitwise that of cyl_chunk.
+// The test is a wave-wide ballot (compares OR-ed in scalar registers) and the
+// candidate block runs for the whole wave when any lane has a candidate:
+// lanes without one only recompute values that cannot lower their minimum.
+// Per skipped pair this costs two subtractions, a multiply, a multiply-add and
+// a compare, all in 32-bit (VOP2/VOPC) encodings, instead of the same four
+// operations plus a square root, a subtraction and a minimum.
+constexpr float kRelSlack = 1.000001f;
+
+template <int G>
+__device__ __forceinline__ void cyl_chunk_filtered(const float (&cx)[G], const float (&cy)[G], const float4 *c,
+                                                   float (&a)[G], float (&thr)[G], float reach) {
+    const float4 cc[4] = {ldg(c, 0), ldg(c, 1), ldg(c, 2), ldg(c, 3)};
+    float d2[G][4];
+    uint64_t need = 0;
+#pragma unroll
+    for (int s = 0; s < G; ++s)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            float dx = cx[s] - cc[u].x, dy = cy[s] - cc[u].y;
+            d2[s][u] = __builtin_fmaf(dx, dx, dy * dy);
+            need |= __builtin_amdgcn_ballot_w64(d2[s][u] < thr[s]);
+        }
+    if (need) {
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
+            // fsqrt(d2) - R is exactly cyl_radial of the pair
+            float r0 = fsqrt(d2[s][0]) - cc[0].z, r1 = fsqrt(d2[s][1]) - cc[1].z;
+            float r2 = fsqrt(d2[s][2]) - cc[2].z, r3 = fsqrt(d2[s][3]) - cc[3].z;
+            a[s] = fminf(a[s], fminf(fminf(r0, r1), fminf(r2, r3)));
+            float t = fmaxf(a[s] + reach, 0.0f) * kRelSlack;
+            thr[s] = t * t;
+        }
+    }
+}
+
+__device__ __forceinline__ float first_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Minimum signed distance over the primitive obstacles (ground, cylinders,
+// boxes) for G sphere centres; the grid term is taken by the caller.
+template <int G>
+__device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&cx)[G], const float (&cy)[G],
+                                               const float (&cz)[G], float (&v)[G]) {
+#pragma unroll
+    for (int s = 0; s < G; ++s) v[s] = P.has_ground ? cz[s] - P.ground_z : kInf;
+    for (int g = 0; g < P.n_groups; ++g) {
+        const GroupDev gr = ldg(P.groups, g);
+        const float4 *c = P.cyl + gr.start;
+        float a[G];
+#pragma unroll
+        for (int s = 0; s < G; ++s) a[s] = kInf;
+        if (P.pair_filter) {
+            // start at the cylinders around the azimuth of the wave's first sphere
+            const float ang = atan2f(first_lane(cy[0]), first_lane(cx[0]));
+            int bin = (int)((ang + 3.14159265f) * (kAngleBins / 6.28318531f));
+            bin = min(max(bin, 0), kAngleBins - 1);
+            const int start = ldg(P.angle_start, g * kAngleBins + bin);
+            const float reach = gr.rmax + 1e-4f;
+            float thr[G];
+#pragma unroll
+            for (int s = 0; s < G; ++s) thr[s] = kInf;
+            for (int o = start; o < gr.count; o += 4) cyl_chunk_filtered<G>(cx, cy, c + o, a, thr, reach);
+            for (int o = 0; o < start; o += 4) cyl_chunk_filtered<G>(cx, cy, c + o, a, thr, reach);
+        } else {
+            for (int o = 0; o < gr.count; o += 4) cyl_chunk<G>(cx, cy, c + o, a);
+        }
+#pragma unroll
+        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], cyl_combine(a[s], fabsf(cz[s] - gr.zc) - gr.hz));
+    }
+    for (int o = 0; o < P.n_box; ++o) {
+        const float4 b0 = ldg(P.box, 2 * o), b1 = ldg(P.box, 2 * o + 1);
+#pragma unroll
+        for (int s = 0; s < G; ++s) v[s] = fminf(v[s], box_sd(cx[s], cy[s], cz[s], b0, b1));
+    }
+}
+
 }  // namespace cp

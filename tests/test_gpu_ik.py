@@ -245,20 +245,22 @@ def test_ik_solve_parity_forest_clear_targets(cp):
 
 
 def test_ik_solve_forest_with_restarts(cp):
-    """The batched workload's shape (c1 forest, random restarts; a reduced
-    target count).  Most targets lie among the trees, so most trajectories
-    cross the collision term, a minimum over sphere-obstacle pairs whose
-    minimising pair switches: there a perturbation of the start in the last
-    place changes the minimum the oracle itself reaches, and row-by-row
-    agreement is not defined.  Checked instead: every row's reported cost is
+    """The batched workload's shape (c1 forest, grasp poses clear of it,
+    random restarts; a reduced target count).  The restarts start all over
+    the forest, so most trajectories cross the collision term, a minimum
+    over sphere-obstacle pairs whose minimising pair switches: there a
+    perturbation of the start in the last place changes the minimum the
+    oracle itself reaches, and row-by-row agreement is not defined.  Checked instead: every row's reported cost is
     the oracle's cost at the returned configuration, no row ends above its
     start's cost, every row stays within the limits; rows whose oracle
     iterates stay out of collision agree; the rest agree in distribution
     (most rows reach the oracle's minimum, neither side systematically
     lower, and the best over the restarts matches for most targets); the
     best row of each group is the lowest device cost (bit-exact)."""
-    prob = synth.ik_c1(n_targets=24, restarts=8)
-    m = oracle.Model(prob.robot, prob.scene, None)
+    cand = synth.ik_c1(n_targets=24, restarts=8)
+    m = oracle.Model(cand.robot, cand.scene, None)
+    d = oracle.eval_configs(m, cand.q_star.astype(np.float64))[0]
+    prob = cand.pick(d > synth.IK_TARGET_CLEARANCE)
     T = np.stack([_pose(m, q) for q in prob.q_star]).astype(np.float32)
     T = np.repeat(T, prob.restarts, axis=0)
     N = T.shape[0]

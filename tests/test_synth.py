@@ -60,13 +60,22 @@ def test_workload_endpoints_clear_of_self_collision(orc, name):
 
 
 def test_ik_workload_layout():
-    p = synth.ik_c1(n_targets=32, restarts=4)
+    p = synth.ik_c1(n_targets=32, restarts=4, oversample=3)
     n = p.robot.n_joints
-    assert p.q_star.shape == (32, n) and p.q_init.shape == (32 * 4, n)
+    assert p.q_star.shape == (96, n) and p.q_init.shape == (96 * 4, n)
     assert p.q_star.dtype == np.float32 and p.q_init.dtype == np.float32
     lo, hi = p.robot.q_min, p.robot.q_max
     assert np.all(p.q_init >= lo) and np.all(p.q_init <= hi)
     assert np.all(p.q_star >= lo) and np.all(p.q_star <= hi)
     # the first start of every target is the crane's start configuration
-    np.testing.assert_array_equal(p.q_init.reshape(32, 4, n)[:, 0], np.broadcast_to(p.q_ref, (32, n)))
+    np.testing.assert_array_equal(p.q_init.reshape(96, 4, n)[:, 0], np.broadcast_to(p.q_ref, (96, n)))
     assert len(p.robot.self_pairs) > 0
+    # picking keeps the first n_targets marked candidates with their own starts
+    mask = np.zeros(96, bool)
+    mask[1::2] = True
+    q = p.pick(mask)
+    assert q.q_star.shape == (32, n) and q.q_init.shape == (128, n)
+    np.testing.assert_array_equal(q.q_star, p.q_star[1:64:2])
+    np.testing.assert_array_equal(q.q_init.reshape(32, 4, n), p.q_init.reshape(96, 4, n)[1:64:2])
+    with pytest.raises(ValueError):
+        p.pick(np.zeros(96, bool))
