@@ -61,14 +61,16 @@ class _Robot(ctypes.Structure):
                 ("q_hold", ctypes.c_void_p), ("active", ctypes.c_void_p), ("n_spheres", ctypes.c_int32),
                 ("sphere_frame", ctypes.c_void_p), ("sphere_center", ctypes.c_void_p),
                 ("sphere_radius", ctypes.c_void_p), ("tip", ctypes.c_void_p), ("n_self", ctypes.c_int32),
-                ("self_pairs", ctypes.c_void_p)]
+                ("self_pairs", ctypes.c_void_p), ("n_hulls", ctypes.c_int32), ("hull_frame", ctypes.c_void_p),
+                ("hull_box", ctypes.c_void_p)]
 
 
 class _Scene(ctypes.Structure):
     _fields_ = [("has_ground", ctypes.c_int32), ("ground_z", ctypes.c_float), ("n_cyl", ctypes.c_int32),
                 ("cyl", ctypes.c_void_p), ("n_box", ctypes.c_int32), ("box", ctypes.c_void_p),
                 ("sdf", ctypes.c_void_p), ("sdf_dims", ctypes.c_int32 * 3),
-                ("sdf_origin", ctypes.c_float * 3), ("voxel", ctypes.c_float)]
+                ("sdf_origin", ctypes.c_float * 3), ("voxel", ctypes.c_float), ("narrow", ctypes.c_int32),
+                ("n_obb", ctypes.c_int32), ("obb", ctypes.c_void_p)]
 
 
 class _Cost(ctypes.Structure):
@@ -105,6 +107,9 @@ def lib():
         L.orc_edt_brute.argtypes = [vp, ctypes.c_uint8, vp, vp]
         L.orc_edt_separable.argtypes = [vp, ctypes.c_uint8, vp, vp]
         L.orc_sdf_from_edt.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.c_float, vp]
+        L.orc_sat_obb_f.argtypes = [vp, vp]
+        L.orc_sat_obb_f.restype = ctypes.c_double
+        L.orc_hulls_world.argtypes = [vp, vp, vp]
         L.orc_so3_log.argtypes = [vp, vp]
         L.orc_so3_jr_inv.argtypes = [vp, vp]
         L.orc_ik_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -146,6 +151,10 @@ class Model:
         pairs = np.asarray(getattr(robot, "self_pairs", np.zeros((0, 2))), np.int32).reshape(-1, 2)
         r.n_self = int(pairs.shape[0])
         r.self_pairs = keep(pairs if pairs.size else np.zeros((1, 2)), np.int32)
+        hb = np.asarray(getattr(robot, "hull_box", np.zeros((0, 15))), np.float32).reshape(-1, 15)
+        r.n_hulls = int(hb.shape[0])
+        r.hull_frame = keep(getattr(robot, "hull_frame", np.zeros(0)) if hb.size else np.zeros(1), np.int32)
+        r.hull_box = keep(hb if hb.size else np.zeros((1, 15)), np.float32)
         s = _Scene()
         s.has_ground = int(scene.has_ground)
         s.ground_z = float(scene.ground_z)
@@ -161,6 +170,13 @@ class Model:
             s.voxel = float(sdf_spec.voxel)
         else:
             s.sdf = None
+        s.narrow = int(getattr(scene, "narrow", 0))
+        ob = np.asarray(getattr(scene, "obb", np.zeros((0, 15))), np.float32).reshape(-1, 15)
+        s.n_obb = int(ob.shape[0])
+        s.obb = keep(ob if ob.size else np.zeros((1, 15)), np.float32)
+        if s.narrow == 1 and r.n_hulls == 0:
+            raise ValueError("the separating-axis narrow phase needs the robot's hulls")
+        self.sat = s.narrow == 1
         c = _Cost()
         if cost is not None:
             c.K, c.M, c.interp, c.jp_mode, c.hinge = cost.K, cost.M, cost.interp, cost.jp_mode, cost.hinge
@@ -197,6 +213,22 @@ def fk(model: Model, q):
     tip = np.zeros(3)
     lib().orc_fk(model.pr, _p(q), _p(frames), _p(cen), _p(tip))
     return frames, cen, tip
+
+
+def sat_obb(a, b) -> float:
+    """SAT signed distance of two oriented boxes (rows of 15: centre,
+    rotation row-major with the box axes as columns, half extents)."""
+    a = np.ascontiguousarray(a, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    return float(lib().orc_sat_obb_f(_p(a), _p(b)))
+
+
+def hulls_world(model: Model, q) -> np.ndarray:
+    """The robot's hulls in world coordinates at q, [H,15]."""
+    q = np.ascontiguousarray(q, np.float64)
+    out = np.zeros((model.r.n_hulls, 15))
+    lib().orc_hulls_world(model.pr, _p(q), _p(out))
+    return out
 
 
 def sd_cylinder(c, cyl, grad=False):
@@ -272,6 +304,8 @@ def eval_paths(model: Model, q_start, q_goal, W, per_checkpoint: bool = False):
 
 def grad_paths(model: Model, q_start, q_goal, W):
     """Analytic d cost / d W [B,K,n] and the cost [B]."""
+    if model.sat:
+        raise ValueError("the separating-axis narrow phase has no gradient here")
     W = np.ascontiguousarray(W, np.float64)
     B = W.shape[0]
     qs = np.ascontiguousarray(q_start, np.float64)
@@ -329,6 +363,8 @@ def ik_residual(model: Model, par, target, q, q_ref, jacobian: bool = True):
     """Residual r [8+n] of the IK problem at q, its Jacobian [8+n, n] (or
     None) and info = (|p_g - p_d|, |Log(R_d^T R_g)|, d(q), |g_p|, argmin
     sphere, argmin obstacle).  ``target`` is R_d row-major then p_d [12]."""
+    if model.sat:
+        raise ValueError("the IK takes the sphere narrow phase")
     n = model.robot.n_joints
     lam = ik_weights(par)
     t = np.ascontiguousarray(target, np.float64)

@@ -48,6 +48,9 @@ typedef struct {
     const float *tip;              /* [3] */
     int32_t n_self;                /* frame pairs checked for self-collision */
     const int32_t *self_pairs;     /* [n_self][2] frame indices */
+    int32_t n_hulls;               /* convex hulls (oriented boxes) of the links */
+    const int32_t *hull_frame;     /* [H] frame of each hull */
+    const float *hull_box;         /* [H][15] centre, rotation (row-major, box axes as columns), half extents */
 } orc_robot;
 
 typedef struct {
@@ -61,6 +64,9 @@ typedef struct {
     int32_t sdf_dims[3];      /* nx ny nz */
     float sdf_origin[3];
     float voxel;
+    int32_t narrow;           /* 0: spheres against the primitives above; 1: hulls against obb (SAT) */
+    int32_t n_obb;
+    const float *obb;         /* [n_obb][15] oriented boxes, the layout of hull_box, world coordinates */
 } orc_scene;
 
 typedef struct {
@@ -286,6 +292,152 @@ static double sd_obstacle(const orc_scene *sc, int o, const double c[3], double 
     return orc_sd_box(c, sc->box + 6 * (o - 1 - sc->n_cyl), grad);
 }
 
+/* ------------------------------------------------------------------------ */
+/* separating-axis narrow phase on oriented boxes (Sec. 3.1)                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double c[3], R[9], h[3]; } orc_obb;
+
+/* Gap of the projections of two boxes onto the unit axis n: the distance
+ * between their centres along n less the two half-widths of the projections
+ * (a box's half-width along n is the sum over its axes of h_i |a_i . n|).
+ * Positive: n separates them by that much; negative: they overlap along n. */
+static double sat_gap(const orc_obb *A, const orc_obb *B, const double n[3]) {
+    double t = 0.0, ra = 0.0, rb = 0.0;
+    for (int i = 0; i < 3; ++i) t += (B->c[i] - A->c[i]) * n[i];
+    for (int i = 0; i < 3; ++i) {
+        double pa = A->R[i] * n[0] + A->R[3 + i] * n[1] + A->R[6 + i] * n[2];
+        double pb = B->R[i] * n[0] + B->R[3 + i] * n[1] + B->R[6 + i] * n[2];
+        ra += A->h[i] * fabs(pa);
+        rb += B->h[i] * fabs(pb);
+    }
+    return fabs(t) - ra - rb;
+}
+
+/* a cross-product axis a_i x b_j is taken only when |a_i x b_j|^2 exceeds
+ * this (edges further than about 3 mrad from parallel); for parallel edges
+ * the face axes already contain every separating direction */
+#define ORC_SAT_PARALLEL 1e-5
+
+/* SAT signed distance of two oriented boxes: the largest projection gap over
+ * the fifteen candidate axes of the separating axis theorem (the three face
+ * normals of each box and the cross products of their edge directions).
+ * Positive: the boxes are disjoint and at least this far apart (exactly this
+ * far when the nearest features are a face and anything, or two edges);
+ * negative or zero: they intersect, and minus the value is the penetration
+ * depth along the best axis (for boxes the minimum over all directions). */
+double orc_sat_obb(const orc_obb *A, const orc_obb *B) {
+    double best = -INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        double na[3] = {A->R[i], A->R[3 + i], A->R[6 + i]};
+        double nb[3] = {B->R[i], B->R[3 + i], B->R[6 + i]};
+        double ga = sat_gap(A, B, na), gb = sat_gap(A, B, nb);
+        if (ga > best) best = ga;
+        if (gb > best) best = gb;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double a[3] = {A->R[i], A->R[3 + i], A->R[6 + i]};
+            double b[3] = {B->R[j], B->R[3 + j], B->R[6 + j]};
+            double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+            double l2 = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+            if (!(l2 > ORC_SAT_PARALLEL)) continue;
+            double l = sqrt(l2);
+            for (int k = 0; k < 3; ++k) n[k] /= l;
+            double g = sat_gap(A, B, n);
+            if (g > best) best = g;
+        }
+    return best;
+}
+
+static void obb_load(const float *f, orc_obb *o) {
+    for (int i = 0; i < 3; ++i) o->c[i] = f[i];
+    for (int i = 0; i < 9; ++i) o->R[i] = f[3 + i];
+    for (int i = 0; i < 3; ++i) o->h[i] = f[12 + i];
+}
+
+/* hull k of the robot in world coordinates at frames F */
+static void hull_world(const orc_robot *rb, const xform *F, int k, orc_obb *o) {
+    orc_obb l;
+    obb_load(rb->hull_box + 15 * k, &l);
+    const xform *T = &F[rb->hull_frame[k]];
+    xf_apply(T, l.c, o->c);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m) s += T->R[3 * i + m] * l.R[3 * m + j];
+            o->R[3 * i + j] = s;
+        }
+    for (int i = 0; i < 3; ++i) o->h[i] = l.h[i];
+}
+
+/* signed distance of a box above the ground plane: its lowest point's height */
+static double obb_ground(const orc_obb *o, double gz) {
+    return o->c[2] - (o->h[0] * fabs(o->R[6]) + o->h[1] * fabs(o->R[7]) + o->h[2] * fabs(o->R[8])) - gz;
+}
+
+/* d(q) with the SAT narrow phase: the minimum over every (hull, obstacle)
+ * pair, the obstacles being the ground (0) and the scene's boxes (1..n_obb),
+ * and over the hull pairs of listed frame pairs (recorded as hull a and
+ * obstacle 0xFF00 + b, a < b).  Ties keep the lowest hull, then its obstacles
+ * in number order, then its self pairs by the other hull. */
+static double config_distance_sat(const orc_robot *rb, const orc_scene *sc, const double *q, int32_t *arg_s,
+                                  int32_t *arg_o, double *second) {
+    xform F[ORC_MAXJ + 1];
+    fk_frames(rb, q, F);
+    double best = INFINITY, best2 = INFINITY;
+    int bs = -1, bo = -1;
+    orc_obb hw[64];
+    int H = rb->n_hulls < 64 ? rb->n_hulls : 64;
+    for (int k = 0; k < H; ++k) hull_world(rb, F, k, &hw[k]);
+    for (int k = 0; k < H; ++k) {
+        for (int o = 0; o <= sc->n_obb; ++o) {
+            double d;
+            if (o == 0) {
+                if (!sc->has_ground) continue;
+                d = obb_ground(&hw[k], (double)sc->ground_z);
+            } else {
+                orc_obb b;
+                obb_load(sc->obb + 15 * (o - 1), &b);
+                d = orc_sat_obb(&hw[k], &b);
+            }
+            if (d < best) { best2 = best; best = d; bs = k; bo = o; }
+            else if (d < best2) best2 = d;
+        }
+        for (int m = k + 1; m < H; ++m) {
+            if (rb->n_self == 0 || !self_listed(rb, rb->hull_frame[k], rb->hull_frame[m])) continue;
+            double d = orc_sat_obb(&hw[k], &hw[m]);
+            if (d < best) { best2 = best; best = d; bs = k; bo = ORC_OBS_SELF + m; }
+            else if (d < best2) best2 = d;
+        }
+    }
+    if (arg_s) *arg_s = bs;
+    if (arg_o) *arg_o = bo;
+    if (second) *second = best2;
+    return best;
+}
+
+/* SAT distance of two boxes given as 15 floats each (tests) */
+double orc_sat_obb_f(const double *a, const double *b) {
+    orc_obb A, B;
+    for (int i = 0; i < 3; ++i) { A.c[i] = a[i]; B.c[i] = b[i]; A.h[i] = a[12 + i]; B.h[i] = b[12 + i]; }
+    for (int i = 0; i < 9; ++i) { A.R[i] = a[3 + i]; B.R[i] = b[3 + i]; }
+    return orc_sat_obb(&A, &B);
+}
+
+/* the robot's hulls in world coordinates at q, [H][15] */
+void orc_hulls_world(const orc_robot *rb, const double *q, double *out) {
+    xform F[ORC_MAXJ + 1];
+    fk_frames(rb, q, F);
+    for (int k = 0; k < rb->n_hulls; ++k) {
+        orc_obb o;
+        hull_world(rb, F, k, &o);
+        for (int i = 0; i < 3; ++i) out[15 * k + i] = o.c[i];
+        for (int i = 0; i < 9; ++i) out[15 * k + 3 + i] = o.R[i];
+        for (int i = 0; i < 3; ++i) out[15 * k + 12 + i] = o.h[i];
+    }
+}
+
 /* d(q): minimum over every (sphere, obstacle) pair of sd(centre) - radius,
  * and over every self-collision pair (spheres a < b on a listed frame pair)
  * of |c_a - c_b| - r_a - r_b (Sec. 3.2 names self-collision beside collision
@@ -293,6 +445,7 @@ static double sd_obstacle(const orc_scene *sc, int o, const double c[3], double 
  * number order, then its self pairs by the other sphere. */
 double orc_config_distance(const orc_robot *rb, const orc_scene *sc, const double *q,
                            int32_t *arg_s, int32_t *arg_o, double *second) {
+    if (sc->narrow == 1) return config_distance_sat(rb, sc, q, arg_s, arg_o, second);
     xform F[ORC_MAXJ + 1];
     fk_frames(rb, q, F);
     double best = INFINITY, best2 = INFINITY;
@@ -464,6 +617,10 @@ static void point_jacobian_col(const orc_robot *rb, const xform *F, int j, const
 /* gradient of d(q) with respect to q through the minimising pair */
 static void distance_grad_q(const orc_robot *rb, const orc_scene *sc, const double *q, int s, int o,
                             double *gq) {
+    if (sc->narrow == 1) {  /* no gradient for the separating-axis distance (refused by the wrapper) */
+        for (int j = 0; j < rb->n_joints; ++j) gq[j] = 0.0;
+        return;
+    }
     xform F[ORC_MAXJ + 1];
     fk_frames(rb, q, F);
     double l[3], c[3], gc[3];

@@ -63,6 +63,11 @@ class Robot:
     # frame pairs whose spheres are checked against each other (self-collision);
     # empty: the environment only
     self_pairs: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 2), np.int32))
+    # convex hulls of the links for the separating-axis narrow phase: oriented
+    # boxes, row = centre (3), rotation (9, row-major, the box axes as its
+    # columns), half extents (3), in the coordinates of frame hull_frame[k]
+    hull_frame: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.int32))
+    hull_box: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 15), np.float32))
 
     @property
     def n_joints(self) -> int:
@@ -88,6 +93,11 @@ class Scene:
     box: np.ndarray          # f32 [Ob,6]
     has_ground: int = 1
     ground_z: float = 0.0
+    # separating-axis narrow phase (narrow = 1): the robot's hulls against
+    # these oriented boxes (rows as Robot.hull_box, world coordinates) and the
+    # ground; cyl and box are then not used
+    narrow: int = 0
+    obb: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 15), np.float32))
 
     @property
     def n_cyl(self) -> int:
@@ -96,6 +106,10 @@ class Scene:
     @property
     def n_box(self) -> int:
         return int(self.box.shape[0])
+
+    @property
+    def n_obb(self) -> int:
+        return int(self.obb.shape[0])
 
 
 @dataclasses.dataclass
@@ -169,8 +183,11 @@ class IkParams:
 class IkProblem:
     """Batched IK: the tip poses of the configurations ``q_star`` [N,n] are the
     targets; ``q_init`` [N*R,n] holds R starting configurations per target
-    (rows r*... grouped by target: rows i*R .. i*R+R-1 belong to target i);
-    ``q_ref`` [n] is the crane's current configuration (regularisation)."""
+    (rows i*R .. i*R+R-1 belong to target i); ``q_ref`` [n] is the crane's
+    current configuration (regularisation).  As drawn, ``q_star`` holds
+    candidate configurations, more than ``n_targets``; a workload is the first
+    ``n_targets`` of them whose grasp pose is clear of the scene (``pick``),
+    clearance being judged by whoever uses the workload."""
 
     name: str
     robot: Robot
@@ -180,6 +197,17 @@ class IkProblem:
     q_ref: np.ndarray
     restarts: int
     params: IkParams
+    n_targets: int = 0
+
+    def pick(self, clear: np.ndarray) -> "IkProblem":
+        """The first ``n_targets`` candidates with ``clear`` set (a boolean per
+        candidate) and their starting configurations."""
+        idx = np.flatnonzero(np.asarray(clear, bool))[: self.n_targets]
+        if len(idx) < self.n_targets:
+            raise ValueError(f"only {len(idx)} clear candidates for {self.n_targets} targets")
+        n = self.robot.n_joints
+        q_init = self.q_init.reshape(-1, self.restarts, n)[idx].reshape(-1, n)
+        return dataclasses.replace(self, q_star=self.q_star[idx], q_init=np.ascontiguousarray(q_init))
 
 
 @dataclasses.dataclass
@@ -274,6 +302,46 @@ def with_self_collision(robot: Robot) -> Robot:
     """The same crane with its non-adjacent link pairs checked for
     self-collision."""
     return dataclasses.replace(robot, self_pairs=crane_self_pairs(robot))
+
+
+def _obb_row(c, R, h) -> np.ndarray:
+    return np.concatenate([np.asarray(c, np.float64), np.asarray(R, np.float64).reshape(9),
+                           np.asarray(h, np.float64)])
+
+
+def with_hulls(robot: Robot) -> Robot:
+    """The crane with one oriented box per link segment for the
+    separating-axis narrow phase: the segment's extent along its own
+    direction plus, across it and beyond its ends, the largest radius of the
+    segment's spheres (the box holds every sphere of the segment).  Segments
+    run along a frame axis, so each box's axes are its frame's."""
+    L1, L2, L3, L4, L5 = (float(x) for x in robot.link_lengths)
+    segs = [(1, (0.0, 0.0, 1.0), (0.0, 0.0, L1)), (2, (0.0, 0.0, 0.0), (L2, 0.0, 0.0)),
+            (3, (0.0, 0.0, 0.0), (L3, 0.0, 0.0)), (4, (0.0, 0.0, 0.0), (L4, 0.0, 0.0)),
+            (6, (0.0, 0.0, 0.0), (0.0, 0.0, -L5))]
+    frames, rows = [], []
+    for f, a, b in segs:
+        a, b = np.array(a), np.array(b)
+        r = float(robot.sphere_radius[robot.sphere_frame == f].max())
+        h = np.abs(b - a) / 2.0 + r
+        frames.append(f)
+        rows.append(_obb_row((a + b) / 2.0, np.eye(3), h))
+    return dataclasses.replace(robot, hull_frame=np.array(frames, np.int32), hull_box=_f32(rows))
+
+
+def hull_scene(rng: np.random.Generator, scene: Scene) -> Scene:
+    """The scene's obstacles as oriented boxes for the separating-axis narrow
+    phase: a tree of radius R over [z0, z1] becomes an upright square prism
+    of half width R turned about z by an angle U(0, pi/2); a log pile keeps
+    its box."""
+    rows = []
+    for x, y, R, z0, z1 in scene.cyl.astype(np.float64):
+        t = rng.uniform(0.0, math.pi / 2)
+        c, s = math.cos(t), math.sin(t)
+        rows.append(_obb_row((x, y, 0.5 * (z0 + z1)), [[c, -s, 0], [s, c, 0], [0, 0, 1]], (R, R, 0.5 * (z1 - z0))))
+    for cx, cy, cz, hx, hy, hz in scene.box.astype(np.float64):
+        rows.append(_obb_row((cx, cy, cz), np.eye(3), (hx, hy, hz)))
+    return dataclasses.replace(scene, narrow=1, obb=_f32(np.array(rows).reshape(-1, 15)))
 
 
 def make_endpoints(rng: np.random.Generator, robot: Robot):
@@ -476,24 +544,31 @@ def hanging_configs(rng: np.random.Generator, robot: Robot, N: int) -> np.ndarra
     return _f32(q)
 
 
-def ik_c1(n_targets: int = 1024, restarts: int = 8) -> IkProblem:
+def ik_c1(n_targets: int = 1024, restarts: int = 8, oversample: int = 24) -> IkProblem:
     """Batched collision-free IK on the c1_full crane (with its non-adjacent
-    link pairs checked for self-collision) and scene: the grasp poses of
-    ``n_targets`` hanging configurations, ``restarts`` starting points each
-    (the crane's start configuration, then configurations uniform within
-    the joint limits with the swing joints at 0)."""
+    link pairs checked for self-collision) and forest: ``oversample`` times
+    ``n_targets`` candidate hanging configurations, whose grasp poses are the
+    targets once the clear ones are picked (about 8 % of them keep 0.1 m from
+    every tree, log pile and link of the crane), ``restarts`` starting points
+    each (the crane's start configuration, then configurations uniform
+    within the joint limits with the swing joints at 0)."""
     base = c1_full()
     robot = with_self_collision(base.robot)
     rng = np.random.default_rng(SCENE_SEED + 5)
-    q_star = hanging_configs(rng, robot, n_targets)
-    q_init = np.empty((n_targets, restarts, robot.n_joints), np.float64)
+    n_cand = n_targets * oversample
+    q_star = hanging_configs(rng, robot, n_cand)
+    q_init = np.empty((n_cand, restarts, robot.n_joints), np.float64)
     q_init[:, 0, :] = base.q_start
     lo = robot.q_min.astype(np.float64)
     hi = robot.q_max.astype(np.float64)
-    q_init[:, 1:, :] = rng.uniform(lo, hi, size=(n_targets, restarts - 1, robot.n_joints))
+    q_init[:, 1:, :] = rng.uniform(lo, hi, size=(n_cand, restarts - 1, robot.n_joints))
     q_init[:, 1:, 4:] = 0.0
     return IkProblem("ik_c1", robot, base.scene, q_star, _f32(q_init.reshape(-1, robot.n_joints)),
-                     _f32(base.q_start), restarts, IkParams())
+                     _f32(base.q_start), restarts, IkParams(), n_targets=n_targets)
+
+
+# clearance of a grasp pose's configuration from the scene and the crane itself (m)
+IK_TARGET_CLEARANCE = 0.1
 
 
 WORKLOADS = {"c0_plain": c0_plain, "c1_full": c1_full, "c2_diff": c2_diff, "c4_sdf": c4_sdf}
