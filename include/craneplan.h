@@ -65,6 +65,7 @@ enum {
 #define CP_MAX_K 64
 #define CP_MAX_ELITES 4096
 #define CP_MAX_DIM 96 /* K * (number of sampled joints) */
+#define CP_MAX_HULLS 16
 
 enum { CP_REVOLUTE = 0, CP_PRISMATIC = 1 };
 enum { CP_INTERP_BSPLINE = 0, CP_INTERP_LINEAR = 1 };
@@ -73,6 +74,8 @@ enum { CP_HINGE_HARD = 0, CP_HINGE_SMOOTH = 1 };
 /* How much of the sphere-obstacle pair work is skipped; every mode returns
  * bitwise the same distances (see cp_cost_params.pair_filter). */
 enum { CP_PAIRS_ALL = 0, CP_PAIRS_LANE = 1, CP_PAIRS_WAVE = 2, CP_PAIRS_AUTO = 3 };
+/* narrow phase of d(q) (cp_scene_desc.narrow) */
+enum { CP_NARROW_SPHERES = 0, CP_NARROW_SAT = 1 };
 
 /* tape entry of a checkpoint: (sphere << 16) | obstacle, where obstacle 0 is
  * the ground, 1..n_cyl the cylinders, n_cyl+1..n_cyl+n_box the boxes, and
@@ -115,6 +118,14 @@ typedef struct {
     /* Tip (grapple centre point) in the last frame: the end-effector point
      * of the inverse kinematics, H_g = (R of frame n, R tip + p of frame n). */
     float tip[3];
+    /* Convex hulls of the links for the separating-axis narrow phase
+     * (scene.narrow = CP_NARROW_SAT): oriented boxes, row = centre (3),
+     * rotation (9, row-major, the box axes as its columns, orthonormal),
+     * half extents (3, > 0), in the coordinates of frame hull_frame[k]
+     * (0..n_joints).  0 / NULL without that narrow phase. */
+    int32_t n_hulls;             /* 0..CP_MAX_HULLS */
+    const int32_t *hull_frame;   /* [n_hulls] */
+    const float *hull_box;       /* [n_hulls][15] */
 } cp_robot_desc;
 
 /*
@@ -137,6 +148,28 @@ typedef struct {
     int32_t sdf_dims[3];         /* nx, ny, nz (each >= 2) */
     float sdf_origin[3];         /* lower corner of voxel (0,0,0), metres */
     float voxel;                 /* voxel edge, metres */
+    /* Narrow phase.  CP_NARROW_SPHERES: the robot's spheres against the
+     * primitives and grid above.  CP_NARROW_SAT (the separating axis test
+     * of Sec. 3.1 on convex hulls): d(q) is the minimum over every pair of a
+     * robot hull and an obstacle (the ground, then the oriented boxes obb in
+     * number order) of their SAT signed distance, and over the hull pairs of
+     * the listed self-collision frame pairs; cyl, box and d_sdf are then not
+     * used.  The SAT distance of two boxes is the largest projection gap
+     * over the fifteen candidate axes (each box's three face normals and the
+     * cross products of their edge directions, an edge pair within about
+     * 5.7 degrees of parallel, |a x b|^2 <= 0.01, giving none): positive, a
+     * lower bound of their
+     * Euclidean distance (exact when the nearest features are a face and
+     * anything, or two edges); otherwise minus the penetration depth.  A
+     * hull against the ground: its lowest corner's height above ground_z.
+     * The tape records (hull << 16) | obstacle, obstacle 0 the ground,
+     * 1..n_obb the boxes, CP_OBS_SELF + m a self pair of hulls k < m; equal
+     * distances keep the lowest hull, then obstacle.  This narrow phase
+     * has no adjoint (cp_eval_paths_backward, the polish, the population
+     * gradient and the IK refuse it) and does not run in batches. */
+    int32_t narrow;              /* CP_NARROW_* */
+    int32_t n_obb;               /* 0..65279 */
+    const float *obb;            /* [n_obb][15], the layout of hull_box, world coordinates */
 } cp_scene_desc;
 
 /* Cost of a path (Sec. 4.1, eqs. for J_p, J_c, J_l).  The collision term is

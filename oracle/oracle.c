@@ -315,13 +315,17 @@ static double sat_gap(const orc_obb *A, const orc_obb *B, const double n[3]) {
 }
 
 /* a cross-product axis a_i x b_j is taken only when |a_i x b_j|^2 exceeds
- * this (edges further than about 3 mrad from parallel); for parallel edges
- * the face axes already contain every separating direction */
-#define ORC_SAT_PARALLEL 1e-5
+ * this (edges more than about 5.7 degrees from parallel): for parallel edges
+ * the face axes already contain every separating direction, and for nearly
+ * parallel ones the axis direction is ill-determined (a rotation error e
+ * turns it by about e / |a_i x b_j|), so single-precision placements could
+ * not reproduce its gap */
+#define ORC_SAT_PARALLEL 1e-2
 
 /* SAT signed distance of two oriented boxes: the largest projection gap over
  * the fifteen candidate axes of the separating axis theorem (the three face
- * normals of each box and the cross products of their edge directions).
+ * normals of each box and the cross products of their edge directions,
+ * near-parallel edge pairs excepted).
  * Positive: the boxes are disjoint and at least this far apart (exactly this
  * far when the nearest features are a face and anything, or two edges);
  * negative or zero: they intersect, and minus the value is the penetration

@@ -29,6 +29,8 @@ CP_OBS_SDF = 0xFFFF
 # cp_cost_params.pair_filter: every pair / lane-level square-root skip / wave-level culling /
 # culling for scenes of at least 48 obstacles, else the lane filter
 PAIRS_ALL, PAIRS_LANE, PAIRS_WAVE, PAIRS_AUTO = 0, 1, 2, 3
+# cp_scene_desc.narrow: spheres against primitives / grid, or the separating axis test on hulls
+NARROW_SPHERES, NARROW_SAT = 0, 1
 EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_endpoints", "cp_plan_n_checkpoints",
            "cp_eval_paths", "cp_eval_paths_backward", "cp_optimizer_create", "cp_optimizer_destroy",
            "cp_optimizer_step", "cp_optimizer_get_state", "cp_optimizer_set_state", "cp_optimizer_last",
@@ -50,13 +52,13 @@ class _Robot(ctypes.Structure):
     _fields_ = [("n_joints", _c_i32), ("type", _vp), ("axis", _vp), ("origin", _vp), ("q_min", _vp),
                 ("q_max", _vp), ("q_hold", _vp), ("active", _vp), ("n_spheres", _c_i32), ("sphere_frame", _vp),
                 ("sphere_center", _vp), ("sphere_radius", _vp), ("n_self_pairs", _c_i32), ("self_pairs", _vp),
-                ("tip", _c_f32 * 3)]
+                ("tip", _c_f32 * 3), ("n_hulls", _c_i32), ("hull_frame", _vp), ("hull_box", _vp)]
 
 
 class _Scene(ctypes.Structure):
     _fields_ = [("has_ground", _c_i32), ("ground_z", _c_f32), ("n_cyl", _c_i32), ("cyl", _vp), ("n_box", _c_i32),
                 ("box", _vp), ("d_sdf", _vp), ("sdf_dims", _c_i32 * 3), ("sdf_origin", _c_f32 * 3),
-                ("voxel", _c_f32)]
+                ("voxel", _c_f32), ("narrow", _c_i32), ("n_obb", _c_i32), ("obb", _vp)]
 
 
 class _Cost(ctypes.Structure):
@@ -177,6 +179,10 @@ def _fill_robot(r, robot, keep):
     tip = _host(getattr(robot, "tip", np.zeros(3)), np.float32).reshape(3)
     for a in range(3):
         r.tip[a] = float(tip[a])
+    hb = _host(getattr(robot, "hull_box", np.zeros((0, 15))), np.float32).reshape(-1, 15)
+    r.n_hulls = int(hb.shape[0])
+    r.hull_frame = _keep_ptr(keep, robot.hull_frame, np.int32) if hb.size else None
+    r.hull_box = _keep_ptr(keep, hb, np.float32) if hb.size else None
 
 
 def _fill_scene(s, scene, keep, sdf=None, sdf_spec=None):
@@ -186,6 +192,10 @@ def _fill_scene(s, scene, keep, sdf=None, sdf_spec=None):
     s.cyl = _keep_ptr(keep, scene.cyl, np.float32) if s.n_cyl else None
     s.n_box = int(scene.box.shape[0])
     s.box = _keep_ptr(keep, scene.box, np.float32) if s.n_box else None
+    s.narrow = int(getattr(scene, "narrow", 0))
+    ob = _host(getattr(scene, "obb", np.zeros((0, 15))), np.float32).reshape(-1, 15)
+    s.n_obb = int(ob.shape[0])
+    s.obb = _keep_ptr(keep, ob, np.float32) if ob.size else None
     if sdf is not None:
         s.d_sdf = sdf.data_ptr()
         for a in range(3):

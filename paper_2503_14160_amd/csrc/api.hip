@@ -134,13 +134,15 @@ struct cp_plan {
     double2 *d_partial = nullptr;
     float *d_sdf_lb = nullptr;
     float *d_clr = nullptr;
+    float4 *d_hulls = nullptr, *d_obb = nullptr;
+    int2 *d_hull_self = nullptr;
     PlanView view{};
 
     ~cp_plan() {
         DeviceGuard g(device);
         void *bufs[] = {d_joints, d_spheres, d_sphere_slot, d_frame_start, d_cyl,  d_cyl_cell, d_cell_start, d_hint, d_groups,
                         d_angle_start, d_cyl_orig, d_box, d_qs, d_qg, d_partial, d_sdf_lb, d_clr,
-                        d_self_pairs, d_frame_bound};
+                        d_self_pairs, d_frame_bound, d_hulls, d_obb, d_hull_self};
         for (void *p : bufs)
             if (p) (void)hipFree(p);
     }
@@ -252,6 +254,31 @@ static int validate_plan_args(const cp_robot_desc *r, const cp_scene_desc *s, co
         for (int a = 0; a < 3; ++a)
             if (s->sdf_dims[a] < 2) return fail(CP_ERR_SIZE, "sdf dims must be >= 2");
         if (!(s->voxel > 0.0f)) return fail(CP_ERR_INVALID_ARG, "sdf voxel must be > 0");
+    }
+    if (s->narrow != CP_NARROW_SPHERES && s->narrow != CP_NARROW_SAT) return fail(CP_ERR_INVALID_ARG, "bad narrow");
+    if (r->n_hulls < 0 || r->n_hulls > CP_MAX_HULLS) return fail(CP_ERR_SIZE, "n_hulls out of range");
+    if (r->n_hulls > 0 && (!r->hull_frame || !r->hull_box)) return fail(CP_ERR_INVALID_ARG, "null hull table");
+    if (s->n_obb < 0 || s->n_obb > (int)CP_OBS_SELF - 1) return fail(CP_ERR_SIZE, "n_obb out of range");
+    if (s->n_obb > 0 && !s->obb) return fail(CP_ERR_INVALID_ARG, "null obb table");
+    if (s->narrow == CP_NARROW_SAT && r->n_hulls < 1)
+        return fail(CP_ERR_INVALID_ARG, "the SAT narrow phase needs the robot's hulls");
+    if (s->narrow == CP_NARROW_SAT && s->d_sdf) return fail(CP_ERR_INVALID_ARG, "the SAT narrow phase takes no grid");
+    for (int k = 0; k < r->n_hulls + s->n_obb; ++k) {
+        const bool hull = k < r->n_hulls;
+        const float *b = hull ? r->hull_box + 15 * k : s->obb + 15 * (k - r->n_hulls);
+        if (hull && (r->hull_frame[k] < 0 || r->hull_frame[k] > r->n_joints))
+            return fail(CP_ERR_INVALID_ARG, "bad hull frame");
+        for (int i = 0; i < 15; ++i)
+            if (!finite(b[i])) return fail(CP_ERR_INVALID_ARG, "non-finite box");
+        if (!(b[12] > 0.0f && b[13] > 0.0f && b[14] > 0.0f)) return fail(CP_ERR_INVALID_ARG, "box half extents must be > 0");
+        // the rotation must be orthonormal (R^T R = I)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double d = 0.0;
+                for (int m = 0; m < 3; ++m) d += (double)b[3 + 3 * m + i] * b[3 + 3 * m + j];
+                if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-4)
+                    return fail(CP_ERR_INVALID_ARG, "box rotation is not orthonormal");
+            }
     }
     if (c->K < 1 || c->K > CP_MAX_K || c->M < 1) return fail(CP_ERR_SIZE, "K or M out of range");
     if (c->interp != CP_INTERP_BSPLINE && c->interp != CP_INTERP_LINEAR) return fail(CP_ERR_INVALID_ARG, "bad interp");
@@ -505,8 +532,36 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
         }
         frame_bound[f] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)(rad * (1.0 + 1e-6) + 1e-6));
     }
+    // separating-axis narrow phase: hulls (caller order) and scene boxes as
+    // four float4 each, the hull's frame in the last word; hull pairs of the
+    // listed frame pairs (k < m), sorted
+    auto pack_box = [](const float *b, int frame, std::vector<float4> &out) {
+        out.push_back(make_float4(b[0], b[1], b[2], b[12]));
+        out.push_back(make_float4(b[3], b[4], b[5], b[13]));
+        out.push_back(make_float4(b[6], b[7], b[8], b[14]));
+        float fw;
+        std::memcpy(&fw, &frame, sizeof(fw));
+        out.push_back(make_float4(b[9], b[10], b[11], fw));
+    };
+    std::vector<float4> hulls, obb;
+    for (int k = 0; k < robot->n_hulls; ++k) pack_box(robot->hull_box + 15 * k, robot->hull_frame[k], hulls);
+    for (int o = 0; o < scene->n_obb; ++o) pack_box(scene->obb + 15 * o, 0, obb);
+    std::vector<int2> hull_self;
+    for (int k = 0; k < robot->n_hulls; ++k)
+        for (int m = k + 1; m < robot->n_hulls; ++m) {
+            const int fa = robot->hull_frame[k], fb = robot->hull_frame[m];
+            bool listed = false;
+            for (int i = 0; i < robot->n_self_pairs; ++i) {
+                const int a = robot->self_pairs[2 * i], b = robot->self_pairs[2 * i + 1];
+                listed = listed || (a == fa && b == fb) || (a == fb && b == fa);
+            }
+            if (listed) hull_self.push_back(make_int2(k, m));
+        }
     std::vector<float> hold(robot->q_hold, robot->q_hold + p->n);
     hipError_t e;
+    if ((e = upload(&p->d_hulls, hulls)) != hipSuccess || (e = upload(&p->d_obb, obb)) != hipSuccess ||
+        (e = upload(&p->d_hull_self, hull_self)) != hipSuccess)
+        return bail(hip_fail(e, "plan hull tables"));
     if ((e = upload(&p->d_joints, p->joints)) != hipSuccess || (e = upload(&p->d_spheres, spheres)) != hipSuccess ||
         (e = upload(&p->d_sphere_slot, sphere_slot)) != hipSuccess ||
         (e = upload(&p->d_frame_start, frame_start)) != hipSuccess || (e = upload(&p->d_cyl, cyl)) != hipSuccess ||
@@ -546,6 +601,13 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     v.self_pairs = p->d_self_pairs;
     v.frame_bound = p->d_frame_bound;
     for (int a = 0; a < 3; ++a) v.tip[a] = robot->tip[a];
+    v.narrow = scene->narrow;
+    v.n_hulls = robot->n_hulls;
+    v.n_obb = scene->n_obb;
+    v.n_hull_self = (int)hull_self.size();
+    v.hulls = p->d_hulls;
+    v.obb = p->d_obb;
+    v.hull_self = p->d_hull_self;
     v.sdf = scene->d_sdf;
     for (int a = 0; a < 3; ++a) {
         v.sdf_n[a] = scene->d_sdf ? scene->sdf_dims[a] : 2;
@@ -663,6 +725,7 @@ int cp_eval_paths_backward(cp_plan *plan, const float *d_waypoints, int32_t B, c
                            const float *d_grad_cost, float *d_grad_waypoints, cp_stream_t stream) {
     if (!plan || !d_waypoints || !d_grad_cost || !d_grad_waypoints) return fail(CP_ERR_INVALID_ARG, "null argument");
     if (B < 1 || B > plan->max_B) return fail(CP_ERR_SIZE, "B out of range (1..max_B)");
+    if (plan->view.narrow == CP_NARROW_SAT) return fail(CP_ERR_INVALID_ARG, "the SAT narrow phase has no adjoint");
     DeviceGuard g(plan->device);
     CP_HIP(launch_eval_bwd(plan->view, d_waypoints, B, d_tape, d_grad_cost, d_grad_waypoints, (hipStream_t)stream),
            "backward launch");
@@ -725,6 +788,7 @@ int cp_ik_solve(cp_plan *plan, const cp_ik_params *params, const float *d_target
     if (N < 1 || N > kMaxIkRows) return fail(CP_ERR_SIZE, "N out of range (1..1048576)");
     if (restarts < 1 || N % restarts != 0) return fail(CP_ERR_SIZE, "N must be a positive multiple of restarts");
     if (d_best && !d_info) return fail(CP_ERR_INVALID_ARG, "d_best needs d_info (the rows' costs)");
+    if (plan->view.narrow == CP_NARROW_SAT) return fail(CP_ERR_INVALID_ARG, "the IK takes the sphere narrow phase");
     DeviceGuard g(plan->device);
     CP_HIP(launch_ik_solve(plan->view, *params, d_target, d_q_init, d_q_ref, N, restarts, d_q, d_info, d_status,
                            d_best, (hipStream_t)stream),
@@ -737,6 +801,7 @@ int cp_debug_ik_residual(cp_plan *plan, const cp_ik_params *params, const float 
     if (!plan || !d_target || !d_q) return fail(CP_ERR_INVALID_ARG, "null argument");
     if (int rc = validate_ik_params(params)) return rc;
     if (N < 1 || N > kMaxIkRows) return fail(CP_ERR_SIZE, "N out of range (1..1048576)");
+    if (plan->view.narrow == CP_NARROW_SAT) return fail(CP_ERR_INVALID_ARG, "the IK takes the sphere narrow phase");
     DeviceGuard g(plan->device);
     CP_HIP(launch_ik_residual(plan->view, *params, d_target, d_q, d_q_ref, N, d_r, d_J, (hipStream_t)stream),
            "IK residual launch");
@@ -760,6 +825,8 @@ int cp_optimizer_create(cp_plan *plan, const cp_opt_params *prm, cp_opt **out) {
     if (prm->polish_elites > 0 && prm->polish_steps > 0 &&
         (!(prm->polish_eta >= 0.0f) || !(prm->polish_clip > 0.0f)))
         return fail(CP_ERR_INVALID_ARG, "bad polish step");
+    if (prm->polish_elites > 0 && prm->polish_steps > 0 && plan->view.narrow == CP_NARROW_SAT)
+        return fail(CP_ERR_INVALID_ARG, "the polish needs the adjoint, which the SAT narrow phase has not");
     int n_act = 0;
     int act[CP_MAX_JOINTS] = {0};
     for (int j = 0; j < plan->n; ++j)
@@ -885,6 +952,8 @@ int cp_optimizer_step(cp_opt *opt, int32_t n_iters, cp_stream_t stream) {
 
 int cp_optimizer_record_tape(cp_opt *opt, int32_t enable) {
     if (!opt) return fail(CP_ERR_INVALID_ARG, "null optimizer");
+    if (enable && opt->plan->view.narrow == CP_NARROW_SAT)
+        return fail(CP_ERR_INVALID_ARG, "the population gradient needs the adjoint, which the SAT narrow phase has not");
     DeviceGuard g(opt->plan->device);
     CP_HIP(hipDeviceSynchronize(), "sync");
     if (!enable) {
@@ -1126,6 +1195,8 @@ int cp_batch_create(int32_t n, const cp_robot_desc *robots, const cp_scene_desc 
         if (costs[i].max_B < opts[i].B) return fail(CP_ERR_SIZE, "cost max_B below opt B");
         if (costs[i].pair_filter != costs[0].pair_filter)
             return fail(CP_ERR_INVALID_ARG, "every problem of a batch needs the same pair_filter");
+        if (scenes[i].narrow != CP_NARROW_SPHERES)
+            return fail(CP_ERR_INVALID_ARG, "batches take the sphere narrow phase");
     }
     cp_batch *b = new (std::nothrow) cp_batch();
     if (!b) return fail(CP_ERR_NOMEM, "host allocation");

@@ -488,44 +488,6 @@ __device__ __forceinline__ uint32_t argmin_of(const PlanView &P, const Best &bes
                 : argmin_obstacle(P, best.cx, best.cy, best.cz);
 }
 
-// Configuration of checkpoint k of path b: q (all joints) and the step
-// q_k - q_{k-1}; also the span window start j and the weights.
-__device__ __forceinline__ void interpolate(const PlanView &P, const float *Wb, int k, float (&q)[CP_MAX_JOINTS],
-                                            float (&dq)[CP_MAX_JOINTS], int &j, float (&bw)[4], float (&db)[4]) {
-    checkpoint_weights(P, k, j, bw, db);
-    const float *p0 = control_point(P, Wb, j), *p1 = control_point(P, Wb, j + 1);
-    const float *p2 = control_point(P, Wb, j + 2), *p3 = control_point(P, Wb, j + 3);
-#pragma unroll
-    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
-        if (i < P.n_joints) {
-            float a0 = ldg(p0, i), a1 = ldg(p1, i), a2 = ldg(p2, i), a3 = ldg(p3, i);
-            q[i] = __builtin_fmaf(bw[0], a0, __builtin_fmaf(bw[1], a1, __builtin_fmaf(bw[2], a2, bw[3] * a3)));
-            // differences centred on the second control point (the db sum to zero)
-            dq[i] = __builtin_fmaf(db[0], a0 - a1, __builtin_fmaf(db[2], a2 - a1, db[3] * (a3 - a1)));
-        } else {
-            q[i] = 0.0f;
-            dq[i] = 0.0f;
-        }
-    }
-}
-
-// J_p and J_l terms of one checkpoint
-__device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[CP_MAX_JOINTS],
-                                           const float (&dq)[CP_MAX_JOINTS], float &jp, float &jl) {
-    float sq = 0.0f, lim = 0.0f;
-#pragma unroll
-    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
-        if (i < P.n_joints) {
-            sq = __builtin_fmaf(dq[i], dq[i], sq);
-            const JointDev J = ldg(P.joints, i);
-            float hi = fmaxf(q[i] - J.qmax, 0.0f), lo = fmaxf(J.qmin - q[i], 0.0f);
-            lim = __builtin_fmaf(hi, hi, __builtin_fmaf(lo, lo, lim));
-        }
-    }
-    jp = P.jp_mode == CP_JP_SQUARED ? sq : fsqrt(sq);
-    jl = lim;
-}
-
 // Per-lane minima of the waves of a workgroup (up to 8), for merging split parts.
 struct MergeBuf {
     float d[8][kWave], r[8][kWave], v[8][kWave], cx[8][kWave], cy[8][kWave], cz[8][kWave];
@@ -595,16 +557,7 @@ __device__ __forceinline__ void eval_one(const PlanView &P, const float *__restr
     if (TAPE && active) {
         tape[g] = ((uint32_t)best.s << 16) | argmin_of<CULL>(P, best);
     }
-    float dk = best.d;
-    if (!active) { c = 0.0f; dk = kInf; }
-
-    // per-path sums of this wave
-    const int bl = active ? b : -1;
-    for (int p = p0; p <= p1; ++p) {
-        double s = wave_sum_d(bl == p ? (double)c : 0.0);
-        float m = wave_min(bl == p ? dk : kInf);
-        if ((threadIdx.x & (kWave - 1)) == 0) partial[w * slots + (p - p0)] = make_double2(s, (double)m);
-    }
+    path_partials(active ? b : -1, c, best.d, p0, p1, w, partial, slots);
 }
 
 // The culling path holds more state than the plain pair loop; five waves per
@@ -1062,6 +1015,15 @@ hipError_t launch_eval_fwd(const PlanView &P0, const float *W, int B, double2 *p
     }
     const int64_t N = (int64_t)B * P.ns;
     const int slots = eval_slots(P.ns);
+    if (P.narrow == CP_NARROW_SAT) {
+        hipError_t e = launch_eval_fwd_sat(P, W, B, partial, tape, st);
+        if (e != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev->end, st)) != hipSuccess) return e;
+        if (!cost && !min_dist && !flags) return hipSuccess;
+        hipLaunchKernelGGL(k_eval_reduce, dim3((B + 255) / 256), dim3(256), 0, st, partial, slots, B, P.ns, P.margin,
+                           cost, min_dist, flags);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((N + 255) / 256));
     const bool cull = use_cull(P);
     const int64_t waves = (N + kWave - 1) / kWave;
@@ -1167,6 +1129,7 @@ hipError_t launch_debug_fk(const PlanView &P, const float *Q, int N, float *cent
 }
 
 hipError_t launch_debug_configs(const PlanView &P, const float *Q, int N, float *dist, uint32_t *arg, hipStream_t st) {
+    if (P.narrow == CP_NARROW_SAT) return launch_debug_configs_sat(P, Q, N, dist, arg, st);
     if (use_cull(P))
         hipLaunchKernelGGL(k_debug_configs<true>, dim3((N + 255) / 256), dim3(256), 0, st, P, Q, N, dist, arg);
     else

@@ -101,6 +101,15 @@ struct PlanView {
     const int2 *self_pairs;
     const float4 *frame_bound;    // [n_joints + 1]
     float tip[3];                 // end-effector point in the last frame
+    // separating-axis narrow phase (narrow = CP_NARROW_SAT): the link hulls
+    // and the scene's oriented boxes, four float4 per box:
+    // (cx, cy, cz, hx), (R00, R01, R02, hy), (R10, R11, R12, hz),
+    // (R20, R21, R22, frame as int bits; 0 for scene boxes)
+    int32_t narrow;
+    int32_t n_hulls, n_obb, n_hull_self;
+    const float4 *hulls;          // [n_hulls][4], caller order
+    const float4 *obb;            // [n_obb][4]
+    const int2 *hull_self;        // [n_hull_self] hull pairs (k < m) of listed frame pairs, sorted
 };
 
 // ---------------------------------------------------------------------------
@@ -691,6 +700,62 @@ __device__ __forceinline__ void spheres_min_sd(const PlanView &P, const float (&
         const float4 b0 = ldg(P.box, 2 * o), b1 = ldg(P.box, 2 * o + 1);
 #pragma unroll
         for (int s = 0; s < G; ++s) v[s] = fminf(v[s], box_sd(cx[s], cy[s], cz[s], b0, b1));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one configuration per lane: interpolation, per-checkpoint terms, per-path sums
+// ---------------------------------------------------------------------------
+
+// Configuration of checkpoint k of path b: q (all joints) and the step
+// q_k - q_{k-1}; also the span window start j and the weights.
+__device__ __forceinline__ void interpolate(const PlanView &P, const float *Wb, int k, float (&q)[CP_MAX_JOINTS],
+                                            float (&dq)[CP_MAX_JOINTS], int &j, float (&bw)[4], float (&db)[4]) {
+    checkpoint_weights(P, k, j, bw, db);
+    const float *p0 = control_point(P, Wb, j), *p1 = control_point(P, Wb, j + 1);
+    const float *p2 = control_point(P, Wb, j + 2), *p3 = control_point(P, Wb, j + 3);
+#pragma unroll
+    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+        if (i < P.n_joints) {
+            float a0 = ldg(p0, i), a1 = ldg(p1, i), a2 = ldg(p2, i), a3 = ldg(p3, i);
+            q[i] = __builtin_fmaf(bw[0], a0, __builtin_fmaf(bw[1], a1, __builtin_fmaf(bw[2], a2, bw[3] * a3)));
+            // differences centred on the second control point (the db sum to zero)
+            dq[i] = __builtin_fmaf(db[0], a0 - a1, __builtin_fmaf(db[2], a2 - a1, db[3] * (a3 - a1)));
+        } else {
+            q[i] = 0.0f;
+            dq[i] = 0.0f;
+        }
+    }
+}
+
+// J_p and J_l terms of one checkpoint
+__device__ __forceinline__ void step_terms(const PlanView &P, const float (&q)[CP_MAX_JOINTS],
+                                           const float (&dq)[CP_MAX_JOINTS], float &jp, float &jl) {
+    float sq = 0.0f, lim = 0.0f;
+#pragma unroll
+    for (int i = 0; i < CP_MAX_JOINTS; ++i) {
+        if (i < P.n_joints) {
+            sq = __builtin_fmaf(dq[i], dq[i], sq);
+            const JointDev J = ldg(P.joints, i);
+            float hi = fmaxf(q[i] - J.qmax, 0.0f), lo = fmaxf(J.qmin - q[i], 0.0f);
+            lim = __builtin_fmaf(hi, hi, __builtin_fmaf(lo, lo, lim));
+        }
+    }
+    jp = P.jp_mode == CP_JP_SQUARED ? sq : fsqrt(sq);
+    jl = lim;
+}
+
+// Per-path sums of a wave: lane l holds checkpoint cost c and distance d of
+// path b (b = -1: a lane past the end); the wave covers paths p0..p1 and
+// writes, per path, the FP64 sum of its lanes' costs and their minimum
+// distance to partial[w * slots + (p - p0)] (fixed-order reductions).
+__device__ __forceinline__ void path_partials(int b, float c, float d, int p0, int p1, int64_t w,
+                                              double2 *__restrict__ partial, int slots) {
+    if (b < 0) { c = 0.0f; d = kInf; }
+    for (int p = p0; p <= p1; ++p) {
+        double s = wave_sum_d(b == p ? (double)c : 0.0);
+        float m = wave_min(b == p ? d : kInf);
+        if ((threadIdx.x & (kWave - 1)) == 0) partial[w * slots + (p - p0)] = make_double2(s, (double)m);
     }
 }
 

@@ -95,6 +95,13 @@ hipError_t launch_update(const PlanView &P, const OptView &O, hipStream_t st);
 hipError_t launch_chol(const OptView &O, hipStream_t st);
 hipError_t launch_init_state(const PlanView &P, const OptView &O, float sigma0, hipStream_t st);
 
+// separating-axis narrow phase (sat.hip): the forward pass into partial sums
+// (and the tape), and configuration distances
+hipError_t launch_eval_fwd_sat(const PlanView &P, const float *W, int B, double2 *partial, uint32_t *tape,
+                               hipStream_t st);
+hipError_t launch_debug_configs_sat(const PlanView &P, const float *Q, int N, float *dist, uint32_t *arg,
+                                    hipStream_t st);
+
 // collision-free inverse kinematics (ik.hip); best needs info
 hipError_t launch_ik_solve(const PlanView &P, const cp_ik_params &prm, const float *target, const float *q_init,
                            const float *q_ref, int N, int restarts, float *q_out, float *info, int32_t *status,
