@@ -15,7 +15,8 @@ Other workloads print their own line: c0_plain (small single problem),
 c2_diff (adjoint: fwd+bwd vs fwd, gradient error, polished iterations),
 c3_batch (many problems: batched graph launch vs one problem at a time),
 c4_sdf (lidar -> signed-distance grid, trilinear queries, fwd+bwd),
-ik (batched collision-free inverse kinematics with restarts).
+ik (batched collision-free inverse kinematics with restarts),
+sat (the separating-axis narrow phase on link hulls and oriented boxes).
 """
 import argparse
 import json
@@ -506,6 +507,90 @@ def cpu_baseline_ik(prob, T, rows=48):
                       f"another (C residual + numpy Levenberg-Marquardt, FP64), {dt:.1f} s"}
 
 
+# ----------------------------------------------------------------------------
+# sat: the separating-axis narrow phase on hulls
+# ----------------------------------------------------------------------------
+
+# algorithmic flops of the SAT distance of two oriented boxes: centre offset 3,
+# its components along both boxes' axes 6 x 5, the cosine matrix 9 x 5, six
+# face axes (half-width sum 5, |T| - two half-widths 2, maximum 1) 6 x 8, nine
+# cross axes (length 2, centre term 3, two half-widths 3 + 3, difference 2,
+# square root 1, division 1, maximum 1) 9 x 16; placing a hull (its chain,
+# centre and axes) 400, its ground distance 8; interpolation and step terms 200
+F_SAT_PAIR, F_HULL, F_HULL_GROUND, F_SAT_CONFIG = 270, 400, 8, 200
+
+
+def sat_problem():
+    import dataclasses
+
+    from paper_2503_14160_amd import synth
+    base = synth.c1_full()
+    robot = synth.with_self_collision(synth.with_hulls(base.robot))
+    scene = synth.hull_scene(np.random.default_rng(synth.SCENE_SEED + 7), base.scene)
+    return dataclasses.replace(base, name="c1_sat", robot=robot, scene=scene)
+
+
+def bench_sat(args, torch, cp, prob):
+    """sat: the c1 population (16384 paths x 608 checkpoints) with the
+    separating-axis narrow phase, 5 link hulls against the c1 forest as 528
+    oriented boxes and the ground (and the hull pairs of the non-adjacent
+    links): optimizer iterations from t = 0; plus the paper's collision
+    benchmark shape, 100 paths x 100 points in one evaluation launch."""
+    import dataclasses
+
+    from paper_2503_14160_amd import synth
+    out, plan, opt = bench_iterations(args, torch, cp, prob, with_roofline=False)
+    H = len(prob.robot.hull_box)
+    n_self = sum(1 for k in range(H) for m in range(k + 1, H)
+                 if any({int(prob.robot.hull_frame[k]), int(prob.robot.hull_frame[m])} == {int(a), int(b)}
+                        for a, b in prob.robot.self_pairs))
+    fpc = (H * (F_HULL + F_HULL_GROUND + prob.scene.n_obb * F_SAT_PAIR) + n_self * (F_SAT_PAIR + 2 * F_HULL)
+           + F_SAT_CONFIG)
+    configs = prob.opt.B * plan.n_s
+    eval_ms = out["eval_ms"]
+    out["config"].update(hulls=H, oriented_boxes=prob.scene.n_obb, hull_self_pairs=n_self, narrow="sat")
+    out["roofline"] = {"bound": "alu", "kernel": "k_eval_fwd_sat<false>", "unit": "TFLOP/s", "peak": PEAK_FP32 / 1e12,
+                       "launch_ms": eval_ms, "launches": out["eval_launches_timed"],
+                       "achieved": fpc * configs / (eval_ms * 1e-3) / 1e12,
+                       "frac": fpc * configs / (eval_ms * 1e-3) / PEAK_FP32, "flops_per_config": fpc,
+                       "traffic": None,
+                       "note": "algorithmic flops of every hull-box SAT test (15 axes), every hull placement and "
+                               "self pair over the launch: the kernel takes every pair"}
+    # the paper's shape: 100 paths, 100 checkpoints each (K = 7, M = 10: (7 + 3) x 10)
+    cost = dataclasses.replace(prob.cost, K=7, M=10)
+    small = cp.Plan(prob.robot, prob.scene, cost, max_B=100)
+    small.set_endpoints(prob.q_start, prob.q_goal)
+    rng = np.random.default_rng(5)
+    W = torch.from_numpy(synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, 100, 7, sigma=0.3)).cuda()
+    c = torch.empty(100, device="cuda")
+    md = torch.empty_like(c)
+    small.eval_into(W, c, md)
+    torch.cuda.synchronize()
+    e1_ms = _timed(torch, lambda: small.eval_into(W, c, md), args.eval_reps)
+    out["paper_shape"] = {"paths": 100, "checkpoints": small.n_s, "configs": 100 * small.n_s, "ms": e1_ms,
+                          "configs_per_s": 100 * small.n_s / (e1_ms * 1e-3),
+                          "paper_context": "10^4 configurations in 0.014 s on an RTX 4090 with MJX SAT on 32 "
+                                           "meshes (other hardware, other geometry)"}
+    return out
+
+
+def cpu_baseline_sat(prob, n_paths=256):
+    import oracle
+    oracle.build()
+    rng = np.random.default_rng(6)
+    from paper_2503_14160_amd import synth
+    W = synth.random_waypoints(rng, prob.robot, prob.q_start, prob.q_goal, n_paths, prob.cost.K, sigma=0.3)
+    m = oracle.Model(prob.robot, prob.scene, prob.cost)
+    t0 = time.perf_counter()
+    oracle.eval_paths(m, prob.q_start, prob.q_goal, W.astype(np.float64))
+    dt = time.perf_counter() - t0
+    n_cfg = n_paths * prob.cost.n_s
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_cfg / dt, "unit": "configs/s", "cores": min(threads, n_paths), "kind": "oracle",
+            "sample": f"{n_paths} random paths of the c1 shape with the SAT narrow phase ({n_cfg} configurations, "
+                      f"evaluation only), FP64, {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,7 +598,7 @@ def main():
                     help="timed iterations (default: the workload's iteration count, 50 for c1_full; 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c1_full",
-                    choices=["c1_full", "c1_self", "c0_plain", "c2_diff", "c3_batch", "c4_sdf", "ik"])
+                    choices=["c1_full", "c1_self", "c0_plain", "c2_diff", "c3_batch", "c4_sdf", "ik", "sat"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eval-reps", type=int, default=10)
     ap.add_argument("--batch-problems", type=int, default=256)
@@ -530,6 +615,8 @@ def main():
 
     if args.steps is None:
         args.steps = 50 if args.workload in ("c1_full", "c1_self", "c4_sdf") else 20
+        if args.workload == "sat":
+            args.steps = 10
     import torch
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
@@ -562,6 +649,12 @@ def main():
         out = bench_diff(args, torch, cp, synth.c2_diff())
     elif args.workload == "c3_batch":
         out = bench_batch(args, torch, cp, synth.c3_batch(args.batch_problems))
+    elif args.workload == "sat":
+        prob = sat_problem()
+        out = bench_sat(args, torch, cp, prob)
+        if not args.no_cpu_baseline:
+            print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline_sat(prob)
     elif args.workload == "ik":
         out, T, prob = bench_ik(args, torch, cp, synth.ik_c1())
         if not args.no_cpu_baseline:
