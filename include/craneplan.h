@@ -166,7 +166,10 @@ typedef struct {
      * 1..n_obb the boxes, CP_OBS_SELF + m a self pair of hulls k < m; equal
      * distances keep the lowest hull, then obstacle.  This narrow phase
      * has no adjoint (cp_eval_paths_backward, the polish, the population
-     * gradient and the IK refuse it) and does not run in batches. */
+     * gradient and the IK refuse it) and does not run in batches.  Unless
+     * cost.pair_filter is CP_PAIRS_ALL, a pair stops after the scene box's
+     * three face axes when their largest gap is above the configuration's
+     * running minimum (bitwise the same results). */
     int32_t narrow;              /* CP_NARROW_* */
     int32_t n_obb;               /* 0..65279 */
     const float *obb;            /* [n_obb][15], the layout of hull_box, world coordinates */

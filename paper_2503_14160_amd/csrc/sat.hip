@@ -7,6 +7,9 @@
 // from the base to the hull's frame, places the box, and takes the SAT
 // distance against every scene box (wave-uniform records, scalar loads) and
 // the ground; then the hull pairs of the listed self-collision frame pairs.
+// A pair whose gaps along the scene box's three face axes already exceed the
+// lane's running minimum stops there (about a third of the arithmetic): it
+// cannot lower or tie the minimum, so results are those of every axis.
 // The fifteen axes follow the separating axis test for oriented boxes of
 // Gottschalk, Lin and Manocha ("OBBTree", 1996): with C = A^T B (the cosines
 // between the boxes' axes) and T the centre offset in A's axes, a face axis
@@ -71,28 +74,39 @@ __device__ __forceinline__ float dot3(const float (&u)[3], const float (&v)[3]) 
     return __builtin_fmaf(u[0], v[0], __builtin_fmaf(u[1], v[1], u[2] * v[2]));
 }
 
-// SAT signed distance of boxes A and B: the largest gap over the fifteen axes
-__device__ __forceinline__ float sat_distance(const Box &A, const Box &B) {
-    float C[3][3], Ca[3][3], Ta[3], Tb[3];
+// SAT signed distance of boxes A and B: the largest gap over the fifteen
+// axes.  B's three face axes come first; if the largest of their gaps is
+// already above `bound` that partial maximum is returned (a lower bound of
+// the SAT value, so still above `bound`: a caller keeping the minimum below
+// `bound` is unaffected), otherwise every axis is taken.  The maximum is
+// exact in floating point, so the full value does not depend on the order.
+__device__ __forceinline__ float sat_distance(const Box &A, const Box &B, float bound) {
+    float C[3][3], Ca[3][3], Tb[3];
     const float T[3] = {B.c[0] - A.c[0], B.c[1] - A.c[1], B.c[2] - A.c[2]};
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        Ta[i] = dot3(T, A.a[i]);
-        Tb[i] = dot3(T, B.a[i]);
+    for (int j = 0; j < 3; ++j) {
+        Tb[j] = dot3(T, B.a[j]);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int i = 0; i < 3; ++i) {
             C[i][j] = dot3(A.a[i], B.a[j]);
             Ca[i][j] = fabsf(C[i][j]);
         }
     }
     float best = -kInf;
-    // face axes of A and of B
+    // face axes of B
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float ra = __builtin_fmaf(A.h[0], Ca[0][j], __builtin_fmaf(A.h[1], Ca[1][j], A.h[2] * Ca[2][j]));
+        best = fmaxf(best, fabsf(Tb[j]) - ra - B.h[j]);
+    }
+    if (best > bound) return best;
+    // face axes of A
+    float Ta[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
+        Ta[i] = dot3(T, A.a[i]);
         const float rb = __builtin_fmaf(B.h[0], Ca[i][0], __builtin_fmaf(B.h[1], Ca[i][1], B.h[2] * Ca[i][2]));
         best = fmaxf(best, fabsf(Ta[i]) - A.h[i] - rb);
-        const float ra = __builtin_fmaf(A.h[0], Ca[0][i], __builtin_fmaf(A.h[1], Ca[1][i], A.h[2] * Ca[2][i]));
-        best = fmaxf(best, fabsf(Tb[i]) - ra - B.h[i]);
     }
     // cross axes a_i x b_j
 #pragma unroll
@@ -136,15 +150,18 @@ __device__ __forceinline__ SatMin sat_config_distance(const PlanView &P, const f
     SatMin m;
     m.d = kInf;
     m.key = 0xFFFFFFFFu;
+    // CP_PAIRS_ALL: every axis of every pair (no early exit)
+    const bool all = P.pair_filter == CP_PAIRS_ALL;
     for (int k = 0; k < P.n_hulls; ++k) {
         const Box A = hull_world(P, q, k);
         const uint32_t kk = (uint32_t)k << 16;
         if (P.has_ground) take(m, ground_distance(A, P.ground_z), kk);
-        for (int o = 0; o < P.n_obb; ++o) take(m, sat_distance(A, load_box(P.obb, o)), kk | (uint32_t)(1 + o));
+        for (int o = 0; o < P.n_obb; ++o)
+            take(m, sat_distance(A, load_box(P.obb, o), all ? kInf : m.d), kk | (uint32_t)(1 + o));
     }
     for (int p = 0; p < P.n_hull_self; ++p) {
         const int2 hp = ldg(P.hull_self, p);
-        take(m, sat_distance(hull_world(P, q, hp.x), hull_world(P, q, hp.y)),
+        take(m, sat_distance(hull_world(P, q, hp.x), hull_world(P, q, hp.y), all ? kInf : m.d),
              ((uint32_t)hp.x << 16) | (CP_OBS_SELF + (uint32_t)hp.y));
     }
     return m;

@@ -169,3 +169,26 @@ def test_sat_refusals(cp):
     p.opt = synth.OptParams(B=16, nu=2, sigma0=0.2, eps=1e-6, seed=1, T=1)
     with pytest.raises(cp.CranePlanError):
         cp.Batch([p])
+
+
+def test_sat_early_exit_is_exact(cp):
+    """Stopping a pair after the box's face axes (every pair_filter but
+    CP_PAIRS_ALL) gives bitwise the results of taking every axis: costs,
+    minimum distances, flags, tapes and configuration distances with their
+    pairs, on random paths and random configurations (many in collision)."""
+    base, robot, scene = _sat_problem()
+    cost = dataclasses.replace(base.cost, M=16)
+    B = 300
+    rng = np.random.default_rng(404)
+    W = torch.from_numpy(synth.random_waypoints(rng, robot, base.q_start, base.q_goal, B, cost.K, sigma=0.4)).cuda()
+    Q = synth.random_configs(rng, robot, 2000)
+    Q[:, 4:] = rng.uniform(-1.2, 1.2, size=(2000, 2)).astype(np.float32)
+    Q = torch.from_numpy(Q).cuda()
+    out = {}
+    for mode in (cp.PAIRS_ALL, cp.PAIRS_LANE, cp.PAIRS_WAVE, cp.PAIRS_AUTO):
+        plan = cp.Plan(robot, scene, cost, max_B=B, pair_filter=mode)
+        plan.set_endpoints(base.q_start, base.q_goal)
+        out[mode] = plan.eval(W, tape=True) + plan.debug_configs(Q)
+    for mode in (cp.PAIRS_LANE, cp.PAIRS_WAVE, cp.PAIRS_AUTO):
+        for a, b in zip(out[cp.PAIRS_ALL], out[mode]):
+            assert torch.equal(a, b), mode
