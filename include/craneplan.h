@@ -399,8 +399,10 @@ int cp_batch_get_tuning(const cp_batch *batch, cp_batch_tuning *tuning);
 
 /* Autotune the launch shape (SYNC): reuse the entry for this batch's shape
  * and device from the text cache at cache_path if there is one, else time
- * every candidate shape on this batch, keep the fastest and append it to the
- * cache (cache_path may be NULL: no cache).  The chosen shape is applied
+ * every candidate shape on this batch (rounds 1, 2, 4, 8, 16, 32 times
+ * workgroups per compute unit 0, 1, 2, 4, 8; each the median of three
+ * evaluation launches after a warm-up), keep the fastest and append it to
+ * the cache (cache_path may be NULL: no cache).  The chosen shape is applied
  * and returned in *chosen (may be NULL). */
 int cp_batch_tune(cp_batch *batch, const char *cache_path, cp_batch_tuning *chosen);
 /* Autotune (SYNC) whatever of plan and batch is given (either may be NULL,

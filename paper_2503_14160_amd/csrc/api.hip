@@ -1383,31 +1383,33 @@ int cp_batch_tune(cp_batch *b, const char *cache_path, cp_batch_tuning *chosen) 
         CP_HIP(hipEventCreate(&e0), "event");
         CP_HIP(hipEventCreate(&e1), "event");
         double best_ms = 1e300;
-        const int rounds_c[] = {1, 4, 16};
-        const int wg_c[] = {0, 2, 4, 8};
-        bool warm = false;
+        // every launch shape: rounds of 256 configurations per work item, and
+        // resident workgroups per compute unit (0: one workgroup per item);
+        // each timed three times after a warm-up launch, the median kept
+        const int rounds_c[] = {1, 2, 4, 8, 16, 32};
+        const int wg_c[] = {0, 1, 2, 4, 8};
+        constexpr int kReps = 3;
         for (int r : rounds_c)
             for (int w : wg_c) {
                 cp_batch_tuning t{r, w};
                 int rc = cp_batch_set_tuning(b, &t);
                 if (rc) return rc;
-                hipError_t e = hipSuccess;
-                if (!warm) {
-                    e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r,
-                                          b->grid(), b->cull, st);
-                    warm = true;
+                float ms[kReps];
+                hipError_t e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r,
+                                                 b->grid(), b->cull, st);
+                for (int k = 0; k < kReps && e == hipSuccess; ++k) {
+                    e = hipEventRecord(e0, st);
+                    if (e == hipSuccess)
+                        e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r,
+                                              b->grid(), b->cull, st);
+                    if (e == hipSuccess) e = hipEventRecord(e1, st);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms[k], e0, e1);
                 }
-                if (e == hipSuccess) e = hipEventRecord(e0, st);
-                if (e == hipSuccess)
-                    e = launch_batch_eval(b->d_probs, b->d_partial, b->n, b->max_B, b->d_items, b->n_items, r,
-                                          b->grid(), b->cull, st);
-                if (e == hipSuccess) e = hipEventRecord(e1, st);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
                 if (e != hipSuccess) return hip_fail(e, "tune timing");
-                if (ms < best_ms) {
-                    best_ms = ms;
+                std::sort(ms, ms + kReps);
+                if (ms[kReps / 2] < best_ms) {
+                    best_ms = ms[kReps / 2];
                     best = t;
                 }
             }
