@@ -519,7 +519,7 @@ def self_sphere_pairs(robot):
     return int(sum(counts[a] * counts[b] for a, b in np.asarray(robot.self_pairs).reshape(-1, 2)))
 
 
-def cpu_baseline_ik(prob, T, rows=48):
+def cpu_baseline_ik(prob, T, rows=1024):
     import oracle
     oracle.build()
     m = oracle.Model(prob.robot, prob.scene, None)
@@ -618,7 +618,7 @@ def bench_sat(args, torch, cp, prob):
     return out
 
 
-def cpu_baseline_sat(prob, n_paths=256):
+def cpu_baseline_sat(prob, n_paths=1024):
     import oracle
     oracle.build()
     rng = np.random.default_rng(6)

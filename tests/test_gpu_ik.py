@@ -324,3 +324,67 @@ def test_ik_edge_cases(cp):
     q, info, status, best = plan.ik_solve(par1, torch.from_numpy(T).cuda(), torch.from_numpy(qs).cuda())
     assert int(status[0]) == 1 and info[0, 5].item() == 0
     np.testing.assert_array_equal(q.cpu().numpy(), qs)
+
+
+def _grapple_crane(n_spheres):
+    """The crane of make_robot with n_spheres spheres, and two joints more at
+    the hanger's end (a rotator about z, actuated, and a tilt about x, not
+    actuated) carrying a grapple sphere each; the tip below the tilt."""
+    rb = synth.make_robot(1000 + 1, n_spheres)
+    L5 = float(rb.link_lengths[4])
+    return dataclasses.replace(
+        rb,
+        joint_type=np.concatenate([rb.joint_type, np.array([synth.REVOLUTE, synth.REVOLUTE], np.int32)]),
+        axis=np.concatenate([rb.axis, np.array([[0, 0, 1], [1, 0, 0]], np.float32)]),
+        origin=np.concatenate([rb.origin, np.array([[0, 0, -L5], [0, 0, -0.3]], np.float32)]),
+        q_min=np.concatenate([rb.q_min, np.array([-np.pi, -1.0], np.float32)]),
+        q_max=np.concatenate([rb.q_max, np.array([np.pi, 1.0], np.float32)]),
+        q_hold=np.concatenate([rb.q_hold, np.zeros(2, np.float32)]),
+        active=np.concatenate([rb.active, np.array([1, 0], np.uint8)]),
+        sphere_frame=np.concatenate([rb.sphere_frame, np.array([7, 8], np.int32)]),
+        sphere_center=np.concatenate([rb.sphere_center, np.array([[0, 0, -0.1], [0, 0, -0.4]], np.float32)]),
+        sphere_radius=np.concatenate([rb.sphere_radius, np.array([0.3, 0.25], np.float32)]),
+        tip=np.array([0, 0, -0.6], np.float32),
+        self_pairs=np.array([[1, 8], [2, 8], [3, 7]], np.int32))
+
+
+@pytest.mark.parametrize("joints,spheres", [(6, 100), (8, 40), (8, 98)])
+def test_ik_other_chain_sizes(cp, joints, spheres):
+    """The kernels instantiated for up to 8 joints and for two spheres per
+    lane: residual and Jacobian against the oracle in a forest, and solves
+    from starts near reachable poses over bare ground."""
+    base = synth.c1_full()
+    if joints == 6:
+        robot = synth.with_self_collision(synth.make_robot(1000 + 1, spheres))
+    else:
+        robot = _grapple_crane(spheres - 2)
+    n = robot.n_joints
+    assert n == joints and robot.n_spheres == spheres
+    rng = np.random.default_rng(341 + joints + spheres)
+    N = 96
+    lo, hi = robot.q_min.astype(np.float64), robot.q_max.astype(np.float64)
+    Q = rng.uniform(lo + 0.1 * (hi - lo), hi - 0.1 * (hi - lo), size=(N, n)).astype(np.float32)
+    m = oracle.Model(robot, base.scene, None)
+    qs = rng.uniform(lo + 0.1 * (hi - lo), hi - 0.1 * (hi - lo), size=(N, n))
+    T = np.stack([_pose(m, q) for q in qs]).astype(np.float32)
+    QR = rng.uniform(lo, hi, size=(N, n)).astype(np.float32)
+    par = synth.IkParams(lambda_q=0.8, lambda_c=5.0, lambda_e=2.0, lambda_r=0.1)
+    n_pair = _check_residuals(cp, robot, base.scene, par, Q, T, QR, f"{joints} joints, {spheres} spheres")
+    assert n_pair >= 5
+    # solves over bare ground from near the generating configurations
+    mo = oracle.Model(robot, _open_scene(), None)
+    qstar = rng.uniform(lo + 0.2 * (hi - lo), hi - 0.2 * (hi - lo), size=(32, n))
+    T = np.stack([_pose(mo, q) for q in qstar]).astype(np.float32)
+    Q0 = (qstar + rng.uniform(-0.1, 0.1, size=qstar.shape)).astype(np.float32)
+    QR = qstar.astype(np.float32)
+    # no equilibrium term: the generating configurations are not hanging ones, and the pose and the
+    # reference then pull towards the same point
+    par = synth.IkParams(max_iters=60, lambda_e=0.0)
+    q, info, status, _, ref = _solve_both(cp, robot, _open_scene(), par, T, Q0, QR, f"{joints} joints")
+    n_cmp = 0
+    for i, (qo, Fo, io, it, st) in enumerate(ref):
+        if st == 0 and io[0] > 1e-3:
+            continue
+        n_cmp += 1
+        assert abs(info[i, 0] - Fo) <= 1e-3 * Fo + 1e-6, (i, info[i, 0], Fo)
+    assert n_cmp >= 16
