@@ -23,10 +23,14 @@ Readings of the paper taken here (each is also listed in the design notes):
   as +inf (a NaN and a +inf then go by index).
 
 Parity status: every function here is pinned by a CPU test (closed forms,
-invariants, brute force, finite differences, published Philox vectors) except
-multi-iteration optimizer trajectories beyond one step, which are chaotic and
-"parity unpinned" (only one-step parity and convergence properties are
-checked).
+invariants, brute force, finite differences, published Philox vectors, scipy's
+rotation maps, MINPACK's Levenberg-Marquardt, exact box distances from a
+bound-constrained least-squares solve) except two chaotic iterations, which
+are "parity unpinned": multi-iteration optimizer trajectories beyond one step
+(one-step parity and convergence properties are checked), and IK trajectories
+that cross the collision term, where a switch of the minimising pair changes
+the rest of the solve (the residual, its Jacobian, single solves that stay
+clear of collision and the validity of every row are checked).
 """
 from __future__ import annotations
 
