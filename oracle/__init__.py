@@ -114,6 +114,7 @@ def lib():
         L.orc_sat_obb_f.argtypes = [vp, vp]
         L.orc_sat_obb_f.restype = ctypes.c_double
         L.orc_hulls_world.argtypes = [vp, vp, vp]
+        L.orc_crane_accel.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
         L.orc_so3_log.argtypes = [vp, vp]
         L.orc_so3_jr_inv.argtypes = [vp, vp]
         L.orc_ik_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -438,6 +439,239 @@ def ik_solve(model: Model, par, target, q_init, q_ref, trace: Optional[list] = N
             mu *= nu
             nu *= 2.0
     return q, F, info, it, status
+
+# ----------------------------------------------------------------------------
+# step two: reduced dynamics and direct collocation (Sec. 2.1, Sec. 4.2)
+# ----------------------------------------------------------------------------
+
+def crane_accel(model: Model, q, qd, u, grav: float, damping: float) -> np.ndarray:
+    """Joint accelerations of the reduced dynamics (u: the actuated joints'
+    accelerations in joint order)."""
+    n = model.robot.n_joints
+    q = np.ascontiguousarray(q, np.float64)
+    qd = np.ascontiguousarray(qd, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    out = np.zeros(n)
+    lib().orc_crane_accel(model.pr, _p(q), _p(qd), _p(u), float(grav), float(damping), _p(out))
+    return out
+
+
+def traj_f(model: Model, par, x, u) -> np.ndarray:
+    """Right-hand side of x' = f(x, u), x = (q, qd)."""
+    n = model.robot.n_joints
+    return np.concatenate([x[n:], crane_accel(model, x[:n], x[n:], u, par.grav, par.damping)])
+
+
+def traj_f_jac(model: Model, par, x, u):
+    """df/dx [2n, 2n] and df/du [2n, n_a] by central differences (steps
+    par.fd_q on positions, 1 on velocities and inputs)."""
+    n = model.robot.n_joints
+    na = len(u)
+    Jx = np.zeros((2 * n, 2 * n))
+    Ju = np.zeros((2 * n, na))
+    for i in range(2 * n):
+        h = par.fd_q if i < n else 1.0
+        e = np.zeros(2 * n)
+        e[i] = h
+        Jx[:, i] = (traj_f(model, par, x + e, u) - traj_f(model, par, x - e, u)) / (2.0 * h)
+    for i in range(na):
+        e = np.zeros(na)
+        e[i] = 1.0
+        Ju[:, i] = (traj_f(model, par, x, u + e) - traj_f(model, par, x, u - e)) / 2.0
+    return Jx, Ju
+
+
+class TrajLayout:
+    """Unknowns z of the collocation problem: per time point k = 0..N the
+    state x_k (for 1 <= k <= N-1; x_0 and x_N are fixed) and the input u_k,
+    time-major, then s with t_F = s^2.  Residuals r: the N defects (2n each,
+    scaled), the state bounds of the interior points (4n each: q above its
+    upper limit, below its lower one, qd above v_max, below -v_max), the
+    input terms sqrt(omega_s) u_k and tracking terms sqrt(omega_t)
+    (q_a,k - q*_a,k) for k = 1..N (n_a each), then s."""
+
+    def __init__(self, n: int, na: int, N: int):
+        self.n, self.na, self.N = n, na, N
+        self.off = np.zeros(N + 2, np.int64)
+        for k in range(N + 1):
+            size = na + (2 * n if 0 < k < N else 0)
+            self.off[k + 1] = self.off[k] + size
+        self.s = int(self.off[N + 1])
+        self.nz = self.s + 1
+        self.r_def = 0
+        self.r_bnd = N * 2 * n
+        self.r_u = self.r_bnd + (N - 1) * 4 * n
+        self.r_q = self.r_u + N * na
+        self.r_s = self.r_q + N * na
+        self.nr = self.r_s + 1
+
+    def x_at(self, z, k):
+        return None if k in (0, self.N) else z[self.off[k]:self.off[k] + 2 * self.n]
+
+    def u_at(self, z, k):
+        o = self.off[k] + (2 * self.n if 0 < k < self.N else 0)
+        return z[o:o + self.na]
+
+
+def _traj_bounds(model, par):
+    rb = model.robot
+    lo = np.concatenate([np.asarray(rb.q_min, np.float64), -np.asarray(par.v_max, np.float64)])
+    hi = np.concatenate([np.asarray(rb.q_max, np.float64), np.asarray(par.v_max, np.float64)])
+    return lo, hi
+
+
+def traj_residual(model: Model, par, q_start, q_goal, q_star, z, lam, mu, jacobian: bool = True):
+    """Residual r [nr] of the collocation problem at z (augmented Lagrangian
+    with multipliers lam [N, 2n] and penalty mu on the defects) and its
+    Jacobian [nr, nz] (or None).  q_star [N+1, n]: the path's points."""
+    rb = model.robot
+    n = rb.n_joints
+    act = np.where(np.asarray(rb.active) != 0)[0]
+    na = len(act)
+    N = par.N
+    L = TrajLayout(n, na, N)
+    xs = np.concatenate([np.asarray(q_start, np.float64), np.zeros(n)])
+    xg = np.concatenate([np.asarray(q_goal, np.float64), np.zeros(n)])
+    X = [xs] + [L.x_at(z, k) for k in range(1, N)] + [xg]
+    U = [L.u_at(z, k) for k in range(N + 1)]
+    s = z[L.s]
+    h2 = s * s / (2.0 * N)  # h / 2 with h = t_F / N
+    F = [traj_f(model, par, X[k], U[k]) for k in range(N + 1)]
+    r = np.zeros(L.nr)
+    J = np.zeros((L.nr, L.nz)) if jacobian else None
+    sm = math.sqrt(mu)
+    for k in range(N):
+        d = X[k + 1] - X[k] - h2 * (F[k] + F[k + 1])
+        r[2 * n * k:2 * n * (k + 1)] = sm * (d + lam[k] / mu)
+    lo, hi = _traj_bounds(model, par)
+    for k in range(1, N):
+        o = L.r_bnd + 4 * n * (k - 1)
+        x = X[k]
+        r[o:o + 2 * n] = sm * np.maximum(x - hi, 0.0)
+        r[o + 2 * n:o + 4 * n] = sm * np.maximum(lo - x, 0.0)
+    for k in range(1, N + 1):
+        r[L.r_u + na * (k - 1):L.r_u + na * k] = math.sqrt(par.omega_s) * U[k]
+        r[L.r_q + na * (k - 1):L.r_q + na * k] = math.sqrt(par.omega_t) * (X[k][act] - np.asarray(q_star[k], np.float64)[act])
+    r[L.r_s] = s
+    if not jacobian:
+        return r, None
+    Jf = [traj_f_jac(model, par, X[k], U[k]) for k in range(N + 1)]
+    I = np.eye(2 * n)
+    for k in range(N):
+        rows = slice(2 * n * k, 2 * n * (k + 1))
+        for kk, sign in ((k, -1.0), (k + 1, 1.0)):
+            Jx, Ju = Jf[kk]
+            if 0 < kk < N:
+                J[rows, L.off[kk]:L.off[kk] + 2 * n] = sm * (sign * I - h2 * Jx)
+            uo = L.off[kk] + (2 * n if 0 < kk < N else 0)
+            J[rows, uo:uo + na] = sm * (-h2 * Ju)
+        J[rows, L.s] = sm * (-(s / N) * (F[k] + F[k + 1]))
+    for k in range(1, N):
+        o = L.r_bnd + 4 * n * (k - 1)
+        x = X[k]
+        for i in range(2 * n):
+            if x[i] > hi[i]:
+                J[o + i, L.off[k] + i] = sm
+            if x[i] < lo[i]:
+                J[o + 2 * n + i, L.off[k] + i] = -sm
+    for k in range(1, N + 1):
+        uo = L.off[k] + (2 * n if 0 < k < N else 0)
+        for i in range(na):
+            J[L.r_u + na * (k - 1) + i, uo + i] = math.sqrt(par.omega_s)
+            if k < N:
+                J[L.r_q + na * (k - 1) + i, L.off[k] + act[i]] = math.sqrt(par.omega_t)
+    J[L.r_s, L.s] = 1.0
+    return r, J
+
+
+def traj_initial(model: Model, par, q_start, q_goal, q_star):
+    """Starting point: the path's points at times k t_f0 / N, velocities and
+    inputs from their differences, s = sqrt(t_f0)."""
+    rb = model.robot
+    n = rb.n_joints
+    act = np.where(np.asarray(rb.active) != 0)[0]
+    N = par.N
+    L = TrajLayout(n, len(act), N)
+    h = par.t_f0 / N
+    Q = np.asarray(q_star, np.float64).copy()
+    Q[0], Q[N] = q_start, q_goal
+    V = np.zeros_like(Q)
+    V[1:N] = (Q[2:] - Q[:N - 1]) / (2.0 * h)
+    z = np.zeros(L.nz)
+    for k in range(N + 1):
+        if 0 < k < N:
+            z[L.off[k]:L.off[k] + n] = Q[k]
+            z[L.off[k] + n:L.off[k] + 2 * n] = V[k]
+        uo = L.off[k] + (2 * n if 0 < k < N else 0)
+        z[uo:uo + len(act)] = ((V[k + 1] - V[k]) / h)[act] if k < N else 0.0
+    z[L.s] = math.sqrt(par.t_f0)
+    return z
+
+
+def traj_refine(model: Model, par, q_start, q_goal, q_star, trace: Optional[list] = None):
+    """Step two (Sec. 4.2, eq. discrete): augmented Lagrangian on the
+    trapezoidal defects around Levenberg-Marquardt (the damping schedule of
+    the IK).  Per outer iteration: minimise |r|^2 / 2 by LM from the current
+    point, then lam += mu d (d the defects), mu *= mu_factor.  Returns
+    dict(t_f, X [N+1, 2n], U [N+1, n_a], z, defect (max |d|), F (the last
+    |r|^2 / 2), iters (trial steps over all outer iterations))."""
+    rb = model.robot
+    n = rb.n_joints
+    act = np.where(np.asarray(rb.active) != 0)[0]
+    N = par.N
+    L = TrajLayout(n, len(act), N)
+    z = traj_initial(model, par, q_start, q_goal, q_star)
+    lam = np.zeros((N, 2 * n))
+    mu = par.mu0
+    iters = 0
+    F = 0.0
+    for _ in range(par.outer):
+        r, J = traj_residual(model, par, q_start, q_goal, q_star, z, lam, mu)
+        F = 0.5 * float(r @ r)
+        A = J.T @ J
+        g = J.T @ r
+        damp = par.tau * float(np.max(np.diag(A)))
+        nu = 2.0
+        it = 0
+        while it < par.max_iters:
+            if float(np.max(np.abs(g))) <= par.eps_grad:
+                break
+            hstep = np.linalg.solve(A + damp * np.eye(L.nz), -g)
+            if float(np.linalg.norm(hstep)) <= par.eps_step * (float(np.linalg.norm(z)) + par.eps_step):
+                break
+            zn = z + hstep
+            rn, Jn = traj_residual(model, par, q_start, q_goal, q_star, zn, lam, mu)
+            Fn = 0.5 * float(rn @ rn)
+            pred = -float(hstep @ g) - 0.5 * float(hstep @ A @ hstep)
+            it += 1
+            if pred > 0.0 and F - Fn > 0.0:
+                rho = (F - Fn) / pred
+                z, r, J, F = zn, rn, Jn, Fn
+                A = J.T @ J
+                g = J.T @ r
+                damp *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+                nu = 2.0
+            else:
+                damp *= nu
+                nu *= 2.0
+        iters += it
+        # multiplier update from the defects at z
+        d = r[:N * 2 * n].reshape(N, 2 * n) / math.sqrt(mu) - lam / mu
+        lam = lam + mu * d
+        mu *= par.mu_factor
+        if trace is not None:
+            trace.append((z.copy(), F, float(np.max(np.abs(d)))))
+    X = np.zeros((N + 1, 2 * n))
+    U = np.zeros((N + 1, len(act)))
+    X[0, :n], X[N, :n] = q_start, q_goal
+    for k in range(N + 1):
+        if 0 < k < N:
+            X[k] = L.x_at(z, k)
+        U[k] = L.u_at(z, k)
+    r0, _ = traj_residual(model, par, q_start, q_goal, q_star, z, np.zeros((N, 2 * n)), 1.0, jacobian=False)
+    return dict(t_f=float(z[L.s] ** 2), X=X, U=U, z=z, defect=float(np.max(np.abs(r0[:N * 2 * n]))), F=F,
+                iters=iters)
+
 
 # ----------------------------------------------------------------------------
 # RNG

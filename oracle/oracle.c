@@ -944,6 +944,89 @@ void orc_ik_residual(const orc_robot *rb, const orc_scene *sc, const double *lam
 }
 
 /* ------------------------------------------------------------------------ */
+/* reduced dynamics (Sec. 2.1) and trapezoidal defects (Sec. 4.2)            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Joint accelerations of the reduced dynamics: the actuated joints
+ * (active[j] = 1) take the commanded accelerations u (in joint order, one per
+ * actuated joint); the passive ones follow from their rows of
+ * M(q) qdd + b(q, qd) = tau with no torque there,
+ *   qdd_p = -M_pp^-1 (M_pa qdd_a + b_p) - damping qd_p.
+ * Mass model (the crane's own is not given): a unit load at the tip on
+ * massless links, so M = J^T J and b = J^T (c + g e_z), with J = d tip / dq
+ * and c = sum_ij H_ij qd_i qd_j the tip's velocity-product acceleration
+ * (H_ij = d^2 tip / dq_i dq_j).  With the passive rows of M invertible this
+ * is the load's equation of motion projected on the passive joints.
+ */
+void orc_crane_accel(const orc_robot *rb, const double *q, const double *qd, const double *u, double grav,
+                     double damping, double *qdd) {
+    const int n = rb->n_joints;
+    xform F[ORC_MAXJ + 1];
+    fk_frames(rb, q, F);
+    double tl[3] = {rb->tip[0], rb->tip[1], rb->tip[2]}, p[3];
+    xf_apply(&F[n], tl, p);
+    double aw[ORC_MAXJ][3], piv[ORC_MAXJ][3], J[ORC_MAXJ][3];
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < 3; ++i)
+            aw[j][i] = F[j].R[3 * i] * rb->axis[3 * j] + F[j].R[3 * i + 1] * rb->axis[3 * j + 1] +
+                       F[j].R[3 * i + 2] * rb->axis[3 * j + 2];
+        for (int i = 0; i < 3; ++i) piv[j][i] = F[j + 1].p[i];
+        point_jacobian_col(rb, F, j, p, J[j]);
+    }
+    /* c = sum_ij H_ij qd_i qd_j */
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double h[3];
+            point_hessian(rb, aw, piv, p, i, j, h);
+            for (int k = 0; k < 3; ++k) c[k] += h[k] * qd[i] * qd[j];
+        }
+    /* tip acceleration from the actuated joints, plus c and gravity */
+    double a[3] = {c[0], c[1], c[2] + grav};
+    int pas[ORC_MAXJ], np_ = 0, ia = 0;
+    for (int j = 0; j < n; ++j) {
+        if (rb->active[j]) {
+            qdd[j] = u[ia++];
+            for (int k = 0; k < 3; ++k) a[k] += J[j][k] * qdd[j];
+        } else {
+            pas[np_++] = j;
+        }
+    }
+    if (np_ == 0) return;
+    /* M_pp x = -J_p^T a (Gaussian elimination with partial pivoting) */
+    double Mp[ORC_MAXJ][ORC_MAXJ + 1];
+    for (int r = 0; r < np_; ++r) {
+        for (int s2 = 0; s2 < np_; ++s2) {
+            double m = 0.0;
+            for (int k = 0; k < 3; ++k) m += J[pas[r]][k] * J[pas[s2]][k];
+            Mp[r][s2] = m;
+        }
+        double b = 0.0;
+        for (int k = 0; k < 3; ++k) b += J[pas[r]][k] * a[k];
+        Mp[r][np_] = -b;
+    }
+    for (int col = 0; col < np_; ++col) {
+        int piv_r = col;
+        for (int r = col + 1; r < np_; ++r)
+            if (fabs(Mp[r][col]) > fabs(Mp[piv_r][col])) piv_r = r;
+        if (piv_r != col)
+            for (int k = 0; k <= np_; ++k) { double t = Mp[col][k]; Mp[col][k] = Mp[piv_r][k]; Mp[piv_r][k] = t; }
+        for (int r = col + 1; r < np_; ++r) {
+            double f = Mp[r][col] / Mp[col][col];
+            for (int k = col; k <= np_; ++k) Mp[r][k] -= f * Mp[col][k];
+        }
+    }
+    double x[ORC_MAXJ];
+    for (int r = np_ - 1; r >= 0; --r) {
+        double t = Mp[r][np_];
+        for (int k = r + 1; k < np_; ++k) t -= Mp[r][k] * x[k];
+        x[r] = t / Mp[r][r];
+    }
+    for (int r = 0; r < np_; ++r) qdd[pas[r]] = x[r] - damping * qd[pas[r]];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as   */
 /* easy as 1, 2, 3", SC'11) and Box-Muller normals                           */
 /* ------------------------------------------------------------------------ */

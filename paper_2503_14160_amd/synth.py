@@ -180,6 +180,41 @@ class IkParams:
 
 
 @dataclasses.dataclass
+class TrajParams:
+    """Step two of the planner (Sec. 4.2, eq. discrete): direct collocation
+    with trapezoidal defects over N intervals of the reduced dynamics (Sec.
+    2.1: the actuated joints' accelerations are the inputs, the passive
+    joints follow a unit load at the tip, with viscous damping ``damping``
+    1/s on them), minimising t_F + omega_s sum |u_k|^2 + omega_t sum
+    |q_a,k - q*_a,k|^2 from rest at q_0 to rest at q_d, within the joint
+    limits and |qd_j| <= v_max[j].  Solved by an augmented Lagrangian on the
+    defects (penalty ``mu0``, times ``mu_factor`` per outer iteration,
+    ``outer`` of them; the state bounds as quadratic penalties of the same
+    weight) around Levenberg-Marquardt (``max_iters`` trial steps per outer
+    iteration, initial damping ``tau`` max diag(J^T J), stops on
+    max |J^T r| <= eps_grad or |h| <= eps_step (|z| + eps_step)); t_F = s^2
+    with s the unknown.  Jacobians of the dynamics by central differences
+    (steps fd_q on positions, 1 on velocities and inputs, where the
+    accelerations are quadratic and linear)."""
+
+    N: int = 100
+    omega_s: float = 0.1
+    omega_t: float = 10.0
+    grav: float = 9.81
+    damping: float = 0.5
+    v_max: tuple = (0.6, 0.4, 0.4, 0.5, 2.0, 2.0)
+    mu0: float = 1e2
+    mu_factor: float = 10.0
+    outer: int = 4
+    max_iters: int = 30
+    tau: float = 1e-6
+    eps_grad: float = 1e-9
+    eps_step: float = 1e-12
+    fd_q: float = 1e-5
+    t_f0: float = 12.0
+
+
+@dataclasses.dataclass
 class IkProblem:
     """Batched IK: the tip poses of the configurations ``q_star`` [N,n] are the
     targets; ``q_init`` [N*R,n] holds R starting configurations per target
