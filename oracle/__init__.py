@@ -488,7 +488,8 @@ class TrajLayout:
     scaled), the state bounds of the interior points (4n each: q above its
     upper limit, below its lower one, qd above v_max, below -v_max), the
     input terms sqrt(omega_s) u_k and tracking terms sqrt(omega_t)
-    (q_a,k - q*_a,k) for k = 1..N (n_a each), then s."""
+    (q_a,k - q*_a,k) for k = 1..N (n_a each), then s, then the penalty of
+    the final-time bound s >= sqrt(t_min)."""
 
     def __init__(self, n: int, na: int, N: int):
         self.n, self.na, self.N = n, na, N
@@ -503,7 +504,8 @@ class TrajLayout:
         self.r_u = self.r_bnd + (N - 1) * 4 * n
         self.r_q = self.r_u + N * na
         self.r_s = self.r_q + N * na
-        self.nr = self.r_s + 1
+        self.r_t = self.r_s + 1
+        self.nr = self.r_t + 1
 
     def x_at(self, z, k):
         return None if k in (0, self.N) else z[self.off[k]:self.off[k] + 2 * self.n]
@@ -518,6 +520,17 @@ def _traj_bounds(model, par):
     lo = np.concatenate([np.asarray(rb.q_min, np.float64), -np.asarray(par.v_max, np.float64)])
     hi = np.concatenate([np.asarray(rb.q_max, np.float64), np.asarray(par.v_max, np.float64)])
     return lo, hi
+
+
+def traj_t_min(model: Model, par, q_start, q_goal):
+    """The shortest final time the velocity limits allow: every joint moves
+    |q_d,j - q_0,j| at speed at most v_max,j, so t_F >= max_j |q_d,j -
+    q_0,j| / v_max,j.  The trapezoidal defects imply the same bound on the
+    discrete problem (q_N - q_0 = sum_k h (qd_k + qd_k+1) / 2), so adding
+    it leaves the feasible set unchanged; it keeps the solver away from
+    t_F = 0, where t_F = s^2 makes every residual stationary in s."""
+    dq = np.abs(np.asarray(q_goal, np.float64) - np.asarray(q_start, np.float64))
+    return float(np.max(dq / np.asarray(par.v_max, np.float64)[:len(dq)]))
 
 
 def traj_residual(model: Model, par, q_start, q_goal, q_star, z, lam, mu, jacobian: bool = True):
@@ -553,6 +566,8 @@ def traj_residual(model: Model, par, q_start, q_goal, q_star, z, lam, mu, jacobi
         r[L.r_u + na * (k - 1):L.r_u + na * k] = math.sqrt(par.omega_s) * U[k]
         r[L.r_q + na * (k - 1):L.r_q + na * k] = math.sqrt(par.omega_t) * (X[k][act] - np.asarray(q_star[k], np.float64)[act])
     r[L.r_s] = s
+    s_min = math.sqrt(traj_t_min(model, par, q_start, q_goal))
+    r[L.r_t] = sm * max(s_min - s, 0.0)
     if not jacobian:
         return r, None
     Jf = [traj_f_jac(model, par, X[k], U[k]) for k in range(N + 1)]
@@ -581,18 +596,21 @@ def traj_residual(model: Model, par, q_start, q_goal, q_star, z, lam, mu, jacobi
             if k < N:
                 J[L.r_q + na * (k - 1) + i, L.off[k] + act[i]] = math.sqrt(par.omega_t)
     J[L.r_s, L.s] = 1.0
+    if s < s_min:
+        J[L.r_t, L.s] = -sm
     return r, J
 
 
 def traj_initial(model: Model, par, q_start, q_goal, q_star):
-    """Starting point: the path's points at times k t_f0 / N, velocities and
-    inputs from their differences, s = sqrt(t_f0)."""
+    """Starting point: the path's points at times k t_0 / N, velocities and
+    inputs from their differences, s = sqrt(t_0), t_0 = max(t_f0, t_min)."""
     rb = model.robot
     n = rb.n_joints
     act = np.where(np.asarray(rb.active) != 0)[0]
     N = par.N
     L = TrajLayout(n, len(act), N)
-    h = par.t_f0 / N
+    t0 = max(par.t_f0, traj_t_min(model, par, q_start, q_goal))
+    h = t0 / N
     Q = np.asarray(q_star, np.float64).copy()
     Q[0], Q[N] = q_start, q_goal
     V = np.zeros_like(Q)
@@ -604,7 +622,7 @@ def traj_initial(model: Model, par, q_start, q_goal, q_star):
             z[L.off[k] + n:L.off[k] + 2 * n] = V[k]
         uo = L.off[k] + (2 * n if 0 < k < N else 0)
         z[uo:uo + len(act)] = ((V[k + 1] - V[k]) / h)[act] if k < N else 0.0
-    z[L.s] = math.sqrt(par.t_f0)
+    z[L.s] = math.sqrt(t0)
     return z
 
 
@@ -614,7 +632,7 @@ def traj_refine(model: Model, par, q_start, q_goal, q_star, trace: Optional[list
     the IK).  Per outer iteration: minimise |r|^2 / 2 by LM from the current
     point, then lam += mu d (d the defects), mu *= mu_factor.  Returns
     dict(t_f, X [N+1, 2n], U [N+1, n_a], z, defect (max |d|), F (the last
-    |r|^2 / 2), iters (trial steps over all outer iterations))."""
+    |r|^2 / 2), iters (trial steps over all outer iterations), t_min)."""
     rb = model.robot
     n = rb.n_joints
     act = np.where(np.asarray(rb.active) != 0)[0]
@@ -670,7 +688,7 @@ def traj_refine(model: Model, par, q_start, q_goal, q_star, trace: Optional[list
         U[k] = L.u_at(z, k)
     r0, _ = traj_residual(model, par, q_start, q_goal, q_star, z, np.zeros((N, 2 * n)), 1.0, jacobian=False)
     return dict(t_f=float(z[L.s] ** 2), X=X, U=U, z=z, defect=float(np.max(np.abs(r0[:N * 2 * n]))), F=F,
-                iters=iters)
+                iters=iters, t_min=traj_t_min(model, par, q_start, q_goal))
 
 
 # ----------------------------------------------------------------------------

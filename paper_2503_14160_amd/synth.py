@@ -193,9 +193,12 @@ class TrajParams:
     weight) around Levenberg-Marquardt (``max_iters`` trial steps per outer
     iteration, initial damping ``tau`` max diag(J^T J), stops on
     max |J^T r| <= eps_grad or |h| <= eps_step (|z| + eps_step)); t_F = s^2
-    with s the unknown.  Jacobians of the dynamics by central differences
+    with s the unknown, kept above t_min = max_j |q_d,j - q_0,j| / v_max[j]
+    (a bound the velocity limits imply) by one more penalty, and started at
+    max(t_f0, t_min).  Jacobians of the dynamics by central differences
     (steps fd_q on positions, 1 on velocities and inputs, where the
-    accelerations are quadratic and linear)."""
+    accelerations are quadratic and linear).  The defaults reach defects
+    near 1e-12 at N = 100 on the crane's moves."""
 
     N: int = 100
     omega_s: float = 0.1
@@ -203,10 +206,10 @@ class TrajParams:
     grav: float = 9.81
     damping: float = 0.5
     v_max: tuple = (0.6, 0.4, 0.4, 0.5, 2.0, 2.0)
-    mu0: float = 1e2
+    mu0: float = 1e3
     mu_factor: float = 10.0
-    outer: int = 4
-    max_iters: int = 30
+    outer: int = 5
+    max_iters: int = 60
     tau: float = 1e-6
     eps_grad: float = 1e-9
     eps_step: float = 1e-12

@@ -223,7 +223,7 @@ def test_crane_against_slsqp(orc):
 
     def obj(z):
         r, _ = orc.traj_residual(m, par, q0, qd, qstar, z, lam0, 1.0, jacobian=False)
-        return float(r[L.r_u:] @ r[L.r_u:])
+        return float(r[L.r_u:L.r_t] @ r[L.r_u:L.r_t])
 
     def defects(z):
         r, _ = orc.traj_residual(m, par, q0, qd, qstar, z, lam0, 1.0, jacobian=False)
@@ -241,3 +241,28 @@ def test_crane_against_slsqp(orc):
     assert res["t_f"] == pytest.approx(ref.x[L.s] ** 2, rel=1e-4)
     np.testing.assert_allclose(res["z"][:L.s], ref.x[:L.s], atol=2e-4)
     assert np.all(np.abs(defects(ref.x)) < 1e-8)
+
+
+def test_low_first_penalty_does_not_collapse_the_final_time(orc):
+    """With a first penalty of 100 a long move can be cheaper to leave
+    infeasible at t_F -> 0 (the defects then cost about mu |q_d - q_0|^2 /
+    (2 N), less than the time the move takes), and at s = 0 every residual
+    is stationary in s: without a bound this case ends at t_F ~ 1e-136 with
+    defects of 0.03.  The bound t_F >= t_min, which the velocity limits
+    imply, keeps the solver off that point: it must end feasible, within
+    the velocity limits, and so above t_min."""
+    from traj_cases import problems
+    base, robot = _crane()
+    m = orc.Model(robot, _empty(), None)
+    N = 12
+    par = synth.TrajParams(N=N, t_f0=6.0, mu0=100.0, outer=6, max_iters=200)
+    q0, qd, qstar = (a[2].astype(np.float64) for a in problems(robot, 4, N, 501))
+    t_min = orc.traj_t_min(m, par, q0, qd)
+    assert t_min == pytest.approx(np.max(np.abs(qd - q0) / np.asarray(par.v_max)))
+    res = orc.traj_refine(m, par, q0, qd, qstar)
+    assert res["defect"] < 1e-8
+    assert res["t_f"] > t_min
+    v = res["X"][:, 6:]
+    assert np.all(np.abs(v) <= np.asarray(par.v_max) + 1e-4)
+    # the discrete bound the defects imply: |q_N - q_0| <= t_F max |qd|
+    assert np.all(np.abs(qd - q0) <= res["t_f"] * np.abs(v).max(axis=0) + 1e-9)
