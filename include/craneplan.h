@@ -485,6 +485,67 @@ int cp_ik_solve(cp_plan *plan, const cp_ik_params *params, const float *d_target
 int cp_debug_ik_residual(cp_plan *plan, const cp_ik_params *params, const float *d_target, const float *d_q,
                          const float *d_q_ref, int32_t N, float *d_r, float *d_J, cp_stream_t stream);
 
+/*
+ * Step two of the planner (Sec. 4.2, eq. discrete): direct collocation with
+ * trapezoidal defects of the reduced dynamics (Sec. 2.1).  State x = (q, qd),
+ * inputs u = the accelerations of the actuated joints (active[j] = 1, in
+ * joint order); the passive joints follow their rows of M qdd + b = tau with
+ * no torque, M and b of a unit load at the tip on massless links (the
+ * crane's mass model is not given):
+ *   qdd_p = -(J_p^T J_p)^-1 J_p^T (J_a u + c + grav e_z) - damping qd_p,
+ * J = d tip / dq, c = sum_ij (d^2 tip / dq_i dq_j) qd_i qd_j.  Over N
+ * intervals of h = t_F / N it minimises
+ *   t_F + omega_s sum_{k=1..N} |u_k|^2 + omega_t sum_{k=1..N} |q_a,k - q*_a,k|^2
+ * subject to x_{k+1} - x_k = h/2 (f(x_k, u_k) + f(x_{k+1}, u_{k+1})),
+ * x_0 = (q_start, 0), x_N = (q_goal, 0), the joint limits and |qd_j| <=
+ * v_max[j] (q* is the path of step one at s = k / N).  Solver (IPOPT and
+ * automatic differentiation are not available here): an augmented
+ * Lagrangian on the defects (multipliers from 0, penalty mu0, times
+ * mu_factor after each of `outer` rounds; the state bounds as quadratic
+ * penalties of the same weight) around Levenberg-Marquardt on the squared
+ * residual (the IK's damping schedule: mu_LM,0 = tau max diag(J^T J); at
+ * most max_iters trial steps per round; stops on max |J^T r| <= eps_grad
+ * or |h| <= eps_step (|z| + eps_step)), t_F = s^2 with s unknown, started
+ * from the path at times k t_0 / N, t_0 = max(t_f0, t_min), with
+ * velocities and inputs from its differences.  t_F >= t_min = max_j
+ * |q_goal,j - q_start,j| / v_max[j], which the velocity limits imply, is
+ * kept as one more penalty of weight mu (it keeps the solver off s = 0,
+ * where every residual is stationary in s).  Dynamics Jacobians by central differences (step fd_q on
+ * positions, 1 on velocities and inputs, where the accelerations are
+ * quadratic and linear).  Everything in double precision, one workgroup
+ * per problem.
+ */
+typedef struct {
+    int32_t N;                    /* intervals, 2..400 */
+    double omega_s, omega_t;      /* >= 0 */
+    double grav;                  /* m/s^2 along -z */
+    double damping;               /* >= 0, on the passive joints (1/s) */
+    double v_max[CP_MAX_JOINTS];  /* > 0 per joint */
+    double mu0, mu_factor;        /* > 0, >= 1 */
+    int32_t outer, max_iters;     /* 1..20, 0..500 */
+    double tau, eps_grad, eps_step, fd_q, t_f0; /* > 0, >= 0, >= 0, > 0, > 0 */
+} cp_traj_params;
+
+/* Bytes of device workspace cp_traj_refine needs for P problems (SYNC, no
+ * device work).  Errors: CP_ERR_SIZE when 2 n + (actuated joints) > 16. */
+int cp_traj_workspace_size(const cp_plan *plan, const cp_traj_params *params, int32_t P, size_t *bytes);
+
+/* Refine P independent trajectories (enqueued on stream; allocates nothing):
+ * d_q_start, d_q_goal [P][n]; d_q_star [P][N+1][n] the step-one paths at
+ * s = k / N (row 0 and N are ignored: the endpoints are q_start, q_goal);
+ * d_work: caller's device workspace of at least cp_traj_workspace_size bytes
+ * (8-byte aligned; its contents on return are scratch); outputs d_x
+ * [P][N+1][2n] states, d_u [P][N+1][n_act] inputs, d_t_f [P] final times,
+ * d_info [P][4] (may be NULL): max |defect| without multipliers, the last
+ * augmented objective |r|^2 / 2, trial steps taken, t_min.  Uses the plan's
+ * robot (joints, tip, actuated set); its scene and costs are not used.
+ * Errors: CP_ERR_INVALID_ARG (null pointers, parameters out of range),
+ * CP_ERR_SIZE (P < 1, N out of range, workspace too small, 2 n + n_act >
+ * 16), CP_ERR_HIP. */
+int cp_traj_refine(cp_plan *plan, const cp_traj_params *params, const float *d_q_start, const float *d_q_goal,
+                   const float *d_q_star, int32_t P, void *d_work, size_t work_bytes, float *d_x, float *d_u,
+                   float *d_t_f, float *d_info, cp_stream_t stream);
+
 /* Test exports.  Forward kinematics of N joint vectors d_q [N][n]:
  * sphere centres [N][S][3] (sphere table order) and frames [N][n+1][12]
  * (row-major rotation then position); either output may be NULL. */

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcraneplan.so")
-SOURCES = ["api.hip", "eval.hip", "opt.hip", "sdf.hip", "ik.hip", "sat.hip"]
+SOURCES = ["api.hip", "eval.hip", "opt.hip", "sdf.hip", "ik.hip", "sat.hip", "traj.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -39,7 +39,8 @@ EXPORTS = ["cp_last_error", "cp_plan_create", "cp_plan_destroy", "cp_plan_set_en
            "cp_batch_get_tuning", "cp_batch_tune", "cp_optimizer_last_elites", "cp_tune",
            "cp_debug_update", "cp_optimizer_last_polished", "cp_batch_last", "cp_eval_paths_noalloc",
            "cp_optimizer_time_eval", "cp_optimizer_eval_time", "cp_optimizer_record_tape",
-           "cp_optimizer_population_grad", "cp_ik_solve", "cp_debug_ik_residual"]
+           "cp_optimizer_population_grad", "cp_ik_solve", "cp_debug_ik_residual", "cp_traj_workspace_size",
+           "cp_traj_refine"]
 
 
 class CranePlanError(RuntimeError):
@@ -71,6 +72,25 @@ class _Ik(ctypes.Structure):
     _fields_ = [("lambda_q", _c_f32), ("lambda_c", _c_f32), ("lambda_e", _c_f32), ("lambda_r", _c_f32),
                 ("max_iters", _c_i32), ("tau", _c_f32), ("eps_grad", _c_f32), ("eps_step", _c_f32),
                 ("clamp", _c_i32)]
+
+
+class _Traj(ctypes.Structure):
+    _fields_ = [("N", _c_i32), ("omega_s", _c_f64), ("omega_t", _c_f64), ("grav", _c_f64), ("damping", _c_f64),
+                ("v_max", _c_f64 * 8), ("mu0", _c_f64), ("mu_factor", _c_f64), ("outer", _c_i32),
+                ("max_iters", _c_i32), ("tau", _c_f64), ("eps_grad", _c_f64), ("eps_step", _c_f64),
+                ("fd_q", _c_f64), ("t_f0", _c_f64)]
+
+
+def _fill_traj(t, par, n):
+    t.N = int(par.N)
+    t.omega_s, t.omega_t, t.grav, t.damping = float(par.omega_s), float(par.omega_t), float(par.grav), float(par.damping)
+    vm = list(par.v_max)
+    for j in range(8):
+        t.v_max[j] = float(vm[j]) if j < len(vm) else 1.0
+    t.mu0, t.mu_factor = float(par.mu0), float(par.mu_factor)
+    t.outer, t.max_iters = int(par.outer), int(par.max_iters)
+    t.tau, t.eps_grad, t.eps_step, t.fd_q, t.t_f0 = (float(par.tau), float(par.eps_grad), float(par.eps_step),
+                                                      float(par.fd_q), float(par.t_f0))
 
 
 class _Opt(ctypes.Structure):
@@ -127,6 +147,8 @@ def lib():
         L.cp_optimizer_population_grad.argtypes = [_vp, _vp, _vp]
         L.cp_ik_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, i32, i32, _vp, _vp, _vp, _vp, _vp]
         L.cp_debug_ik_residual.argtypes = [_vp, _vp, _vp, _vp, _vp, i32, _vp, _vp, _vp]
+        L.cp_traj_workspace_size.argtypes = [_vp, _vp, i32, _vp]
+        L.cp_traj_refine.argtypes = [_vp, _vp, _vp, _vp, _vp, i32, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -366,6 +388,32 @@ class Plan:
         _check(lib().cp_debug_ik_residual(self._h, ctypes.byref(k), _ptr(target), _ptr(q), _ptr(q_ref), N, _ptr(r),
                                           _ptr(J), _stream()))
         return r, J
+
+
+    def traj_refine(self, params, q_start: torch.Tensor, q_goal: torch.Tensor, q_star: torch.Tensor):
+        """cp_traj_refine: states [P,N+1,2n], inputs [P,N+1,n_act], final
+        times [P] and info [P,4] for P problems (q_start, q_goal [P,n], the
+        step-one paths q_star [P,N+1,n]); the workspace is allocated here."""
+        P = q_start.shape[0]
+        n = self.n_joints
+        N = int(params.N)
+        q_start = self._rows(q_start, P, n, "q_start")
+        q_goal = self._rows(q_goal, P, n, "q_goal")
+        if q_star.dtype != torch.float32 or tuple(q_star.shape) != (P, N + 1, n) or q_star.device != self.device:
+            raise ValueError(f"q_star must be float32 [{P},{N + 1},{n}] on {self.device}")
+        q_star = q_star.contiguous()
+        t = _Traj()
+        _fill_traj(t, params, n)
+        nbytes = ctypes.c_size_t()
+        _check(lib().cp_traj_workspace_size(self._h, ctypes.byref(t), P, ctypes.byref(nbytes)))
+        work = torch.empty(max(8, nbytes.value), dtype=torch.uint8, device=self.device)
+        X = torch.empty((P, N + 1, 2 * n), dtype=torch.float32, device=self.device)
+        U = torch.empty((P, N + 1, self.n_active), dtype=torch.float32, device=self.device)
+        tf = torch.empty(P, dtype=torch.float32, device=self.device)
+        info = torch.empty((P, 4), dtype=torch.float32, device=self.device)
+        _check(lib().cp_traj_refine(self._h, ctypes.byref(t), _ptr(q_start), _ptr(q_goal), _ptr(q_star), P, _ptr(work),
+                                    nbytes.value, _ptr(X), _ptr(U), _ptr(tf), _ptr(info), _stream()))
+        return X, U, tf, info
 
 
 class EvalPaths(torch.autograd.Function):

@@ -809,6 +809,57 @@ int cp_debug_ik_residual(cp_plan *plan, const cp_ik_params *params, const float 
 }
 
 // ---------------------------------------------------------------------------
+// step two: direct collocation
+// ---------------------------------------------------------------------------
+
+static int validate_traj(const cp_plan *plan, const cp_traj_params *p, int *act, int *n_act) {
+    if (!plan || !p) return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (p->N < 2 || p->N > 400) return fail(CP_ERR_SIZE, "N out of range (2..400)");
+    auto ok = [](double v) { return std::isfinite(v); };
+    if (!ok(p->omega_s) || p->omega_s < 0.0 || !ok(p->omega_t) || p->omega_t < 0.0 || !ok(p->grav) ||
+        !ok(p->damping) || p->damping < 0.0 || !ok(p->mu0) || !(p->mu0 > 0.0) || !ok(p->mu_factor) ||
+        !(p->mu_factor >= 1.0) || !ok(p->tau) || !(p->tau > 0.0) || !ok(p->eps_grad) || p->eps_grad < 0.0 ||
+        !ok(p->eps_step) || p->eps_step < 0.0 || !ok(p->fd_q) || !(p->fd_q > 0.0) || !ok(p->t_f0) ||
+        !(p->t_f0 > 0.0))
+        return fail(CP_ERR_INVALID_ARG, "step-two parameters out of range");
+    if (p->outer < 1 || p->outer > 20 || p->max_iters < 0 || p->max_iters > 500)
+        return fail(CP_ERR_INVALID_ARG, "outer (1..20) or max_iters (0..500) out of range");
+    for (int j = 0; j < plan->n; ++j)
+        if (!ok(p->v_max[j]) || !(p->v_max[j] > 0.0)) return fail(CP_ERR_INVALID_ARG, "v_max must be > 0");
+    *n_act = 0;
+    for (int j = 0; j < plan->n; ++j)
+        if (plan->joints[j].active) act[(*n_act)++] = j;
+    if (2 * plan->n + *n_act > kTrajBlock) return fail(CP_ERR_SIZE, "2 n + actuated joints exceeds 16");
+    return CP_OK;
+}
+
+int cp_traj_workspace_size(const cp_plan *plan, const cp_traj_params *params, int32_t P, size_t *bytes) {
+    int act[CP_MAX_JOINTS], na = 0;
+    if (int rc = validate_traj(plan, params, act, &na)) return rc;
+    if (!bytes) return fail(CP_ERR_INVALID_ARG, "null bytes");
+    if (P < 1) return fail(CP_ERR_SIZE, "P must be >= 1");
+    *bytes = traj_workspace_bytes(params->N, plan->n, na, P);
+    return CP_OK;
+}
+
+int cp_traj_refine(cp_plan *plan, const cp_traj_params *params, const float *d_q_start, const float *d_q_goal,
+                   const float *d_q_star, int32_t P, void *d_work, size_t work_bytes, float *d_x, float *d_u,
+                   float *d_t_f, float *d_info, cp_stream_t stream) {
+    int act[CP_MAX_JOINTS], na = 0;
+    if (int rc = validate_traj(plan, params, act, &na)) return rc;
+    if (!d_q_start || !d_q_goal || !d_q_star || !d_work || !d_x || !d_u || !d_t_f)
+        return fail(CP_ERR_INVALID_ARG, "null argument");
+    if (P < 1 || P > (1 << 20)) return fail(CP_ERR_SIZE, "P out of range (1..1048576)");
+    if (work_bytes < traj_workspace_bytes(params->N, plan->n, na, P)) return fail(CP_ERR_SIZE, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(d_work) % 8 != 0) return fail(CP_ERR_INVALID_ARG, "workspace not 8-byte aligned");
+    DeviceGuard g(plan->device);
+    CP_HIP(launch_traj_refine(plan->view, *params, act, na, d_q_start, d_q_goal, d_q_star, P, d_work, d_x, d_u, d_t_f,
+                              d_info, (hipStream_t)stream),
+           "step-two launch");
+    return CP_OK;
+}
+
+// ---------------------------------------------------------------------------
 // optimizer
 // ---------------------------------------------------------------------------
 

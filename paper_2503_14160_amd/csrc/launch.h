@@ -109,6 +109,13 @@ hipError_t launch_ik_solve(const PlanView &P, const cp_ik_params &prm, const flo
 hipError_t launch_ik_residual(const PlanView &P, const cp_ik_params &prm, const float *target, const float *q,
                               const float *q_ref, int N, float *r, float *J, hipStream_t st);
 
+// step two: direct collocation (traj.hip); kMB = 16 bounds 2 n + n_act
+constexpr int kTrajBlock = 16;
+size_t traj_workspace_bytes(int N, int n, int na, int P);
+hipError_t launch_traj_refine(const PlanView &P, const cp_traj_params &prm, const int *act, int n_act,
+                              const float *q_start, const float *q_goal, const float *q_star, int n_prob, void *work,
+                              float *x_out, float *u_out, float *tf_out, float *info_out, hipStream_t st);
+
 // signed-distance grid (sdf.hip)
 hipError_t launch_sdf_build(const float *points, int64_t N, const int32_t dims[3], const float origin[3], float voxel,
                             float *sdf, uint8_t *occ, int32_t *edt_occ, int32_t *edt_free, int32_t *work,

@@ -1,0 +1,807 @@
+// Step two of the planner (Sec. 4.2, eq. discrete): direct collocation of the
+// reduced dynamics (Sec. 2.1) with trapezoidal defects, solved by an
+// augmented Lagrangian on the defects around Levenberg-Marquardt, in double
+// precision.  One workgroup of 256 threads per problem.
+//
+// Unknowns, per time point k = 0..N, a block [x_k (2n), u_k (n_a)] of MB =
+// 2n + n_a entries (x_0 and x_N are fixed: their entries stay in the block
+// with identity rows in the normal equations and no gradient), and s with
+// t_F = s^2.  The normal equations J^T J + damping I are block tridiagonal
+// in these blocks (a defect couples k and k + 1) with a dense last column
+// for s; they are solved by a block Cholesky sweep (the block Thomas
+// algorithm) for two right-hand sides and a Schur complement on s.
+// The final time has the lower bound t_min = max_j |q_d,j - q_0,j| / v_max,j
+// that the velocity limits imply (a penalty of weight mu on s < sqrt(t_min),
+// like the state bounds): without it t_F = s^2 makes s = 0 a stationary
+// point of every residual, which a low first penalty can fall into.
+// Dynamics: the actuated joints' accelerations are the inputs; the passive
+// joints follow a unit load at the tip on massless links:
+//   qdd_p = -(J_p^T J_p)^-1 J_p^T (J_a u + c + g e_z) - damping qd_p,
+// J = d tip / dq, c = sum_ij (d^2 tip / dq_i dq_j) qd_i qd_j.  Jacobians of
+// the dynamics by central differences (positions: step fd_q; velocities and
+// inputs, where the accelerations are quadratic and linear: step 1).
+#include "launch.h"
+
+namespace cp {
+namespace {
+
+constexpr int kTrajThreads = 256;
+constexpr int kMB = kTrajBlock;  // block size 2n + n_a (padded)
+
+struct TrajDev {
+    int N, n, na, MB, outer, max_iters;
+    double omega_s, omega_t, grav, damping, mu0, mu_factor, tau, eps_grad, eps_step, fd_q, t_f0;
+    double v_max[CP_MAX_JOINTS];
+    int act[CP_MAX_JOINTS];
+};
+
+// per-problem workspace (doubles), offsets in units of doubles
+struct TrajWork {
+    double *z, *zt;      // [(N+1) MB + 1]
+    double *f, *ft;      // [N+1][2n] at z and at the trial point
+    double *Jx, *Ju;     // [N+1][2n][2n], [N+1][2n][na]
+    double *lam;         // [N][2n]
+    double *D, *E;       // [N+1][MB][MB], [N][MB][MB]
+    double *c, *g;       // [(N+1) MB + 1] each (g's last entry: g_s)
+    double *LD, *LX;     // factors [N+1][MB][MB], [N][MB][MB]
+    double *y, *w, *h;   // [(N+1) MB + 1]
+};
+
+__host__ __device__ inline size_t traj_nz(int N) { return (size_t)(N + 1) * kMB + 1; }
+
+__host__ __device__ inline size_t traj_work_doubles(int N, int n, int na) {
+    const size_t nz = traj_nz(N);
+    return 2 * nz + 2 * (size_t)(N + 1) * 2 * n + (size_t)(N + 1) * 4 * n * n + (size_t)(N + 1) * 2 * n * na +
+           (size_t)N * 2 * n + 2 * (size_t)(N + 1) * kMB * kMB + 2 * (size_t)N * kMB * kMB + 5 * nz;
+}
+
+__device__ inline TrajWork traj_work(double *base, int N, int n, int na) {
+    TrajWork w;
+    const size_t nz = traj_nz(N);
+    double *p = base;
+    w.z = p; p += nz;
+    w.zt = p; p += nz;
+    w.f = p; p += (size_t)(N + 1) * 2 * n;
+    w.ft = p; p += (size_t)(N + 1) * 2 * n;
+    w.Jx = p; p += (size_t)(N + 1) * 4 * n * n;
+    w.Ju = p; p += (size_t)(N + 1) * 2 * n * na;
+    w.lam = p; p += (size_t)N * 2 * n;
+    w.D = p; p += (size_t)(N + 1) * kMB * kMB;
+    w.E = p; p += (size_t)N * kMB * kMB;
+    w.LD = p; p += (size_t)(N + 1) * kMB * kMB;
+    w.LX = p; p += (size_t)N * kMB * kMB;
+    w.c = p; p += nz;
+    w.g = p; p += nz;
+    w.y = p; p += nz;
+    w.w = p; p += nz;
+    w.h = p; p += nz;
+    return w;
+}
+
+// ---------------------------------------------------------------------------
+// dynamics in double precision
+// ---------------------------------------------------------------------------
+
+struct XfD {
+    double r[9], p[3];
+};
+
+__device__ inline void xfd_step(XfD &T, const JointDev &J, double q) {
+    double o[3] = {J.ox, J.oy, J.oz};
+    const double a[3] = {J.ax, J.ay, J.az};
+    if (J.type == CP_PRISMATIC)
+        for (int i = 0; i < 3; ++i) o[i] += q * a[i];
+    double np[3];
+    for (int i = 0; i < 3; ++i) np[i] = T.r[3 * i] * o[0] + T.r[3 * i + 1] * o[1] + T.r[3 * i + 2] * o[2] + T.p[i];
+    for (int i = 0; i < 3; ++i) T.p[i] = np[i];
+    if (J.type == CP_REVOLUTE) {
+        const double s = sin(q), c = cos(q), v = 1.0 - c;
+        // rotation by q about the unit axis a (Rodrigues)
+        const double R[9] = {c + a[0] * a[0] * v,        a[0] * a[1] * v - a[2] * s, a[0] * a[2] * v + a[1] * s,
+                             a[1] * a[0] * v + a[2] * s, c + a[1] * a[1] * v,        a[1] * a[2] * v - a[0] * s,
+                             a[2] * a[0] * v - a[1] * s, a[2] * a[1] * v + a[0] * s, c + a[2] * a[2] * v};
+        double nr[9];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) nr[3 * i + k] = T.r[3 * i] * R[k] + T.r[3 * i + 1] * R[3 + k] + T.r[3 * i + 2] * R[6 + k];
+        for (int i = 0; i < 9; ++i) T.r[i] = nr[i];
+    }
+}
+
+__device__ inline void cross_d(const double *a, const double *b, double *o) {
+    const double x = a[1] * b[2] - a[2] * b[1], y = a[2] * b[0] - a[0] * b[2], z = a[0] * b[1] - a[1] * b[0];
+    o[0] = x; o[1] = y; o[2] = z;
+}
+
+// joint accelerations qdd [n] at (q, qd) with actuated inputs u [na]
+__device__ void crane_accel_d(const PlanView &P, const TrajDev &T, const double *q, const double *qd, const double *u,
+                              double *qdd) {
+    const int n = T.n;
+    double aw[CP_MAX_JOINTS][3], piv[CP_MAX_JOINTS][3];
+    XfD F;
+    for (int i = 0; i < 9; ++i) F.r[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    F.p[0] = F.p[1] = F.p[2] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const JointDev J = P.joints[j];
+        const double a[3] = {J.ax, J.ay, J.az};
+        for (int i = 0; i < 3; ++i) aw[j][i] = F.r[3 * i] * a[0] + F.r[3 * i + 1] * a[1] + F.r[3 * i + 2] * a[2];
+        xfd_step(F, J, q[j]);
+        for (int i = 0; i < 3; ++i) piv[j][i] = F.p[i];
+    }
+    const double t[3] = {P.tip[0], P.tip[1], P.tip[2]};
+    double tip[3];
+    for (int i = 0; i < 3; ++i) tip[i] = F.r[3 * i] * t[0] + F.r[3 * i + 1] * t[1] + F.r[3 * i + 2] * t[2] + F.p[i];
+    // tip Jacobian columns and the rotation arms
+    double Jc[CP_MAX_JOINTS][3], arm[CP_MAX_JOINTS][3];
+    bool rev[CP_MAX_JOINTS];
+    for (int j = 0; j < n; ++j) {
+        rev[j] = P.joints[j].type == CP_REVOLUTE;
+        for (int i = 0; i < 3; ++i) arm[j][i] = tip[i] - piv[j][i];
+        if (rev[j]) cross_d(aw[j], arm[j], Jc[j]);
+        else for (int i = 0; i < 3; ++i) Jc[j][i] = aw[j][i];
+    }
+    // c = sum_ij H_ij qd_i qd_j, H_ij (i <= j, the earlier joint first):
+    // revolute j: a_i x (a_j x arm_j) for revolute i, 0 for prismatic i;
+    // prismatic j: a_i x a_j for revolute i < j, 0 otherwise
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < n; ++i) {
+        for (int j = i; j < n; ++j) {
+            double h[3] = {0.0, 0.0, 0.0};
+            if (rev[j]) {
+                if (rev[i]) {
+                    double tmp[3];
+                    cross_d(aw[j], arm[j], tmp);
+                    cross_d(aw[i], tmp, h);
+                }
+            } else if (rev[i] && i < j) {
+                cross_d(aw[i], aw[j], h);
+            }
+            const double wgt = (i == j ? 1.0 : 2.0) * qd[i] * qd[j];
+            for (int k = 0; k < 3; ++k) c[k] += wgt * h[k];
+        }
+    }
+    double acc[3] = {c[0], c[1], c[2] + T.grav};
+    int pas[CP_MAX_JOINTS];
+    int npas = 0, ia = 0;
+    for (int j = 0; j < n; ++j) {
+        if (P.joints[j].active) {
+            qdd[j] = u[ia++];
+            for (int k = 0; k < 3; ++k) acc[k] += Jc[j][k] * qdd[j];
+        } else {
+            pas[npas++] = j;
+        }
+    }
+    if (npas == 0) return;
+    // (J_p^T J_p) x = -J_p^T acc, Gaussian elimination with partial pivoting
+    double M[CP_MAX_JOINTS][CP_MAX_JOINTS + 1];
+    for (int r = 0; r < npas; ++r) {
+        for (int s = 0; s < npas; ++s)
+            M[r][s] = Jc[pas[r]][0] * Jc[pas[s]][0] + Jc[pas[r]][1] * Jc[pas[s]][1] + Jc[pas[r]][2] * Jc[pas[s]][2];
+        M[r][npas] = -(Jc[pas[r]][0] * acc[0] + Jc[pas[r]][1] * acc[1] + Jc[pas[r]][2] * acc[2]);
+    }
+    for (int col = 0; col < npas; ++col) {
+        int best = col;
+        for (int r = col + 1; r < npas; ++r)
+            if (fabs(M[r][col]) > fabs(M[best][col])) best = r;
+        if (best != col)
+            for (int k = 0; k <= npas; ++k) {
+                const double tmp = M[col][k];
+                M[col][k] = M[best][k];
+                M[best][k] = tmp;
+            }
+        for (int r = col + 1; r < npas; ++r) {
+            const double fct = M[r][col] / M[col][col];
+            for (int k = col; k <= npas; ++k) M[r][k] -= fct * M[col][k];
+        }
+    }
+    double x[CP_MAX_JOINTS];
+    for (int r = npas - 1; r >= 0; --r) {
+        double v = M[r][npas];
+        for (int k = r + 1; k < npas; ++k) v -= M[r][k] * x[k];
+        x[r] = v / M[r][r];
+    }
+    for (int r = 0; r < npas; ++r) qdd[pas[r]] = x[r] - T.damping * qd[pas[r]];
+}
+
+// x' = f(x, u): (qd, qdd)
+__device__ inline void traj_rhs(const PlanView &P, const TrajDev &T, const double *x, const double *u, double *out) {
+    const int n = T.n;
+    for (int i = 0; i < n; ++i) out[i] = x[n + i];
+    crane_accel_d(P, T, x, x + n, u, out + n);
+}
+
+// ---------------------------------------------------------------------------
+// the problem's points
+// ---------------------------------------------------------------------------
+
+struct TrajIn {
+    const float *qs, *qg, *qstar;  // [n], [n], [N+1][n]
+    double t_min, s_min;           // the final-time bound and its root
+};
+
+// t_min of the problem: max_j |q_d,j - q_0,j| / v_max,j
+__device__ inline double traj_t_min(const TrajDev &T, const float *qs, const float *qg) {
+    double t = 0.0;
+    for (int j = 0; j < T.n; ++j) t = fmax(t, fabs((double)qg[j] - (double)qs[j]) / T.v_max[j]);
+    return t;
+}
+
+// state x_k and input u_k of z (x_0, x_N: the fixed rest states)
+__device__ inline void point_of(const TrajDev &T, const TrajIn &in, const double *z, int k, double *x, double *u) {
+    const int n = T.n;
+    const double *b = z + (size_t)k * kMB;
+    if (k == 0 || k == T.N) {
+        const float *q = k == 0 ? in.qs : in.qg;
+        for (int i = 0; i < n; ++i) { x[i] = q[i]; x[n + i] = 0.0; }
+    } else {
+        for (int i = 0; i < 2 * n; ++i) x[i] = b[i];
+    }
+    for (int i = 0; i < T.na; ++i) u[i] = b[2 * n + i];
+}
+
+// f at every point (and with jac its central-difference Jacobians): the
+// threads share out (point, direction) tasks, a direction's two evaluations
+// on one thread
+__device__ void eval_points(const PlanView &P, const TrajDev &T, const TrajIn &in, const double *z, double *f,
+                            double *Jx, double *Ju, bool jac) {
+    const int n = T.n, na = T.na, N = T.N, nx = 2 * n;
+    const int per = jac ? 1 + nx + na : 1;
+    const int total = (N + 1) * per;
+    for (int t = threadIdx.x; t < total; t += kTrajThreads) {
+        const int k = t / per, e = t % per;
+        double x[2 * CP_MAX_JOINTS], u[CP_MAX_JOINTS], fp[2 * CP_MAX_JOINTS], fm[2 * CP_MAX_JOINTS];
+        point_of(T, in, z, k, x, u);
+        if (e == 0) {
+            traj_rhs(P, T, x, u, fp);
+            for (int i = 0; i < nx; ++i) f[(size_t)k * nx + i] = fp[i];
+            continue;
+        }
+        const int d = e - 1;
+        if (d < nx) {
+            const double step = d < n ? T.fd_q : 1.0, x0 = x[d];
+            x[d] = x0 + step;
+            traj_rhs(P, T, x, u, fp);
+            x[d] = x0 - step;
+            traj_rhs(P, T, x, u, fm);
+            for (int i = 0; i < nx; ++i) Jx[((size_t)k * nx + i) * nx + d] = (fp[i] - fm[i]) / (2.0 * step);
+        } else {
+            const int j = d - nx;
+            const double u0 = u[j];
+            u[j] = u0 + 1.0;
+            traj_rhs(P, T, x, u, fp);
+            u[j] = u0 - 1.0;
+            traj_rhs(P, T, x, u, fm);
+            for (int i = 0; i < nx; ++i) Ju[((size_t)k * nx + i) * na + j] = (fp[i] - fm[i]) / 2.0;
+        }
+    }
+}
+
+// block reductions over the workgroup (fixed order: thread partials, then
+// a serial sum over the threads' slots)
+struct TrajShared {
+    double red[kTrajThreads];
+    double A[kMB][kMB + 1];     // the block being factored
+    double X[kMB][kMB + 1];     // L^-1 E of the previous block
+    double v[2][kMB];           // right-hand sides in flight
+    double scal[8];
+};
+
+__device__ double block_sum(TrajShared &sh, double v) {
+    sh.red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kTrajThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh.red[threadIdx.x] += sh.red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh.red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_max(TrajShared &sh, double v) {
+    sh.red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kTrajThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh.red[threadIdx.x] = fmax(sh.red[threadIdx.x], sh.red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double r = sh.red[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// residual pieces
+// ---------------------------------------------------------------------------
+
+// the scaled residual of defect k (row i): sqrt(mu) (d_k + lam_k / mu) with
+// d_k = x_{k+1} - x_k - h/2 (f_k + f_{k+1}); and the raw defect
+__device__ inline double defect_row(const TrajDev &T, const TrajIn &in, const double *z, const double *f,
+                                    const double *lam, double mu, int k, int i, double *raw) {
+    const int n = T.n, nx = 2 * n;
+    const double s = z[(size_t)(T.N + 1) * kMB];
+    const double h2 = s * s / (2.0 * T.N);
+    double xa, xb;
+    // state entry i of points k and k + 1
+    auto st = [&](int kk) {
+        if (kk == 0) return i < n ? (double)in.qs[i] : 0.0;
+        if (kk == T.N) return i < n ? (double)in.qg[i] : 0.0;
+        return z[(size_t)kk * kMB + i];
+    };
+    xa = st(k);
+    xb = st(k + 1);
+    const double d = xb - xa - h2 * (f[(size_t)k * nx + i] + f[(size_t)(k + 1) * nx + i]);
+    if (raw) *raw = d;
+    return sqrt(mu) * (d + lam[(size_t)k * nx + i] / mu);
+}
+
+// F = |r|^2 / 2 at z (f evaluated at z)
+__device__ double objective(const PlanView &P, const TrajDev &T, const TrajIn &in, const double *z, const double *f,
+                            const double *lam, double mu, TrajShared &sh) {
+    const int n = T.n, na = T.na, N = T.N, nx = 2 * n;
+    double acc = 0.0;
+    // defects
+    for (int t = threadIdx.x; t < N * nx; t += kTrajThreads) {
+        const double r = defect_row(T, in, z, f, lam, mu, t / nx, t % nx, nullptr);
+        acc += r * r;
+    }
+    // bounds of the interior states
+    for (int t = threadIdx.x; t < (N - 1) * nx; t += kTrajThreads) {
+        const int k = 1 + t / nx, i = t % nx;
+        const double x = z[(size_t)k * kMB + i];
+        const double lo = i < n ? (double)P.joints[i].qmin : -T.v_max[i - n];
+        const double hi = i < n ? (double)P.joints[i].qmax : T.v_max[i - n];
+        const double e = fmax(x - hi, 0.0) + fmax(lo - x, 0.0);
+        acc += mu * e * e;
+    }
+    // inputs and tracking, k = 1..N
+    for (int t = threadIdx.x; t < N * na; t += kTrajThreads) {
+        const int k = 1 + t / na, j = t % na, a = T.act[j];
+        const double u = z[(size_t)k * kMB + nx + j];
+        const double qa = k == N ? (double)in.qg[a] : z[(size_t)k * kMB + a];
+        const double dq = qa - (double)in.qstar[(size_t)k * n + a];
+        acc += T.omega_s * u * u + T.omega_t * dq * dq;
+    }
+    const double s = z[(size_t)(N + 1) * kMB], lo = fmax(in.s_min - s, 0.0);
+    const double tot = block_sum(sh, acc);
+    return 0.5 * (tot + s * s + mu * lo * lo);
+}
+
+// ---------------------------------------------------------------------------
+// normal equations J^T J (blocks D_k, E_k, column c, corner a_ss) and
+// gradient g = J^T r at z
+// ---------------------------------------------------------------------------
+
+// entry (row i of defect k, column col of block kk in {k, k+1}) of the
+// scaled defect Jacobian, 0 outside the state / input entries
+__device__ inline double jd(const TrajDev &T, const double *Jx, const double *Ju, double h2, double sm, int k, int kk,
+                            int i, int col) {
+    const int n = T.n, na = T.na, nx = 2 * n;
+    if ((kk == 0 || kk == T.N) && col < nx) return 0.0;  // fixed states
+    double v;
+    if (col < nx) {
+        v = -h2 * Jx[((size_t)kk * nx + i) * nx + col];
+        if (col == i) v += kk == k ? -1.0 : 1.0;
+    } else if (col < nx + na) {
+        v = -h2 * Ju[((size_t)kk * nx + i) * na + (col - nx)];
+    } else {
+        v = 0.0;
+    }
+    return sm * v;
+}
+
+__device__ void normal_equations(const PlanView &P, const TrajDev &T, const TrajIn &in, const double *z,
+                                 const double *f, const double *Jx, const double *Ju, const double *lam, double mu,
+                                 double *D, double *E, double *c, double *g, double &a_ss, TrajShared &sh) {
+    const int n = T.n, na = T.na, N = T.N, nx = 2 * n, MB = kMB;
+    const double s = z[(size_t)(N + 1) * MB];
+    const double h2 = s * s / (2.0 * N), sm = sqrt(mu);
+    const int ti = threadIdx.x / MB, tj = threadIdx.x % MB;
+    double gs_part = 0.0, ass_part = 0.0;
+    for (int k = 0; k <= N; ++k) {
+        // D_k (ti, tj) and E_k (ti, tj)
+        double dsum = 0.0, esum = 0.0;
+        for (int r = 0; r < nx; ++r) {
+            if (k < N) {
+                const double l_i = jd(T, Jx, Ju, h2, sm, k, k, r, ti), l_j = jd(T, Jx, Ju, h2, sm, k, k, r, tj);
+                dsum += l_i * l_j;
+                esum += l_i * jd(T, Jx, Ju, h2, sm, k, k + 1, r, tj);
+            }
+            if (k > 0) {
+                const double r_i = jd(T, Jx, Ju, h2, sm, k - 1, k, r, ti), r_j = jd(T, Jx, Ju, h2, sm, k - 1, k, r, tj);
+                dsum += r_i * r_j;
+            }
+        }
+        // diagonal terms: bounds (active ones), inputs, tracking; fixed states: identity
+        if (ti == tj) {
+            if ((k == 0 || k == N) && ti < nx) {
+                dsum = 1.0;
+            } else if (ti < nx) {
+                const double x = z[(size_t)k * MB + ti];
+                const double lo = ti < n ? (double)P.joints[ti].qmin : -T.v_max[ti - n];
+                const double hi = ti < n ? (double)P.joints[ti].qmax : T.v_max[ti - n];
+                if (x > hi || x < lo) dsum += mu;
+                for (int j = 0; j < na; ++j)
+                    if (T.act[j] == ti && k < N) dsum += T.omega_t;
+            } else if (ti < nx + na) {
+                if (k >= 1) dsum += T.omega_s;
+            } else {
+                dsum = 1.0;  // padding
+            }
+        }
+        if ((k == 0 || k == N) && ti < nx && ti != tj) dsum = 0.0;
+        if ((k == 0 || k == N) && tj < nx && ti != tj) dsum = 0.0;
+        if (ti >= nx + na || tj >= nx + na) dsum = ti == tj ? 1.0 : 0.0;
+        D[(size_t)k * MB * MB + ti * MB + tj] = dsum;
+        if (k < N) E[(size_t)k * MB * MB + ti * MB + tj] = esum;
+        // c_k, g_k (threads 0..MB-1 hold one entry each)
+        if ((int)threadIdx.x < MB) {
+            const int col = threadIdx.x;
+            double cs = 0.0, gsum = 0.0;
+            for (int r = 0; r < nx; ++r) {
+                if (k < N) {
+                    const double js = -sm * (s / N) * (f[(size_t)k * nx + r] + f[(size_t)(k + 1) * nx + r]);
+                    const double rr = defect_row(T, in, z, f, lam, mu, k, r, nullptr);
+                    const double l = jd(T, Jx, Ju, h2, sm, k, k, r, col);
+                    cs += l * js;
+                    gsum += l * rr;
+                }
+                if (k > 0) {
+                    const double js = -sm * (s / N) * (f[(size_t)(k - 1) * nx + r] + f[(size_t)k * nx + r]);
+                    const double rr = defect_row(T, in, z, f, lam, mu, k - 1, r, nullptr);
+                    const double rj = jd(T, Jx, Ju, h2, sm, k - 1, k, r, col);
+                    cs += rj * js;
+                    gsum += rj * rr;
+                }
+            }
+            if (!((k == 0 || k == N) && col < nx)) {
+                if (col < nx) {
+                    const double x = z[(size_t)k * MB + col];
+                    const double lo = col < n ? (double)P.joints[col].qmin : -T.v_max[col - n];
+                    const double hi = col < n ? (double)P.joints[col].qmax : T.v_max[col - n];
+                    if (x > hi) gsum += mu * (x - hi);
+                    if (x < lo) gsum -= mu * (lo - x);
+                    for (int j = 0; j < na; ++j)
+                        if (T.act[j] == col && k < N)
+                            gsum += T.omega_t * (x - (double)in.qstar[(size_t)k * n + col]);
+                } else if (col < nx + na && k >= 1) {
+                    gsum += T.omega_s * z[(size_t)k * MB + col];
+                }
+            } else {
+                cs = 0.0;
+                gsum = 0.0;
+            }
+            if (col >= nx + na) { cs = 0.0; gsum = 0.0; }
+            c[(size_t)k * MB + col] = cs;
+            g[(size_t)k * MB + col] = gsum;
+        }
+        __syncthreads();
+    }
+    // corner and g_s: sums over the defect rows
+    for (int t = threadIdx.x; t < N * nx; t += kTrajThreads) {
+        const int k = t / nx, r = t % nx;
+        const double js = -sm * (s / N) * (f[(size_t)k * nx + r] + f[(size_t)(k + 1) * nx + r]);
+        ass_part += js * js;
+        gs_part += js * defect_row(T, in, z, f, lam, mu, k, r, nullptr);
+    }
+    const bool below = s < in.s_min;
+    a_ss = block_sum(sh, ass_part) + 1.0 + (below ? mu : 0.0);
+    const double gs = block_sum(sh, gs_part) + s + (below ? mu * (s - in.s_min) : 0.0);
+    if (threadIdx.x == 0) {
+        g[(size_t)(N + 1) * MB] = gs;
+        c[(size_t)(N + 1) * MB] = a_ss;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// (A + damp I) h = -g: block Cholesky sweep and the Schur complement on s
+// ---------------------------------------------------------------------------
+
+// Cholesky of sh.A in place (lower), one column at a time
+__device__ void chol_block(TrajShared &sh) {
+    const int MB = kMB;
+    const int ti = threadIdx.x / MB, tj = threadIdx.x % MB;
+    for (int j = 0; j < MB; ++j) {
+        if (threadIdx.x == 0) sh.A[j][j] = sqrt(sh.A[j][j]);
+        __syncthreads();
+        if ((int)threadIdx.x > j && (int)threadIdx.x < MB) sh.A[threadIdx.x][j] /= sh.A[j][j];
+        __syncthreads();
+        if (ti > j && tj > j && tj <= ti) sh.A[ti][tj] -= sh.A[ti][j] * sh.A[tj][j];
+        __syncthreads();
+    }
+}
+
+__device__ void factor(const double *D, const double *E, double damp, int nreal_last, double *LD, double *LX,
+                       int N, TrajShared &sh) {
+    const int MB = kMB;
+    const int ti = threadIdx.x / MB, tj = threadIdx.x % MB;
+    for (int k = 0; k <= N; ++k) {
+        double a = D[(size_t)k * MB * MB + ti * MB + tj];
+        if (ti == tj) a += damp;
+        if (k > 0) {
+            // minus X_{k-1}^T X_{k-1}, X_{k-1} = L_{k-1}^-1 E_{k-1} (in sh.X)
+            double s = 0.0;
+            for (int m = 0; m < MB; ++m) s += sh.X[m][ti] * sh.X[m][tj];
+            a -= s;
+        }
+        __syncthreads();
+        sh.A[ti][tj] = a;
+        __syncthreads();
+        chol_block(sh);
+        LD[(size_t)k * MB * MB + ti * MB + tj] = tj <= ti ? sh.A[ti][tj] : 0.0;
+        if (k < N) {
+            // X_k = L_k^-1 E_k: forward substitution, one column per thread
+            if ((int)threadIdx.x < MB) {
+                const int col = threadIdx.x;
+                for (int i = 0; i < MB; ++i) {
+                    double v = E[(size_t)k * MB * MB + i * MB + col];
+                    for (int m = 0; m < i; ++m) v -= sh.A[i][m] * sh.X[m][col];
+                    sh.X[i][col] = v / sh.A[i][i];
+                }
+            }
+            __syncthreads();
+            LX[(size_t)k * MB * MB + ti * MB + tj] = sh.X[ti][tj];
+        }
+        __syncthreads();
+    }
+}
+
+// solve L L^T x = b for two right-hand sides b0, b1 (length (N+1) MB), x in place
+__device__ void solve2(const double *LD, const double *LX, double *b0, double *b1, int N, TrajShared &sh) {
+    const int MB = kMB;
+    // forward: y_k = L_k^-1 (b_k - X_{k-1}^T y_{k-1})
+    for (int k = 0; k <= N; ++k) {
+        if ((int)threadIdx.x < 2 * MB) {
+            const int which = threadIdx.x / MB, i = threadIdx.x % MB;
+            double *b = which ? b1 : b0;
+            double v = b[(size_t)k * MB + i];
+            if (k > 0)
+                for (int m = 0; m < MB; ++m) v -= LX[(size_t)(k - 1) * MB * MB + m * MB + i] * b[(size_t)(k - 1) * MB + m];
+            sh.v[which][i] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < 2) {
+            const int which = threadIdx.x;
+            double *b = which ? b1 : b0;
+            for (int i = 0; i < MB; ++i) {
+                double v = sh.v[which][i];
+                for (int m = 0; m < i; ++m) v -= LD[(size_t)k * MB * MB + i * MB + m] * b[(size_t)k * MB + m];
+                b[(size_t)k * MB + i] = v / LD[(size_t)k * MB * MB + i * MB + i];
+            }
+        }
+        __syncthreads();
+    }
+    // backward: x_k = L_k^-T (y_k - X_k x_{k+1})
+    for (int k = N; k >= 0; --k) {
+        if ((int)threadIdx.x < 2 * MB) {
+            const int which = threadIdx.x / MB, i = threadIdx.x % MB;
+            double *b = which ? b1 : b0;
+            double v = b[(size_t)k * MB + i];
+            if (k < N)
+                for (int m = 0; m < MB; ++m) v -= LX[(size_t)k * MB * MB + i * MB + m] * b[(size_t)(k + 1) * MB + m];
+            sh.v[which][i] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < 2) {
+            const int which = threadIdx.x;
+            double *b = which ? b1 : b0;
+            for (int i = MB - 1; i >= 0; --i) {
+                double v = sh.v[which][i];
+                for (int m = i + 1; m < MB; ++m) v -= LD[(size_t)k * MB * MB + m * MB + i] * b[(size_t)k * MB + m];
+                b[(size_t)k * MB + i] = v / LD[(size_t)k * MB * MB + i * MB + i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// h = -(A + damp I)^-1 g with the s entry last
+__device__ void damped_step(const TrajDev &T, const TrajWork &W, double a_ss, double damp, TrajShared &sh) {
+    const int N = T.N;
+    const size_t nb = (size_t)(N + 1) * kMB;
+    factor(W.D, W.E, damp, 0, W.LD, W.LX, N, sh);
+    for (size_t t = threadIdx.x; t < nb; t += kTrajThreads) {
+        W.y[t] = -W.g[t];
+        W.w[t] = W.c[t];
+    }
+    __syncthreads();
+    solve2(W.LD, W.LX, W.y, W.w, N, sh);
+    double p0 = 0.0, p1 = 0.0;
+    for (size_t t = threadIdx.x; t < nb; t += kTrajThreads) {
+        p0 += W.c[t] * W.y[t];
+        p1 += W.c[t] * W.w[t];
+    }
+    const double cy = block_sum(sh, p0), cw = block_sum(sh, p1);
+    const double hs = (-W.g[nb] - cy) / (a_ss + damp - cw);
+    for (size_t t = threadIdx.x; t < nb; t += kTrajThreads) W.h[t] = W.y[t] - W.w[t] * hs;
+    if (threadIdx.x == 0) W.h[nb] = hs;
+    __syncthreads();
+}
+
+// h . (A h) with A the undamped normal matrix
+__device__ double quad_form(const TrajDev &T, const TrajWork &W, double a_ss, TrajShared &sh) {
+    const int N = T.N, MB = kMB;
+    const size_t nb = (size_t)(N + 1) * MB;
+    double acc = 0.0;
+    for (size_t t = threadIdx.x; t < nb; t += kTrajThreads) {
+        const int k = (int)(t / MB), i = (int)(t % MB);
+        double v = 0.0;
+        for (int m = 0; m < MB; ++m) v += W.D[(size_t)k * MB * MB + i * MB + m] * W.h[(size_t)k * MB + m];
+        if (k < N)
+            for (int m = 0; m < MB; ++m) v += W.E[(size_t)k * MB * MB + i * MB + m] * W.h[(size_t)(k + 1) * MB + m];
+        if (k > 0)
+            for (int m = 0; m < MB; ++m) v += W.E[(size_t)(k - 1) * MB * MB + m * MB + i] * W.h[(size_t)(k - 1) * MB + m];
+        v += W.c[t] * W.h[nb];
+        acc += W.h[t] * v;
+        acc += W.h[nb] * W.c[t] * W.h[t];
+    }
+    const double tot = block_sum(sh, acc);
+    return tot + W.h[nb] * a_ss * W.h[nb];
+}
+
+// the starting point: the path's points at times k t_0 / N, velocities and
+// inputs from their differences, s = sqrt(t_0), t_0 = max(t_f0, t_min)
+__device__ void init_point(const TrajDev &T, const TrajIn &in, double *z) {
+    const int n = T.n, na = T.na, N = T.N, nx = 2 * n, MB = kMB;
+    const double t0 = fmax(T.t_f0, in.t_min), h = t0 / N;
+    auto qpt = [&](int k, int i) {
+        if (k <= 0) return (double)in.qs[i];
+        if (k >= N) return (double)in.qg[i];
+        return (double)in.qstar[(size_t)k * n + i];
+    };
+    auto vel = [&](int k, int i) { return (k <= 0 || k >= N) ? 0.0 : (qpt(k + 1, i) - qpt(k - 1, i)) / (2.0 * h); };
+    for (size_t t = threadIdx.x; t < (size_t)(N + 1) * MB; t += kTrajThreads) {
+        const int k = (int)(t / MB), i = (int)(t % MB);
+        double v = 0.0;
+        if (i < n) v = (k == 0 || k == N) ? qpt(k, i) : qpt(k, i);
+        else if (i < nx) v = vel(k, i - n);
+        else if (i < nx + na) v = k < N ? (vel(k + 1, T.act[i - nx]) - vel(k, T.act[i - nx])) / h : 0.0;
+        z[t] = v;
+    }
+    if (threadIdx.x == 0) z[(size_t)(N + 1) * MB] = sqrt(t0);
+    __syncthreads();
+}
+
+// is entry t of z an unknown (not a fixed state, not padding)?
+__device__ inline bool real_entry(const TrajDev &T, size_t t) {
+    const int k = (int)(t / kMB), i = (int)(t % kMB);
+    if (k > T.N) return true;  // s
+    if (i >= 2 * T.n + T.na) return false;
+    return !((k == 0 || k == T.N) && i < 2 * T.n);
+}
+
+__global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDev T, const float *__restrict__ qs,
+                                                              const float *__restrict__ qg,
+                                                              const float *__restrict__ qstar, double *work,
+                                                              size_t stride, float *__restrict__ x_out,
+                                                              float *__restrict__ u_out, float *__restrict__ tf_out,
+                                                              float *__restrict__ info_out) {
+    __shared__ TrajShared sh;
+    const int pr = blockIdx.x;
+    const int n = T.n, na = T.na, N = T.N, nx = 2 * n, MB = kMB;
+    const float *q0 = qs + (size_t)pr * n, *q1 = qg + (size_t)pr * n;
+    const double t_min = traj_t_min(T, q0, q1);
+    const TrajIn in{q0, q1, qstar + (size_t)pr * (N + 1) * n, t_min, sqrt(t_min)};
+    const TrajWork W = traj_work(work + (size_t)pr * stride, N, n, na);
+    const size_t nb = (size_t)(N + 1) * MB, nz = nb + 1;
+    init_point(T, in, W.z);
+    for (size_t t = threadIdx.x; t < (size_t)N * nx; t += kTrajThreads) W.lam[t] = 0.0;
+    __syncthreads();
+    double mu = T.mu0, F = 0.0, a_ss = 0.0;
+    int iters = 0;
+    for (int outer = 0; outer < T.outer; ++outer) {
+        eval_points(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
+        __syncthreads();
+        F = objective(P, T, in, W.z, W.f, W.lam, mu, sh);
+        normal_equations(P, T, in, W.z, W.f, W.Jx, W.Ju, W.lam, mu, W.D, W.E, W.c, W.g, a_ss, sh);
+        // initial damping: tau times the largest diagonal entry over the unknowns
+        double dm = 0.0;
+        for (size_t t = threadIdx.x; t < nb; t += kTrajThreads)
+            if (real_entry(T, t)) dm = fmax(dm, W.D[(t / MB) * MB * MB + (t % MB) * MB + (t % MB)]);
+        double damp = T.tau * fmax(block_max(sh, dm), a_ss);
+        double nu = 2.0;
+        int it = 0;
+        while (it < T.max_iters) {
+            double gm = 0.0;
+            for (size_t t = threadIdx.x; t < nz; t += kTrajThreads) gm = fmax(gm, fabs(W.g[t]));
+            if (block_max(sh, gm) <= T.eps_grad) break;
+            damped_step(T, W, a_ss, damp, sh);
+            double hh = 0.0, zz = 0.0;
+            for (size_t t = threadIdx.x; t < nz; t += kTrajThreads)
+                if (real_entry(T, t)) {
+                    hh += W.h[t] * W.h[t];
+                    zz += W.z[t] * W.z[t];
+                }
+            const double hn = sqrt(block_sum(sh, hh)), zn = sqrt(block_sum(sh, zz));
+            if (!(hn > T.eps_step * (zn + T.eps_step))) break;
+            for (size_t t = threadIdx.x; t < nz; t += kTrajThreads) W.zt[t] = W.z[t] + W.h[t];
+            __syncthreads();
+            eval_points(P, T, in, W.zt, W.ft, W.Jx, W.Ju, false);
+            __syncthreads();
+            const double Ft = objective(P, T, in, W.zt, W.ft, W.lam, mu, sh);
+            double hg = 0.0;
+            for (size_t t = threadIdx.x; t < nz; t += kTrajThreads) hg += W.h[t] * W.g[t];
+            const double pred = -block_sum(sh, hg) - 0.5 * quad_form(T, W, a_ss, sh);
+            ++it;
+            if (pred > 0.0 && F - Ft > 0.0) {
+                const double rho = (F - Ft) / pred, tt = 2.0 * rho - 1.0;
+                for (size_t t = threadIdx.x; t < nz; t += kTrajThreads) W.z[t] = W.zt[t];
+                __syncthreads();
+                F = Ft;
+                eval_points(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
+                __syncthreads();
+                normal_equations(P, T, in, W.z, W.f, W.Jx, W.Ju, W.lam, mu, W.D, W.E, W.c, W.g, a_ss, sh);
+                damp *= fmax(1.0 / 3.0, 1.0 - tt * tt * tt);
+                nu = 2.0;
+            } else {
+                damp *= nu;
+                nu *= 2.0;
+            }
+        }
+        iters += it;
+        // multipliers from the defects at z: lam += mu d
+        for (size_t t = threadIdx.x; t < (size_t)N * nx; t += kTrajThreads) {
+            double d;
+            defect_row(T, in, W.z, W.f, W.lam, mu, (int)(t / nx), (int)(t % nx), &d);
+            W.lam[t] += mu * d;
+        }
+        __syncthreads();
+        mu *= T.mu_factor;
+    }
+    // outputs
+    double dmax = 0.0;
+    for (size_t t = threadIdx.x; t < (size_t)N * nx; t += kTrajThreads) {
+        double d;
+        defect_row(T, in, W.z, W.f, W.lam, 1.0, (int)(t / nx), (int)(t % nx), &d);
+        dmax = fmax(dmax, fabs(d));
+    }
+    dmax = block_max(sh, dmax);
+    for (size_t t = threadIdx.x; t < (size_t)(N + 1) * nx; t += kTrajThreads) {
+        const int k = (int)(t / nx), i = (int)(t % nx);
+        double v;
+        if (k == 0 || k == N) v = i < n ? (double)(k == 0 ? in.qs[i] : in.qg[i]) : 0.0;
+        else v = W.z[(size_t)k * MB + i];
+        x_out[(size_t)pr * (N + 1) * nx + t] = (float)v;
+    }
+    for (size_t t = threadIdx.x; t < (size_t)(N + 1) * na; t += kTrajThreads) {
+        const int k = (int)(t / na), j = (int)(t % na);
+        u_out[(size_t)pr * (N + 1) * na + t] = (float)W.z[(size_t)k * MB + nx + j];
+    }
+    if (threadIdx.x == 0) {
+        const double sv = W.z[nb];
+        tf_out[pr] = (float)(sv * sv);
+        if (info_out) {
+            float *o = info_out + (size_t)pr * 4;
+            o[0] = (float)dmax; o[1] = (float)F; o[2] = (float)iters; o[3] = (float)t_min;
+        }
+    }
+}
+
+}  // namespace
+
+size_t traj_workspace_bytes(int N, int n, int na, int P) {
+    return traj_work_doubles(N, n, na) * sizeof(double) * (size_t)P;
+}
+
+hipError_t launch_traj_refine(const PlanView &P, const cp_traj_params &prm, const int *act, int n_act,
+                              const float *q_start, const float *q_goal, const float *q_star, int n_prob, void *work,
+                              float *x_out, float *u_out, float *tf_out, float *info_out, hipStream_t st) {
+    TrajDev T{};
+    T.N = prm.N;
+    T.n = P.n_joints;
+    T.na = n_act;
+    for (int j = 0; j < CP_MAX_JOINTS; ++j) T.act[j] = j < n_act ? act[j] : 0;
+    T.MB = kMB;
+    T.outer = prm.outer;
+    T.max_iters = prm.max_iters;
+    T.omega_s = prm.omega_s; T.omega_t = prm.omega_t; T.grav = prm.grav; T.damping = prm.damping;
+    T.mu0 = prm.mu0; T.mu_factor = prm.mu_factor; T.tau = prm.tau; T.eps_grad = prm.eps_grad;
+    T.eps_step = prm.eps_step; T.fd_q = prm.fd_q; T.t_f0 = prm.t_f0;
+    for (int j = 0; j < CP_MAX_JOINTS; ++j) T.v_max[j] = j < T.n ? prm.v_max[j] : 0.0;
+    const size_t stride = traj_work_doubles(T.N, T.n, T.na);
+    hipLaunchKernelGGL(k_traj_refine, dim3(n_prob), dim3(kTrajThreads), 0, st, P, T, q_start, q_goal, q_star,
+                       static_cast<double *>(work), stride, x_out, u_out, tf_out, info_out);
+    return hipGetLastError();
+}
+
+}  // namespace cp

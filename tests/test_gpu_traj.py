@@ -1,0 +1,144 @@
+"""Step two of the planner on the GPU (Sec. 4.2, eq. discrete) against the
+oracle, through the C ABI.
+
+Both sides run the same double-precision algorithm (augmented Lagrangian
+around Levenberg-Marquardt with the same damping schedule, central-
+difference dynamics Jacobians, the same starting point); they differ in the
+order of their sums and in the linear solve (the device factors the block-
+tridiagonal normal equations block by block, the oracle solves them
+densely).  Two bars follow from that:
+
+* early iterations, while the penalty is low and the normal equations well
+  conditioned: the same steps are accepted and rejected, so iteration counts
+  agree exactly and states, inputs (returned in FP32) and t_F agree to 1e-6
+  of their scale (FP32 rounding is 6e-8 of it);
+* converged solves (defects below 1e-9 on both sides): both sit on the same
+  local minimiser, whose position is fixed to the conditioning of the last
+  penalty (mu up to 1e7) times the rounding, so 2e-6 of the scale; the
+  count of trial steps at which the stopping tests fire at the noise floor
+  may differ.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2503_14160_amd import synth
+from traj_cases import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_14160_amd import craneplan
+    craneplan.lib()
+    return craneplan
+
+
+def _plan(cp, robot):
+    return cp.Plan(robot, synth.c0_plain().scene, synth.CostParams(K=4, M=4), max_B=1)
+
+
+def _run(cp, robot, par, q0, qg, qstar, label):
+    print(f"[traj] {label}: P={len(q0)} N={par.N} outer={par.outer} max_iters={par.max_iters}", flush=True)
+    X, U, tf, info = _plan(cp, robot).traj_refine(par, torch.from_numpy(q0).cuda(), torch.from_numpy(qg).cuda(),
+                                                  torch.from_numpy(qstar).cuda())
+    return tuple(t.cpu().numpy().astype(np.float64) for t in (X, U, tf, info))
+
+
+def _oracle(robot, par, q0, qg, qstar):
+    m = oracle.Model(robot, synth.c0_plain().scene, None)
+    return [oracle.traj_refine(m, par, q0[p].astype(np.float64), qg[p].astype(np.float64),
+                               qstar[p].astype(np.float64)) for p in range(len(q0))]
+
+
+def _check(dev, refs, tol, label, same_iters):
+    X, U, tf, info = dev
+    for p, ref in enumerate(refs):
+        assert tf[p] == pytest.approx(ref["t_f"], rel=tol), (label, p)
+        np.testing.assert_allclose(X[p], ref["X"], rtol=0, atol=tol * max(1.0, np.abs(ref["X"]).max()),
+                                   err_msg=f"{label} states {p}")
+        np.testing.assert_allclose(U[p], ref["U"], rtol=0, atol=tol * max(1.0, np.abs(ref["U"]).max()),
+                                   err_msg=f"{label} inputs {p}")
+        assert info[p, 3] == pytest.approx(ref["t_min"], rel=1e-7), (label, p)
+        if same_iters:
+            assert int(info[p, 2]) == ref["iters"], (label, p)
+            assert info[p, 1] == pytest.approx(ref["F"], rel=1e-6), (label, p)
+            assert info[p, 0] == pytest.approx(ref["defect"], rel=1e-3, abs=1e-9), (label, p)
+        else:
+            assert info[p, 0] < 1e-9 and ref["defect"] < 1e-9, (label, p, info[p, 0], ref["defect"])
+
+
+def test_traj_early_iterations_match(cp):
+    robot = synth.c1_full().robot
+    par = synth.TrajParams(N=12, t_f0=6.0, mu0=100.0, outer=2, max_iters=40)
+    q0, qg, qstar = problems(robot, 4, par.N, 501)
+    dev = _run(cp, robot, par, q0, qg, qstar, "early")
+    _check(dev, _oracle(robot, par, q0, qg, qstar), 1e-6, "early", True)
+
+
+def test_traj_converged_match(cp):
+    robot = synth.c1_full().robot
+    par = synth.TrajParams(N=12, t_f0=6.0)
+    q0, qg, qstar = problems(robot, 4, par.N, 601)
+    dev = _run(cp, robot, par, q0, qg, qstar, "converged")
+    _check(dev, _oracle(robot, par, q0, qg, qstar), 2e-6, "converged", False)
+    X = dev[0]
+    # rest to rest, inside the joint limits to the penalty's resolution
+    assert np.all(X[:, 0, 6:] == 0) and np.all(X[:, -1, 6:] == 0)
+    assert np.all(X[:, :, :6] <= robot.q_max + 1e-4) and np.all(X[:, :, :6] >= robot.q_min - 1e-4)
+
+
+def test_traj_paper_horizon(cp):
+    """The paper's discretisation: 100 collocation intervals, 1617 unknowns
+    once the fixed end states are removed, default solver settings."""
+    robot = synth.c1_full().robot
+    par = synth.TrajParams(N=100)
+    q0, qg, qstar = problems(robot, 1, par.N, 502)
+    dev = _run(cp, robot, par, q0, qg, qstar, "N=100")
+    _check(dev, _oracle(robot, par, q0, qg, qstar), 2e-6, "N=100", False)
+
+
+def test_traj_edge_cases(cp):
+    """No trial steps (the starting point comes back with t_F = max(t_f0,
+    t_min)); a start above t_f0 set by t_min; two intervals; one problem; a
+    robot whose blocks do not fit (refused)."""
+    robot = synth.c1_full().robot
+    par0 = synth.TrajParams(N=8, max_iters=0, outer=1)
+    q0, qg, qstar = problems(robot, 2, par0.N, 503)
+    refs = _oracle(robot, par0, q0, qg, qstar)
+    dev = _run(cp, robot, par0, q0, qg, qstar, "no steps")
+    _check(dev, refs, 1e-6, "no steps", True)
+    np.testing.assert_allclose(dev[2], np.maximum(par0.t_f0, dev[3][:, 3]), rtol=1e-6)
+    assert np.all(dev[3][:, 2] == 0)
+    parm = synth.TrajParams(N=8, max_iters=0, outer=1, t_f0=0.01)
+    dev = _run(cp, robot, parm, q0, qg, qstar, "t_min start")
+    _check(dev, _oracle(robot, parm, q0, qg, qstar), 1e-6, "t_min start", True)
+    np.testing.assert_allclose(dev[2], dev[3][:, 3], rtol=1e-6)
+    par2 = synth.TrajParams(N=2, outer=1, max_iters=20)
+    q0, qg, qstar = problems(robot, 2, 2, 504)
+    _check(_run(cp, robot, par2, q0, qg, qstar, "N=2"), _oracle(robot, par2, q0, qg, qstar), 1e-6, "N=2", True)
+    par1 = synth.TrajParams(N=8)
+    q0, qg, qstar = problems(robot, 1, 8, 505)
+    _check(_run(cp, robot, par1, q0, qg, qstar, "P=1"), _oracle(robot, par1, q0, qg, qstar), 2e-6, "P=1", False)
+    stiff = dataclasses.replace(robot, active=np.ones(6, np.uint8))
+    with pytest.raises(cp.CranePlanError):
+        # 2 n + 6 actuated joints = 18 entries per point: more than the block of 16
+        _run(cp, stiff, par1, q0, qg, qstar, "all actuated")
+
+
+def test_traj_argument_errors(cp):
+    robot = synth.c1_full().robot
+    plan = _plan(cp, robot)
+    z = torch.zeros((1, 6), device="cuda")
+    for bad in (dict(N=1), dict(N=401), dict(outer=0), dict(outer=21), dict(max_iters=-1), dict(max_iters=501),
+                dict(mu0=0.0), dict(mu_factor=0.5), dict(tau=0.0), dict(fd_q=0.0), dict(t_f0=-1.0),
+                dict(omega_s=float("nan")), dict(v_max=(0.6, 0.4, 0.0, 0.5, 2.0, 2.0))):
+        par = synth.TrajParams(**bad)
+        with pytest.raises(cp.CranePlanError):
+            plan.traj_refine(par, z, z, torch.zeros((1, par.N + 1, 6), device="cuda"))
