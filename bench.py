@@ -16,7 +16,8 @@ c2_diff (adjoint: fwd+bwd vs fwd, gradient error, polished iterations),
 c3_batch (many problems: batched graph launch vs one problem at a time),
 c4_sdf (lidar -> signed-distance grid, trilinear queries, fwd+bwd),
 ik (batched collision-free inverse kinematics with restarts),
-sat (the separating-axis narrow phase on link hulls and oriented boxes).
+sat (the separating-axis narrow phase on link hulls and oriented boxes),
+traj (step two: batched trajectory refinement by direct collocation).
 """
 import argparse
 import json
@@ -635,6 +636,99 @@ def cpu_baseline_sat(prob, n_paths=1024):
                       f"evaluation only), FP64, {dt:.1f} s"}
 
 
+# ----------------------------------------------------------------------------
+# traj: step two, batched trajectory refinement
+# ----------------------------------------------------------------------------
+
+PEAK_FP64 = 78.6e12  # MI355X FP64 vector peak
+
+
+def traj_flops(N, n, na, robot):
+    """Algorithmic FP64 flops of one assembly (dynamics Jacobians by central
+    differences and the normal equations) and of one trial step (block
+    factorisation, two solves, the trial point's dynamics and objective, the
+    predicted decrease) at the kernel's block of MB = 16 entries per point.
+    One evaluation of the dynamics: the chain (a revolute joint 107, a
+    prismatic one 40: world axis 15, origin 18, rotation 27 + 2, product
+    45), the tip 18, the Jacobian columns 12 per joint, the velocity term
+    (a revolute pair 27, a revolute-prismatic pair 18), the inputs and the
+    passive joints' 2 x 2 solve 50."""
+    jt = np.asarray(robot.joint_type)
+    rev = int(np.sum(jt == 0))
+    pri = len(jt) - rev
+    f_dyn = 107 * rev + 40 * pri + 18 + 12 * n + 27 * rev * (rev + 1) // 2 + 18 * rev * pri + 50
+    MB, nx = 16, 2 * n
+    jac = (N + 1) * (1 + 2 * (nx + na)) * f_dyn + (N + 1) * (nx + na) * nx * 2
+    normal = (N + 1) * MB * MB * 2 * nx * 2 + N * MB * MB * nx * 2 + (N + 1) * MB * 2 * nx * 2 * 2 + N * nx * 4
+    chol = sum((MB - 1 - j) * (MB - j) for j in range(MB)) + MB + MB * (MB - 1) // 2
+    factor = (N + 1) * (MB * MB * MB * 2 + chol + MB * MB * (MB + 1))
+    solve = (N + 1) * 2 * 2 * (MB * MB * 2 + MB * (MB + 1)) + 2 * (N + 1) * MB * 2 * 2
+    trial = (N + 1) * f_dyn + (N * nx + (N - 1) * nx + N * na) * 4 + (N + 1) * MB * (3 * MB * 2 + 4)
+    return {"assembly": jac + normal, "trial": factor + solve + trial, "dynamics": f_dyn}
+
+
+def bench_traj(args, torch, cp):
+    """traj: step two on P problems at the paper's 100 collocation intervals
+    (the c1 crane's chain; start/goal moves and bent step-one paths from the
+    seeded recipe), default solver settings, one launch refining all of
+    them; reports trajectories per second and the launch against the FP64
+    vector roofline (algorithmic flops from each problem's own counts of
+    assemblies and trial steps)."""
+    from paper_2503_14160_amd import synth
+    robot = synth.c1_full().robot
+    par = synth.TrajParams(N=100)
+    P = args.batch_problems
+    q0, qg, qs = synth.traj_problems(robot, P, par.N, synth.SCENE_SEED + 11)
+    plan = cp.Plan(robot, synth.c0_plain().scene, synth_cost_any(), max_B=1)
+    a = [torch.from_numpy(x).cuda() for x in (q0, qg, qs)]
+    for _ in range(max(1, args.warmup)):
+        plan.traj_refine(par, *a)
+    torch.cuda.synchronize()
+    print(f"[bench] traj: {P} problems, N = {par.N}, {args.steps} timed launches", file=sys.stderr, flush=True)
+    ms = _timed(torch, lambda: plan.traj_refine(par, *a), args.steps)
+    X, U, tf, info = plan.traj_refine(par, *a)
+    inf = info.cpu().numpy().astype(np.float64)
+    n = robot.n_joints
+    na = int(np.sum(robot.active))
+    fl = traj_flops(par.N, n, na, robot)
+    flops = float(np.sum(inf[:, 2]) * fl["trial"] + np.sum(inf[:, 3] + par.outer) * fl["assembly"])
+    config = {"workload": "traj_n100", "problems": P, "intervals": par.N, "unknowns_per_problem": 16 * (par.N - 1) + 4 * 2 + 1,
+              "outer": par.outer, "max_iters": par.max_iters, "mu0": par.mu0, "omega_s": par.omega_s,
+              "omega_t": par.omega_t}
+    roof = {"bound": "alu", "kernel": "k_traj_refine", "unit": "TFLOP/s", "peak": PEAK_FP64 / 1e12, "launch_ms": ms,
+            "achieved": flops / (ms * 1e-3) / 1e12, "frac": flops / (ms * 1e-3) / PEAK_FP64, "traffic": None,
+            "flops_per_launch": flops, "flops_per_assembly": fl["assembly"], "flops_per_trial": fl["trial"],
+            "note": "algorithmic FP64 flops of the assemblies (accepted steps plus one per outer round) and trial "
+                    "steps each problem took, over the launch; the solve is a sequential sweep over the 101 blocks "
+                    "of each problem, bound by latency rather than by the vector units"}
+    out = base_line(args, "trajectories refined/s", P / (ms * 1e-3), "trajectories/s", ms, config,
+                    ms_per_trajectory_in_batch=ms / P, trial_steps_mean=float(inf[:, 2].mean()),
+                    accepted_steps_mean=float(inf[:, 3].mean()), defect_median=float(np.median(inf[:, 0])),
+                    defect_below_1e_8=float(np.mean(inf[:, 0] < 1e-8)), t_f_median=float(np.median(tf.cpu().numpy())),
+                    roofline=roof)
+    out["dtype"] = "f64"
+    return out, (robot, par, q0, qg, qs)
+
+
+def cpu_baseline_traj(robot, par, q0, qg, qs, problems=1):
+    import oracle
+    oracle.build()
+    m = oracle.Model(robot, synth_scene_empty(), None)
+    t0 = time.perf_counter()
+    for p in range(problems):
+        oracle.traj_refine(m, par, q0[p].astype(np.float64), qg[p].astype(np.float64), qs[p].astype(np.float64))
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": problems / dt, "unit": "trajectories/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {problems} of the traj workload's problems (N = {par.N}, dense FP64 "
+                      f"Levenberg-Marquardt in numpy, the C dynamics), {dt:.1f} s"}
+
+
+def synth_scene_empty():
+    from paper_2503_14160_amd import synth
+    return synth.c0_plain().scene
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -642,7 +736,7 @@ def main():
                     help="timed iterations (default: the workload's iteration count, 50 for c1_full; 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c1_full",
-                    choices=["c1_full", "c1_self", "c0_plain", "c2_diff", "c3_batch", "c4_sdf", "ik", "sat"])
+                    choices=["c1_full", "c1_self", "c0_plain", "c2_diff", "c3_batch", "c4_sdf", "ik", "sat", "traj"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eval-reps", type=int, default=10)
     ap.add_argument("--batch-problems", type=int, default=256)
@@ -661,6 +755,8 @@ def main():
         args.steps = 50 if args.workload in ("c1_full", "c1_self", "c4_sdf") else 20
         if args.workload == "sat":
             args.steps = 10
+        if args.workload == "traj":
+            args.steps = 3
     import torch
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
@@ -699,6 +795,11 @@ def main():
         if not args.no_cpu_baseline:
             print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
             out["cpu_baseline"] = cpu_baseline_sat(prob)
+    elif args.workload == "traj":
+        out, ctx = bench_traj(args, torch, cp)
+        if not args.no_cpu_baseline:
+            print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline_traj(*ctx)
     elif args.workload == "ik":
         out, T, prob = bench_ik(args, torch, cp, synth.ik_c1())
         if not args.no_cpu_baseline:

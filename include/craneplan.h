@@ -537,7 +537,7 @@ int cp_traj_workspace_size(const cp_plan *plan, const cp_traj_params *params, in
  * (8-byte aligned; its contents on return are scratch); outputs d_x
  * [P][N+1][2n] states, d_u [P][N+1][n_act] inputs, d_t_f [P] final times,
  * d_info [P][4] (may be NULL): max |defect| without multipliers, the last
- * augmented objective |r|^2 / 2, trial steps taken, t_min.  Uses the plan's
+ * augmented objective |r|^2 / 2, trial steps, accepted steps.  Uses the plan's
  * robot (joints, tip, actuated set); its scene and costs are not used.
  * Errors: CP_ERR_INVALID_ARG (null pointers, parameters out of range),
  * CP_ERR_SIZE (P < 1, N out of range, workspace too small, 2 n + n_act >

@@ -632,7 +632,8 @@ def traj_refine(model: Model, par, q_start, q_goal, q_star, trace: Optional[list
     the IK).  Per outer iteration: minimise |r|^2 / 2 by LM from the current
     point, then lam += mu d (d the defects), mu *= mu_factor.  Returns
     dict(t_f, X [N+1, 2n], U [N+1, n_a], z, defect (max |d|), F (the last
-    |r|^2 / 2), iters (trial steps over all outer iterations), t_min)."""
+    |r|^2 / 2), iters (trial steps over all outer iterations), accepted (the
+    trial steps taken), t_min)."""
     rb = model.robot
     n = rb.n_joints
     act = np.where(np.asarray(rb.active) != 0)[0]
@@ -642,6 +643,7 @@ def traj_refine(model: Model, par, q_start, q_goal, q_star, trace: Optional[list
     lam = np.zeros((N, 2 * n))
     mu = par.mu0
     iters = 0
+    accepted = 0
     F = 0.0
     for _ in range(par.outer):
         r, J = traj_residual(model, par, q_start, q_goal, q_star, z, lam, mu)
@@ -664,6 +666,7 @@ def traj_refine(model: Model, par, q_start, q_goal, q_star, trace: Optional[list
             it += 1
             if pred > 0.0 and F - Fn > 0.0:
                 rho = (F - Fn) / pred
+                accepted += 1
                 z, r, J, F = zn, rn, Jn, Fn
                 A = J.T @ J
                 g = J.T @ r
@@ -688,7 +691,7 @@ def traj_refine(model: Model, par, q_start, q_goal, q_star, trace: Optional[list
         U[k] = L.u_at(z, k)
     r0, _ = traj_residual(model, par, q_start, q_goal, q_star, z, np.zeros((N, 2 * n)), 1.0, jacobian=False)
     return dict(t_f=float(z[L.s] ** 2), X=X, U=U, z=z, defect=float(np.max(np.abs(r0[:N * 2 * n]))), F=F,
-                iters=iters, t_min=traj_t_min(model, par, q_start, q_goal))
+                iters=iters, accepted=accepted, t_min=traj_t_min(model, par, q_start, q_goal))
 
 
 # ----------------------------------------------------------------------------

@@ -688,7 +688,7 @@ __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDe
     for (size_t t = threadIdx.x; t < (size_t)N * nx; t += kTrajThreads) W.lam[t] = 0.0;
     __syncthreads();
     double mu = T.mu0, F = 0.0, a_ss = 0.0;
-    int iters = 0;
+    int iters = 0, accepted = 0;
     for (int outer = 0; outer < T.outer; ++outer) {
         eval_points(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
         __syncthreads();
@@ -725,6 +725,7 @@ __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDe
             ++it;
             if (pred > 0.0 && F - Ft > 0.0) {
                 const double rho = (F - Ft) / pred, tt = 2.0 * rho - 1.0;
+                ++accepted;
                 for (size_t t = threadIdx.x; t < nz; t += kTrajThreads) W.z[t] = W.zt[t];
                 __syncthreads();
                 F = Ft;
@@ -772,7 +773,7 @@ __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDe
         tf_out[pr] = (float)(sv * sv);
         if (info_out) {
             float *o = info_out + (size_t)pr * 4;
-            o[0] = (float)dmax; o[1] = (float)F; o[2] = (float)iters; o[3] = (float)t_min;
+            o[0] = (float)dmax; o[1] = (float)F; o[2] = (float)iters; o[3] = (float)accepted;
         }
     }
 }

@@ -609,6 +609,27 @@ def ik_c1(n_targets: int = 1024, restarts: int = 8, oversample: int = 24) -> IkP
 IK_TARGET_CLEARANCE = 0.1
 
 
+def traj_problems(robot: Robot, P: int, N: int, seed: int):
+    """P step-two problems: start/goal pairs (hanging configurations, then a
+    slew of U(-0.8, 0.8) rad, a boom move of U(-0.15, 0.15) rad and a
+    telescope move of U(-0.5, 0.5) m clipped to [0.1, 2.9], the grapple
+    kept hanging) and bent paths between them sampled at s = k / N: the
+    straight line plus a smooth bump of 0.1 sin(pi s) rad on the boom, as a
+    step-one path bends over an obstacle.  float32 [P, n], [P, n],
+    [P, N+1, n]."""
+    rng = np.random.default_rng(seed)
+    q0 = hanging_configs(rng, robot, P).astype(np.float64)
+    qg = q0.copy()
+    qg[:, 0] += rng.uniform(-0.8, 0.8, P)
+    qg[:, 1] += rng.uniform(-0.15, 0.15, P)
+    qg[:, 3] = np.clip(qg[:, 3] + rng.uniform(-0.5, 0.5, P), 0.1, 2.9)
+    qg[:, 5] = qg[:, 1] + qg[:, 2]
+    s = np.linspace(0.0, 1.0, N + 1)
+    qstar = q0[:, None, :] + s[None, :, None] * (qg - q0)[:, None, :]
+    qstar[:, :, 1] += 0.1 * np.sin(np.pi * s)[None, :]
+    return _f32(q0), _f32(qg), _f32(qstar)
+
+
 WORKLOADS = {"c0_plain": c0_plain, "c1_full": c1_full, "c2_diff": c2_diff, "c4_sdf": c4_sdf}
 
 

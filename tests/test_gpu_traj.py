@@ -65,9 +65,9 @@ def _check(dev, refs, tol, label, same_iters):
                                    err_msg=f"{label} states {p}")
         np.testing.assert_allclose(U[p], ref["U"], rtol=0, atol=tol * max(1.0, np.abs(ref["U"]).max()),
                                    err_msg=f"{label} inputs {p}")
-        assert info[p, 3] == pytest.approx(ref["t_min"], rel=1e-7), (label, p)
         if same_iters:
             assert int(info[p, 2]) == ref["iters"], (label, p)
+            assert int(info[p, 3]) == ref["accepted"], (label, p)
             assert info[p, 1] == pytest.approx(ref["F"], rel=1e-6), (label, p)
             assert info[p, 0] == pytest.approx(ref["defect"], rel=1e-3, abs=1e-9), (label, p)
         else:
@@ -75,8 +75,12 @@ def _check(dev, refs, tol, label, same_iters):
 
 
 def test_traj_early_iterations_match(cp):
+    """Two rounds of 20 trial steps with the stopping tests off: every
+    problem is still far from the noise floor (where an accept or reject
+    decision turns on rounding), so both sides take and refuse the same
+    steps."""
     robot = synth.c1_full().robot
-    par = synth.TrajParams(N=12, t_f0=6.0, mu0=100.0, outer=2, max_iters=40)
+    par = synth.TrajParams(N=12, t_f0=6.0, mu0=100.0, outer=2, max_iters=20, eps_grad=0.0, eps_step=0.0)
     q0, qg, qstar = problems(robot, 4, par.N, 501)
     dev = _run(cp, robot, par, q0, qg, qstar, "early")
     _check(dev, _oracle(robot, par, q0, qg, qstar), 1e-6, "early", True)
@@ -95,7 +99,7 @@ def test_traj_converged_match(cp):
 
 
 def test_traj_paper_horizon(cp):
-    """The paper's discretisation: 100 collocation intervals, 1617 unknowns
+    """The paper's discretisation: 100 collocation intervals, 1593 unknowns
     once the fixed end states are removed, default solver settings."""
     robot = synth.c1_full().robot
     par = synth.TrajParams(N=100)
@@ -114,12 +118,14 @@ def test_traj_edge_cases(cp):
     refs = _oracle(robot, par0, q0, qg, qstar)
     dev = _run(cp, robot, par0, q0, qg, qstar, "no steps")
     _check(dev, refs, 1e-6, "no steps", True)
-    np.testing.assert_allclose(dev[2], np.maximum(par0.t_f0, dev[3][:, 3]), rtol=1e-6)
-    assert np.all(dev[3][:, 2] == 0)
+    t_min = np.array([r["t_min"] for r in refs])
+    assert np.all(t_min < par0.t_f0)
+    np.testing.assert_allclose(dev[2], par0.t_f0, rtol=1e-6)
+    assert np.all(dev[3][:, 2] == 0) and np.all(dev[3][:, 3] == 0)
     parm = synth.TrajParams(N=8, max_iters=0, outer=1, t_f0=0.01)
     dev = _run(cp, robot, parm, q0, qg, qstar, "t_min start")
     _check(dev, _oracle(robot, parm, q0, qg, qstar), 1e-6, "t_min start", True)
-    np.testing.assert_allclose(dev[2], dev[3][:, 3], rtol=1e-6)
+    np.testing.assert_allclose(dev[2], t_min, rtol=1e-6)
     par2 = synth.TrajParams(N=2, outer=1, max_iters=20)
     q0, qg, qstar = problems(robot, 2, 2, 504)
     _check(_run(cp, robot, par2, q0, qg, qstar, "N=2"), _oracle(robot, par2, q0, qg, qstar), 1e-6, "N=2", True)
