@@ -6,10 +6,11 @@ binding) never imports this package, and this package imports nothing of the
 product except the seeded input generator.
 
 The heavy loops (kinematics, distances, spline, cost, gradient, Philox, EDT,
-the IK residual and its Jacobian) are in ``oracle.c``; the optimizer of
-Algorithm 1 (sampling, selection, log-rank weights, mean and covariance
-update) and the Levenberg-Marquardt loop of the collision-free IK (Sec. 3.2)
-are written out here with numpy, step by step.
+the IK residual and its Jacobian, the reduced crane dynamics) are in
+``oracle.c``; the optimizer of Algorithm 1 (sampling, selection, log-rank
+weights, mean and covariance update), the Levenberg-Marquardt loop of the
+collision-free IK (Sec. 3.2) and step two's collocation problem and solver
+(Sec. 4.2) are written out here with numpy, step by step.
 
 Readings of the paper taken here (each is also listed in the design notes):
 * the spline keeps the paper's four copies of the start and goal control
@@ -20,12 +21,19 @@ Readings of the paper taken here (each is also listed in the design notes):
   (C_0 = sigma0^2 I), sampled through the lower Cholesky factor;
 * the covariance update uses the freshly updated mean;
 * elites are the first nu of the stable order on (cost, index), NaN ranked
-  as +inf (a NaN and a +inf then go by index).
+  as +inf (a NaN and a +inf then go by index);
+* step two: a unit load at the tip on massless links stands for the crane's
+  mass model (passive rows of Sec. 2.1's state-space form with M = J^T J,
+  b = J^T (c + g e_z)), viscous damping on the passive joints, R = I,
+  defects over k = 0..N-1, the final-time bound t_F >= t_min that the
+  velocity limits imply, and an augmented-Lagrangian Levenberg-Marquardt
+  solver in place of IPOPT.
 
 Parity status: every function here is pinned by a CPU test (closed forms,
 invariants, brute force, finite differences, published Philox vectors, scipy's
 rotation maps, MINPACK's Levenberg-Marquardt, exact box distances from a
-bound-constrained least-squares solve) except two chaotic iterations, which
+bound-constrained least-squares solve, the pendulum frequency, energy
+conservation, an exact KKT optimum and SLSQP) except two chaotic iterations, which
 are "parity unpinned": multi-iteration optimizer trajectories beyond one step
 (one-step parity and convergence properties are checked), and IK trajectories
 that cross the collision term, where a switch of the minimising pair changes
