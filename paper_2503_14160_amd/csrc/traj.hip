@@ -533,11 +533,16 @@ __device__ void factor(const double *D, const double *E, double damp, int nreal_
             // X_k = L_k^-1 E_k: forward substitution, one column per thread
             if ((int)threadIdx.x < MB) {
                 const int col = threadIdx.x;
-                for (int i = 0; i < MB; ++i) {
-                    double v = E[(size_t)k * MB * MB + i * MB + col];
-                    for (int m = 0; m < i; ++m) v -= sh.A[i][m] * sh.X[m][col];
-                    sh.X[i][col] = v / sh.A[i][i];
+                // the column of E_k first (its loads all in flight at once), then the
+                // substitution in registers
+                double x[kMB];
+                for (int i = 0; i < kMB; ++i) x[i] = E[(size_t)k * MB * MB + i * MB + col];
+                for (int i = 0; i < kMB; ++i) {
+                    double v = x[i];
+                    for (int m = 0; m < i; ++m) v -= sh.A[i][m] * x[m];
+                    x[i] = v / sh.A[i][i];
                 }
+                for (int i = 0; i < kMB; ++i) sh.X[i][col] = x[i];
             }
             __syncthreads();
             LX[(size_t)k * MB * MB + ti * MB + tj] = sh.X[ti][tj];
@@ -546,52 +551,55 @@ __device__ void factor(const double *D, const double *E, double damp, int nreal_
     }
 }
 
-// solve L L^T x = b for two right-hand sides b0, b1 (length (N+1) MB), x in place
-__device__ void solve2(const double *LD, const double *LX, double *b0, double *b1, int N, TrajShared &sh) {
+// solve L L^T x = b for two right-hand sides b0, b1 (length (N+1) MB), x in
+// place, on lanes 0..2 MB - 1 of the first wave (lane which * MB + i holds
+// entry i of right-hand side `which`; a block's unknowns pass between lanes
+// by 16-wide shuffles); no workgroup barrier inside, the caller synchronises
+__device__ void solve2(const double *LD, const double *LX, double *b0, double *b1, int N) {
     const int MB = kMB;
+    if ((int)threadIdx.x >= 2 * MB) return;
+    const int which = threadIdx.x / MB, i = threadIdx.x % MB;
+    double *b = which ? b1 : b0;
     // forward: y_k = L_k^-1 (b_k - X_{k-1}^T y_{k-1})
+    double prev = 0.0;
     for (int k = 0; k <= N; ++k) {
-        if ((int)threadIdx.x < 2 * MB) {
-            const int which = threadIdx.x / MB, i = threadIdx.x % MB;
-            double *b = which ? b1 : b0;
-            double v = b[(size_t)k * MB + i];
-            if (k > 0)
-                for (int m = 0; m < MB; ++m) v -= LX[(size_t)(k - 1) * MB * MB + m * MB + i] * b[(size_t)(k - 1) * MB + m];
-            sh.v[which][i] = v;
+        const double *Lk = LD + (size_t)k * MB * MB;
+        double row[kMB];  // row i of L_k
+        for (int m = 0; m < kMB; ++m) row[m] = Lk[i * MB + m];
+        const double rinv = 1.0 / Lk[i * MB + i];
+        double v = b[(size_t)k * MB + i];
+        if (k > 0) {
+            const double *Xp = LX + (size_t)(k - 1) * MB * MB;
+            double col[kMB];  // column i of X_{k-1}
+            for (int m = 0; m < kMB; ++m) col[m] = Xp[m * MB + i];
+            for (int m = 0; m < kMB; ++m) v -= col[m] * __shfl(prev, m, kMB);
         }
-        __syncthreads();
-        if ((int)threadIdx.x < 2) {
-            const int which = threadIdx.x;
-            double *b = which ? b1 : b0;
-            for (int i = 0; i < MB; ++i) {
-                double v = sh.v[which][i];
-                for (int m = 0; m < i; ++m) v -= LD[(size_t)k * MB * MB + i * MB + m] * b[(size_t)k * MB + m];
-                b[(size_t)k * MB + i] = v / LD[(size_t)k * MB * MB + i * MB + i];
-            }
+        for (int j = 0; j < kMB; ++j) {
+            const double xj = __shfl(v * rinv, j, kMB);
+            if (i > j) v -= row[j] * xj;
         }
-        __syncthreads();
+        prev = v * rinv;
+        b[(size_t)k * MB + i] = prev;
     }
     // backward: x_k = L_k^-T (y_k - X_k x_{k+1})
     for (int k = N; k >= 0; --k) {
-        if ((int)threadIdx.x < 2 * MB) {
-            const int which = threadIdx.x / MB, i = threadIdx.x % MB;
-            double *b = which ? b1 : b0;
-            double v = b[(size_t)k * MB + i];
-            if (k < N)
-                for (int m = 0; m < MB; ++m) v -= LX[(size_t)k * MB * MB + i * MB + m] * b[(size_t)(k + 1) * MB + m];
-            sh.v[which][i] = v;
+        const double *Lk = LD + (size_t)k * MB * MB;
+        double col[kMB];  // column i of L_k
+        for (int m = 0; m < kMB; ++m) col[m] = Lk[m * MB + i];
+        const double rinv = 1.0 / Lk[i * MB + i];
+        double v = b[(size_t)k * MB + i];
+        if (k < N) {
+            const double *Xk = LX + (size_t)k * MB * MB;
+            double row[kMB];  // row i of X_k
+            for (int m = 0; m < kMB; ++m) row[m] = Xk[i * MB + m];
+            for (int m = 0; m < kMB; ++m) v -= row[m] * __shfl(prev, m, kMB);
         }
-        __syncthreads();
-        if ((int)threadIdx.x < 2) {
-            const int which = threadIdx.x;
-            double *b = which ? b1 : b0;
-            for (int i = MB - 1; i >= 0; --i) {
-                double v = sh.v[which][i];
-                for (int m = i + 1; m < MB; ++m) v -= LD[(size_t)k * MB * MB + m * MB + i] * b[(size_t)k * MB + m];
-                b[(size_t)k * MB + i] = v / LD[(size_t)k * MB * MB + i * MB + i];
-            }
+        for (int j = kMB - 1; j >= 0; --j) {
+            const double xj = __shfl(v * rinv, j, kMB);
+            if (i < j) v -= col[j] * xj;
         }
-        __syncthreads();
+        prev = v * rinv;
+        b[(size_t)k * MB + i] = prev;
     }
 }
 
@@ -605,7 +613,8 @@ __device__ void damped_step(const TrajDev &T, const TrajWork &W, double a_ss, do
         W.w[t] = W.c[t];
     }
     __syncthreads();
-    solve2(W.LD, W.LX, W.y, W.w, N, sh);
+    solve2(W.LD, W.LX, W.y, W.w, N);
+    __syncthreads();
     double p0 = 0.0, p1 = 0.0;
     for (size_t t = threadIdx.x; t < nb; t += kTrajThreads) {
         p0 += W.c[t] * W.y[t];
