@@ -371,49 +371,66 @@ __device__ double objective(const PlanView &P, const TrajDev &T, const TrajIn &i
 // gradient g = J^T r at z
 // ---------------------------------------------------------------------------
 
-// entry (row i of defect k, column col of block kk in {k, k+1}) of the
-// scaled defect Jacobian, 0 outside the state / input entries
-__device__ inline double jd(const TrajDev &T, const double *Jx, const double *Ju, double h2, double sm, int k, int kk,
-                            int i, int col) {
-    const int n = T.n, na = T.na, nx = 2 * n;
-    if ((kk == 0 || kk == T.N) && col < nx) return 0.0;  // fixed states
-    double v;
-    if (col < nx) {
-        v = -h2 * Jx[((size_t)kk * nx + i) * nx + col];
-        if (col == i) v += kk == k ? -1.0 : 1.0;
-    } else if (col < nx + na) {
-        v = -h2 * Ju[((size_t)kk * nx + i) * na + (col - nx)];
-    } else {
-        v = 0.0;
-    }
-    return sm * v;
+// entry (r, c) of -h/2 [Jx_k | Ju_k], 0 for the fixed states of the end
+// points and the padding (the defect Jacobians are sqrt(mu) times this block
+// minus or plus the identity on the free states)
+__device__ inline double bentry(const TrajDev &T, const double *Jx, const double *Ju, double h2, int kk, int r, int c) {
+    const int nx = 2 * T.n, na = T.na;
+    if (r >= nx || c >= nx + na || ((kk == 0 || kk == T.N) && c < nx)) return 0.0;
+    return c < nx ? -h2 * Jx[((size_t)kk * nx + r) * nx + c] : -h2 * Ju[((size_t)kk * nx + r) * na + (c - nx)];
 }
 
+// rr, js: scratch vectors of (N+1) MB entries (the defects' scaled residuals
+// and their column for s, filled here)
 __device__ void normal_equations(const PlanView &P, const TrajDev &T, const TrajIn &in, const double *z,
                                  const double *f, const double *Jx, const double *Ju, const double *lam, double mu,
-                                 double *D, double *E, double *c, double *g, double &a_ss, TrajShared &sh) {
+                                 double *D, double *E, double *c, double *g, double &a_ss, double *rr, double *js,
+                                 TrajShared &sh) {
     const int n = T.n, na = T.na, N = T.N, nx = 2 * n, MB = kMB;
     const double s = z[(size_t)(N + 1) * MB];
     const double h2 = s * s / (2.0 * N), sm = sqrt(mu);
+    // the defects' scaled residuals and s-columns, once each
+    for (int t = threadIdx.x; t < N * nx; t += kTrajThreads) {
+        const int k = t / nx, r = t % nx;
+        rr[(size_t)k * MB + r] = defect_row(T, in, z, f, lam, mu, k, r, nullptr);
+        js[(size_t)k * MB + r] = -sm * (s / N) * (f[(size_t)k * nx + r] + f[(size_t)(k + 1) * nx + r]);
+    }
+    __syncthreads();
     const int ti = threadIdx.x / MB, tj = threadIdx.x % MB;
-    double gs_part = 0.0, ass_part = 0.0;
     for (int k = 0; k <= N; ++k) {
-        // D_k (ti, tj) and E_k (ti, tj)
+        const bool fixed = k == 0 || k == N;
+        // columns ti, tj of point k's block and column tj of point k + 1's
+        double bi[kMB], bj[kMB], bn[kMB];
+#pragma unroll
+        for (int r = 0; r < kMB; ++r) {
+            bi[r] = bentry(T, Jx, Ju, h2, k, r, ti);
+            bj[r] = bentry(T, Jx, Ju, h2, k, r, tj);
+            bn[r] = k < N ? bentry(T, Jx, Ju, h2, k + 1, r, tj) : 0.0;
+        }
+        // identity parts: free state columns of point k (both defects) and k + 1
+        const bool free_i = ti < nx && !fixed, free_j = tj < nx && !fixed;
+        const bool free_n = tj < nx && k + 1 != N;
+        // D_k (ti, tj) and E_k (ti, tj): defect k (left block L_k = sqrt(mu) (B_k - I)), defect
+        // k - 1 (right block R_{k-1} = sqrt(mu) (B_k + I)), E_k = L_k^T R_k
         double dsum = 0.0, esum = 0.0;
-        for (int r = 0; r < nx; ++r) {
+#pragma unroll
+        for (int r = 0; r < kMB; ++r) {
+            if (r >= nx) continue;
             if (k < N) {
-                const double l_i = jd(T, Jx, Ju, h2, sm, k, k, r, ti), l_j = jd(T, Jx, Ju, h2, sm, k, k, r, tj);
+                const double l_i = sm * (bi[r] + (free_i && r == ti ? -1.0 : 0.0));
+                const double l_j = sm * (bj[r] + (free_j && r == tj ? -1.0 : 0.0));
                 dsum += l_i * l_j;
-                esum += l_i * jd(T, Jx, Ju, h2, sm, k, k + 1, r, tj);
+                esum += l_i * (sm * (bn[r] + (free_n && r == tj ? 1.0 : 0.0)));
             }
             if (k > 0) {
-                const double r_i = jd(T, Jx, Ju, h2, sm, k - 1, k, r, ti), r_j = jd(T, Jx, Ju, h2, sm, k - 1, k, r, tj);
+                const double r_i = sm * (bi[r] + (free_i && r == ti ? 1.0 : 0.0));
+                const double r_j = sm * (bj[r] + (free_j && r == tj ? 1.0 : 0.0));
                 dsum += r_i * r_j;
             }
         }
         // diagonal terms: bounds (active ones), inputs, tracking; fixed states: identity
         if (ti == tj) {
-            if ((k == 0 || k == N) && ti < nx) {
+            if (fixed && ti < nx) {
                 dsum = 1.0;
             } else if (ti < nx) {
                 const double x = z[(size_t)k * MB + ti];
@@ -428,32 +445,30 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
                 dsum = 1.0;  // padding
             }
         }
-        if ((k == 0 || k == N) && ti < nx && ti != tj) dsum = 0.0;
-        if ((k == 0 || k == N) && tj < nx && ti != tj) dsum = 0.0;
+        if (fixed && ti < nx && ti != tj) dsum = 0.0;
+        if (fixed && tj < nx && ti != tj) dsum = 0.0;
         if (ti >= nx + na || tj >= nx + na) dsum = ti == tj ? 1.0 : 0.0;
         D[(size_t)k * MB * MB + ti * MB + tj] = dsum;
         if (k < N) E[(size_t)k * MB * MB + ti * MB + tj] = esum;
-        // c_k, g_k (threads 0..MB-1 hold one entry each)
+        // c_k, g_k (threads 0..MB-1: ti = 0, tj = col, so bj is column col of B_k)
         if ((int)threadIdx.x < MB) {
-            const int col = threadIdx.x;
+            const int col = tj;
             double cs = 0.0, gsum = 0.0;
-            for (int r = 0; r < nx; ++r) {
+    #pragma unroll
+        for (int r = 0; r < kMB; ++r) {
+                if (r >= nx) continue;
                 if (k < N) {
-                    const double js = -sm * (s / N) * (f[(size_t)k * nx + r] + f[(size_t)(k + 1) * nx + r]);
-                    const double rr = defect_row(T, in, z, f, lam, mu, k, r, nullptr);
-                    const double l = jd(T, Jx, Ju, h2, sm, k, k, r, col);
-                    cs += l * js;
-                    gsum += l * rr;
+                    const double l = sm * (bj[r] + (free_j && r == col ? -1.0 : 0.0));
+                    cs += l * js[(size_t)k * MB + r];
+                    gsum += l * rr[(size_t)k * MB + r];
                 }
                 if (k > 0) {
-                    const double js = -sm * (s / N) * (f[(size_t)(k - 1) * nx + r] + f[(size_t)k * nx + r]);
-                    const double rr = defect_row(T, in, z, f, lam, mu, k - 1, r, nullptr);
-                    const double rj = jd(T, Jx, Ju, h2, sm, k - 1, k, r, col);
-                    cs += rj * js;
-                    gsum += rj * rr;
+                    const double rj = sm * (bj[r] + (free_j && r == col ? 1.0 : 0.0));
+                    cs += rj * js[(size_t)(k - 1) * MB + r];
+                    gsum += rj * rr[(size_t)(k - 1) * MB + r];
                 }
             }
-            if (!((k == 0 || k == N) && col < nx)) {
+            if (!(fixed && col < nx)) {
                 if (col < nx) {
                     const double x = z[(size_t)k * MB + col];
                     const double lo = col < n ? (double)P.joints[col].qmin : -T.v_max[col - n];
@@ -474,14 +489,14 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
             c[(size_t)k * MB + col] = cs;
             g[(size_t)k * MB + col] = gsum;
         }
-        __syncthreads();
     }
-    // corner and g_s: sums over the defect rows
+    // corner and g_s: sums over the defect rows, plus the final-time bound
+    double gs_part = 0.0, ass_part = 0.0;
     for (int t = threadIdx.x; t < N * nx; t += kTrajThreads) {
         const int k = t / nx, r = t % nx;
-        const double js = -sm * (s / N) * (f[(size_t)k * nx + r] + f[(size_t)(k + 1) * nx + r]);
-        ass_part += js * js;
-        gs_part += js * defect_row(T, in, z, f, lam, mu, k, r, nullptr);
+        const double jsv = js[(size_t)k * MB + r];
+        ass_part += jsv * jsv;
+        gs_part += jsv * rr[(size_t)k * MB + r];
     }
     const bool below = s < in.s_min;
     a_ss = block_sum(sh, ass_part) + 1.0 + (below ? mu : 0.0);
@@ -702,7 +717,7 @@ __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDe
         eval_points(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
         __syncthreads();
         F = objective(P, T, in, W.z, W.f, W.lam, mu, sh);
-        normal_equations(P, T, in, W.z, W.f, W.Jx, W.Ju, W.lam, mu, W.D, W.E, W.c, W.g, a_ss, sh);
+        normal_equations(P, T, in, W.z, W.f, W.Jx, W.Ju, W.lam, mu, W.D, W.E, W.c, W.g, a_ss, W.y, W.w, sh);
         // initial damping: tau times the largest diagonal entry over the unknowns
         double dm = 0.0;
         for (size_t t = threadIdx.x; t < nb; t += kTrajThreads)
@@ -740,7 +755,7 @@ __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDe
                 F = Ft;
                 eval_points(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
                 __syncthreads();
-                normal_equations(P, T, in, W.z, W.f, W.Jx, W.Ju, W.lam, mu, W.D, W.E, W.c, W.g, a_ss, sh);
+                normal_equations(P, T, in, W.z, W.f, W.Jx, W.Ju, W.lam, mu, W.D, W.E, W.c, W.g, a_ss, W.y, W.w, sh);
                 damp *= fmax(1.0 / 3.0, 1.0 - tt * tt * tt);
                 nu = 2.0;
             } else {
