@@ -82,131 +82,140 @@ __device__ inline TrajWork traj_work(double *base, int N, int n, int na) {
 // dynamics in double precision
 // ---------------------------------------------------------------------------
 
-struct XfD {
-    double r[9], p[3];
-};
-
-__device__ inline void xfd_step(XfD &T, const JointDev &J, double q) {
-    double o[3] = {J.ox, J.oy, J.oz};
-    const double a[3] = {J.ax, J.ay, J.az};
-    if (J.type == CP_PRISMATIC)
-        for (int i = 0; i < 3; ++i) o[i] += q * a[i];
-    double np[3];
-    for (int i = 0; i < 3; ++i) np[i] = T.r[3 * i] * o[0] + T.r[3 * i + 1] * o[1] + T.r[3 * i + 2] * o[2] + T.p[i];
-    for (int i = 0; i < 3; ++i) T.p[i] = np[i];
-    if (J.type == CP_REVOLUTE) {
-        const double s = sin(q), c = cos(q), v = 1.0 - c;
-        // rotation by q about the unit axis a (Rodrigues)
-        const double R[9] = {c + a[0] * a[0] * v,        a[0] * a[1] * v - a[2] * s, a[0] * a[2] * v + a[1] * s,
-                             a[1] * a[0] * v + a[2] * s, c + a[1] * a[1] * v,        a[1] * a[2] * v - a[0] * s,
-                             a[2] * a[0] * v - a[1] * s, a[2] * a[1] * v + a[0] * s, c + a[2] * a[2] * v};
-        double nr[9];
-        for (int i = 0; i < 3; ++i)
-            for (int k = 0; k < 3; ++k) nr[3 * i + k] = T.r[3 * i] * R[k] + T.r[3 * i + 1] * R[3 + k] + T.r[3 * i + 2] * R[6 + k];
-        for (int i = 0; i < 9; ++i) T.r[i] = nr[i];
-    }
+// The dynamics are templated on the chain's joint count NJ (6: the crane,
+// every loop bound fixed; CP_MAX_JOINTS: any chain of at most that many
+// joints, the joints past n skipped), so every array below is indexed by
+// constants and lives in registers.
+template <int NJ>
+__device__ inline int chain_n(const TrajDev &T) {
+    return NJ == 6 ? 6 : T.n;
 }
 
-__device__ inline void cross_d(const double *a, const double *b, double *o) {
-    const double x = a[1] * b[2] - a[2] * b[1], y = a[2] * b[0] - a[0] * b[2], z = a[0] * b[1] - a[1] * b[0];
-    o[0] = x; o[1] = y; o[2] = z;
-}
-
-// joint accelerations qdd [n] at (q, qd) with actuated inputs u [na]
-__device__ void crane_accel_d(const PlanView &P, const TrajDev &T, const double *q, const double *qd, const double *u,
-                              double *qdd) {
-    const int n = T.n;
-    double aw[CP_MAX_JOINTS][3], piv[CP_MAX_JOINTS][3];
-    XfD F;
-    for (int i = 0; i < 9; ++i) F.r[i] = (i % 4 == 0) ? 1.0 : 0.0;
-    F.p[0] = F.p[1] = F.p[2] = 0.0;
-    for (int j = 0; j < n; ++j) {
+// joint accelerations qdd at (q, qd) with uf the actuated joints'
+// accelerations (entries of passive joints unused)
+template <int NJ>
+__device__ void crane_accel(const PlanView &P, const TrajDev &T, const double (&q)[NJ], const double (&qd)[NJ],
+                            const double (&uf)[NJ], double (&qdd)[NJ]) {
+    const int n = chain_n<NJ>(T);
+    double aw[NJ][3], pv[NJ][3];
+    bool rev[NJ], act[NJ];
+    double R[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0}, p[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        rev[j] = false;
+        act[j] = true;
+        for (int i = 0; i < 3; ++i) aw[j][i] = pv[j][i] = 0.0;
+        if (j >= n) continue;
         const JointDev J = P.joints[j];
         const double a[3] = {J.ax, J.ay, J.az};
-        for (int i = 0; i < 3; ++i) aw[j][i] = F.r[3 * i] * a[0] + F.r[3 * i + 1] * a[1] + F.r[3 * i + 2] * a[2];
-        xfd_step(F, J, q[j]);
-        for (int i = 0; i < 3; ++i) piv[j][i] = F.p[i];
+        rev[j] = J.type == CP_REVOLUTE;
+        act[j] = J.active != 0;
+        for (int i = 0; i < 3; ++i) aw[j][i] = R[3 * i] * a[0] + R[3 * i + 1] * a[1] + R[3 * i + 2] * a[2];
+        // the joint's origin (moved along its axis if prismatic), then its rotation
+        double o[3] = {J.ox, J.oy, J.oz};
+        if (J.type == CP_PRISMATIC)
+            for (int i = 0; i < 3; ++i) o[i] += q[j] * a[i];
+        double np[3];
+        for (int i = 0; i < 3; ++i) np[i] = R[3 * i] * o[0] + R[3 * i + 1] * o[1] + R[3 * i + 2] * o[2] + p[i];
+        for (int i = 0; i < 3; ++i) p[i] = np[i];
+        if (rev[j]) {
+            const double sn = sin(q[j]), cs = cos(q[j]), v = 1.0 - cs;
+            // rotation by q about the unit axis a (Rodrigues)
+            const double Q[9] = {cs + a[0] * a[0] * v,        a[0] * a[1] * v - a[2] * sn, a[0] * a[2] * v + a[1] * sn,
+                                 a[1] * a[0] * v + a[2] * sn, cs + a[1] * a[1] * v,        a[1] * a[2] * v - a[0] * sn,
+                                 a[2] * a[0] * v - a[1] * sn, a[2] * a[1] * v + a[0] * sn, cs + a[2] * a[2] * v};
+            double nr[9];
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) nr[3 * i + k] = R[3 * i] * Q[k] + R[3 * i + 1] * Q[3 + k] + R[3 * i + 2] * Q[6 + k];
+            for (int i = 0; i < 9; ++i) R[i] = nr[i];
+        }
+        for (int i = 0; i < 3; ++i) pv[j][i] = p[i];
     }
     const double t[3] = {P.tip[0], P.tip[1], P.tip[2]};
     double tip[3];
-    for (int i = 0; i < 3; ++i) tip[i] = F.r[3 * i] * t[0] + F.r[3 * i + 1] * t[1] + F.r[3 * i + 2] * t[2] + F.p[i];
+    for (int i = 0; i < 3; ++i) tip[i] = R[3 * i] * t[0] + R[3 * i + 1] * t[1] + R[3 * i + 2] * t[2] + p[i];
     // tip Jacobian columns and the rotation arms
-    double Jc[CP_MAX_JOINTS][3], arm[CP_MAX_JOINTS][3];
-    bool rev[CP_MAX_JOINTS];
-    for (int j = 0; j < n; ++j) {
-        rev[j] = P.joints[j].type == CP_REVOLUTE;
-        for (int i = 0; i < 3; ++i) arm[j][i] = tip[i] - piv[j][i];
-        if (rev[j]) cross_d(aw[j], arm[j], Jc[j]);
-        else for (int i = 0; i < 3; ++i) Jc[j][i] = aw[j][i];
+    double Jc[NJ][3], arm[NJ][3];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        for (int i = 0; i < 3; ++i) arm[j][i] = tip[i] - pv[j][i];
+        if (rev[j]) {
+            Jc[j][0] = aw[j][1] * arm[j][2] - aw[j][2] * arm[j][1];
+            Jc[j][1] = aw[j][2] * arm[j][0] - aw[j][0] * arm[j][2];
+            Jc[j][2] = aw[j][0] * arm[j][1] - aw[j][1] * arm[j][0];
+        } else {
+            for (int i = 0; i < 3; ++i) Jc[j][i] = aw[j][i];
+        }
     }
     // c = sum_ij H_ij qd_i qd_j, H_ij (i <= j, the earlier joint first):
     // revolute j: a_i x (a_j x arm_j) for revolute i, 0 for prismatic i;
-    // prismatic j: a_i x a_j for revolute i < j, 0 otherwise
+    // prismatic j: a_i x a_j for revolute i < j, 0 otherwise (joints past n:
+    // prismatic with a zero axis, so they add nothing)
     double c[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < n; ++i) {
-        for (int j = i; j < n; ++j) {
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+        for (int j = i; j < NJ; ++j) {
             double h[3] = {0.0, 0.0, 0.0};
             if (rev[j]) {
                 if (rev[i]) {
-                    double tmp[3];
-                    cross_d(aw[j], arm[j], tmp);
-                    cross_d(aw[i], tmp, h);
+                    // a_j x arm_j is the column Jc[j]
+                    h[0] = aw[i][1] * Jc[j][2] - aw[i][2] * Jc[j][1];
+                    h[1] = aw[i][2] * Jc[j][0] - aw[i][0] * Jc[j][2];
+                    h[2] = aw[i][0] * Jc[j][1] - aw[i][1] * Jc[j][0];
                 }
             } else if (rev[i] && i < j) {
-                cross_d(aw[i], aw[j], h);
+                h[0] = aw[i][1] * aw[j][2] - aw[i][2] * aw[j][1];
+                h[1] = aw[i][2] * aw[j][0] - aw[i][0] * aw[j][2];
+                h[2] = aw[i][0] * aw[j][1] - aw[i][1] * aw[j][0];
             }
             const double wgt = (i == j ? 1.0 : 2.0) * qd[i] * qd[j];
             for (int k = 0; k < 3; ++k) c[k] += wgt * h[k];
         }
     }
     double acc[3] = {c[0], c[1], c[2] + T.grav};
-    int pas[CP_MAX_JOINTS];
-    int npas = 0, ia = 0;
-    for (int j = 0; j < n; ++j) {
-        if (P.joints[j].active) {
-            qdd[j] = u[ia++];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        qdd[j] = 0.0;
+        if (j < n && act[j]) {
+            qdd[j] = uf[j];
             for (int k = 0; k < 3; ++k) acc[k] += Jc[j][k] * qdd[j];
-        } else {
-            pas[npas++] = j;
         }
     }
-    if (npas == 0) return;
-    // (J_p^T J_p) x = -J_p^T acc, Gaussian elimination with partial pivoting
-    double M[CP_MAX_JOINTS][CP_MAX_JOINTS + 1];
-    for (int r = 0; r < npas; ++r) {
-        for (int s = 0; s < npas; ++s)
-            M[r][s] = Jc[pas[r]][0] * Jc[pas[s]][0] + Jc[pas[r]][1] * Jc[pas[s]][1] + Jc[pas[r]][2] * Jc[pas[s]][2];
-        M[r][npas] = -(Jc[pas[r]][0] * acc[0] + Jc[pas[r]][1] * acc[1] + Jc[pas[r]][2] * acc[2]);
+    // passive joints: (J_p^T J_p) x = -J_p^T acc, written as one NJ x NJ
+    // system G y = b that is the identity on the other joints (G is then
+    // symmetric positive definite: Gaussian elimination without pivoting)
+    double G[NJ][NJ], b[NJ];
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+        const bool pr = r < n && !act[r];
+#pragma unroll
+        for (int s2 = 0; s2 < NJ; ++s2) {
+            const bool ps = s2 < n && !act[s2];
+            G[r][s2] = (pr && ps) ? Jc[r][0] * Jc[s2][0] + Jc[r][1] * Jc[s2][1] + Jc[r][2] * Jc[s2][2]
+                                  : (r == s2 ? 1.0 : 0.0);
+        }
+        b[r] = pr ? -(Jc[r][0] * acc[0] + Jc[r][1] * acc[1] + Jc[r][2] * acc[2]) : 0.0;
     }
-    for (int col = 0; col < npas; ++col) {
-        int best = col;
-        for (int r = col + 1; r < npas; ++r)
-            if (fabs(M[r][col]) > fabs(M[best][col])) best = r;
-        if (best != col)
-            for (int k = 0; k <= npas; ++k) {
-                const double tmp = M[col][k];
-                M[col][k] = M[best][k];
-                M[best][k] = tmp;
-            }
-        for (int r = col + 1; r < npas; ++r) {
-            const double fct = M[r][col] / M[col][col];
-            for (int k = col; k <= npas; ++k) M[r][k] -= fct * M[col][k];
+#pragma unroll
+    for (int col = 0; col < NJ; ++col) {
+#pragma unroll
+        for (int r = col + 1; r < NJ; ++r) {
+            const double fct = G[r][col] / G[col][col];
+            for (int k = col; k < NJ; ++k) G[r][k] -= fct * G[col][k];
+            b[r] -= fct * b[col];
         }
     }
-    double x[CP_MAX_JOINTS];
-    for (int r = npas - 1; r >= 0; --r) {
-        double v = M[r][npas];
-        for (int k = r + 1; k < npas; ++k) v -= M[r][k] * x[k];
-        x[r] = v / M[r][r];
+    double y[NJ];
+#pragma unroll
+    for (int r = NJ - 1; r >= 0; --r) {
+        double v = b[r];
+        for (int k = r + 1; k < NJ; ++k) v -= G[r][k] * y[k];
+        y[r] = v / G[r][r];
     }
-    for (int r = 0; r < npas; ++r) qdd[pas[r]] = x[r] - T.damping * qd[pas[r]];
-}
-
-// x' = f(x, u): (qd, qdd)
-__device__ inline void traj_rhs(const PlanView &P, const TrajDev &T, const double *x, const double *u, double *out) {
-    const int n = T.n;
-    for (int i = 0; i < n; ++i) out[i] = x[n + i];
-    crane_accel_d(P, T, x, x + n, u, out + n);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        if (j < n && !act[j]) qdd[j] = y[j] - T.damping * qd[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -225,51 +234,87 @@ __device__ inline double traj_t_min(const TrajDev &T, const float *qs, const flo
     return t;
 }
 
-// state x_k and input u_k of z (x_0, x_N: the fixed rest states)
-__device__ inline void point_of(const TrajDev &T, const TrajIn &in, const double *z, int k, double *x, double *u) {
-    const int n = T.n;
-    const double *b = z + (size_t)k * kMB;
-    if (k == 0 || k == T.N) {
-        const float *q = k == 0 ? in.qs : in.qg;
-        for (int i = 0; i < n; ++i) { x[i] = q[i]; x[n + i] = 0.0; }
-    } else {
-        for (int i = 0; i < 2 * n; ++i) x[i] = b[i];
-    }
-    for (int i = 0; i < T.na; ++i) u[i] = b[2 * n + i];
+// x' = f(x, u) = (qd, qdd) of one point into out[2n]
+template <int NJ>
+__device__ inline void traj_rhs(const PlanView &P, const TrajDev &T, const double (&q)[NJ], const double (&qd)[NJ],
+                                const double (&uf)[NJ], double *out) {
+    const int n = chain_n<NJ>(T);
+    double qdd[NJ];
+    crane_accel<NJ>(P, T, q, qd, uf, qdd);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i)
+        if (i < n) {
+            out[i] = qd[i];
+            out[n + i] = qdd[i];
+        }
 }
 
 // f at every point (and with jac its central-difference Jacobians): the
 // threads share out (point, direction) tasks, a direction's two evaluations
-// on one thread
+// on one thread; the perturbed coordinate is picked by comparison, never by
+// a per-lane index
+template <int NJ>
 __device__ void eval_points(const PlanView &P, const TrajDev &T, const TrajIn &in, const double *z, double *f,
                             double *Jx, double *Ju, bool jac) {
-    const int n = T.n, na = T.na, N = T.N, nx = 2 * n;
+    const int n = chain_n<NJ>(T), na = T.na, N = T.N, nx = 2 * n;
     const int per = jac ? 1 + nx + na : 1;
     const int total = (N + 1) * per;
     for (int t = threadIdx.x; t < total; t += kTrajThreads) {
         const int k = t / per, e = t % per;
-        double x[2 * CP_MAX_JOINTS], u[CP_MAX_JOINTS], fp[2 * CP_MAX_JOINTS], fm[2 * CP_MAX_JOINTS];
-        point_of(T, in, z, k, x, u);
+        // state and full-length inputs of point k (x_0, x_N: the fixed rest states)
+        const double *b = z + (size_t)k * kMB;
+        double q[NJ], qd[NJ], uf[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            q[j] = qd[j] = uf[j] = 0.0;
+            if (j >= n) continue;
+            if (k == 0) q[j] = in.qs[j];
+            else if (k == N) q[j] = in.qg[j];
+            else {
+                q[j] = b[j];
+                qd[j] = b[n + j];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NJ; ++a) {
+            if (a >= na) continue;
+            const int ja = T.act[a];
+            const double ua = b[2 * n + a];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                if (j == ja) uf[j] = ua;
+        }
+        double fp[2 * NJ], fm[2 * NJ];
         if (e == 0) {
-            traj_rhs(P, T, x, u, fp);
+            traj_rhs<NJ>(P, T, q, qd, uf, fp);
             for (int i = 0; i < nx; ++i) f[(size_t)k * nx + i] = fp[i];
             continue;
         }
-        const int d = e - 1;
+        const int d = e - 1;  // 0..n-1 positions, n..2n-1 velocities, 2n.. inputs
+        const double step = d < n ? T.fd_q : 1.0;
+        int ju = -1;  // the joint of the perturbed input
+#pragma unroll
+        for (int a = 0; a < NJ; ++a)
+            if (a < na && d == nx + a) ju = T.act[a];
+        double q1[NJ], qd1[NJ], u1[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            q1[j] = d == j ? q[j] + step : q[j];
+            qd1[j] = d == n + j ? qd[j] + step : qd[j];
+            u1[j] = j == ju ? uf[j] + step : uf[j];
+        }
+        traj_rhs<NJ>(P, T, q1, qd1, u1, fp);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            q1[j] = d == j ? q[j] - step : q[j];
+            qd1[j] = d == n + j ? qd[j] - step : qd[j];
+            u1[j] = j == ju ? uf[j] - step : uf[j];
+        }
+        traj_rhs<NJ>(P, T, q1, qd1, u1, fm);
         if (d < nx) {
-            const double step = d < n ? T.fd_q : 1.0, x0 = x[d];
-            x[d] = x0 + step;
-            traj_rhs(P, T, x, u, fp);
-            x[d] = x0 - step;
-            traj_rhs(P, T, x, u, fm);
             for (int i = 0; i < nx; ++i) Jx[((size_t)k * nx + i) * nx + d] = (fp[i] - fm[i]) / (2.0 * step);
         } else {
             const int j = d - nx;
-            const double u0 = u[j];
-            u[j] = u0 + 1.0;
-            traj_rhs(P, T, x, u, fp);
-            u[j] = u0 - 1.0;
-            traj_rhs(P, T, x, u, fm);
             for (int i = 0; i < nx; ++i) Ju[((size_t)k * nx + i) * na + j] = (fp[i] - fm[i]) / 2.0;
         }
     }
@@ -512,18 +557,37 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
 // (A + damp I) h = -g: block Cholesky sweep and the Schur complement on s
 // ---------------------------------------------------------------------------
 
-// Cholesky of sh.A in place (lower), one column at a time
-__device__ void chol_block(TrajShared &sh) {
-    const int MB = kMB;
-    const int ti = threadIdx.x / MB, tj = threadIdx.x % MB;
-    for (int j = 0; j < MB; ++j) {
-        if (threadIdx.x == 0) sh.A[j][j] = sqrt(sh.A[j][j]);
-        __syncthreads();
-        if ((int)threadIdx.x > j && (int)threadIdx.x < MB) sh.A[threadIdx.x][j] /= sh.A[j][j];
-        __syncthreads();
-        if (ti > j && tj > j && tj <= ti) sh.A[ti][tj] -= sh.A[ti][j] * sh.A[tj][j];
-        __syncthreads();
+// the value v holds in lane `lane` of this wave (lane: a wave-uniform index)
+__device__ inline double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Cholesky of sh.A in place (lower), right-looking, on lanes 0..2 MB - 1 of
+// the first wave: lane i holds row i mod MB in registers and the columns pass
+// between lanes by lane reads from the first half-wave (the second repeats the
+// computation, the first writes the factor back); no workgroup barrier inside
+__device__ void chol_rows(TrajShared &sh) {
+    const int i = threadIdx.x % kMB;
+    double a[kMB];
+#pragma unroll
+    for (int m = 0; m < kMB; ++m) a[m] = sh.A[i][m];
+#pragma unroll
+    for (int j = 0; j < kMB; ++j) {
+        const double piv = sqrt(lane_value(a[j], j));
+        if (i == j) a[j] = piv;
+        else if (i > j) a[j] /= piv;
+#pragma unroll
+        for (int m = j + 1; m < kMB; ++m) {
+            const double lmj = lane_value(a[j], m);
+            if (i >= m) a[m] -= a[j] * lmj;
+        }
     }
+    if ((int)threadIdx.x < kMB)
+#pragma unroll
+        for (int m = 0; m < kMB; ++m) sh.A[i][m] = a[m];
 }
 
 __device__ void factor(const double *D, const double *E, double damp, int nreal_last, double *LD, double *LX,
@@ -542,7 +606,8 @@ __device__ void factor(const double *D, const double *E, double damp, int nreal_
         __syncthreads();
         sh.A[ti][tj] = a;
         __syncthreads();
-        chol_block(sh);
+        if ((int)threadIdx.x < 2 * MB) chol_rows(sh);
+        __syncthreads();
         LD[(size_t)k * MB * MB + ti * MB + tj] = tj <= ti ? sh.A[ti][tj] : 0.0;
         if (k < N) {
             // X_k = L_k^-1 E_k: forward substitution, one column per thread
@@ -569,7 +634,13 @@ __device__ void factor(const double *D, const double *E, double damp, int nreal_
 // solve L L^T x = b for two right-hand sides b0, b1 (length (N+1) MB), x in
 // place, on lanes 0..2 MB - 1 of the first wave (lane which * MB + i holds
 // entry i of right-hand side `which`; a block's unknowns pass between lanes
-// by 16-wide shuffles); no workgroup barrier inside, the caller synchronises
+// by lane reads); no workgroup barrier inside, the caller synchronises
+// entry m of this lane's right-hand side: lane m or MB + m
+__device__ inline double of_rhs(double v, int m, int which) {
+    const double v0 = lane_value(v, m), v1 = lane_value(v, kMB + m);
+    return which ? v1 : v0;
+}
+
 __device__ void solve2(const double *LD, const double *LX, double *b0, double *b1, int N) {
     const int MB = kMB;
     if ((int)threadIdx.x >= 2 * MB) return;
@@ -587,10 +658,12 @@ __device__ void solve2(const double *LD, const double *LX, double *b0, double *b
             const double *Xp = LX + (size_t)(k - 1) * MB * MB;
             double col[kMB];  // column i of X_{k-1}
             for (int m = 0; m < kMB; ++m) col[m] = Xp[m * MB + i];
-            for (int m = 0; m < kMB; ++m) v -= col[m] * __shfl(prev, m, kMB);
+#pragma unroll
+            for (int m = 0; m < kMB; ++m) v -= col[m] * of_rhs(prev, m, which);
         }
+#pragma unroll
         for (int j = 0; j < kMB; ++j) {
-            const double xj = __shfl(v * rinv, j, kMB);
+            const double xj = of_rhs(v * rinv, j, which);
             if (i > j) v -= row[j] * xj;
         }
         prev = v * rinv;
@@ -607,10 +680,12 @@ __device__ void solve2(const double *LD, const double *LX, double *b0, double *b
             const double *Xk = LX + (size_t)k * MB * MB;
             double row[kMB];  // row i of X_k
             for (int m = 0; m < kMB; ++m) row[m] = Xk[i * MB + m];
-            for (int m = 0; m < kMB; ++m) v -= row[m] * __shfl(prev, m, kMB);
+#pragma unroll
+            for (int m = 0; m < kMB; ++m) v -= row[m] * of_rhs(prev, m, which);
         }
+#pragma unroll
         for (int j = kMB - 1; j >= 0; --j) {
-            const double xj = __shfl(v * rinv, j, kMB);
+            const double xj = of_rhs(v * rinv, j, which);
             if (i < j) v -= col[j] * xj;
         }
         prev = v * rinv;
@@ -694,6 +769,7 @@ __device__ inline bool real_entry(const TrajDev &T, size_t t) {
     return !((k == 0 || k == T.N) && i < 2 * T.n);
 }
 
+template <int NJ>
 __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDev T, const float *__restrict__ qs,
                                                               const float *__restrict__ qg,
                                                               const float *__restrict__ qstar, double *work,
@@ -714,7 +790,7 @@ __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDe
     double mu = T.mu0, F = 0.0, a_ss = 0.0;
     int iters = 0, accepted = 0;
     for (int outer = 0; outer < T.outer; ++outer) {
-        eval_points(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
+        eval_points<NJ>(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
         __syncthreads();
         F = objective(P, T, in, W.z, W.f, W.lam, mu, sh);
         normal_equations(P, T, in, W.z, W.f, W.Jx, W.Ju, W.lam, mu, W.D, W.E, W.c, W.g, a_ss, W.y, W.w, sh);
@@ -740,7 +816,7 @@ __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDe
             if (!(hn > T.eps_step * (zn + T.eps_step))) break;
             for (size_t t = threadIdx.x; t < nz; t += kTrajThreads) W.zt[t] = W.z[t] + W.h[t];
             __syncthreads();
-            eval_points(P, T, in, W.zt, W.ft, W.Jx, W.Ju, false);
+            eval_points<NJ>(P, T, in, W.zt, W.ft, W.Jx, W.Ju, false);
             __syncthreads();
             const double Ft = objective(P, T, in, W.zt, W.ft, W.lam, mu, sh);
             double hg = 0.0;
@@ -753,7 +829,7 @@ __global__ __launch_bounds__(kTrajThreads) void k_traj_refine(PlanView P, TrajDe
                 for (size_t t = threadIdx.x; t < nz; t += kTrajThreads) W.z[t] = W.zt[t];
                 __syncthreads();
                 F = Ft;
-                eval_points(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
+                eval_points<NJ>(P, T, in, W.z, W.f, W.Jx, W.Ju, true);
                 __syncthreads();
                 normal_equations(P, T, in, W.z, W.f, W.Jx, W.Ju, W.lam, mu, W.D, W.E, W.c, W.g, a_ss, W.y, W.w, sh);
                 damp *= fmax(1.0 / 3.0, 1.0 - tt * tt * tt);
@@ -824,8 +900,12 @@ hipError_t launch_traj_refine(const PlanView &P, const cp_traj_params &prm, cons
     T.eps_step = prm.eps_step; T.fd_q = prm.fd_q; T.t_f0 = prm.t_f0;
     for (int j = 0; j < CP_MAX_JOINTS; ++j) T.v_max[j] = j < T.n ? prm.v_max[j] : 0.0;
     const size_t stride = traj_work_doubles(T.N, T.n, T.na);
-    hipLaunchKernelGGL(k_traj_refine, dim3(n_prob), dim3(kTrajThreads), 0, st, P, T, q_start, q_goal, q_star,
-                       static_cast<double *>(work), stride, x_out, u_out, tf_out, info_out);
+    if (T.n == 6)
+        hipLaunchKernelGGL(k_traj_refine<6>, dim3(n_prob), dim3(kTrajThreads), 0, st, P, T, q_start, q_goal, q_star,
+                           static_cast<double *>(work), stride, x_out, u_out, tf_out, info_out);
+    else
+        hipLaunchKernelGGL(k_traj_refine<CP_MAX_JOINTS>, dim3(n_prob), dim3(kTrajThreads), 0, st, P, T, q_start,
+                           q_goal, q_star, static_cast<double *>(work), stride, x_out, u_out, tf_out, info_out);
     return hipGetLastError();
 }
 

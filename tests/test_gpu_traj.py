@@ -138,6 +138,36 @@ def test_traj_edge_cases(cp):
         _run(cp, stiff, par1, q0, qg, qstar, "all actuated")
 
 
+def _cart_pendulum():
+    """A cart on a rail (actuated, prismatic along x) carrying a pendulum of
+    length 1 m (passive, about y): the smallest underactuated chain, run by
+    the kernel built for chains other than the six-joint crane."""
+    f32 = np.float32
+    return synth.Robot(joint_type=np.array([synth.PRISMATIC, synth.REVOLUTE], np.int32),
+                       axis=f32([[1, 0, 0], [0, 1, 0]]), origin=f32([[0, 0, 0], [0, 0, 0]]),
+                       q_min=f32([-10.0, -3.0]), q_max=f32([10.0, 3.0]), q_hold=f32([0.0, 0.0]),
+                       active=np.array([1, 0], np.uint8), sphere_frame=np.array([2], np.int32),
+                       sphere_center=f32([[0, 0, 0]]), sphere_radius=f32([0.1]), tip=f32([0, 0, -1.0]),
+                       link_lengths=f32([1, 1, 1, 1, 1]))
+
+
+def test_traj_other_chain(cp):
+    """The kernel for any chain of at most eight joints (the crane has its
+    own): a cart-pendulum moved by 1 m with the pendulum at rest at both
+    ends, early iterations step for step and a converged solve."""
+    robot = _cart_pendulum()
+    N = 10
+    q0 = np.array([[0.0, 0.0], [0.5, 0.0]], np.float32)
+    qg = np.array([[1.0, 0.0], [-0.5, 0.0]], np.float32)
+    qstar = np.stack([q0[p] + np.linspace(0, 1, N + 1)[:, None] * (qg[p] - q0[p]) for p in range(2)]).astype(np.float32)
+    early = synth.TrajParams(N=N, v_max=(2.0, 5.0), t_f0=3.0, outer=2, max_iters=6, eps_grad=0.0, eps_step=0.0)
+    _check(_run(cp, robot, early, q0, qg, qstar, "cart early"), _oracle(robot, early, q0, qg, qstar), 1e-6,
+           "cart early", True)
+    conv = synth.TrajParams(N=N, v_max=(2.0, 5.0), t_f0=3.0)
+    _check(_run(cp, robot, conv, q0, qg, qstar, "cart converged"), _oracle(robot, conv, q0, qg, qstar), 2e-6,
+           "cart converged", False)
+
+
 def test_traj_argument_errors(cp):
     robot = synth.c1_full().robot
     plan = _plan(cp, robot)
