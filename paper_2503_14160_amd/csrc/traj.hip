@@ -442,15 +442,65 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
     }
     __syncthreads();
     const int ti = threadIdx.x / MB, tj = threadIdx.x % MB;
+    // Point k's block B_k and the rows of defect k pass through LDS one step
+    // ahead of their use: the block in the factorisation's two buffers (row r,
+    // column c at [r][c], thread (r, c) loads it), the defect rows in a ring of
+    // three slots of the reduction array (rr then js), both free here.
+    double(*const buf[2])[kMB + 1] = {sh.A, sh.X};
+    double *const ring = sh.red;
+    buf[0][ti][tj] = bentry(T, Jx, Ju, h2, 0, ti, tj);
+    double nxt = bentry(T, Jx, Ju, h2, 1, ti, tj);
+    double nrr = 0.0, njs = 0.0;
+    if ((int)threadIdx.x < MB) {
+        ring[threadIdx.x] = rr[threadIdx.x];
+        ring[MB + threadIdx.x] = js[threadIdx.x];
+        nrr = rr[(size_t)MB + threadIdx.x];
+        njs = js[(size_t)MB + threadIdx.x];
+    }
+    // bounds and tracking of entries ti and tj (point independent); their
+    // entries of z and of the path, one point ahead
+    auto lo_of = [&](int e) { return e < n ? (double)P.joints[e].qmin : e < nx ? -T.v_max[e - n] : 0.0; };
+    auto hi_of = [&](int e) { return e < n ? (double)P.joints[e].qmax : e < nx ? T.v_max[e - n] : 0.0; };
+    const double lo_i = lo_of(ti), hi_i = hi_of(ti), lo_j = lo_of(tj), hi_j = hi_of(tj);
+    bool track_i = false, track_j = false;
+    for (int j = 0; j < na; ++j) {
+        track_i = track_i || T.act[j] == ti;
+        track_j = track_j || T.act[j] == tj;
+    }
+    double zi = z[ti], zj = z[tj], qj = tj < n ? (double)in.qstar[tj] : 0.0;
     for (int k = 0; k <= N; ++k) {
         const bool fixed = k == 0 || k == N;
+        const double zi_k = zi, zj_k = zj, qj_k = qj;
+        if (k + 1 <= N) {
+            zi = z[(size_t)(k + 1) * MB + ti];
+            zj = z[(size_t)(k + 1) * MB + tj];
+            qj = tj < n ? (double)in.qstar[(size_t)(k + 1) * n + tj] : 0.0;
+        }
+        if (k + 1 <= N) buf[(k + 1) & 1][ti][tj] = nxt;
+        nxt = k + 2 <= N ? bentry(T, Jx, Ju, h2, k + 2, ti, tj) : 0.0;
+        if ((int)threadIdx.x < MB) {
+            if (k + 1 < N) {
+                double *sl = ring + ((k + 1) % 3) * 2 * MB;
+                sl[threadIdx.x] = nrr;
+                sl[MB + threadIdx.x] = njs;
+            }
+            if (k + 2 < N) {
+                nrr = rr[(size_t)(k + 2) * MB + threadIdx.x];
+                njs = js[(size_t)(k + 2) * MB + threadIdx.x];
+            }
+        }
+        __syncthreads();
+        const double(*Bk)[kMB + 1] = buf[k & 1];
+        const double(*Bn)[kMB + 1] = buf[(k + 1) & 1];
+        const double *dk = ring + (k % 3) * 2 * MB;             // defect k (k < N)
+        const double *dp = ring + ((k + 2) % 3) * 2 * MB;       // defect k - 1 (k > 0)
         // columns ti, tj of point k's block and column tj of point k + 1's
         double bi[kMB], bj[kMB], bn[kMB];
 #pragma unroll
         for (int r = 0; r < kMB; ++r) {
-            bi[r] = bentry(T, Jx, Ju, h2, k, r, ti);
-            bj[r] = bentry(T, Jx, Ju, h2, k, r, tj);
-            bn[r] = k < N ? bentry(T, Jx, Ju, h2, k + 1, r, tj) : 0.0;
+            bi[r] = Bk[r][ti];
+            bj[r] = Bk[r][tj];
+            bn[r] = k < N ? Bn[r][tj] : 0.0;
         }
         // identity parts: free state columns of point k (both defects) and k + 1
         const bool free_i = ti < nx && !fixed, free_j = tj < nx && !fixed;
@@ -478,12 +528,9 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
             if (fixed && ti < nx) {
                 dsum = 1.0;
             } else if (ti < nx) {
-                const double x = z[(size_t)k * MB + ti];
-                const double lo = ti < n ? (double)P.joints[ti].qmin : -T.v_max[ti - n];
-                const double hi = ti < n ? (double)P.joints[ti].qmax : T.v_max[ti - n];
-                if (x > hi || x < lo) dsum += mu;
-                for (int j = 0; j < na; ++j)
-                    if (T.act[j] == ti && k < N) dsum += T.omega_t;
+                const double x = zi_k;
+                if (x > hi_i || x < lo_i) dsum += mu;
+                if (track_i && k < N) dsum += T.omega_t;
             } else if (ti < nx + na) {
                 if (k >= 1) dsum += T.omega_s;
             } else {
@@ -504,27 +551,23 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
                 if (r >= nx) continue;
                 if (k < N) {
                     const double l = sm * (bj[r] + (free_j && r == col ? -1.0 : 0.0));
-                    cs += l * js[(size_t)k * MB + r];
-                    gsum += l * rr[(size_t)k * MB + r];
+                    cs += l * dk[MB + r];
+                    gsum += l * dk[r];
                 }
                 if (k > 0) {
                     const double rj = sm * (bj[r] + (free_j && r == col ? 1.0 : 0.0));
-                    cs += rj * js[(size_t)(k - 1) * MB + r];
-                    gsum += rj * rr[(size_t)(k - 1) * MB + r];
+                    cs += rj * dp[MB + r];
+                    gsum += rj * dp[r];
                 }
             }
             if (!(fixed && col < nx)) {
                 if (col < nx) {
-                    const double x = z[(size_t)k * MB + col];
-                    const double lo = col < n ? (double)P.joints[col].qmin : -T.v_max[col - n];
-                    const double hi = col < n ? (double)P.joints[col].qmax : T.v_max[col - n];
-                    if (x > hi) gsum += mu * (x - hi);
-                    if (x < lo) gsum -= mu * (lo - x);
-                    for (int j = 0; j < na; ++j)
-                        if (T.act[j] == col && k < N)
-                            gsum += T.omega_t * (x - (double)in.qstar[(size_t)k * n + col]);
+                    const double x = zj_k;
+                    if (x > hi_j) gsum += mu * (x - hi_j);
+                    if (x < lo_j) gsum -= mu * (lo_j - x);
+                    if (track_j && k < N) gsum += T.omega_t * (x - qj_k);
                 } else if (col < nx + na && k >= 1) {
-                    gsum += T.omega_s * z[(size_t)k * MB + col];
+                    gsum += T.omega_s * zj_k;
                 }
             } else {
                 cs = 0.0;
@@ -534,6 +577,7 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
             c[(size_t)k * MB + col] = cs;
             g[(size_t)k * MB + col] = gsum;
         }
+        __syncthreads();
     }
     // corner and g_s: sums over the defect rows, plus the final-time bound
     double gs_part = 0.0, ass_part = 0.0;
@@ -594,8 +638,9 @@ __device__ void factor(const double *D, const double *E, double damp, int nreal_
                        int N, TrajShared &sh) {
     const int MB = kMB;
     const int ti = threadIdx.x / MB, tj = threadIdx.x % MB;
+    double dcur = D[ti * MB + tj];
     for (int k = 0; k <= N; ++k) {
-        double a = D[(size_t)k * MB * MB + ti * MB + tj];
+        double a = dcur;
         if (ti == tj) a += damp;
         if (k > 0) {
             // minus X_{k-1}^T X_{k-1}, X_{k-1} = L_{k-1}^-1 E_{k-1} (in sh.X)
@@ -603,25 +648,30 @@ __device__ void factor(const double *D, const double *E, double damp, int nreal_
             for (int m = 0; m < MB; ++m) s += sh.X[m][ti] * sh.X[m][tj];
             a -= s;
         }
+        // E_k's entry and the next block's D: their loads run under the factorisation
+        const double ek = k < N ? E[(size_t)k * MB * MB + ti * MB + tj] : 0.0;
+        if (k < N) dcur = D[(size_t)(k + 1) * MB * MB + ti * MB + tj];
         __syncthreads();
         sh.A[ti][tj] = a;
+        sh.X[ti][tj] = ek;
         __syncthreads();
         if ((int)threadIdx.x < 2 * MB) chol_rows(sh);
         __syncthreads();
         LD[(size_t)k * MB * MB + ti * MB + tj] = tj <= ti ? sh.A[ti][tj] : 0.0;
         if (k < N) {
-            // X_k = L_k^-1 E_k: forward substitution, one column per thread
+            // X_k = L_k^-1 E_k: forward substitution, one column per thread, in place in sh.X
             if ((int)threadIdx.x < MB) {
                 const int col = threadIdx.x;
-                // the column of E_k first (its loads all in flight at once), then the
-                // substitution in registers
                 double x[kMB];
-                for (int i = 0; i < kMB; ++i) x[i] = E[(size_t)k * MB * MB + i * MB + col];
+#pragma unroll
+                for (int i = 0; i < kMB; ++i) x[i] = sh.X[i][col];
+#pragma unroll
                 for (int i = 0; i < kMB; ++i) {
                     double v = x[i];
                     for (int m = 0; m < i; ++m) v -= sh.A[i][m] * x[m];
                     x[i] = v / sh.A[i][i];
                 }
+#pragma unroll
                 for (int i = 0; i < kMB; ++i) sh.X[i][col] = x[i];
             }
             __syncthreads();
