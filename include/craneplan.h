@@ -241,7 +241,10 @@ const char *cp_last_error(void);
  * hold configuration. */
 int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const cp_cost_params *cost,
                    int device, cp_plan **out);
-int cp_plan_destroy(cp_plan *plan); /* SYNC; NULL is a no-op */
+/* Release the caller's handle (SYNC; NULL is a no-op).  The plan's memory is
+ * freed now, or, if optimizers created on it are still alive, when the last
+ * of them is destroyed; the handle must not be used again either way. */
+int cp_plan_destroy(cp_plan *plan);
 
 /* Start and goal configurations q_0 and q_d (host [n_joints]) (SYNC). */
 int cp_plan_set_endpoints(cp_plan *plan, const float *q_start, const float *q_goal);
@@ -286,7 +289,8 @@ int cp_eval_paths_backward(cp_plan *plan, const float *d_waypoints, int32_t B, c
 
 /* Optimizer on a plan (SYNC).  mu_0 = evenly spaced waypoints on the segment
  * from q_start to q_goal (sampled joints only), C_0 = sigma0^2 I, t = 0.  The
- * plan must outlive the optimizer; its endpoints are read at every step. */
+ * optimizer keeps the plan alive (cp_plan_destroy and cp_optimizer_destroy
+ * may come in either order); the plan's endpoints are read at every step. */
 int cp_optimizer_create(cp_plan *plan, const cp_opt_params *params, cp_opt **out);
 int cp_optimizer_destroy(cp_opt *opt); /* SYNC; NULL is a no-op */
 

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <string>
@@ -111,6 +112,10 @@ hipError_t scratch_on(int dev, double2 **out) {
 }  // namespace
 
 struct cp_plan {
+    // the caller's handle plus one per optimizer created on the plan: the
+    // plan is freed when the last of them lets go (cp_plan_destroy and
+    // cp_optimizer_destroy may come in either order)
+    std::atomic<int> refs{1};
     int device = 0;
     int n = 0, S = 0, K = 0, M = 0, ns = 0, max_B = 0;
     int n_cyl = 0, n_box = 0;
@@ -668,13 +673,17 @@ int cp_plan_create(const cp_robot_desc *robot, const cp_scene_desc *scene, const
     return CP_OK;
 }
 
+static void plan_release(cp_plan *plan) {
+    if (plan->refs.fetch_sub(1) == 1) delete plan;
+}
+
 int cp_plan_destroy(cp_plan *plan) {
     if (!plan) return CP_OK;
     {
         DeviceGuard g(plan->device);
         (void)hipDeviceSynchronize();
     }
-    delete plan;
+    plan_release(plan);
     return CP_OK;
 }
 
@@ -925,17 +934,20 @@ int cp_optimizer_create(cp_plan *plan, const cp_opt_params *prm, cp_opt **out) {
         delete o;
         return hip_fail(e, "optimizer init");
     }
+    plan->refs.fetch_add(1);
     *out = o;
     return CP_OK;
 }
 
 int cp_optimizer_destroy(cp_opt *opt) {
     if (!opt) return CP_OK;
+    cp_plan *plan = opt->plan;
     {
-        DeviceGuard g(opt->plan->device);
+        DeviceGuard g(plan->device);
         (void)hipDeviceSynchronize();
     }
     delete opt;
+    plan_release(plan);
     return CP_OK;
 }
 

@@ -655,6 +655,27 @@ def test_update_parity_many_elites(cp, K, B, nu):
         opt.debug_update(torch.from_numpy(bad.astype(np.int32)))
 
 
+def test_plan_destroyed_before_its_optimizer(cp):
+    """cp_plan_destroy before cp_optimizer_destroy (the order a garbage
+    collector may pick for a plan and an optimizer in one reference cycle):
+    the optimizer keeps its plan alive and still steps, and destroying it
+    afterwards leaves no HIP error behind for the next caller."""
+    import ctypes
+    prob = synth.c0_plain()
+    plan = cp.Plan(prob.robot, prob.scene, prob.cost, max_B=prob.opt.B)
+    plan.set_endpoints(prob.q_start, prob.q_goal)
+    opt = cp.Optimizer(plan, prob.opt)
+    opt.step(1)
+    plan.close()
+    opt.step(2)
+    torch.cuda.synchronize()
+    assert np.isfinite(opt.get_state()["best_cost"])
+    opt.close()
+    hip = ctypes.CDLL("libamdhip64.so")
+    assert hip.hipPeekAtLastError() == 0
+    assert torch.ones(4, device="cuda").sum().item() == 4.0
+
+
 def test_optimizer_runs_and_is_deterministic(cp):
     prob = synth.c0_plain()
     out = []
