@@ -326,7 +326,7 @@ struct TrajShared {
     double red[kTrajThreads];
     double A[kMB][kMB + 1];     // the block being factored
     double X[kMB][kMB + 1];     // L^-1 E of the previous block
-    double v[2][kMB];           // right-hand sides in flight
+    double v[2][kMB];           // v[0]: 1 / L_jj of the block being factored
     double scal[8];
 };
 
@@ -620,9 +620,11 @@ __device__ void chol_rows(TrajShared &sh) {
     for (int m = 0; m < kMB; ++m) a[m] = sh.A[i][m];
 #pragma unroll
     for (int j = 0; j < kMB; ++j) {
-        const double piv = sqrt(lane_value(a[j], j));
-        if (i == j) a[j] = piv;
-        else if (i > j) a[j] /= piv;
+        // column j: L_jj = a_jj / sqrt(a_jj), L_ij = a_ij / sqrt(a_jj); 1 / L_jj kept for the
+        // substitutions
+        const double rp = rsqrt(lane_value(a[j], j));
+        if (i >= j) a[j] *= rp;
+        if (i == j && (int)threadIdx.x < kMB) sh.v[0][j] = rp;
 #pragma unroll
         for (int m = j + 1; m < kMB; ++m) {
             const double lmj = lane_value(a[j], m);
@@ -659,17 +661,19 @@ __device__ void factor(const double *D, const double *E, double damp, int nreal_
         __syncthreads();
         LD[(size_t)k * MB * MB + ti * MB + tj] = tj <= ti ? sh.A[ti][tj] : 0.0;
         if (k < N) {
-            // X_k = L_k^-1 E_k: forward substitution, one column per thread, in place in sh.X
+            // X_k = L_k^-1 E_k: forward substitution, one column per thread, in place in
+            // sh.X, column by column of L (each solved entry updates the rows below it, so
+            // the updates of one step are independent)
             if ((int)threadIdx.x < MB) {
                 const int col = threadIdx.x;
                 double x[kMB];
 #pragma unroll
                 for (int i = 0; i < kMB; ++i) x[i] = sh.X[i][col];
 #pragma unroll
-                for (int i = 0; i < kMB; ++i) {
-                    double v = x[i];
-                    for (int m = 0; m < i; ++m) v -= sh.A[i][m] * x[m];
-                    x[i] = v / sh.A[i][i];
+                for (int m = 0; m < kMB; ++m) {
+                    x[m] *= sh.v[0][m];
+#pragma unroll
+                    for (int i = m + 1; i < kMB; ++i) x[i] -= sh.A[i][m] * x[m];
                 }
 #pragma unroll
                 for (int i = 0; i < kMB; ++i) sh.X[i][col] = x[i];
