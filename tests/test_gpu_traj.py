@@ -108,6 +108,35 @@ def test_traj_paper_horizon(cp):
     _check(dev, _oracle(robot, par, q0, qg, qstar), 2e-6, "N=100", False)
 
 
+def test_traj_bench_launch_sampled(cp):
+    """The benchmark's own launch: 256 problems at N = 100 with the default
+    settings in one call.  Problems 0, 128 and 255 against the oracle one by
+    one (converged solves, 2e-6 as above); every problem checked for what
+    holds at any size: the fixed end states exactly, finite outputs, step
+    counts within the limits, and where the defects are below 1e-8 the
+    velocity limits and t_F >= t_min."""
+    robot = synth.c1_full().robot
+    par = synth.TrajParams(N=100)
+    P = 256
+    q0, qg, qstar = synth.traj_problems(robot, P, par.N, synth.SCENE_SEED + 11)
+    X, U, tf, info = _run(cp, robot, par, q0, qg, qstar, "bench launch")
+    n = robot.n_joints
+    np.testing.assert_array_equal(X[:, 0, :n], q0.astype(np.float64))
+    np.testing.assert_array_equal(X[:, -1, :n], qg.astype(np.float64))
+    assert np.all(X[:, 0, n:] == 0) and np.all(X[:, -1, n:] == 0)
+    assert np.all(np.isfinite(X)) and np.all(np.isfinite(U)) and np.all(np.isfinite(tf))
+    assert np.all(info[:, 3] <= info[:, 2]) and np.all(info[:, 2] <= par.outer * par.max_iters)
+    m = oracle.Model(robot, synth.c0_plain().scene, None)
+    t_min = np.array([oracle.traj_t_min(m, par, q0[p].astype(np.float64), qg[p].astype(np.float64)) for p in range(P)])
+    ok = info[:, 0] < 1e-8
+    assert ok.mean() > 0.8
+    assert np.all(tf[ok] >= t_min[ok] * (1 - 1e-6))
+    assert np.all(np.abs(X[ok][:, :, n:]) <= np.asarray(par.v_max)[None, None, :] + 1e-4)
+    idx = [0, 128, 255]
+    refs = _oracle(robot, par, q0[idx], qg[idx], qstar[idx])
+    _check(tuple(a[idx] for a in (X, U, tf, info)), refs, 2e-6, "bench launch", False)
+
+
 def test_traj_edge_cases(cp):
     """No trial steps (the starting point comes back with t_F = max(t_f0,
     t_min)); a start above t_f0 set by t_min; two intervals; one problem; a
