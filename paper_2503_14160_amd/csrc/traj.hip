@@ -29,7 +29,7 @@ constexpr int kTrajThreads = 256;
 constexpr int kMB = kTrajBlock;  // block size 2n + n_a (padded)
 
 struct TrajDev {
-    int N, n, na, MB, outer, max_iters;
+    int N, n, na, outer, max_iters;
     double omega_s, omega_t, grav, damping, mu0, mu_factor, tau, eps_grad, eps_step, fd_q, t_f0;
     double v_max[CP_MAX_JOINTS];
     int act[CP_MAX_JOINTS];
@@ -327,7 +327,6 @@ struct TrajShared {
     double A[kMB][kMB + 1];     // the block being factored
     double X[kMB][kMB + 1];     // L^-1 E of the previous block
     double v[2][kMB];           // v[0]: 1 / L_jj of the block being factored
-    double scal[8];
 };
 
 __device__ double block_sum(TrajShared &sh, double v) {
@@ -636,7 +635,7 @@ __device__ void chol_rows(TrajShared &sh) {
         for (int m = 0; m < kMB; ++m) sh.A[i][m] = a[m];
 }
 
-__device__ void factor(const double *D, const double *E, double damp, int nreal_last, double *LD, double *LX,
+__device__ void factor(const double *D, const double *E, double damp, double *LD, double *LX,
                        int N, TrajShared &sh) {
     const int MB = kMB;
     const int ti = threadIdx.x / MB, tj = threadIdx.x % MB;
@@ -751,7 +750,7 @@ __device__ void solve2(const double *LD, const double *LX, double *b0, double *b
 __device__ void damped_step(const TrajDev &T, const TrajWork &W, double a_ss, double damp, TrajShared &sh) {
     const int N = T.N;
     const size_t nb = (size_t)(N + 1) * kMB;
-    factor(W.D, W.E, damp, 0, W.LD, W.LX, N, sh);
+    factor(W.D, W.E, damp, W.LD, W.LX, N, sh);
     for (size_t t = threadIdx.x; t < nb; t += kTrajThreads) {
         W.y[t] = -W.g[t];
         W.w[t] = W.c[t];
@@ -946,7 +945,6 @@ hipError_t launch_traj_refine(const PlanView &P, const cp_traj_params &prm, cons
     T.n = P.n_joints;
     T.na = n_act;
     for (int j = 0; j < CP_MAX_JOINTS; ++j) T.act[j] = j < n_act ? act[j] : 0;
-    T.MB = kMB;
     T.outer = prm.outer;
     T.max_iters = prm.max_iters;
     T.omega_s = prm.omega_s; T.omega_t = prm.omega_t; T.grav = prm.grav; T.damping = prm.damping;
