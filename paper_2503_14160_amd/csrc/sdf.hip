@@ -82,6 +82,59 @@ __global__ __launch_bounds__(64) void k_edt_row(const uint8_t *__restrict__ occ,
     }
 }
 
+// the same pass for rows of at most 256 voxels: one wave per row, four
+// consecutive voxels per lane.  Each lane finds its own nearest target at or
+// before / at or after each of its voxels; the nearest one in the lanes
+// before / after it comes from a ballot of the lanes holding a target, the
+// bit of the closest such lane, and one shuffle of that lane's last / first
+// target.  The same integers as the two sweeps above.
+__global__ __launch_bounds__(256) void k_edt_row_wave(const uint8_t *__restrict__ occ, uint8_t target, int nx,
+                                                      int rows, int32_t *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= rows) return;  // whole waves leave together
+    const uint8_t *src = occ + (size_t)row * nx;
+    const int x0 = 4 * lane;
+    bool hit[4];
+    int first = -1, last = -1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        hit[j] = x0 + j < nx && src[x0 + j] == target;
+        if (hit[j]) {
+            if (first < 0) first = x0 + j;
+            last = x0 + j;
+        }
+    }
+    const unsigned long long m = __ballot(last >= 0);
+    const unsigned long long below = m & ((1ull << lane) - 1ull);
+    const unsigned long long above = lane == 63 ? 0ull : m & ~((2ull << lane) - 1ull);
+    const int src_b = below ? 63 - __clzll((long long)below) : 0;
+    const int src_a = above ? __ffsll((long long)above) - 1 : 0;
+    const int last_before = __shfl(last, src_b);
+    const int first_after = __shfl(first, src_a);
+    int prev = below ? last_before : -1;
+    int next = above ? first_after : -1;
+    // forward within the lane: the nearest target at or before each voxel
+    int pv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (hit[j]) prev = x0 + j;
+        pv[j] = prev;
+    }
+    int32_t *dst = out + (size_t)row * nx;
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+        if (hit[j]) next = x0 + j;
+        const int x = x0 + j;
+        int32_t r = pv[j] < 0 ? kEdtInf : (x - pv[j]) * (x - pv[j]);
+        if (next >= 0) {
+            const int32_t d = (next - x) * (next - x);
+            if (d < r) r = d;
+        }
+        if (x < nx) dst[x] = r;
+    }
+}
+
 // pass along a strided axis of length L (y: stride nx; z: stride nx*ny):
 // out(q) = min over l of f(l) + (q - l)^2, the lower envelope of the
 // parabolas rooted at the finite samples (Felzenszwalb and Huttenlocher,
@@ -231,9 +284,13 @@ static hipError_t edt3(const uint8_t *occ, uint8_t target, int nx, int ny, int n
                        hipStream_t st) {
     // x pass into out, y pass out -> tmp, z pass tmp -> out
     const int rows = ny * nz;
-    const int xl = edt_lines(nx, 5);
-    hipLaunchKernelGGL(k_edt_row, dim3((rows + xl - 1) / xl), dim3(xl), (size_t)nx * xl * 5, st, occ, target, nx, rows,
-                       out);
+    if (nx <= 256) {
+        hipLaunchKernelGGL(k_edt_row_wave, dim3((rows + 3) / 4), dim3(256), 0, st, occ, target, nx, rows, out);
+    } else {
+        const int xl = edt_lines(nx, 5);
+        hipLaunchKernelGGL(k_edt_row, dim3((rows + xl - 1) / xl), dim3(xl), (size_t)nx * xl * 5, st, occ, target, nx,
+                           rows, out);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // y lines: (x, z), stride nx; z lines: (x, y), stride nx * ny
