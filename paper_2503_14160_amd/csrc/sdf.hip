@@ -240,13 +240,30 @@ __global__ __launch_bounds__(256) void k_edt_short(const int32_t *__restrict__ i
         tile[idx] = min(f, kEdtInf) + l * l;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < L * kEdtCols; idx += blockDim.x) {
-        const int l = idx / kEdtCols, c = idx % kEdtCols;
+    // eight outputs per thread, rows l0 + 8 r of one column (the block covers 8
+    // rows per pass): each staged sample read from LDS serves all eight
+    constexpr int kRows = 8;
+    const int rows_per_pass = blockDim.x / kEdtCols;
+    for (int idx = threadIdx.x; idx < L * kEdtCols; idx += blockDim.x * kRows) {
+        const int l0 = idx / kEdtCols, c = idx % kEdtCols;
         if (c >= ncol) continue;
-        const int m2l = -2 * l;
-        int32_t best = 2 * kEdtInf;
-        for (int l2 = 0; l2 < L; ++l2) best = min(best, tile[l2 * kEdtCols + c] + __mul24(m2l, l2));
-        out[base + (size_t)l * stride + c] = min(best + l * l, kEdtInf);
+        int m2l[kRows];
+        int32_t best[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            m2l[r] = -2 * (l0 + r * rows_per_pass);
+            best[r] = 2 * kEdtInf;
+        }
+        for (int l2 = 0; l2 < L; ++l2) {
+            const int32_t v = tile[l2 * kEdtCols + c];
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) best[r] = min(best[r], v + __mul24(m2l[r], l2));
+        }
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const int l = l0 + r * rows_per_pass;
+            if (l < L) out[base + (size_t)l * stride + c] = min(best[r] + l * l, kEdtInf);
+        }
     }
 }
 
