@@ -493,32 +493,25 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
         const double(*Bn)[kMB + 1] = buf[(k + 1) & 1];
         const double *dk = ring + (k % 3) * 2 * MB;             // defect k (k < N)
         const double *dp = ring + ((k + 2) % 3) * 2 * MB;       // defect k - 1 (k > 0)
-        // columns ti, tj of point k's block and column tj of point k + 1's
-        double bi[kMB], bj[kMB], bn[kMB];
-#pragma unroll
-        for (int r = 0; r < kMB; ++r) {
-            bi[r] = Bk[r][ti];
-            bj[r] = Bk[r][tj];
-            bn[r] = k < N ? Bn[r][tj] : 0.0;
-        }
+        // columns ti, tj of point k's block and column tj of point k + 1's are read
+        // from LDS row by row below
         // identity parts: free state columns of point k (both defects) and k + 1
         const bool free_i = ti < nx && !fixed, free_j = tj < nx && !fixed;
         const bool free_n = tj < nx && k + 1 != N;
         // D_k (ti, tj) and E_k (ti, tj): defect k (left block L_k = sqrt(mu) (B_k - I)), defect
         // k - 1 (right block R_{k-1} = sqrt(mu) (B_k + I)), E_k = L_k^T R_k
         double dsum = 0.0, esum = 0.0;
-#pragma unroll
-        for (int r = 0; r < kMB; ++r) {
-            if (r >= nx) continue;
+        for (int r = 0; r < nx; ++r) {
+            const double bi = Bk[r][ti], bj = Bk[r][tj];
             if (k < N) {
-                const double l_i = sm * (bi[r] + (free_i && r == ti ? -1.0 : 0.0));
-                const double l_j = sm * (bj[r] + (free_j && r == tj ? -1.0 : 0.0));
+                const double l_i = sm * (bi + (free_i && r == ti ? -1.0 : 0.0));
+                const double l_j = sm * (bj + (free_j && r == tj ? -1.0 : 0.0));
                 dsum += l_i * l_j;
-                esum += l_i * (sm * (bn[r] + (free_n && r == tj ? 1.0 : 0.0)));
+                esum += l_i * (sm * (Bn[r][tj] + (free_n && r == tj ? 1.0 : 0.0)));
             }
             if (k > 0) {
-                const double r_i = sm * (bi[r] + (free_i && r == ti ? 1.0 : 0.0));
-                const double r_j = sm * (bj[r] + (free_j && r == tj ? 1.0 : 0.0));
+                const double r_i = sm * (bi + (free_i && r == ti ? 1.0 : 0.0));
+                const double r_j = sm * (bj + (free_j && r == tj ? 1.0 : 0.0));
                 dsum += r_i * r_j;
             }
         }
@@ -545,16 +538,15 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
         if ((int)threadIdx.x < MB) {
             const int col = tj;
             double cs = 0.0, gsum = 0.0;
-    #pragma unroll
-        for (int r = 0; r < kMB; ++r) {
-                if (r >= nx) continue;
+            for (int r = 0; r < nx; ++r) {
+                const double bj = Bk[r][tj];
                 if (k < N) {
-                    const double l = sm * (bj[r] + (free_j && r == col ? -1.0 : 0.0));
+                    const double l = sm * (bj + (free_j && r == col ? -1.0 : 0.0));
                     cs += l * dk[MB + r];
                     gsum += l * dk[r];
                 }
                 if (k > 0) {
-                    const double rj = sm * (bj[r] + (free_j && r == col ? 1.0 : 0.0));
+                    const double rj = sm * (bj + (free_j && r == col ? 1.0 : 0.0));
                     cs += rj * dp[MB + r];
                     gsum += rj * dp[r];
                 }
