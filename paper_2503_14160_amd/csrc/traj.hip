@@ -534,39 +534,33 @@ __device__ void normal_equations(const PlanView &P, const TrajDev &T, const Traj
         if (ti >= nx + na || tj >= nx + na) dsum = ti == tj ? 1.0 : 0.0;
         D[(size_t)k * MB * MB + ti * MB + tj] = dsum;
         if (k < N) E[(size_t)k * MB * MB + ti * MB + tj] = esum;
-        // c_k, g_k (threads 0..MB-1: ti = 0, tj = col, so bj is column col of B_k)
-        if ((int)threadIdx.x < MB) {
+        // c_k on the second wave (ti = 4), g_k on the third (ti = 8): one entry per thread,
+        // column col = tj of B_k, so that no wave carries both beside its D and E entries
+        if (ti == 4 || ti == 8) {
             const int col = tj;
-            double cs = 0.0, gsum = 0.0;
+            const bool is_c = ti == 4;
+            const int off = is_c ? MB : 0;  // js or rr within a defect's slot
+            double sum = 0.0;
             for (int r = 0; r < nx; ++r) {
                 const double bj = Bk[r][tj];
-                if (k < N) {
-                    const double l = sm * (bj + (free_j && r == col ? -1.0 : 0.0));
-                    cs += l * dk[MB + r];
-                    gsum += l * dk[r];
-                }
-                if (k > 0) {
-                    const double rj = sm * (bj + (free_j && r == col ? 1.0 : 0.0));
-                    cs += rj * dp[MB + r];
-                    gsum += rj * dp[r];
-                }
+                if (k < N) sum += sm * (bj + (free_j && r == col ? -1.0 : 0.0)) * dk[off + r];
+                if (k > 0) sum += sm * (bj + (free_j && r == col ? 1.0 : 0.0)) * dp[off + r];
             }
-            if (!(fixed && col < nx)) {
-                if (col < nx) {
-                    const double x = zj_k;
-                    if (x > hi_j) gsum += mu * (x - hi_j);
-                    if (x < lo_j) gsum -= mu * (lo_j - x);
-                    if (track_j && k < N) gsum += T.omega_t * (x - qj_k);
-                } else if (col < nx + na && k >= 1) {
-                    gsum += T.omega_s * zj_k;
+            if (!(fixed && col < nx) && col < nx + na) {
+                if (!is_c) {
+                    if (col < nx) {
+                        const double x = zj_k;
+                        if (x > hi_j) sum += mu * (x - hi_j);
+                        if (x < lo_j) sum -= mu * (lo_j - x);
+                        if (track_j && k < N) sum += T.omega_t * (x - qj_k);
+                    } else if (k >= 1) {
+                        sum += T.omega_s * zj_k;
+                    }
                 }
             } else {
-                cs = 0.0;
-                gsum = 0.0;
+                sum = 0.0;
             }
-            if (col >= nx + na) { cs = 0.0; gsum = 0.0; }
-            c[(size_t)k * MB + col] = cs;
-            g[(size_t)k * MB + col] = gsum;
+            (is_c ? c : g)[(size_t)k * MB + col] = sum;
         }
         __syncthreads();
     }
